@@ -1,0 +1,224 @@
+"""CPU oracle of the FastAtlas per-frame atlasing path (TEST INFRASTRUCTURE).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU-baseline
+leg may import this package. The GPU library never uses it. The arithmetic
+lives in ``fa_oracle.cpp`` (single-threaded, float32 in a fixed order, built
+with ``-ffp-contract=off``); this module only marshals numpy arrays and calls
+the steps in the paper's order:
+
+  clip -> charts -> per-triangle boxes -> chart frames/sizes -> order ->
+  J candidate packings -> selection -> UVs -> occupancy.
+
+No step here is parity-unpinned: every step has an independent pin in
+``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fa_oracle.cpp")
+_LIB = os.path.join(_HERE, "libfa_oracle.so")
+
+STATUS_OK = 0
+STATUS_NOFIT = 4
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (-O2, no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(build())
+        P = ctypes.c_void_p
+        i64, i32, f32 = ctypes.c_int64, ctypes.c_int32, ctypes.c_float
+        L.oracle_clip.argtypes = [P, i64, P, P]
+        L.oracle_adjacency.argtypes = [P, i64, P]
+        L.oracle_charts.argtypes = [P, i64, i64, P, P, P, P]
+        L.oracle_charts.restype = i64
+        L.oracle_triangle_boxes.argtypes = [P, P, P, i64, ctypes.c_int, P, P]
+        L.oracle_chart_frames.argtypes = [P, P, P, i64, i64, i32, i32, f32, P, P, P, P, P]
+        L.oracle_order.argtypes = [P, i64, P]
+        L.oracle_candidate.argtypes = [P, P, i64, i32, i32, i32, i32, i32, P, P, P, P, P]
+        L.oracle_select.argtypes = [P, i32]
+        L.oracle_select.restype = i32
+        L.oracle_uv.argtypes = [P, i64, P, P, P, P, P, P, i32, i32, f32, i32, i32, i32, i64, i32, P]
+        L.oracle_occupancy.argtypes = [P, P, P, P, i64, P, P, P, P, P, P, P, i32, i32, f32, i32,
+                                       i32, i32, i64, i32, P]
+        L.oracle_occupancy.restype = i64
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+# ---------------------------------------------------------------------------
+# individual steps
+# ---------------------------------------------------------------------------
+def clip(positions, view_proj):
+    pos = _c(positions, np.float32)
+    M = _c(view_proj, np.float32).ravel()
+    out = np.empty((pos.shape[0], 4), np.float32)
+    lib().oracle_clip(_p(pos), pos.shape[0], _p(M), _p(out))
+    return out
+
+
+def adjacency(indices):
+    idx = _c(indices, np.int32)
+    out = np.empty((idx.shape[0], 3), np.int32)
+    lib().oracle_adjacency(_p(idx), idx.shape[0], _p(out))
+    return out
+
+
+def charts(indices, num_vertices, visible):
+    idx = _c(indices, np.int32)
+    vis = _c(visible, np.uint8)
+    T = idx.shape[0]
+    cot = np.empty(T, np.int32)
+    cov = np.empty(num_vertices, np.int32)
+    roots = np.empty(max(T, 1), np.int32)
+    C = lib().oracle_charts(_p(idx), T, num_vertices, _p(vis), _p(cot), _p(cov), _p(roots))
+    return cot, cov, roots[:C].copy()
+
+
+def triangle_boxes(clip_xyzw, indices, visible, side_clip=True):
+    c = _c(clip_xyzw, np.float32)
+    idx = _c(indices, np.int32)
+    vis = _c(visible, np.uint8)
+    T = idx.shape[0]
+    box = np.empty((T, 4), np.float32)
+    ne = np.empty(T, np.uint8)
+    lib().oracle_triangle_boxes(_p(c), _p(idx), _p(vis), T, int(side_clip), _p(box), _p(ne))
+    return box, ne
+
+
+def chart_frames(box, nonempty, chart_of_tri, C, W, H, rate):
+    box, ne, cot = _c(box, np.float32), _c(nonempty, np.uint8), _c(chart_of_tri, np.int32)
+    frame = np.zeros((C, 4), np.float32)
+    target = np.zeros((C, 2), np.float32)
+    oriented = np.zeros((C, 2), np.float32)
+    rot = np.zeros(C, np.int32)
+    key = np.zeros(C, np.int32)
+    lib().oracle_chart_frames(_p(box), _p(ne), _p(cot), cot.shape[0], C, W, H, float(rate),
+                              _p(frame), _p(target), _p(oriented), _p(rot), _p(key))
+    return frame, target, oriented, rot, key
+
+
+def order(key):
+    k = _c(key, np.int32)
+    out = np.empty(k.shape[0], np.int32)
+    lib().oracle_order(_p(k), k.shape[0], _p(out))
+    return out
+
+
+def candidate(sbw, sbh, j, J, omega, gutter=1, min_box=2):
+    """One candidate packing. Returns dict(fit, m, L, H, rows, x, y, a, b)
+    with per-box arrays in sorted order."""
+    w, h = _c(sbw, np.float32), _c(sbh, np.float32)
+    C = w.shape[0]
+    x, y, a, b = (np.empty(C, np.int32) for _ in range(4))
+    out = np.zeros(5, np.int64)
+    lib().oracle_candidate(_p(w), _p(h), C, j, J, omega, gutter, min_box, _p(x), _p(y), _p(a),
+                           _p(b), _p(out))
+    return dict(fit=bool(out[0]), m=int(out[1]), L=int(out[2]), H=int(out[3]), rows=int(out[4]),
+                x=x, y=y, a=a, b=b)
+
+
+def select(cand_table):
+    ct = _c(cand_table, np.int64)
+    return int(lib().oracle_select(_p(ct), ct.shape[0]))
+
+
+# ---------------------------------------------------------------------------
+# the whole path
+# ---------------------------------------------------------------------------
+def build_atlas(positions, indices, visible, view_proj, width, height, atlas_size, rate,
+                J=64, gutter=1, min_box=2, side_clip=True, want_occupancy=True,
+                want_adjacency=False):
+    """Run every step on one frame. Returns a dict of all intermediate and
+    final results (per-chart arrays are indexed by chart index)."""
+    pos = _c(positions, np.float32)
+    idx = _c(indices, np.int32)
+    vis = _c(visible, np.uint8)
+    T, V = idx.shape[0], pos.shape[0]
+    omega, W, H = int(atlas_size), int(width), int(height)
+    r = dict()
+    r["clip"] = clip(pos, view_proj)
+    if want_adjacency:
+        r["nbr"] = adjacency(idx)
+    cot, cov, roots = charts(idx, V, vis)
+    C = roots.shape[0]
+    r.update(chart_of_tri=cot, chart_of_vert=cov, roots=roots, num_charts=C)
+    box, ne = triangle_boxes(r["clip"], idx, vis, side_clip)
+    r.update(tri_box=box, nonempty=ne)
+    frame, target, oriented, rot, key = chart_frames(box, ne, cot, C, W, H, rate)
+    r.update(frame=frame, target=target, oriented=oriented, rotated=rot, key=key)
+    o = order(key)
+    rank = np.empty(C, np.int32)
+    rank[o] = np.arange(C, dtype=np.int32)
+    r.update(order=o, rank=rank)
+    sbw = np.ascontiguousarray(oriented[o, 0])
+    sbh = np.ascontiguousarray(oriented[o, 1])
+    table = np.zeros((J, 5), np.int64)
+    cands = []
+    for j in range(1, J + 1):
+        cd = candidate(sbw, sbh, j, J, omega, gutter, min_box)
+        cands.append(cd)
+        table[j - 1] = [cd["fit"], cd["m"], cd["L"], cd["H"], cd["rows"]]
+    r["cand"] = table
+    js = select(table)
+    r["jstar"] = js
+    px = np.zeros(C, np.int32)
+    py = np.zeros(C, np.int32)
+    pa = np.zeros(C, np.int32)
+    pb = np.zeros(C, np.int32)
+    if js == 0:
+        r.update(status=STATUS_NOFIT, L=0, H=0, s_eff=0.0, x=px, y=py, a=pa, b=pb)
+        return r
+    w = cands[js - 1]
+    px[o], py[o], pa[o], pb[o] = w["x"], w["y"], w["a"], w["b"]
+    L = w["L"]
+    s = np.float32(js) / np.float32(J)
+    q = np.float32(omega) / np.float32(L)
+    r.update(status=STATUS_OK, L=L, H=w["H"], s_eff=float(np.float32(s * q)), x=px, y=py, a=pa,
+             b=pb)
+    uv = np.empty((V, 2), np.float32)
+    clip_c = r["clip"]
+    lib().oracle_uv(_p(clip_c), V, _p(cov), _p(frame), _p(target), _p(rot), _p(px), _p(py), W, H,
+                    float(rate), js, J, omega, L, gutter, _p(uv))
+    r["uv"] = uv
+    if want_occupancy:
+        occ = np.empty((omega, omega), np.int32)
+        n = lib().oracle_occupancy(_p(clip_c), _p(idx), _p(ne), _p(cot), T, _p(frame), _p(target),
+                                   _p(rot), _p(px), _p(py), _p(pa), _p(pb), W, H, float(rate), js,
+                                   J, omega, L, gutter, _p(occ))
+        r.update(occupancy=occ, occupied=int(n))
+    return r
+
+
+def build_frame(frame, **kw):
+    """build_atlas on a synth.scenes.Frame."""
+    return build_atlas(frame.positions, frame.indices, frame.visible, frame.view_proj,
+                       frame.width, frame.height, frame.atlas_size, frame.rate, **kw)

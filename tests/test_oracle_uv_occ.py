@@ -1,0 +1,147 @@
+"""Pins for the oracle's UV map and occupancy (CPU only).
+
+* UV (Appendix "Shading and Rasterization": uniform scale S then a rigid map
+  per chart): for every visible triangle the screen-pixel -> atlas-texel map is
+  a similarity with factor rate * S_eff and positive orientation, so texture
+  stretch L2 = Linf = 1 / (rate * S_eff); at S_eff = 1 this reproduces the
+  paper's Table of stretch at fixed scale factors (tests/golden).
+* occupancy: every claimed texel lies in its chart's placed box, each texel
+  has at most one owner, and away from triangle edges the claim agrees with an
+  exact float64 point-in-triangle test of the texel centre against the
+  unsnapped UV triangles.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import scenes
+
+STRETCH = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "stretch_fixed_rate.json")))
+
+
+def _pixel_coords(clip, W, H):
+    c = clip.astype(np.float64)
+    nx, ny = c[:, 0] / c[:, 3], c[:, 1] / c[:, 3]
+    return np.stack([(nx + 1) * 0.5 * W, (1 - ny) * 0.5 * H], 1)
+
+
+def _jacobians(frame_, r):
+    clip = r["clip"]
+    P = _pixel_coords(clip, frame_.width, frame_.height)
+    uv = r["uv"].astype(np.float64)
+    idx = frame_.indices
+    vis = frame_.visible.astype(bool) & (clip[idx, 3] > 0).all(1)
+    t = np.nonzero(vis)[0]
+    p0, p1, p2 = P[idx[t, 0]], P[idx[t, 1]], P[idx[t, 2]]
+    u0, u1, u2 = uv[idx[t, 0]], uv[idx[t, 1]], uv[idx[t, 2]]
+    A = np.stack([p1 - p0, p2 - p0], 2)  # columns
+    B = np.stack([u1 - u0, u2 - u0], 2)
+    area = np.abs(np.linalg.det(A)) / 2
+    keep = area > 30.0  # well-conditioned triangles only
+    Jm = B[keep] @ np.linalg.inv(A[keep])
+    return Jm, area[keep]
+
+
+@pytest.mark.parametrize("maker", [lambda: scenes.grid_frame(2, 1024), lambda: scenes.orbit_frame(17)])
+def test_uv_similarity(maker):
+    f = maker()
+    r = oracle.build_frame(f, want_occupancy=False)
+    Jm, _ = _jacobians(f, r)
+    assert Jm.shape[0] > 20
+    sv = np.linalg.svd(Jm, compute_uv=False)
+    scale = f.rate * r["s_eff"]
+    assert np.allclose(sv, scale, rtol=1e-3)
+    assert (np.linalg.det(Jm) > 0).all()
+
+
+def test_stretch_matches_paper_table():
+    for row in STRETCH["rows"]:
+        sf = row["scale_factor"]
+        f = scenes.grid_frame(4, atlas_size=2048, rate=sf)
+        r = oracle.build_frame(f, want_occupancy=False)
+        assert r["s_eff"] == 1.0 and r["jstar"] == 64
+        Jm, area = _jacobians(f, r)
+        sv = np.linalg.svd(Jm, compute_uv=False)  # texels per pixel
+        stretch = 1.0 / sv  # pixels per texel along each axis
+        L2 = np.sqrt((area * (stretch ** 2).mean(1)).sum() / area.sum())
+        Linf = stretch.max()
+        assert abs(L2 - row["L2"]) < 1e-3 and abs(Linf - row["Linf"]) < 1e-3
+
+
+def test_uv_inside_placed_box():
+    f = scenes.orbit_frame(33)
+    r = oracle.build_frame(f, want_occupancy=False)
+    clip = r["clip"]
+    cov = r["chart_of_vert"]
+    inside = (np.abs(clip[:, 0]) <= clip[:, 3]) & (np.abs(clip[:, 1]) <= clip[:, 3]) & (clip[:, 3] > 0)
+    v = np.nonzero((cov >= 0) & inside)[0]
+    c = cov[v]
+    q = f.atlas_size / r["L"]
+    uv = r["uv"][v].astype(np.float64)
+    lo_u, hi_u = (r["x"][c] + 1) * q, (r["x"][c] + r["a"][c] - 1) * q
+    lo_v, hi_v = (r["y"][c] + 1) * q, (r["y"][c] + r["b"][c] - 1) * q
+    eps = 1e-3
+    assert ((uv[:, 0] >= lo_u - eps) & (uv[:, 0] <= hi_u + eps)).all()
+    assert ((uv[:, 1] >= lo_v - eps) & (uv[:, 1] <= hi_v + eps)).all()
+    assert np.isnan(r["uv"][cov < 0]).all()
+
+
+def _edge_dist(px, py, ax, ay, bx, by):
+    ex, ey = bx - ax, by - ay
+    ln = np.hypot(ex, ey)
+    return np.abs(ex * (py - ay) - ey * (px - ax)) / np.maximum(ln, 1e-300)
+
+
+@pytest.mark.parametrize("seed,omega,rate", [(5, 256, 0.25), (9, 512, 0.5)])
+def test_occupancy_vs_exact_point_in_triangle(seed, omega, rate):
+    f = scenes.grid_frame(seed, atlas_size=omega, rate=rate)
+    r = oracle.build_frame(f)
+    occ = r["occupancy"]
+    clip, uv = r["clip"], r["uv"].astype(np.float64)
+    assert not ((clip[:, 3] + clip[:, 2]) < 0).any()  # no near crossing in this case
+    want = np.full((omega, omega), -1, np.int64)
+    ambiguous = np.zeros((omega, omega), bool)
+    L = r["L"]
+    tx = np.arange(omega)
+    for t in np.nonzero(r["nonempty"])[0]:
+        c = r["chart_of_tri"][t]
+        P = uv[f.indices[t]]
+        x0, x1 = int(np.floor(P[:, 0].min() - 1)), int(np.ceil(P[:, 0].max() + 1))
+        y0, y1 = int(np.floor(P[:, 1].min() - 1)), int(np.ceil(P[:, 1].max() + 1))
+        xs = tx[max(0, x0):max(0, min(omega, x1))]
+        ys = tx[max(0, y0):max(0, min(omega, y1))]
+        if xs.size == 0 or ys.size == 0:
+            continue
+        X, Y = np.meshgrid(xs + 0.5, ys + 0.5)
+        e = [(P[(k + 1) % 3, 0] - P[k, 0]) * (Y - P[k, 1]) - (P[(k + 1) % 3, 1] - P[k, 1]) * (X - P[k, 0])
+             for k in range(3)]
+        inside = ((e[0] >= 0) & (e[1] >= 0) & (e[2] >= 0)) | ((e[0] <= 0) & (e[1] <= 0) & (e[2] <= 0))
+        d = np.minimum.reduce([_edge_dist(X, Y, P[k, 0], P[k, 1], P[(k + 1) % 3, 0], P[(k + 1) % 3, 1])
+                               for k in range(3)])
+        bx, by, ba, bb = r["x"][c], r["y"][c], r["a"][c], r["b"][c]
+        inbox = ((2 * bx * omega <= (2 * X - 0) * L) & ((2 * X) * L < 2 * (bx + ba) * omega) &
+                 (2 * by * omega <= (2 * Y) * L) & ((2 * Y) * L < 2 * (by + bb) * omega))
+        sub_w = want[ys[0]:ys[-1] + 1, xs[0]:xs[-1] + 1]
+        sub_a = ambiguous[ys[0]:ys[-1] + 1, xs[0]:xs[-1] + 1]
+        sub_w[inside & inbox] = c
+        sub_a |= d < 4.0 / 256
+    agree = (occ == want) | ambiguous
+    assert agree.all(), int((~agree).sum())
+    assert (occ >= 0).sum() > 1000
+
+
+def test_occupancy_owner_inside_box_and_count():
+    f = scenes.orbit_frame(40, atlas_size=1024)
+    r = oracle.build_frame(f)
+    occ = r["occupancy"]
+    omega, L = f.atlas_size, r["L"]
+    ty, tx = np.nonzero(occ >= 0)
+    c = occ[ty, tx]
+    assert (2 * r["x"][c].astype(np.int64) * omega <= (2 * tx + 1) * L).all()
+    assert ((2 * tx + 1) * L < 2 * (r["x"][c] + r["a"][c]).astype(np.int64) * omega).all()
+    assert (2 * r["y"][c].astype(np.int64) * omega <= (2 * ty + 1) * L).all()
+    assert ((2 * ty + 1) * L < 2 * (r["y"][c] + r["b"][c]).astype(np.int64) * omega).all()
+    assert r["occupied"] == int((occ >= 0).sum())
