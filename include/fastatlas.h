@@ -1,0 +1,202 @@
+/*
+ * fastatlas.h - C ABI of the MI355X (gfx950) per-frame atlasing library.
+ *
+ * The library implements the per-frame part of FastAtlas ("FastAtlas:
+ * Real-Time Compact Atlases for Texture Space Shading", Vining et al.,
+ * Eurographics 2025): it groups the visible triangles of a frame into charts
+ * (Sec. "Chart Computation", Appendix "GPU Union Find", Alg. 1), bounds each
+ * chart's visible projection (Sec. "Computing Bounding Boxes of Projected
+ * Visible Sub-Charts"), orders the boxes (Sec. "Box Ordering via Cuckoo
+ * Hashing"), searches J candidate scales and packs the boxes into a fixed
+ * omega x omega atlas (Secs. "Parallel Atlas and Scale Factor Computation",
+ * "Box Packing"), and maps every chart vertex into the atlas (Appendix
+ * "Shading and Rasterization").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every array pointer is a DEVICE pointer on the context's device, owned by
+ *   the caller, unless a comment says "host". The context owns its scratch
+ *   memory and the resident per-scene adjacency.
+ * - Calls enqueue work on `stream` (a hipStream_t; NULL = the legacy default
+ *   stream) and return immediately. Inputs must stay alive and unmodified and
+ *   outputs must not be read until that work has completed.
+ * - The synchronous return value reports argument and capacity errors found
+ *   on the host (FA_ERR_INVALID_ARG, FA_ERR_CAPACITY, FA_ERR_OUT_OF_MEMORY,
+ *   FA_ERR_DEVICE). Conditions discovered on the device (no candidate scale
+ *   fits: FA_ERR_NOFIT; more charts than max_charts: FA_ERR_CAPACITY) are
+ *   written to meta->status when the stream work completes.
+ * - A context is not thread-safe: use it from one host thread at a time.
+ *   Calls on one context must not overlap on different streams (they share
+ *   the context's scratch); use one context per concurrent stream.
+ * - Float arithmetic is IEEE float32 in a fixed order without contraction, so
+ *   every integer result (chart ids, sizes, placements, occupancy) is exactly
+ *   reproducible.
+ */
+#ifndef FASTATLAS_H
+#define FASTATLAS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum fa_status {
+  FA_OK = 0,
+  FA_ERR_INVALID_ARG = 1,   /* bad pointer, size, atlas size or rate          */
+  FA_ERR_OUT_OF_MEMORY = 2, /* device allocation failed                       */
+  FA_ERR_CAPACITY = 3,      /* above max_triangles / max_vertices / max_charts */
+  FA_ERR_NOFIT = 4,         /* no candidate scale fits the atlas              */
+  FA_ERR_DEVICE = 5,        /* a HIP call failed, or the device is not gfx950 */
+  FA_ERR_UNSUPPORTED = 6
+};
+
+/* Option bits of fa_config.flags. */
+enum {
+  /* Clip straddling triangles against the near plane only (Blinn's estimate
+     otherwise); the default also tries the side and far planes and keeps the
+     smallest box (Sec. bounding boxes). */
+  FA_FLAG_NO_SIDE_CLIP = 1u << 0
+};
+
+typedef struct fa_config {
+  int32_t device;        /* HIP device ordinal                                  */
+  int32_t num_scales;    /* J candidate scales j/J, 1..64 (paper: 64)           */
+  int64_t max_triangles; /* capacity, >= every mesh's triangle count            */
+  int64_t max_vertices;  /* capacity, >= every mesh's vertex count              */
+  int32_t max_charts;    /* capacity for charts per frame (<= 1048576)          */
+  int32_t max_atlas;     /* largest atlas side, power of two 16..8192           */
+  int32_t gutter;        /* texels added on each side of every box (usually 1)  */
+  int32_t min_box;       /* minimum box side in texels before the gutter (2)    */
+  uint32_t flags;        /* FA_FLAG_*                                           */
+  int32_t max_views;     /* views per fa_build_atlas_batch call (>= 1)          */
+} fa_config;
+
+typedef struct fa_mesh {
+  const float* positions;   /* [V][3] object-space xyz                          */
+  const int32_t* indices;   /* [T][3] vertex indices, 0 <= i < V                 */
+  int64_t num_vertices;     /* V                                                */
+  int64_t num_triangles;    /* T                                                */
+  uint64_t scene_key;       /* adjacency is built once per key and kept resident */
+} fa_mesh;
+
+typedef struct fa_camera {
+  float view_proj[16]; /* host: row-major 4x4, clip = M * (x, y, z, 1), GL clip
+                          volume -w <= x, y, z <= w                             */
+  int32_t width;       /* viewport in pixels                                   */
+  int32_t height;
+} fa_camera;
+
+/* One chart of the frame (64 bytes). Layout-space boxes are integers in a
+ * square of side layout_width L; atlas texel = layout * atlas_size / L. */
+typedef struct fa_chart {
+  int32_t root_tri;   /* lowest triangle index of the chart                     */
+  int32_t x, y;       /* layout-space top-left of the box (gutter included)     */
+  int32_t w, h;       /* layout-space box size (gutter included)                */
+  int32_t rotated;    /* 1: turned 90 degrees so the box is at least as tall    */
+  int32_t order_rank; /* position in the packing order                          */
+  int32_t key;        /* ordering key: min(ceil(oriented height), 8191)         */
+  float ndc_box[4];   /* conservative NDC box x0, y0, x1, y1                    */
+  float target_w;     /* screen size in pixels times rate (before rotation)    */
+  float target_h;
+  float oriented_w;   /* target size after the optional rotation               */
+  float oriented_h;
+} fa_chart;
+
+typedef struct fa_atlas_meta {
+  int32_t status;        /* fa_status of the device-side work                    */
+  int32_t num_charts;    /* C                                                    */
+  int32_t chosen_j;      /* chosen candidate j (scale j over J), 0 if none fits  */
+  int32_t num_scales;    /* J                                                    */
+  int32_t atlas_size;    /* omega                                                */
+  int32_t layout_width;  /* L = omega + horizontal overflow of the chosen scale  */
+  int32_t layout_height; /* H, highest box top of the chosen packing            */
+  int32_t rows;          /* folded rows of the chosen packing                    */
+  float s_eff;           /* effective uniform scale (j / J) times omega / L      */
+  float rate;            /* requested texels per pixel (per axis)                */
+  int64_t occupied_texels; /* texels claimed in the occupancy map (0 if none)    */
+  int64_t visible_triangles;
+  int64_t reserved;
+} fa_atlas_meta;
+
+typedef struct fa_atlas_out {
+  int32_t* chart_of_tri;  /* [T] chart index, -1 for invisible triangles        */
+  int32_t* chart_of_vert; /* [V] chart index, -1 if unused; may be NULL         */
+  float* uv;              /* [V][2] atlas texels, origin top-left, v down; NaN
+                             when the vertex is unmapped or has w <= 0; may be
+                             NULL                                                */
+  fa_chart* charts;       /* [max_charts]                                       */
+  int32_t* occupancy;     /* [omega][omega] owning chart or -1; may be NULL      */
+  fa_atlas_meta* meta;    /* [1]                                                */
+  int32_t* candidates;    /* [J][4] fit, m, L, H per candidate; may be NULL      */
+} fa_atlas_out;
+
+typedef struct fa_view {
+  const uint8_t* visible; /* [T] 0/1 visible-triangle buffer                    */
+  fa_camera cam;
+  int32_t atlas_size;
+  float texel_per_pixel;
+  fa_atlas_out out;
+} fa_view;
+
+typedef struct fa_ctx fa_ctx;
+
+/* Create a context on cfg->device: checks the device is gfx950 and allocates
+ * scratch sized from the capacities. Unset fields (0) take defaults: J=64,
+ * min_box=2, max_atlas=8192, max_charts=65536, max_views=1 (gutter 0 means
+ * no gutter; the usual value is 1).
+ * Returns FA_OK and *out_ctx, or an error and *out_ctx = NULL. */
+int fa_create(const fa_config* cfg, fa_ctx** out_ctx);
+
+/* Free the context, its scratch and every resident scene. No work may be in
+ * flight on the context. */
+void fa_destroy(fa_ctx* ctx);
+
+const char* fa_status_string(int status);
+
+/* Build (or reuse) the resident triangle adjacency of mesh->scene_key: the
+ * twin relation of the half-edge structure in the paper's data-structure
+ * table. Half-edge h = 3t+e joins indices[t][e] -> indices[t][(e+1)%3];
+ * half-edges with the same undirected edge, taken in order of h, point to
+ * the triangle of the next one cyclically; lone and degenerate edges give -1.
+ * nbr_out ([T][3], may be NULL) receives a copy. */
+int fa_scene_adjacency(fa_ctx* ctx, const fa_mesh* mesh, int32_t* nbr_out, void* stream);
+
+/* Drop the resident adjacency of one scene (no work may be in flight). */
+int fa_scene_evict(fa_ctx* ctx, uint64_t scene_key);
+
+/* Atlas one frame: charts, boxes, order, J-candidate packing, selection,
+ * per-vertex UVs and (if out->occupancy) the atlas occupancy map.
+ * visible: [T] 0/1. atlas_size: power of two, 16 <= atlas_size <= max_atlas.
+ * texel_per_pixel: rate r > 0, per axis (paper's shading-rate multiplier). */
+int fa_build_atlas(fa_ctx* ctx, const fa_mesh* mesh, const uint8_t* visible,
+                   const fa_camera* cam, int32_t atlas_size, float texel_per_pixel,
+                   fa_atlas_out* out, void* stream);
+
+/* Atlas n views of one mesh in one pass over the stages (views: host array of
+ * n descriptors, each with its own visibility, camera, atlas size, rate and
+ * outputs). Every view's results equal what fa_build_atlas gives for it. */
+int fa_build_atlas_batch(fa_ctx* ctx, const fa_mesh* mesh, int32_t n, const fa_view* views,
+                         void* stream);
+
+/* FastAtlas packing alone (Sec. "FastAtlas Packing": its only input is the
+ * box dimensions). sizes: [n][2] box width and height in texels at scale 1.
+ * Boxes are oriented, ordered by (ceil(height) desc, index asc), packed at J
+ * candidate scales and the best fitting one is chosen.
+ * placements: [n][5] x, y, w, h, rotated (layout space, gutter included).
+ * meta: as for fa_build_atlas (num_charts = n, no occupancy). */
+int fa_pack_boxes(fa_ctx* ctx, const float* sizes, int32_t n, int32_t atlas_size,
+                  int32_t* placements, fa_atlas_meta* meta, int32_t* candidates, void* stream);
+
+/* Per-stage timing: when enabled, fa_build_atlas records events between its
+ * stages; fa_stage_times (after the stream completed) fills up to n floats
+ * with milliseconds for: charts, boxes, order, packing, uv, occupancy, and
+ * returns the number of stages. Enabling costs a little host time. */
+int fa_set_stage_timing(fa_ctx* ctx, int enable);
+int fa_stage_times(fa_ctx* ctx, float* ms_host, int n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTATLAS_H */

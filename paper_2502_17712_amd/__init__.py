@@ -1,0 +1,284 @@
+"""Python binding of the gfx950 per-frame atlasing library (libfastatlas.so).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels. PyTorch provides device memory and streams. The library must be
+built (``python -m paper_2502_17712_amd.build`` or ``__graft_entry__.build()``)
+and is loaded after ``torch`` so that both share one HIP runtime. There is no
+fallback: importing without the built library raises.
+
+C-ABI names are mirrored one to one (``fa_create``, ``fa_build_atlas``, ...);
+``Context`` is a convenience wrapper that allocates the output tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_float, c_int, c_int32, c_int64, c_uint32, c_uint64, c_void_p
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfastatlas.so")
+
+FA_OK, FA_ERR_INVALID_ARG, FA_ERR_OUT_OF_MEMORY, FA_ERR_CAPACITY = 0, 1, 2, 3
+FA_ERR_NOFIT, FA_ERR_DEVICE, FA_ERR_UNSUPPORTED = 4, 5, 6
+FA_FLAG_NO_SIDE_CLIP = 1
+
+
+class fa_config(ctypes.Structure):
+    _fields_ = [("device", c_int32), ("num_scales", c_int32), ("max_triangles", c_int64),
+                ("max_vertices", c_int64), ("max_charts", c_int32), ("max_atlas", c_int32),
+                ("gutter", c_int32), ("min_box", c_int32), ("flags", c_uint32),
+                ("max_views", c_int32)]
+
+
+class fa_mesh(ctypes.Structure):
+    _fields_ = [("positions", c_void_p), ("indices", c_void_p), ("num_vertices", c_int64),
+                ("num_triangles", c_int64), ("scene_key", c_uint64)]
+
+
+class fa_camera(ctypes.Structure):
+    _fields_ = [("view_proj", c_float * 16), ("width", c_int32), ("height", c_int32)]
+
+
+class fa_atlas_out(ctypes.Structure):
+    _fields_ = [("chart_of_tri", c_void_p), ("chart_of_vert", c_void_p), ("uv", c_void_p),
+                ("charts", c_void_p), ("occupancy", c_void_p), ("meta", c_void_p),
+                ("candidates", c_void_p)]
+
+
+class fa_view(ctypes.Structure):
+    _fields_ = [("visible", c_void_p), ("cam", fa_camera), ("atlas_size", c_int32),
+                ("texel_per_pixel", c_float), ("out", fa_atlas_out)]
+
+
+CHART_DTYPE = np.dtype([("root_tri", "<i4"), ("x", "<i4"), ("y", "<i4"), ("w", "<i4"),
+                        ("h", "<i4"), ("rotated", "<i4"), ("order_rank", "<i4"), ("key", "<i4"),
+                        ("ndc_box", "<f4", (4,)), ("target_w", "<f4"), ("target_h", "<f4"),
+                        ("oriented_w", "<f4"), ("oriented_h", "<f4")])
+META_DTYPE = np.dtype([("status", "<i4"), ("num_charts", "<i4"), ("chosen_j", "<i4"),
+                       ("num_scales", "<i4"), ("atlas_size", "<i4"), ("layout_width", "<i4"),
+                       ("layout_height", "<i4"), ("rows", "<i4"), ("s_eff", "<f4"),
+                       ("rate", "<f4"), ("occupied_texels", "<i8"), ("visible_triangles", "<i8"),
+                       ("reserved", "<i8")])
+assert CHART_DTYPE.itemsize == 64 and META_DTYPE.itemsize == 64
+
+EXPORTS = ["fa_create", "fa_destroy", "fa_status_string", "fa_scene_adjacency", "fa_scene_evict",
+           "fa_build_atlas", "fa_build_atlas_batch", "fa_pack_boxes", "fa_set_stage_timing",
+           "fa_stage_times"]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2502_17712_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.fa_create.argtypes = [POINTER(fa_config), POINTER(c_void_p)]
+    lib.fa_create.restype = c_int
+    lib.fa_destroy.argtypes = [c_void_p]
+    lib.fa_destroy.restype = None
+    lib.fa_status_string.argtypes = [c_int]
+    lib.fa_status_string.restype = ctypes.c_char_p
+    lib.fa_scene_adjacency.argtypes = [c_void_p, POINTER(fa_mesh), c_void_p, c_void_p]
+    lib.fa_scene_evict.argtypes = [c_void_p, c_uint64]
+    lib.fa_build_atlas.argtypes = [c_void_p, POINTER(fa_mesh), c_void_p, POINTER(fa_camera),
+                                   c_int32, c_float, POINTER(fa_atlas_out), c_void_p]
+    lib.fa_build_atlas_batch.argtypes = [c_void_p, POINTER(fa_mesh), c_int32, POINTER(fa_view),
+                                         c_void_p]
+    lib.fa_pack_boxes.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p,
+                                  c_void_p, c_void_p]
+    lib.fa_set_stage_timing.argtypes = [c_void_p, c_int]
+    lib.fa_stage_times.argtypes = [c_void_p, POINTER(c_float), c_int]
+    for n in ("fa_scene_adjacency", "fa_scene_evict", "fa_build_atlas", "fa_build_atlas_batch",
+              "fa_pack_boxes", "fa_set_stage_timing", "fa_stage_times"):
+        getattr(lib, n).restype = c_int
+    return lib
+
+
+_lib = _load()
+
+# same names as the C ABI
+fa_create = _lib.fa_create
+fa_destroy = _lib.fa_destroy
+fa_status_string = _lib.fa_status_string
+fa_scene_adjacency = _lib.fa_scene_adjacency
+fa_scene_evict = _lib.fa_scene_evict
+fa_build_atlas = _lib.fa_build_atlas
+fa_build_atlas_batch = _lib.fa_build_atlas_batch
+fa_pack_boxes = _lib.fa_pack_boxes
+fa_set_stage_timing = _lib.fa_set_stage_timing
+fa_stage_times = _lib.fa_stage_times
+
+STAGES = ["charts", "chart_sizes", "order", "packing", "uv", "occupancy"]
+
+
+class FastAtlasError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {fa_status_string(code).decode()} ({code})")
+        self.code = code
+
+
+def _check(code, what):
+    if code != FA_OK:
+        raise FastAtlasError(code, what)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def parse_meta(meta_tensor) -> dict:
+    a = meta_tensor.detach().cpu().numpy().view(META_DTYPE)[0]
+    return {k: a[k].item() for k in META_DTYPE.names}
+
+
+def parse_charts(charts_tensor, n) -> np.ndarray:
+    return charts_tensor.detach().cpu().numpy().view(CHART_DTYPE).reshape(-1)[:n].copy()
+
+
+class Mesh:
+    """Device copy of a mesh (positions float32 [V,3], indices int32 [T,3])."""
+
+    def __init__(self, positions, indices, scene_key, device="cuda"):
+        self.positions = torch.as_tensor(np.ascontiguousarray(positions, np.float32)).to(device)
+        self.indices = torch.as_tensor(np.ascontiguousarray(indices, np.int32)).to(device)
+        self.scene_key = int(scene_key)
+        self.c = fa_mesh(self.positions.data_ptr(), self.indices.data_ptr(),
+                         self.positions.shape[0], self.indices.shape[0], self.scene_key)
+
+    @property
+    def num_triangles(self):
+        return int(self.indices.shape[0])
+
+    @property
+    def num_vertices(self):
+        return int(self.positions.shape[0])
+
+
+def make_camera(view_proj, width, height) -> fa_camera:
+    cam = fa_camera()
+    vp = np.asarray(view_proj, np.float32).ravel()
+    for i in range(16):
+        cam.view_proj[i] = float(vp[i])
+    cam.width, cam.height = int(width), int(height)
+    return cam
+
+
+class AtlasOutputs:
+    """Device output buffers of one view."""
+
+    def __init__(self, T, V, max_charts, atlas_size, J, uv=True, occupancy=True,
+                 candidates=True, device="cuda"):
+        self.chart_of_tri = torch.empty(T, dtype=torch.int32, device=device)
+        self.chart_of_vert = torch.empty(V, dtype=torch.int32, device=device)
+        self.uv = torch.empty((V, 2), dtype=torch.float32, device=device) if uv else None
+        self.charts = torch.zeros((max_charts, 16), dtype=torch.int32, device=device)
+        self.occupancy = (torch.empty((atlas_size, atlas_size), dtype=torch.int32, device=device)
+                          if occupancy else None)
+        self.meta = torch.zeros(16, dtype=torch.int32, device=device)
+        self.candidates = (torch.zeros((J, 4), dtype=torch.int32, device=device)
+                           if candidates else None)
+        self.atlas_size = atlas_size
+
+    def c(self) -> fa_atlas_out:
+        return fa_atlas_out(self.chart_of_tri.data_ptr(), self.chart_of_vert.data_ptr(),
+                            None if self.uv is None else self.uv.data_ptr(),
+                            self.charts.data_ptr(),
+                            None if self.occupancy is None else self.occupancy.data_ptr(),
+                            self.meta.data_ptr(),
+                            None if self.candidates is None else self.candidates.data_ptr())
+
+    def to_numpy(self) -> dict:
+        m = parse_meta(self.meta)
+        r = dict(meta=m, chart_of_tri=self.chart_of_tri.cpu().numpy(),
+                 chart_of_vert=self.chart_of_vert.cpu().numpy(),
+                 charts=parse_charts(self.charts, max(m["num_charts"], 0)
+                                     if m["status"] in (FA_OK, FA_ERR_NOFIT) else 0))
+        if self.uv is not None:
+            r["uv"] = self.uv.cpu().numpy()
+        if self.occupancy is not None:
+            r["occupancy"] = self.occupancy.cpu().numpy()
+        if self.candidates is not None:
+            r["candidates"] = self.candidates.cpu().numpy()
+        return r
+
+
+class Context:
+    """Owns an fa_ctx (scratch + resident scene adjacency) on one device."""
+
+    def __init__(self, max_triangles, max_vertices, max_charts=65536, max_atlas=8192,
+                 num_scales=64, gutter=1, min_box=2, flags=0, device=0, max_views=1):
+        cfg = fa_config(device, num_scales, max_triangles, max_vertices, max_charts, max_atlas,
+                        gutter, min_box, flags, max_views)
+        h = c_void_p()
+        _check(fa_create(ctypes.byref(cfg), ctypes.byref(h)), "fa_create")
+        self.h = h
+        self.cfg = cfg
+
+    def close(self):
+        if getattr(self, "h", None):
+            fa_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def outputs(self, mesh: Mesh, atlas_size, uv=True, occupancy=True, candidates=True):
+        return AtlasOutputs(mesh.num_triangles, mesh.num_vertices, self.cfg.max_charts, atlas_size,
+                            self.cfg.num_scales, uv, occupancy, candidates)
+
+    def adjacency(self, mesh: Mesh, stream=None):
+        nbr = torch.empty((mesh.num_triangles, 3), dtype=torch.int32, device="cuda")
+        _check(fa_scene_adjacency(self.h, ctypes.byref(mesh.c), _ptr(nbr), _stream_handle(stream)),
+               "fa_scene_adjacency")
+        return nbr
+
+    def build_atlas(self, mesh: Mesh, visible, view_proj, width, height, atlas_size, rate,
+                    out: AtlasOutputs = None, stream=None):
+        if out is None:
+            out = self.outputs(mesh, atlas_size)
+        cam = make_camera(view_proj, width, height)
+        oc = out.c()
+        _check(fa_build_atlas(self.h, ctypes.byref(mesh.c), _ptr(visible), ctypes.byref(cam),
+                              int(atlas_size), float(rate), ctypes.byref(oc),
+                              _stream_handle(stream)), "fa_build_atlas")
+        return out
+
+    def build_atlas_batch(self, mesh: Mesh, views, outs, stream=None):
+        """views: list of (visible, view_proj, width, height, atlas_size, rate)."""
+        arr = (fa_view * len(views))()
+        for i, (vis, vp, W, H, om, r) in enumerate(views):
+            arr[i].visible = vis.data_ptr()
+            arr[i].cam = make_camera(vp, W, H)
+            arr[i].atlas_size = int(om)
+            arr[i].texel_per_pixel = float(r)
+            arr[i].out = outs[i].c()
+        _check(fa_build_atlas_batch(self.h, ctypes.byref(mesh.c), len(views), arr,
+                                    _stream_handle(stream)), "fa_build_atlas_batch")
+        return outs
+
+    def pack_boxes(self, sizes, atlas_size, stream=None):
+        """sizes: float32 cuda tensor [n,2]. Returns (placements [n,5], meta, candidates)."""
+        n = int(sizes.shape[0])
+        pl = torch.empty((max(n, 1), 5), dtype=torch.int32, device="cuda")
+        meta = torch.zeros(16, dtype=torch.int32, device="cuda")
+        cand = torch.zeros((self.cfg.num_scales, 4), dtype=torch.int32, device="cuda")
+        _check(fa_pack_boxes(self.h, _ptr(sizes), n, int(atlas_size), _ptr(pl), _ptr(meta),
+                             _ptr(cand), _stream_handle(stream)), "fa_pack_boxes")
+        return pl[:n], meta, cand
+
+    def set_stage_timing(self, enable=True):
+        _check(fa_set_stage_timing(self.h, int(enable)), "fa_set_stage_timing")
+
+    def stage_times(self):
+        buf = (c_float * 8)()
+        n = fa_stage_times(self.h, buf, 8)
+        return {STAGES[i]: buf[i] for i in range(n)}

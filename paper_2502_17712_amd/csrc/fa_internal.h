@@ -1,0 +1,227 @@
+// Internal declarations of the gfx950 atlasing library: device-side frame
+// state, per-frame parameters, wave/block primitives and the host-side launch
+// functions of each stage. Not part of the public ABI (include/fastatlas.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fastatlas.h"
+
+namespace fa {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;          // default threads per workgroup
+constexpr int kMaxScales = 64;       // J <= 64 candidate scales
+constexpr int kKeyCap = 8191;        // height keys are 13-bit (max box height 8192)
+constexpr int kTriTile = 1024;       // triangles per workgroup in the root scan
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSortTile = 2048;      // keys per workgroup in one radix pass
+constexpr int kCandStride = 8;       // int32 per candidate in the table
+constexpr int kMaxAtlas = 8192;
+
+// Device-resident results of one frame that later stages read (kept on the
+// device so that no stage needs a host round trip).
+struct FrameState {
+  int32_t status;
+  int32_t num_charts;
+  int32_t jstar;
+  int32_t layout_w;
+  int32_t layout_h;
+  int32_t rows;
+  float s_star;       // j*/J
+  float q_star;       // omega/L*
+  uint32_t big_count; // large occupancy work items
+  uint32_t pad;
+  unsigned long long occupied;
+  unsigned long long visible;
+};
+
+// Per-frame constants passed by value.
+struct FrameParams {
+  float M[16];
+  int32_t W, H;
+  int32_t omega, log2omega;
+  float rate;
+  int32_t J, gutter, min_box;
+  uint32_t flags;
+  int32_t max_charts;
+};
+
+// Scratch buffers of one context (sized by the capacities).
+struct Work {
+  float4* clip;          // [V]
+  int32_t* parent;       // [T]
+  int32_t* vmin;         // [V]
+  int32_t* cov;          // [V] when the caller passes no chart_of_vert
+  uint32_t* tile_count;  // [T/kTriTile + 1]
+  uint32_t* tile_off;    // [T/kTriTile + 1]
+  uint32_t* accum;       // [max_charts][4] order-preserving encoded min/max
+  uint32_t* keys_a;      // [max_charts]
+  int32_t* vals_a;
+  uint32_t* keys_b;
+  int32_t* vals_b;
+  uint32_t* hist;        // [kRadix * tiles(max_charts)]
+  float2* sorted_wh;     // [max_charts] oriented sizes in packing order
+  long long* cand_x;     // [J][max_charts] prefix sums
+  uint32_t* cand_ab;     // [J][max_charts] a | b << 16
+  int32_t* cand_y;       // [J][max_charts]
+  int32_t* cand_tab;     // [J][kCandStride] fit, m, L, H, rows
+  uint32_t* big;         // [2*T] large occupancy work items
+  fa_chart* pack_charts; // [max_charts] chart records of the packer-only entry
+  FrameState* state;     // [1]
+};
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+__device__ __forceinline__ unsigned long long lanes_below() {
+  return (1ull << lane_id()) - 1ull;
+}
+
+// Order-preserving map float -> uint32 (after turning -0 into +0), so that
+// integer atomics compute exact float min/max independent of order.
+__device__ __forceinline__ uint32_t ord_of(float f) {
+  f = f + 0.0f;
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float float_of(uint32_t e) {
+  return __uint_as_float((e & 0x80000000u) ? (e & 0x7FFFFFFFu) : ~e);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, (T)__shfl_xor(v, o, kWave));
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (T)__shfl_xor(v, o, kWave));
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += (T)__shfl_xor(v, o, kWave);
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    T u = (T)__shfl_up(v, o, kWave);
+    if (l >= o) v += u;
+  }
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_incl_max_scan(T v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    T u = (T)__shfl_up(v, o, kWave);
+    if (l >= o) v = max(v, u);
+  }
+  return v;
+}
+
+// Block-wide inclusive sum scan; `sh` holds blockDim.x/64 elements. Ends
+// with a barrier so `sh` may be reused afterwards. *total gets the block sum.
+template <typename T>
+__device__ __forceinline__ T block_incl_scan(T v, T* sh, T* total) {
+  const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  T x = wave_incl_scan(v);
+  if (lane_id() == kWave - 1) sh[w] = x;
+  __syncthreads();
+  T before = 0, all = 0;
+  for (int k = 0; k < nw; ++k) {
+    T s = sh[k];
+    if (k < w) before += s;
+    all += s;
+  }
+  __syncthreads();
+  *total = all;
+  return x + before;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_max(T v, T* sh) {
+  const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  T x = wave_max(v);
+  if (lane_id() == 0) sh[w] = x;
+  __syncthreads();
+  T m = sh[0];
+  for (int k = 1; k < nw; ++k) m = max(m, sh[k]);
+  __syncthreads();
+  return m;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* sh) {
+  const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  T x = wave_sum(v);
+  if (lane_id() == 0) sh[w] = x;
+  __syncthreads();
+  T m = 0;
+  for (int k = 0; k < nw; ++k) m += sh[k];
+  __syncthreads();
+  return m;
+}
+
+__host__ __device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+__host__ __device__ __forceinline__ int64_t ceil_div64(int64_t a, int64_t b) {
+  return -floor_div64(-a, b);
+}
+
+// ---------------------------------------------------------------------------
+// host-side stage launchers (each enqueues on `st`)
+// ---------------------------------------------------------------------------
+hipError_t launch_frame_init(const Work& w, hipStream_t st);
+hipError_t launch_clip(const float* pos, int64_t V, const FrameParams& p, const Work& w,
+                       int32_t* cov, hipStream_t st);
+hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* nbr, int64_t T,
+                         const FrameParams& p, const Work& w, int32_t* cot, int32_t* cov,
+                         fa_chart* charts, hipStream_t st);
+hipError_t launch_chart_sizes(const FrameParams& p, const Work& w, fa_chart* charts,
+                              hipStream_t st);
+hipError_t launch_order(const FrameParams& p, const Work& w, fa_chart* charts, hipStream_t st);
+hipError_t launch_pack(const FrameParams& p, const Work& w, int block, hipStream_t st);
+hipError_t launch_select_place(const FrameParams& p, const Work& w, fa_chart* charts,
+                               int32_t* cand_out, hipStream_t st);
+hipError_t launch_uv(const int64_t V, const FrameParams& p, const Work& w, const int32_t* cov,
+                     const fa_chart* charts, float* uv, hipStream_t st);
+hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
+                            const int32_t* cot, const fa_chart* charts, int32_t* occ,
+                            int small_texels, hipStream_t st);
+hipError_t launch_meta(const FrameParams& p, const Work& w, fa_atlas_meta* meta, hipStream_t st);
+
+// packer-only path: sizes [n][2] -> charts' oriented sizes and keys
+hipError_t launch_pack_prepare(const float* sizes, int32_t n, const FrameParams& p,
+                               const Work& w, fa_chart* charts, hipStream_t st);
+hipError_t launch_pack_emit(int32_t n, const fa_chart* charts, int32_t* placements,
+                            const Work& w, hipStream_t st);
+hipError_t pack_kernel_attributes(int max_dyn_bytes);
+
+// adjacency (per scene): sorts 3T half-edge keys; tmp buffers from the caller
+struct AdjTmp {
+  unsigned long long* keys_a;
+  unsigned long long* keys_b;
+  int32_t* vals_a;
+  int32_t* vals_b;
+  uint32_t* hist;
+  uint32_t* n_dev;
+};
+size_t adjacency_hist_words(int64_t T);
+hipError_t launch_adjacency(const int32_t* idx, int64_t T, int64_t V, const AdjTmp& tmp,
+                            int32_t* nbr, hipStream_t st);
+
+}  // namespace fa

@@ -1,0 +1,341 @@
+// FastAtlas packing on gfx950 (Secs. "Parallel Atlas and Scale Factor
+// Computation" and "Box Packing").
+//
+// One workgroup evaluates one candidate scale j/J:
+//   sizes   a = max(m_min, ceil(w * j/J)) + 2g, b likewise for the height;
+//   fold    exclusive prefix sum X of the widths (64-bit), row = X >> log2(omega),
+//           offset = X & (omega - 1), overflow m = max(offset + a - omega);
+//           layout width L = omega + m (the rows are later rescaled by omega/L);
+//   mirror  rows with row % 3 != 0 run right to left;
+//   push    row by row, a box rises to the top of the frontline under its span
+//           and raises that span by its height. The frontline (L <= 2 omega
+//           columns) lives in LDS; threads own contiguous column ranges, find
+//           the box entering their range with a tagged max-scan over start
+//           markers and reduce per-box maxima with LDS atomics.
+// A candidate fits iff m <= omega and the layout height H <= L. Selection takes
+// the largest effective scale (j/J) * omega / L, compared exactly.
+#include <climits>
+
+#include "fa_internal.h"
+
+namespace fa {
+namespace {
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
+                                             const FrameState* __restrict__ st, FrameParams p,
+                                             long long* __restrict__ cand_x,
+                                             uint32_t* __restrict__ cand_ab,
+                                             int32_t* __restrict__ cand_y,
+                                             int32_t* __restrict__ cand_tab, int64_t stride) {
+  extern __shared__ int32_t F[];  // [2 * omega]
+  __shared__ uint32_t marker[NT];
+  __shared__ int32_t bx[NT], ba[NT], bb[NT], ym[NT];
+  __shared__ long long sh64[NT / kWave];
+  __shared__ int32_t sh32[NT / kWave];
+  __shared__ uint32_t shu[NT / kWave];
+  __shared__ int32_t Hsh;
+
+  if (st->status != FA_OK) return;
+  const int j = blockIdx.x + 1;
+  const int tid = threadIdx.x, w = tid / kWave;
+  const int C = st->num_charts;
+  const int omega = p.omega, lg = p.log2omega;
+  long long* X = cand_x + (int64_t)(j - 1) * stride;
+  uint32_t* AB = cand_ab + (int64_t)(j - 1) * stride;
+  int32_t* Y = cand_y + (int64_t)(j - 1) * stride;
+  int32_t* tab = cand_tab + (j - 1) * kCandStride;
+  const float s = (float)j / (float)p.J;
+  const int pad = 2 * p.gutter;
+
+  // ---- sizes, fold and overflow -------------------------------------------
+  long long run = 0, mloc = 0;
+  int bad = 0;
+  for (int base = 0; base < C; base += NT) {
+    const int i = base + tid;
+    int a = 0, b = 0;
+    if (i < C) {
+      const float2 v = wh[i];
+      const int wi = (int)ceilf(v.x * s);
+      const int hi = (int)ceilf(v.y * s);
+      a = max(p.min_box, wi) + pad;
+      b = max(p.min_box, hi) + pad;
+    }
+    long long tot;
+    const long long incl = block_incl_scan<long long>((long long)a, sh64, &tot);
+    const long long Xi = run + incl - a;
+    run += tot;
+    if (i < C) {
+      X[i] = Xi;
+      if (a > 2 * omega || b > 2 * omega) bad = 1;  // cannot fit: m > omega or H > L
+      const uint32_t ca = (uint32_t)min(a, 2 * omega + 1), cb = (uint32_t)min(b, 2 * omega + 1);
+      AB[i] = ca | (cb << 16);
+      mloc = max(mloc, (Xi & (long long)(omega - 1)) + a - omega);
+    }
+  }
+  const long long m = block_max<long long>(mloc, sh64);
+  bad = block_max<int>(bad, sh32);
+  const long long rows = C > 0 ? (X[C - 1] >> lg) + 1 : 0;
+  if (m > omega || bad) {
+    if (tid == 0) {
+      tab[0] = 0;
+      tab[1] = (int32_t)min(m, (long long)INT_MAX);
+      tab[2] = (int32_t)min(m + omega, (long long)INT_MAX);
+      tab[3] = -1;
+      tab[4] = (int32_t)min(rows, (long long)INT_MAX);
+    }
+    return;
+  }
+  const int L = omega + (int)m;
+
+  // ---- push ----------------------------------------------------------------
+  for (int c = tid; c < L; c += NT) F[c] = 0;
+  marker[tid] = 0u;
+  if (tid == 0) Hsh = 0;
+  const int K = (L + NT - 1) / NT;  // columns per thread
+  const int c0 = tid * K, c1 = min(c0 + K, L);
+  __syncthreads();
+
+  long long sidx = 0;
+  uint32_t seq = 0;
+  while (sidx < C) {
+    const long long r = X[sidx] >> lg;
+    const long long row_end = (r + 1) << lg;
+    const bool right = (r % 3) != 0;
+    const long long i = sidx + tid;
+    long long Xi = 0;
+    bool inrow = false;
+    if (i < C) {
+      Xi = X[i];
+      inrow = Xi < row_end;
+    }
+    const int n = __syncthreads_count(inrow);
+    ++seq;
+    if (inrow) {
+      const uint32_t ab = AB[i];
+      const int a = (int)(ab & 0xFFFFu), b = (int)(ab >> 16);
+      const int o = (int)(Xi - (r << lg));
+      const int x = right ? L - o - a : o;
+      bx[tid] = x;
+      ba[tid] = a;
+      bb[tid] = b;
+      ym[tid] = 0;
+      const int ci = (x + K - 1) / K;
+      if (ci < NT) atomicMax(&marker[ci], (seq << 12) | (uint32_t)(right ? 4095 - tid : tid));
+    }
+    __syncthreads();
+    // box covering column c0: tagged inclusive max-scan of the start markers
+    uint32_t mk = wave_incl_max_scan<uint32_t>(marker[tid]);
+    if (lane_id() == kWave - 1) shu[w] = mk;
+    __syncthreads();
+    for (int k = 0; k < w; ++k) mk = max(mk, shu[k]);
+    const int step = right ? -1 : 1;
+    int k0;
+    if ((mk >> 12) == seq) {
+      const int lo = (int)(mk & 4095u);
+      k0 = right ? 4095 - lo : lo;
+    } else {
+      k0 = right ? n - 1 : 0;
+    }
+    {  // reads: per-box maximum of the frontline
+      int kk = k0;
+      bool ok = kk >= 0 && kk < n;
+      int bxk = ok ? bx[kk] : 0, bek = ok ? bxk + ba[kk] : 0;
+      int cur = -1;
+      for (int c = c0; c < c1; ++c) {
+        while (ok && c >= bek) {
+          if (cur >= 0) atomicMax(&ym[kk], cur);
+          cur = -1;
+          kk += step;
+          ok = kk >= 0 && kk < n;
+          if (ok) { bxk = bx[kk]; bek = bxk + ba[kk]; }
+        }
+        if (!ok) break;
+        if (c >= bxk) cur = max(cur, F[c]);
+      }
+      if (ok && cur >= 0) atomicMax(&ym[kk], cur);
+    }
+    __syncthreads();
+    {  // writes: raise the spans
+      int kk = k0;
+      bool ok = kk >= 0 && kk < n;
+      int bxk = ok ? bx[kk] : 0, bek = ok ? bxk + ba[kk] : 0;
+      int top = ok ? ym[kk] + bb[kk] : 0;
+      for (int c = c0; c < c1; ++c) {
+        while (ok && c >= bek) {
+          kk += step;
+          ok = kk >= 0 && kk < n;
+          if (ok) { bxk = bx[kk]; bek = bxk + ba[kk]; top = ym[kk] + bb[kk]; }
+        }
+        if (!ok) break;
+        if (c >= bxk) F[c] = top;
+      }
+    }
+    if (inrow) {
+      const int y = ym[tid];
+      Y[i] = y;
+      atomicMax(&Hsh, y + bb[tid]);
+    }
+    __syncthreads();
+    sidx += n;
+    if (Hsh > L) break;
+  }
+  if (tid == 0) {
+    tab[0] = Hsh <= L ? 1 : 0;
+    tab[1] = (int32_t)m;
+    tab[2] = L;
+    tab[3] = Hsh;
+    tab[4] = (int32_t)min(rows, (long long)INT_MAX);
+  }
+}
+
+// Largest effective scale j/L_j among fitting candidates (ties -> larger j).
+__global__ void k_select(FrameParams p, const int32_t* __restrict__ cand_tab, FrameState* st,
+                         int32_t* __restrict__ cand_out) {
+  if (threadIdx.x < p.J && cand_out) {
+    const int32_t* t = cand_tab + threadIdx.x * kCandStride;
+    int32_t* o = cand_out + 4 * threadIdx.x;
+    if (st->status == FA_OK) { o[0] = t[0]; o[1] = t[1]; o[2] = t[2]; o[3] = t[3]; }
+    else { o[0] = 0; o[1] = 0; o[2] = 0; o[3] = 0; }
+  }
+  if (threadIdx.x != 0 || st->status != FA_OK) return;
+  int best = 0;
+  long long bestL = 1;
+  for (int j = 1; j <= p.J; ++j) {
+    const int32_t* t = cand_tab + (j - 1) * kCandStride;
+    if (!t[0]) continue;
+    const long long L = t[2];
+    if (best == 0 || (long long)j * bestL >= (long long)best * L) {
+      best = j;
+      bestL = L;
+    }
+  }
+  st->jstar = best;
+  if (!best) {
+    st->status = FA_ERR_NOFIT;
+    return;
+  }
+  const int32_t* t = cand_tab + (best - 1) * kCandStride;
+  st->layout_w = t[2];
+  st->layout_h = t[3];
+  st->rows = t[4];
+  st->s_star = (float)best / (float)p.J;
+  st->q_star = (float)p.omega / (float)t[2];
+}
+
+// Final placement of every chart from the chosen candidate.
+__global__ void k_place(FrameParams p, const int32_t* __restrict__ order,
+                        const long long* __restrict__ cand_x, const uint32_t* __restrict__ cand_ab,
+                        const int32_t* __restrict__ cand_y, int64_t stride,
+                        fa_chart* __restrict__ charts, const FrameState* __restrict__ st) {
+  if (st->status != FA_OK) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= st->num_charts) return;
+  const int jm = st->jstar - 1;
+  const int L = st->layout_w;
+  const long long Xi = cand_x[(int64_t)jm * stride + i];
+  const uint32_t ab = cand_ab[(int64_t)jm * stride + i];
+  const int a = (int)(ab & 0xFFFFu), b = (int)(ab >> 16);
+  const long long r = Xi >> p.log2omega;
+  const int o = (int)(Xi - (r << p.log2omega));
+  fa_chart& ch = charts[order[i]];
+  ch.x = (r % 3 == 0) ? o : L - o - a;
+  ch.y = cand_y[(int64_t)jm * stride + i];
+  ch.w = a;
+  ch.h = b;
+}
+
+// ---- packer-only entry: box sizes in, placements out ---------------------
+__global__ void k_pack_prepare(const float* __restrict__ sizes, int32_t n,
+                               fa_chart* __restrict__ charts, uint32_t* __restrict__ keys,
+                               int32_t* __restrict__ vals, FrameState* st) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c == 0) st->num_charts = n;
+  if (c >= n) return;
+  const float tw = sizes[2 * c], th = sizes[2 * c + 1];
+  const float lim = 16777216.0f;  // 2^24 texels
+  if (!(tw >= 0.0f && tw <= lim && th >= 0.0f && th <= lim)) {
+    atomicExch(&st->status, (int32_t)FA_ERR_INVALID_ARG);
+    return;
+  }
+  const int rot = tw > th ? 1 : 0;
+  const float bw = rot ? th : tw, bh = rot ? tw : th;
+  const int key = min((int)ceilf(bh), kKeyCap);
+  fa_chart& ch = charts[c];
+  ch.root_tri = c;
+  ch.ndc_box[0] = ch.ndc_box[1] = ch.ndc_box[2] = ch.ndc_box[3] = 0.0f;
+  ch.target_w = tw;
+  ch.target_h = th;
+  ch.oriented_w = bw;
+  ch.oriented_h = bh;
+  ch.rotated = rot;
+  ch.key = key;
+  keys[c] = (uint32_t)(kKeyCap - key);
+  vals[c] = c;
+}
+
+__global__ void k_pack_emit(int32_t n, const fa_chart* __restrict__ charts,
+                            int32_t* __restrict__ out, const FrameState* __restrict__ st) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n || st->status != FA_OK) return;
+  const fa_chart& ch = charts[c];
+  out[5 * c + 0] = ch.x;
+  out[5 * c + 1] = ch.y;
+  out[5 * c + 2] = ch.w;
+  out[5 * c + 3] = ch.h;
+  out[5 * c + 4] = ch.rotated;
+}
+
+}  // namespace
+
+hipError_t pack_kernel_attributes(int max_dyn_bytes) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_pack<256>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn_bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_pack<512>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          max_dyn_bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_pack<1024>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn_bytes);
+}
+
+hipError_t launch_pack(const FrameParams& p, const Work& w, int block, hipStream_t st) {
+  const size_t dyn = (size_t)2 * p.omega * sizeof(int32_t);
+  const int64_t stride = p.max_charts;
+  if (block == 1024)
+    k_pack<1024><<<p.J, 1024, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab, w.cand_y,
+                                         w.cand_tab, stride);
+  else if (block == 512)
+    k_pack<512><<<p.J, 512, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab, w.cand_y,
+                                       w.cand_tab, stride);
+  else
+    k_pack<256><<<p.J, 256, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab, w.cand_y,
+                                       w.cand_tab, stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_place(const FrameParams& p, const Work& w, fa_chart* charts,
+                               int32_t* cand_out, hipStream_t st) {
+  k_select<<<1, kMaxScales, 0, st>>>(p, w.cand_tab, w.state, cand_out);
+  k_place<<<(unsigned)((p.max_charts + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+      p, w.vals_a, w.cand_x, w.cand_ab, w.cand_y, p.max_charts, charts, w.state);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_prepare(const float* sizes, int32_t n, const FrameParams& p, const Work& w,
+                               fa_chart* charts, hipStream_t st) {
+  (void)p;
+  k_pack_prepare<<<(unsigned)((n + kBlock - 1) / kBlock) + 1, kBlock, 0, st>>>(
+      sizes, n, charts, w.keys_a, w.vals_a, w.state);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_emit(int32_t n, const fa_chart* charts, int32_t* placements,
+                            const Work& w, hipStream_t st) {
+  if (n > 0)
+    k_pack_emit<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(n, charts, placements,
+                                                                         w.state);
+  return hipGetLastError();
+}
+
+}  // namespace fa

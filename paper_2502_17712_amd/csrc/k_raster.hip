@@ -1,0 +1,292 @@
+// Atlas-space stages on gfx950:
+//   UV emission (Appendix "Shading and Rasterization": every chart is scaled
+//   by the chosen uniform scale, then moved rigidly from its NDC box to its
+//   atlas box) and the atlas occupancy map (which chart owns each texel).
+//
+// Occupancy of texel (tx, ty) is chart c iff its centre lies in c's placed
+// box (exact integer test in layout space, gutter included) and inside one of
+// c's visible triangles mapped to the atlas (near-clipped when the triangle
+// crosses the near plane), snapped to 1/256 texel with round-to-nearest-even,
+// fan-triangulated from the first vertex, edges inclusive. Small footprints
+// are rasterized by one thread; large ones are queued and rasterized by a
+// whole workgroup each.
+#include <algorithm>
+
+#include "fa_internal.h"
+
+namespace fa {
+namespace {
+
+struct ChartXform {
+  float x0, y1, tw, halfW, halfH, rate, s, q, ox, oy;
+  int rot;
+};
+
+__device__ __forceinline__ ChartXform chart_xform(const fa_chart& ch, const FrameParams& p,
+                                                  const FrameState& st) {
+  ChartXform m;
+  m.x0 = ch.ndc_box[0];
+  m.y1 = ch.ndc_box[3];
+  m.tw = ch.target_w;
+  m.halfW = 0.5f * (float)p.W;
+  m.halfH = 0.5f * (float)p.H;
+  m.rate = p.rate;
+  m.s = st.s_star;
+  m.q = st.q_star;
+  m.ox = (float)(ch.x + p.gutter);
+  m.oy = (float)(ch.y + p.gutter);
+  m.rot = ch.rotated;
+  return m;
+}
+
+// clip-space point (w > 0) -> atlas texel coordinates
+__device__ __forceinline__ float2 to_atlas(const ChartXform& m, float X, float Y, float w) {
+  const float nx = X / w, ny = Y / w;
+  const float px = ((nx - m.x0) * m.halfW) * m.rate;
+  const float py = ((m.y1 - ny) * m.halfH) * m.rate;
+  const float lx = m.rot ? py : px;
+  const float ly = m.rot ? (m.tw - px) : py;
+  return make_float2((m.ox + lx * m.s) * m.q, (m.oy + ly * m.s) * m.q);
+}
+
+__global__ void k_uv(int64_t V, FrameParams p, const float4* __restrict__ clip,
+                     const int32_t* __restrict__ cov, const fa_chart* __restrict__ charts,
+                     float2* __restrict__ uv, const FrameState* __restrict__ stp) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const FrameState st = *stp;
+  const int c = st.status == FA_OK ? cov[v] : -1;
+  const float4 q = clip[v];
+  float2 r = make_float2(__builtin_nanf(""), __builtin_nanf(""));
+  if (c >= 0 && q.w > 0.0f) r = to_atlas(chart_xform(charts[c], p, st), q.x, q.y, q.w);
+  uv[v] = r;
+}
+
+// ---------------------------------------------------------------------------
+// occupancy
+// ---------------------------------------------------------------------------
+struct Footprint {
+  int64_t ax, ay, bx, by, cx, cy;  // snapped vertices (1/256 texel)
+  int64_t area;
+  int tx0, tx1, ty0, ty1;          // inclusive texel range to test (may be empty)
+  int chart;
+};
+
+template <int P>
+__device__ __forceinline__ float pd(const float4& q) {
+  if (P == 0) return q.w + q.x;
+  if (P == 1) return q.w - q.x;
+  if (P == 2) return q.w + q.y;
+  if (P == 3) return q.w - q.y;
+  if (P == 4) return q.w + q.z;
+  return q.w - q.z;
+}
+template <int P>
+__device__ __forceinline__ bool outside(const float4& a, const float4& b, const float4& c) {
+  return pd<P>(a) < 0.0f && pd<P>(b) < 0.0f && pd<P>(c) < 0.0f;
+}
+
+// near-plane Sutherland-Hodgman of one triangle into up to 4 vertices
+__device__ __forceinline__ int near_clip(const float4& a, const float4& b, const float4& c,
+                                         float4* o) {
+  int n = 0;
+  const float4 in[3] = {a, b, c};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float4 S = in[i], E = in[i == 2 ? 0 : i + 1];
+    const float dS = pd<4>(S), dE = pd<4>(E);
+    const bool iS = dS >= 0.0f, iE = dE >= 0.0f;
+    if (iS != iE) {
+      const float4 A = iS ? S : E, B = iS ? E : S;
+      const float dA = iS ? dS : dE, dB = iS ? dE : dS;
+      const float t = dA / (dA - dB);
+      float4 I;
+      I.x = A.x + t * (B.x - A.x);
+      I.y = A.y + t * (B.y - A.y);
+      I.z = A.z + t * (B.z - A.z);
+      I.w = A.w + t * (B.w - A.w);
+      o[n++] = I;
+    }
+    if (iE) o[n++] = E;
+  }
+  return n;
+}
+
+__device__ __forceinline__ int32_t snap(float u) {
+  const float lim = 268435456.0f;  // 2^28 (1/256-texel units)
+  return (int32_t)__builtin_rintf(fminf(fmaxf(u * 256.0f, -lim), lim));
+}
+
+// Footprint of fan triangle f (0 or 1) of visible triangle t; false when it
+// claims nothing.
+__device__ bool footprint(int64_t t, int f, const int32_t* __restrict__ idx,
+                          const float4* __restrict__ clip, const int32_t* __restrict__ cot,
+                          const fa_chart* __restrict__ charts, const FrameParams& p,
+                          const FrameState& st, Footprint& fp) {
+  const int c = cot[t];
+  if (c < 0) return false;
+  const float4 a = clip[idx[3 * t]], b = clip[idx[3 * t + 1]], cc = clip[idx[3 * t + 2]];
+  if (outside<0>(a, b, cc) || outside<1>(a, b, cc) || outside<2>(a, b, cc) ||
+      outside<3>(a, b, cc) || outside<4>(a, b, cc) || outside<5>(a, b, cc))
+    return false;
+  float4 poly[4];
+  int n;
+  if (pd<4>(a) < 0.0f || pd<4>(b) < 0.0f || pd<4>(cc) < 0.0f) {
+    n = near_clip(a, b, cc, poly);
+  } else {
+    poly[0] = a; poly[1] = b; poly[2] = cc; n = 3;
+  }
+  if (f + 2 >= n) return false;
+  for (int k = 0; k < n; ++k)
+    if (!(poly[k].w > 0.0f)) return false;
+  const fa_chart& ch = charts[c];
+  const ChartXform m = chart_xform(ch, p, st);
+  const float2 u0 = to_atlas(m, poly[0].x, poly[0].y, poly[0].w);
+  const float2 u1 = to_atlas(m, poly[f + 1].x, poly[f + 1].y, poly[f + 1].w);
+  const float2 u2 = to_atlas(m, poly[f + 2].x, poly[f + 2].y, poly[f + 2].w);
+  fp.ax = snap(u0.x); fp.ay = snap(u0.y);
+  fp.bx = snap(u1.x); fp.by = snap(u1.y);
+  fp.cx = snap(u2.x); fp.cy = snap(u2.y);
+  fp.area = (fp.bx - fp.ax) * (fp.cy - fp.ay) - (fp.by - fp.ay) * (fp.cx - fp.ax);
+  if (fp.area == 0) return false;
+  // texel range of the placed box: 2*x*omega <= (2t+1)*L < 2*(x+w)*omega
+  const int64_t om = p.omega, L = st.layout_w;
+  int64_t lo_x = ceil_div64(2 * (int64_t)ch.x * om - L, 2 * L);
+  int64_t hi_x = ceil_div64(2 * ((int64_t)ch.x + ch.w) * om - L, 2 * L) - 1;
+  int64_t lo_y = ceil_div64(2 * (int64_t)ch.y * om - L, 2 * L);
+  int64_t hi_y = ceil_div64(2 * ((int64_t)ch.y + ch.h) * om - L, 2 * L) - 1;
+  // texel centres 256*t + 128 inside the bounding box of the snapped triangle
+  const int64_t umin = min(fp.ax, min(fp.bx, fp.cx)), umax = max(fp.ax, max(fp.bx, fp.cx));
+  const int64_t vmin = min(fp.ay, min(fp.by, fp.cy)), vmax = max(fp.ay, max(fp.by, fp.cy));
+  lo_x = max(lo_x, max((int64_t)0, floor_div64(umin - 128 + 255, 256)));
+  hi_x = min(hi_x, min(om - 1, floor_div64(umax - 128, 256)));
+  lo_y = max(lo_y, max((int64_t)0, floor_div64(vmin - 128 + 255, 256)));
+  hi_y = min(hi_y, min(om - 1, floor_div64(vmax - 128, 256)));
+  if (lo_x > hi_x || lo_y > hi_y) return false;
+  fp.tx0 = (int)lo_x; fp.tx1 = (int)hi_x; fp.ty0 = (int)lo_y; fp.ty1 = (int)hi_y;
+  fp.chart = c;
+  return true;
+}
+
+__device__ __forceinline__ bool covers(const Footprint& fp, int tx, int ty) {
+  const int64_t px = 256 * (int64_t)tx + 128, py = 256 * (int64_t)ty + 128;
+  const int64_t e0 = (fp.bx - fp.ax) * (py - fp.ay) - (fp.by - fp.ay) * (px - fp.ax);
+  const int64_t e1 = (fp.cx - fp.bx) * (py - fp.by) - (fp.cy - fp.by) * (px - fp.bx);
+  const int64_t e2 = (fp.ax - fp.cx) * (py - fp.cy) - (fp.ay - fp.cy) * (px - fp.cx);
+  return fp.area > 0 ? (e0 >= 0 && e1 >= 0 && e2 >= 0) : (e0 <= 0 && e1 <= 0 && e2 <= 0);
+}
+
+__global__ void k_occ_fill(int4* __restrict__ occ, int64_t n4, const FrameState* __restrict__ st) {
+  const int4 neg = make_int4(-1, -1, -1, -1);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+       i += (int64_t)gridDim.x * blockDim.x)
+    occ[i] = neg;
+}
+
+__global__ void k_occ_small(const int32_t* __restrict__ idx, int64_t T, FrameParams p,
+                            const float4* __restrict__ clip, const int32_t* __restrict__ cot,
+                            const fa_chart* __restrict__ charts, int32_t* __restrict__ occ,
+                            uint32_t* __restrict__ big, int small_texels, FrameState* stp) {
+  const FrameState st = *stp;
+  if (st.status != FA_OK) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  for (int f = 0; f < 2; ++f) {
+    Footprint fp;
+    if (!footprint(t, f, idx, clip, cot, charts, p, st, fp)) continue;
+    const int nx = fp.tx1 - fp.tx0 + 1, ny = fp.ty1 - fp.ty0 + 1;
+    if ((int64_t)nx * ny > small_texels) {
+      const uint32_t slot = atomicAdd(&stp->big_count, 1u);
+      big[slot] = (uint32_t)(2 * t + f);
+      continue;
+    }
+    for (int ty = fp.ty0; ty <= fp.ty1; ++ty)
+      for (int tx = fp.tx0; tx <= fp.tx1; ++tx)
+        if (covers(fp, tx, ty)) occ[(int64_t)ty * p.omega + tx] = fp.chart;
+  }
+}
+
+__global__ void k_occ_big(const int32_t* __restrict__ idx, FrameParams p,
+                          const float4* __restrict__ clip, const int32_t* __restrict__ cot,
+                          const fa_chart* __restrict__ charts, int32_t* __restrict__ occ,
+                          const uint32_t* __restrict__ big, const FrameState* __restrict__ stp) {
+  const FrameState st = *stp;
+  if (st.status != FA_OK) return;
+  for (uint32_t e = blockIdx.x; e < st.big_count; e += gridDim.x) {
+    const uint32_t code = big[e];
+    Footprint fp;
+    if (!footprint((int64_t)(code >> 1), (int)(code & 1u), idx, clip, cot, charts, p, st, fp))
+      continue;
+    const int nx = fp.tx1 - fp.tx0 + 1;
+    const int64_t total = (int64_t)nx * (fp.ty1 - fp.ty0 + 1);
+    for (int64_t k = threadIdx.x; k < total; k += blockDim.x) {
+      const int ty = fp.ty0 + (int)(k / nx), tx = fp.tx0 + (int)(k % nx);
+      if (covers(fp, tx, ty)) occ[(int64_t)ty * p.omega + tx] = fp.chart;
+    }
+  }
+}
+
+__global__ void k_occ_count(const int4* __restrict__ occ, int64_t n4, FrameState* st) {
+  __shared__ unsigned long long sh[kBlock / kWave];
+  unsigned long long cnt = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int4 v = occ[i];
+    cnt += (v.x >= 0) + (v.y >= 0) + (v.z >= 0) + (v.w >= 0);
+  }
+  cnt = block_sum<unsigned long long>(cnt, sh);
+  if (threadIdx.x == 0 && cnt) atomicAdd(&st->occupied, cnt);
+}
+
+__global__ void k_meta(FrameParams p, const FrameState* __restrict__ stp,
+                       fa_atlas_meta* __restrict__ meta) {
+  if (threadIdx.x != 0) return;
+  const FrameState st = *stp;
+  fa_atlas_meta m;
+  m.status = st.status;
+  m.num_charts = st.num_charts;
+  m.chosen_j = st.jstar;
+  m.num_scales = p.J;
+  m.atlas_size = p.omega;
+  m.layout_width = st.layout_w;
+  m.layout_height = st.layout_h;
+  m.rows = st.rows;
+  m.s_eff = st.status == FA_OK ? st.s_star * st.q_star : 0.0f;
+  m.rate = p.rate;
+  m.occupied_texels = (int64_t)st.occupied;
+  m.visible_triangles = (int64_t)st.visible;
+  m.reserved = 0;
+  *meta = m;
+}
+
+}  // namespace
+
+hipError_t launch_uv(const int64_t V, const FrameParams& p, const Work& w, const int32_t* cov,
+                     const fa_chart* charts, float* uv, hipStream_t st) {
+  if (V > 0)
+    k_uv<<<(unsigned)((V + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        V, p, w.clip, cov, charts, reinterpret_cast<float2*>(uv), w.state);
+  return hipGetLastError();
+}
+
+hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
+                            const int32_t* cot, const fa_chart* charts, int32_t* occ,
+                            int small_texels, hipStream_t st) {
+  const int64_t n4 = (int64_t)p.omega * p.omega / 4;
+  const unsigned fill_grid = (unsigned)std::min<int64_t>((n4 + kBlock - 1) / kBlock, 4096);
+  k_occ_fill<<<fill_grid, kBlock, 0, st>>>(reinterpret_cast<int4*>(occ), n4, w.state);
+  if (T > 0) {
+    k_occ_small<<<(unsigned)((T + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        idx, T, p, w.clip, cot, charts, occ, w.big, small_texels, w.state);
+    k_occ_big<<<2048, kBlock, 0, st>>>(idx, p, w.clip, cot, charts, occ, w.big, w.state);
+  }
+  k_occ_count<<<fill_grid, kBlock, 0, st>>>(reinterpret_cast<const int4*>(occ), n4, w.state);
+  return hipGetLastError();
+}
+
+hipError_t launch_meta(const FrameParams& p, const Work& w, fa_atlas_meta* meta, hipStream_t st) {
+  k_meta<<<1, 64, 0, st>>>(p, w.state, meta);
+  return hipGetLastError();
+}
+
+}  // namespace fa

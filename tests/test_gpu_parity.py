@@ -1,0 +1,292 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs, element by element.
+
+Bar: bit-exact chart ids, chart boxes (float bits), sizes, order, candidate
+table, placements, layout meta and occupancy; UVs within 1e-4 texels (they
+are computed with the same float32 operations, so they are expected to be
+bit-identical too).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import scenes
+
+pytestmark = pytest.mark.gpu
+
+_CTX = {}
+
+
+def _fa():
+    import paper_2502_17712_amd as fa
+    return fa
+
+
+def ctx_for(J=64, gutter=1, flags=0, max_charts=65536, T=2_300_000, V=1_200_000):
+    key = (J, gutter, flags, max_charts, T, V)
+    if key not in _CTX:
+        _CTX[key] = _fa().Context(T, V, max_charts=max_charts, max_atlas=8192, num_scales=J,
+                                  gutter=gutter, flags=flags)
+    return _CTX[key]
+
+
+_MESH = {}
+
+
+def mesh_for(frame):
+    fa = _fa()
+    k = (frame.scene_key, frame.num_triangles)
+    if k not in _MESH:
+        _MESH[k] = fa.Mesh(frame.positions, frame.indices, frame.scene_key)
+    return _MESH[k]
+
+
+def run_gpu(frame, ctx, occupancy=True):
+    print(f"[gpu] {frame.name} T={frame.num_triangles} omega={frame.atlas_size} r={frame.rate}",
+          flush=True)
+    mesh = mesh_for(frame)
+    vis = torch.as_tensor(frame.visible).cuda()
+    out = ctx.outputs(mesh, frame.atlas_size, occupancy=occupancy)
+    ctx.build_atlas(mesh, vis, frame.view_proj, frame.width, frame.height, frame.atlas_size,
+                    frame.rate, out=out)
+    torch.cuda.synchronize()
+    return out.to_numpy()
+
+
+def bits(a):
+    return np.ascontiguousarray(a, np.float32).view(np.uint32)
+
+
+def compare(g, r, occupancy=True):
+    m = g["meta"]
+    assert m["status"] == r["status"], (m, r["status"])
+    assert m["num_charts"] == r["num_charts"]
+    assert m["visible_triangles"] == int(np.count_nonzero(r["chart_of_tri"] >= 0))
+    assert np.array_equal(g["chart_of_tri"], r["chart_of_tri"])
+    assert np.array_equal(g["chart_of_vert"], r["chart_of_vert"])
+    ch = g["charts"]
+    C = r["num_charts"]
+    assert ch.shape[0] == C
+    assert np.array_equal(ch["root_tri"], r["roots"])
+    assert np.array_equal(bits(ch["ndc_box"]), bits(r["frame"]))
+    assert np.array_equal(bits(ch["target_w"]), bits(r["target"][:, 0]))
+    assert np.array_equal(bits(ch["target_h"]), bits(r["target"][:, 1]))
+    assert np.array_equal(bits(ch["oriented_w"]), bits(r["oriented"][:, 0]))
+    assert np.array_equal(bits(ch["oriented_h"]), bits(r["oriented"][:, 1]))
+    assert np.array_equal(ch["rotated"], r["rotated"])
+    assert np.array_equal(ch["key"], r["key"])
+    assert np.array_equal(ch["order_rank"], r["rank"])
+    cand = g["candidates"]
+    rc = r["cand"]
+    assert np.array_equal(cand[:, 0], rc[:, 0])
+    assert np.array_equal(cand[:, 1], rc[:, 1]) and np.array_equal(cand[:, 2], rc[:, 2])
+    fit = rc[:, 0] == 1
+    assert np.array_equal(cand[fit, 3], rc[fit, 3])
+    assert m["chosen_j"] == r["jstar"]
+    if r["status"] != 0:
+        return
+    assert (m["layout_width"], m["layout_height"]) == (r["L"], r["H"])
+    assert m["rows"] == r["cand"][r["jstar"] - 1, 4]
+    assert np.float32(m["s_eff"]) == np.float32(r["s_eff"])
+    for k in ("x", "y"):
+        assert np.array_equal(ch[k], r[k]), k
+    assert np.array_equal(ch["w"], r["a"]) and np.array_equal(ch["h"], r["b"])
+    gu, ru = g["uv"], r["uv"]
+    assert np.array_equal(np.isnan(gu), np.isnan(ru))
+    fin = ~np.isnan(ru)
+    if fin.any():
+        assert np.abs(gu[fin] - ru[fin]).max() <= 1e-4
+        print(f"  uv bit-identical: {np.mean(bits(gu[fin]) == bits(ru[fin])):.6f}")
+    if occupancy:
+        assert m["occupied_texels"] == r["occupied"]
+        assert np.array_equal(g["occupancy"], r["occupancy"])
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", list(range(0, 64, 4)))
+def test_grid_frames(seed):
+    f = scenes.grid_frame(seed)
+    g = run_gpu(f, ctx_for())
+    compare(g, oracle.build_frame(f))
+
+
+@pytest.mark.parametrize("J,gutter,omega,rate", [(16, 0, 256, 1.0), (32, 1, 128, 1.0),
+                                                 (64, 0, 512, 2.0), (64, 1, 64, 0.5)])
+def test_grid_variants(J, gutter, omega, rate):
+    f = scenes.grid_frame(5, atlas_size=omega, rate=rate)
+    g = run_gpu(f, ctx_for(J=J, gutter=gutter))
+    compare(g, oracle.build_frame(f, J=J, gutter=gutter))
+
+
+@pytest.mark.parametrize("frame", [0, 17, 60, 119])
+def test_orbit_frames(frame):
+    f = scenes.orbit_frame(frame)
+    g = run_gpu(f, ctx_for())
+    compare(g, oracle.build_frame(f))
+
+
+def test_orbit_no_side_clip():
+    f = scenes.orbit_frame(33)
+    g = run_gpu(f, ctx_for(flags=_fa().FA_FLAG_NO_SIDE_CLIP))
+    compare(g, oracle.build_frame(f, side_clip=False))
+
+
+@pytest.mark.parametrize("rate", [1.0, 0.5, 2.0])
+def test_city_frame_full(rate):
+    f = scenes.city_frame(0, rate=rate)
+    g = run_gpu(f, ctx_for())
+    compare(g, oracle.build_frame(f))
+
+
+def test_city_frames_more():
+    for fr in (9, 23):
+        f = scenes.city_frame(fr)
+        g = run_gpu(f, ctx_for())
+        compare(g, oracle.build_frame(f, want_occupancy=False), occupancy=False)
+
+
+# ---------------------------------------------------------------------------
+def _random_mesh(rng, T, V):
+    idx = rng.integers(0, V, size=(T, 3)).astype(np.int32)
+    for t in range(1, T, 3):
+        idx[t, 0], idx[t, 1] = idx[t - 1, 1], idx[t - 1, 0]
+    idx[5] = [3, 3, 4]  # degenerate edges
+    return idx
+
+
+@pytest.mark.parametrize("which", ["grid", "orbit", "city", "random"])
+def test_adjacency(which):
+    fa = _fa()
+    if which == "grid":
+        f = scenes.grid_frame(0)
+        pos, idx, key = f.positions, f.indices, 77001
+    elif which == "orbit":
+        f = scenes.orbit_frame(0)
+        pos, idx, key = f.positions, f.indices, 77002
+    elif which == "city":
+        pos, idx = scenes.city_scene()
+        key = 77003
+    else:
+        rng = np.random.default_rng(3)
+        idx = _random_mesh(rng, 3000, 400)
+        pos = rng.normal(size=(400, 3)).astype(np.float32)
+        key = 77004
+    print(f"[gpu] adjacency {which} T={idx.shape[0]}", flush=True)
+    mesh = fa.Mesh(pos, idx, key)
+    nbr = ctx_for().adjacency(mesh)
+    torch.cuda.synchronize()
+    assert np.array_equal(nbr.cpu().numpy(), oracle.adjacency(idx))
+
+
+# ---------------------------------------------------------------------------
+def _oracle_pack(sizes, omega, J=64, g=1, mmin=2):
+    w, h = sizes[:, 0], sizes[:, 1]
+    rot = (w > h).astype(np.int32)
+    bw, bh = np.where(rot == 1, h, w), np.where(rot == 1, w, h)
+    key = np.minimum(np.ceil(bh).astype(np.int64), 8191).astype(np.int32)
+    o = oracle.order(key)
+    sbw, sbh = np.ascontiguousarray(bw[o]), np.ascontiguousarray(bh[o])
+    table = np.zeros((J, 5), np.int64)
+    cands = []
+    for j in range(1, J + 1):
+        cd = oracle.candidate(sbw, sbh, j, J, omega, g, mmin)
+        cands.append(cd)
+        table[j - 1] = [cd["fit"], cd["m"], cd["L"], cd["H"], cd["rows"]]
+    js = oracle.select(table)
+    pl = np.zeros((sizes.shape[0], 5), np.int64)
+    if js:
+        w_ = cands[js - 1]
+        pl[o, 0], pl[o, 1], pl[o, 2], pl[o, 3] = w_["x"], w_["y"], w_["a"], w_["b"]
+    pl[:, 4] = rot
+    return js, table, pl
+
+
+@pytest.mark.parametrize("n,omega,seed", [(0, 1024, 0), (1, 64, 1), (7, 64, 2), (1000, 1024, 3),
+                                          (20000, 4096, 4), (60000, 8192, 5)])
+def test_pack_boxes(n, omega, seed):
+    rng = np.random.default_rng(seed)
+    # heavy-tailed sizes: many tiny boxes, some large ones
+    sizes = (rng.pareto(1.6, size=(n, 2)) * 6.0).astype(np.float32)
+    sizes = np.minimum(sizes, omega * 0.9).astype(np.float32)
+    print(f"[gpu] pack n={n} omega={omega}", flush=True)
+    ctx = ctx_for()
+    pl, meta, cand = ctx.pack_boxes(torch.as_tensor(sizes).cuda(), omega)
+    torch.cuda.synchronize()
+    m = _fa().parse_meta(meta)
+    js, table, want = _oracle_pack(sizes, omega)
+    assert m["chosen_j"] == js and m["num_charts"] == n
+    c = cand.cpu().numpy()
+    assert np.array_equal(c[:, 0], table[:, 0]) and np.array_equal(c[:, 2], table[:, 2])
+    if js:
+        assert m["layout_width"] == table[js - 1, 2] and m["layout_height"] == table[js - 1, 3]
+        assert np.array_equal(pl.cpu().numpy(), want)
+
+
+# ---------------------------------------------------------------------------
+def test_empty_and_single_visible():
+    fa = _fa()
+    f = scenes.grid_frame(1)
+    for vis in (np.zeros_like(f.visible), np.eye(1, f.num_triangles, 4000, dtype=np.uint8)[0]):
+        f.visible = vis
+        g = run_gpu(f, ctx_for())
+        compare(g, oracle.build_frame(f))
+
+
+def test_nofit_reported_on_device():
+    f = scenes.grid_frame(2, atlas_size=16, rate=2.0)
+    g = run_gpu(f, ctx_for())
+    r = oracle.build_frame(f)
+    assert r["status"] == oracle.STATUS_NOFIT
+    compare(g, r)
+
+
+def test_capacity_reported_on_device():
+    f = scenes.orbit_frame(2)
+    ctx = ctx_for(max_charts=8)
+    g = run_gpu(f, ctx, occupancy=False)
+    assert g["meta"]["status"] == _fa().FA_ERR_CAPACITY
+    assert g["meta"]["num_charts"] > 8
+
+
+def test_invalid_arguments_raise():
+    fa = _fa()
+    f = scenes.grid_frame(0)
+    ctx = ctx_for()
+    mesh = mesh_for(f)
+    vis = torch.as_tensor(f.visible).cuda()
+    for om, r in ((1000, 1.0), (16384, 1.0), (1024, 0.0), (1024, float("nan"))):
+        with pytest.raises(fa.FastAtlasError) as e:
+            ctx.build_atlas(mesh, vis, f.view_proj, f.width, f.height, om, r)
+        assert e.value.code == fa.FA_ERR_INVALID_ARG
+    bad = fa.Mesh(f.positions, np.where(f.indices == 7, 10**6, f.indices), 99123)
+    with pytest.raises(fa.FastAtlasError):
+        ctx.build_atlas(bad, vis, f.view_proj, f.width, f.height, 1024, 1.0)
+
+
+def test_deterministic_repeats():
+    f = scenes.orbit_frame(45)
+    ctx = ctx_for()
+    outs = [run_gpu(f, ctx) for _ in range(3)]
+    for o in outs[1:]:
+        for k in ("chart_of_tri", "chart_of_vert", "occupancy", "candidates"):
+            assert np.array_equal(o[k], outs[0][k])
+        assert np.array_equal(o["charts"], outs[0]["charts"])
+        assert np.array_equal(bits(o["uv"]), bits(outs[0]["uv"]))
+
+
+def test_batch_equals_single():
+    fa = _fa()
+    ctx = ctx_for()
+    frames = [scenes.orbit_frame(k, atlas_size=om, rate=r)
+              for k, om, r in ((3, 1024, 1.0), (40, 2048, 0.5), (80, 512, 2.0))]
+    mesh = mesh_for(frames[0])
+    outs = [ctx.outputs(mesh, f.atlas_size) for f in frames]
+    vis = [torch.as_tensor(f.visible).cuda() for f in frames]
+    ctx.build_atlas_batch(mesh, [(vis[i], f.view_proj, f.width, f.height, f.atlas_size, f.rate)
+                                 for i, f in enumerate(frames)], outs)
+    torch.cuda.synchronize()
+    for f, o in zip(frames, outs):
+        compare(o.to_numpy(), oracle.build_frame(f))
