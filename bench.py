@@ -38,6 +38,27 @@ def algorithmic_bytes(T, V, Tv, Vv, C, J, omega):
             + omega * omega * 4)
 
 
+def kernel_bytes(name, T, V, Tv, Vv, C, J, omega, occupied):
+    """Algorithmic bytes of one launch of a kernel (what it must read and write
+    at minimum); the per-unit figures are listed in the design doc."""
+    per = {
+        "prologue": V * (12 + 16 + 4 + 4) + T * (1 + 4) + Tv * 12,
+        "uf_hook": T * 1 + Tv * (12 + 12 + 4),
+        "uf_vertex_hook": T * 1 + Tv * (12 + 12),
+        "uf_flatten": T * 1 + Tv * 8,
+        "gather_boxes": T * (1 + 4) + Tv * (12 + 48 + 12 + 4),
+        "sizes_order": C * (16 + 64 + 8 + 16),
+        "pack": J * C * (8 + 16),
+        "select_place": C * (16 + 16),
+        "uv": V * (16 + 4 + 8) + C * 64,
+        "occ_fill": omega * omega * 4,
+        "occ_small": T * 4 + Tv * (12 + 48) + occupied * 4,
+        "occ_big": occupied * 4,
+        "occ_count": omega * omega * 4,
+    }
+    return per.get(name)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,6 +70,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=4)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=1000.0)
+    ap.add_argument("--serve-requests", type=int, default=1000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -88,6 +113,11 @@ def main():
         ctx.build_atlas(mesh, vis[k % len(frames)], f.view_proj, f.width, f.height,
                         f.atlas_size, f.rate, out=out, stream=stream)
 
+    tuning = None
+    if not args.no_autotune:
+        from paper_2502_17712_amd import autotune
+        tuning = autotune.tune(ctx, lambda: step(0), out)
+        log("autotune:", json.dumps(tuning))
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
@@ -105,7 +135,7 @@ def main():
     meta = fa.parse_meta(out.meta)
     assert meta["status"] == fa.FA_OK, meta
 
-    # per-stage breakdown (separate pass with stage events)
+    # per-kernel live times (separate pass with an event after every kernel)
     ctx.set_stage_timing(True)
     stage_acc = {}
     for k in range(min(64, args.steps)):
@@ -127,6 +157,15 @@ def main():
         stats.append((int(f.visible.sum()), int(used.sum()), m["num_charts"]))
     Tv, Vv, C = (float(np.mean([s[i] for s in stats])) for i in range(3))
     B = algorithmic_bytes(T, V, Tv, Vv, C, 64, args.atlas)
+    occupied = float(meta["occupied_texels"])
+    dom = max(stages, key=stages.get) if stages else None
+    roofline = None
+    if dom is not None:
+        kb = kernel_bytes(dom, T, V, Tv, Vv, C, 64, args.atlas, occupied)
+        ach = kb / (stages[dom] * 1e-3) / 1e9 if kb else None
+        roofline = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": (ach / HBM_PEAK_GBS) if ach else None,
+                    "traffic": None, "kernel_ms": stages[dom], "algorithmic_bytes": kb}
 
     # batched views vs the plain per-view path
     batch = None
@@ -154,6 +193,43 @@ def main():
         tp = (time.perf_counter() - w2) / reps
         batch = dict(views=16, batched_views_per_s=16 / tb, plain_views_per_s=16 / tp,
                      speedup=tp / tb)
+
+    # served: continuous batching over the three scenes vs one-at-a-time FIFO
+    served = None
+    if not args.no_serve:
+        from paper_2502_17712_amd import serve
+        from synth import requests as rq
+        mnp = rq.scene_meshes()
+        smeshes = {k: fa.Mesh(p_, t_, key) for k, (p_, t_, key) in mnp.items()}
+        pools = {"grid": rq.pose_pool("grid", 16, 1), "orbit": rq.pose_pool("orbit", 16, 2),
+                 "city": rq.pose_pool("city", 4, 3)}
+        svis = {(s, i): torch.as_tensor(pools[s][i].visible).to(dev) for s in pools
+                for i in range(len(pools[s]))}
+
+        def make_reqs(lam, n):
+            out_ = []
+            for rid, (a, c, s, i, om, r) in enumerate(rq.poisson_stream(lam, n, pools, seed=7)):
+                pz = pools[s][i]
+                out_.append(serve.Request(rid, s, svis[(s, i)], pz.view_proj, pz.width,
+                                          pz.height, om, r, arrival=a, client=c))
+            return out_
+        served = {}
+        for slots in (8, 1):
+            srv = serve.Server(smeshes, slots=slots, hbm_budget=16 << 30, max_atlas=4096,
+                               tuning={fa.FA_TUNE_OCC_SMALL_TEXELS:
+                                       ctx.get_tuning(fa.FA_TUNE_OCC_SMALL_TEXELS),
+                                       fa.FA_TUNE_UF_LINK_INIT:
+                                       ctx.get_tuning(fa.FA_TUNE_UF_LINK_INIT)})
+            srv.run(make_reqs(args.serve_rate, 64))  # warm-up
+            reqs = make_reqs(args.serve_rate, args.serve_requests)
+            w3 = time.perf_counter()
+            res_ = srv.run(reqs)
+            wall3 = time.perf_counter() - w3
+            srv.close()
+            assert all(r.meta["status"] == 0 for r in res_)
+            served["continuous" if slots > 1 else "fifo"] = dict(
+                slots=slots, offered_req_per_s=args.serve_rate, **serve.summarize(res_, wall3))
+        log("served:", json.dumps(served))
 
     # CPU oracle on a bounded sample of the same workload
     cpu = None
@@ -191,11 +267,14 @@ def main():
         "triangles_per_s": T / (ms * 1e-3),
         "adjacency_ms": adjacency_ms,
         "stages_ms": stages,
+        "tuning": tuning,
+        "large_tiles": meta["large_tiles"],
         "algorithmic_bytes_per_frame": B,
         "frame_hbm_roofline_frac": B / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "batch": batch,
+        "served": served,
         "cpu_baseline": cpu,
-        "roofline": None,
+        "roofline": roofline,
     }
     print(json.dumps(res))
 

@@ -116,7 +116,7 @@ typedef struct fa_atlas_meta {
   float rate;            /* requested texels per pixel (per axis)                */
   int64_t occupied_texels; /* texels claimed in the occupancy map (0 if none)    */
   int64_t visible_triangles;
-  int64_t reserved;
+  int64_t large_tiles;   /* diagnostic: 16x16-texel tiles rasterized cooperatively */
 } fa_atlas_meta;
 
 typedef struct fa_atlas_out {
@@ -173,9 +173,12 @@ int fa_build_atlas(fa_ctx* ctx, const fa_mesh* mesh, const uint8_t* visible,
                    const fa_camera* cam, int32_t atlas_size, float texel_per_pixel,
                    fa_atlas_out* out, void* stream);
 
-/* Atlas n views of one mesh in one pass over the stages (views: host array of
- * n descriptors, each with its own visibility, camera, atlas size, rate and
- * outputs). Every view's results equal what fa_build_atlas gives for it. */
+/* Atlas n views of one mesh (views: host array of n descriptors, each with its
+ * own visibility, camera, atlas size, rate and outputs). Views run
+ * concurrently on the context's max_views scratch slots and streams, forked
+ * from and joined back into `stream`. Every view's results equal what
+ * fa_build_atlas gives for it. The outputs of different views must not
+ * overlap. */
 int fa_build_atlas_batch(fa_ctx* ctx, const fa_mesh* mesh, int32_t n, const fa_view* views,
                          void* stream);
 
@@ -188,10 +191,31 @@ int fa_build_atlas_batch(fa_ctx* ctx, const fa_mesh* mesh, int32_t n, const fa_v
 int fa_pack_boxes(fa_ctx* ctx, const float* sizes, int32_t n, int32_t atlas_size,
                   int32_t* placements, fa_atlas_meta* meta, int32_t* candidates, void* stream);
 
-/* Per-stage timing: when enabled, fa_build_atlas records events between its
- * stages; fa_stage_times (after the stream completed) fills up to n floats
- * with milliseconds for: charts, boxes, order, packing, uv, occupancy, and
- * returns the number of stages. Enabling costs a little host time. */
+/* Performance knobs of one context. Every accepted value produces identical
+ * results; only the speed changes (an autotuner may pick any of them).
+ *   FA_TUNE_PACK_BLOCK        threads per candidate packing: 256, 512, 1024
+ *   FA_TUNE_OCC_SMALL_TEXELS  footprints up to this many texels are
+ *                             rasterized by one thread (0..4096)
+ *   FA_TUNE_UF_LINK_INIT      1: a triangle starts linked to its smallest
+ *                             visible edge neighbour (Alg. 1); 0: to itself
+ *   FA_TUNE_BATCH_GRAPH       1: fa_build_atlas_batch captures its views into
+ *                             a hipGraph once per distinct set of view
+ *                             descriptors and replays it (one launch); 0: off
+ * fa_set_tuning returns FA_ERR_INVALID_ARG for unknown knobs or values;
+ * fa_get_tuning returns the current value or -1. */
+enum { FA_TUNE_PACK_BLOCK = 1, FA_TUNE_OCC_SMALL_TEXELS = 2, FA_TUNE_UF_LINK_INIT = 3,
+       FA_TUNE_BATCH_GRAPH = 4 };
+int fa_set_tuning(fa_ctx* ctx, int knob, int value);
+int fa_get_tuning(fa_ctx* ctx, int knob);
+
+/* Per-kernel timing: when enabled, fa_build_atlas (with uv and occupancy
+ * outputs) records an event after each of its 16 kernels; fa_stage_times
+ * (after the stream completed) fills up to n floats with milliseconds for, in
+ * order: prologue (state, clip transform, union-find start), uf_hook,
+ * uf_vertex_hook, uf_flatten, scan_tiles, assign_roots, gather_boxes,
+ * sizes_order, pack, select_place, uv, occ_fill, occ_small, occ_big,
+ * occ_count, meta; it returns the number filled (0 if none recorded).
+ * Enabling costs a little host time and device idle time between kernels. */
 int fa_set_stage_timing(fa_ctx* ctx, int enable);
 int fa_stage_times(fa_ctx* ctx, float* ms_host, int n);
 

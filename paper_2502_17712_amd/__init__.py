@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libfastatlas.so")
 FA_OK, FA_ERR_INVALID_ARG, FA_ERR_OUT_OF_MEMORY, FA_ERR_CAPACITY = 0, 1, 2, 3
 FA_ERR_NOFIT, FA_ERR_DEVICE, FA_ERR_UNSUPPORTED = 4, 5, 6
 FA_FLAG_NO_SIDE_CLIP = 1
+FA_TUNE_PACK_BLOCK, FA_TUNE_OCC_SMALL_TEXELS, FA_TUNE_UF_LINK_INIT, FA_TUNE_BATCH_GRAPH = 1, 2, 3, 4
 
 
 class fa_config(ctypes.Structure):
@@ -61,12 +62,12 @@ META_DTYPE = np.dtype([("status", "<i4"), ("num_charts", "<i4"), ("chosen_j", "<
                        ("num_scales", "<i4"), ("atlas_size", "<i4"), ("layout_width", "<i4"),
                        ("layout_height", "<i4"), ("rows", "<i4"), ("s_eff", "<f4"),
                        ("rate", "<f4"), ("occupied_texels", "<i8"), ("visible_triangles", "<i8"),
-                       ("reserved", "<i8")])
+                       ("large_tiles", "<i8")])
 assert CHART_DTYPE.itemsize == 64 and META_DTYPE.itemsize == 64
 
 EXPORTS = ["fa_create", "fa_destroy", "fa_status_string", "fa_scene_adjacency", "fa_scene_evict",
-           "fa_build_atlas", "fa_build_atlas_batch", "fa_pack_boxes", "fa_set_stage_timing",
-           "fa_stage_times"]
+           "fa_build_atlas", "fa_build_atlas_batch", "fa_pack_boxes", "fa_set_tuning",
+           "fa_get_tuning", "fa_set_stage_timing", "fa_stage_times"]
 
 
 def _load():
@@ -87,10 +88,13 @@ def _load():
                                          c_void_p]
     lib.fa_pack_boxes.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p,
                                   c_void_p, c_void_p]
+    lib.fa_set_tuning.argtypes = [c_void_p, c_int, c_int]
+    lib.fa_get_tuning.argtypes = [c_void_p, c_int]
     lib.fa_set_stage_timing.argtypes = [c_void_p, c_int]
     lib.fa_stage_times.argtypes = [c_void_p, POINTER(c_float), c_int]
     for n in ("fa_scene_adjacency", "fa_scene_evict", "fa_build_atlas", "fa_build_atlas_batch",
-              "fa_pack_boxes", "fa_set_stage_timing", "fa_stage_times"):
+              "fa_pack_boxes", "fa_set_tuning", "fa_get_tuning", "fa_set_stage_timing",
+              "fa_stage_times"):
         getattr(lib, n).restype = c_int
     return lib
 
@@ -106,10 +110,14 @@ fa_scene_evict = _lib.fa_scene_evict
 fa_build_atlas = _lib.fa_build_atlas
 fa_build_atlas_batch = _lib.fa_build_atlas_batch
 fa_pack_boxes = _lib.fa_pack_boxes
+fa_set_tuning = _lib.fa_set_tuning
+fa_get_tuning = _lib.fa_get_tuning
 fa_set_stage_timing = _lib.fa_set_stage_timing
 fa_stage_times = _lib.fa_stage_times
 
-STAGES = ["charts", "chart_sizes", "order", "packing", "uv", "occupancy"]
+STAGES = ["prologue", "uf_hook", "uf_vertex_hook", "uf_flatten", "scan_tiles", "assign_roots",
+          "gather_boxes", "sizes_order", "pack", "select_place", "uv", "occ_fill", "occ_small",
+          "occ_big", "occ_count", "meta"]
 
 
 class FastAtlasError(RuntimeError):
@@ -275,10 +283,16 @@ class Context:
                              _ptr(cand), _stream_handle(stream)), "fa_pack_boxes")
         return pl[:n], meta, cand
 
+    def set_tuning(self, knob, value):
+        _check(fa_set_tuning(self.h, int(knob), int(value)), "fa_set_tuning")
+
+    def get_tuning(self, knob):
+        return int(fa_get_tuning(self.h, int(knob)))
+
     def set_stage_timing(self, enable=True):
         _check(fa_set_stage_timing(self.h, int(enable)), "fa_set_stage_timing")
 
     def stage_times(self):
-        buf = (c_float * 8)()
-        n = fa_stage_times(self.h, buf, 8)
+        buf = (c_float * 32)()
+        n = fa_stage_times(self.h, buf, 32)
         return {STAGES[i]: buf[i] for i in range(n)}

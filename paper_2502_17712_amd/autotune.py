@@ -1,0 +1,80 @@
+"""Autotuner for the library's performance knobs (fa_set_tuning).
+
+Greedy coordinate descent over the knobs on a representative workload: for
+each knob in turn, every allowed value is timed with HIP events (median of
+`reps` runs) and the fastest is kept. Every knob value must give identical
+results; the tuner checks that by comparing all outputs of each trial with
+the reference run, and refuses (raises) on any difference.
+"""
+from __future__ import annotations
+
+import json
+
+import torch
+
+from . import (FA_TUNE_OCC_SMALL_TEXELS, FA_TUNE_PACK_BLOCK, FA_TUNE_UF_LINK_INIT, AtlasOutputs,
+               Context)
+
+KNOBS = {
+    FA_TUNE_OCC_SMALL_TEXELS: [64, 128, 256, 512, 1024],
+    FA_TUNE_UF_LINK_INIT: [1, 0],
+    FA_TUNE_PACK_BLOCK: [256, 512, 1024],
+}
+NAMES = {FA_TUNE_PACK_BLOCK: "pack_block", FA_TUNE_OCC_SMALL_TEXELS: "occ_small_texels",
+         FA_TUNE_UF_LINK_INIT: "uf_link_init"}
+
+
+def _snapshot(out: AtlasOutputs):
+    ts = [out.chart_of_tri, out.chart_of_vert, out.charts, out.meta[:12]]
+    for t in (out.uv, out.occupancy, out.candidates):
+        if t is not None:
+            ts.append(t)
+    return [t.clone() for t in ts]
+
+
+def _same(a, b):
+    return all(torch.equal(x.view(torch.int32) if x.dtype == torch.float32 else x,
+                           y.view(torch.int32) if y.dtype == torch.float32 else y)
+               for x, y in zip(a, b))
+
+
+def _time(run, reps, stream):
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    run()
+    for a, b in evs:
+        a.record(stream)
+        run()
+        b.record(stream)
+    torch.cuda.synchronize()
+    ts = sorted(a.elapsed_time(b) for a, b in evs)
+    return ts[len(ts) // 2]
+
+
+def tune(ctx: Context, run, out: AtlasOutputs, reps: int = 15, knobs=None, stream=None):
+    """run(): enqueue one representative call writing into `out`.
+    Returns {"choice": {name: value}, "trials": {name: {value: ms}}}."""
+    knobs = knobs or KNOBS
+    stream = stream or torch.cuda.current_stream()
+    run()
+    torch.cuda.synchronize()
+    ref = _snapshot(out)
+    report = {"choice": {}, "trials": {}}
+    for knob, values in knobs.items():
+        trials = {}
+        for v in values:
+            ctx.set_tuning(knob, v)
+            ms = _time(run, reps, stream)
+            if not _same(_snapshot(out), ref):
+                raise RuntimeError(f"knob {NAMES[knob]}={v} changed the results")
+            trials[v] = ms
+        best = min(trials, key=trials.get)
+        ctx.set_tuning(knob, best)
+        report["choice"][NAMES[knob]] = best
+        report["trials"][NAMES[knob]] = trials
+    return report
+
+
+def save(report, path):
+    with open(path, "w") as f:
+        json.dump(report, f, indent=1)

@@ -20,6 +20,8 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortTile = 2048;      // keys per workgroup in one radix pass
 constexpr int kCandStride = 8;       // int32 per candidate in the table
 constexpr int kMaxAtlas = 8192;
+constexpr int kCountGrid = 1024;     // blocks of the occupancy count
+constexpr int kOccBigGrid = 2048;    // blocks of the large-footprint raster
 
 // Device-resident results of one frame that later stages read (kept on the
 // device so that no stage needs a host round trip).
@@ -32,8 +34,8 @@ struct FrameState {
   int32_t rows;
   float s_star;       // j*/J
   float q_star;       // omega/L*
-  uint32_t big_count; // large occupancy work items
-  uint32_t pad;
+  uint32_t pad0;
+  uint32_t pad1;
   unsigned long long occupied;
   unsigned long long visible;
 };
@@ -57,6 +59,7 @@ struct Work {
   int32_t* cov;          // [V] when the caller passes no chart_of_vert
   uint32_t* tile_count;  // [T/kTriTile + 1]
   uint32_t* tile_off;    // [T/kTriTile + 1]
+  uint32_t* tile_vis;    // [T/kTriTile + 1] visible triangles per tile
   uint32_t* accum;       // [max_charts][4] order-preserving encoded min/max
   uint32_t* keys_a;      // [max_charts]
   int32_t* vals_a;
@@ -68,7 +71,9 @@ struct Work {
   uint32_t* cand_ab;     // [J][max_charts] a | b << 16
   int32_t* cand_y;       // [J][max_charts]
   int32_t* cand_tab;     // [J][kCandStride] fit, m, L, H, rows
-  uint32_t* big;         // [2*T] large occupancy work items
+  ulonglong2* big;       // [min(2T, 2^24)] large occupancy footprints
+  unsigned long long* big_counter; // [1] queued footprints << 40 | queued tiles
+  unsigned long long* partial;     // [kCountGrid] per-block partial counts
   fa_chart* pack_charts; // [max_charts] chart records of the packer-only entry
   FrameState* state;     // [1]
 };
@@ -185,15 +190,23 @@ __host__ __device__ __forceinline__ int64_t ceil_div64(int64_t a, int64_t b) {
 // ---------------------------------------------------------------------------
 // host-side stage launchers (each enqueues on `st`)
 // ---------------------------------------------------------------------------
-hipError_t launch_frame_init(const Work& w, hipStream_t st);
-hipError_t launch_clip(const float* pos, int64_t V, const FrameParams& p, const Work& w,
-                       int32_t* cov, hipStream_t st);
+// Records an event after each kernel when per-kernel timing is on.
+struct Marker {
+  hipEvent_t* ev = nullptr;
+  int n = 0, cap = 0;
+  void operator()(hipStream_t s) {
+    if (ev && n < cap) (void)hipEventRecord(ev[n++], s);
+  }
+};
+
+hipError_t launch_prologue(const float* pos, int64_t V, const uint8_t* vis, const int32_t* nbr,
+                           int64_t T, const FrameParams& p, const Work& w, int32_t* cov,
+                           int uf_link_init, hipStream_t st);
 hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* nbr, int64_t T,
                          const FrameParams& p, const Work& w, int32_t* cot, int32_t* cov,
-                         fa_chart* charts, hipStream_t st);
-hipError_t launch_chart_sizes(const FrameParams& p, const Work& w, fa_chart* charts,
-                              hipStream_t st);
-hipError_t launch_order(const FrameParams& p, const Work& w, fa_chart* charts, hipStream_t st);
+                         fa_chart* charts, Marker& mk, hipStream_t st);
+hipError_t launch_order(const FrameParams& p, const Work& w, fa_chart* charts, int from_accum,
+                        hipStream_t st);
 hipError_t launch_pack(const FrameParams& p, const Work& w, int block, hipStream_t st);
 hipError_t launch_select_place(const FrameParams& p, const Work& w, fa_chart* charts,
                                int32_t* cand_out, hipStream_t st);
@@ -201,8 +214,9 @@ hipError_t launch_uv(const int64_t V, const FrameParams& p, const Work& w, const
                      const fa_chart* charts, float* uv, hipStream_t st);
 hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
                             const int32_t* cot, const fa_chart* charts, int32_t* occ,
-                            int small_texels, hipStream_t st);
-hipError_t launch_meta(const FrameParams& p, const Work& w, fa_atlas_meta* meta, hipStream_t st);
+                            int small_texels, Marker& mk, hipStream_t st);
+hipError_t launch_meta(const FrameParams& p, const Work& w, fa_atlas_meta* meta,
+                       int with_occupancy, hipStream_t st);
 
 // packer-only path: sizes [n][2] -> charts' oriented sizes and keys
 hipError_t launch_pack_prepare(const float* sizes, int32_t n, const FrameParams& p,

@@ -22,7 +22,7 @@ struct Scene {
   int64_t T = 0, V = 0;
 };
 
-enum { kStages = 6 };
+enum { kStages = 16 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -38,15 +38,25 @@ int log2i(int64_t x) {
 
 struct fa_ctx {
   fa_config cfg{};
-  Work w{};
-  void* arena = nullptr;
+  std::vector<Work> slots;          // one scratch set per concurrent view
+  std::vector<void*> arenas;
+  std::vector<hipStream_t> slot_streams;
+  std::vector<hipEvent_t> slot_join;
+  hipEvent_t ev_fork = nullptr, ev_done = nullptr;
+  hipStream_t cap_stream = nullptr;  // batch graphs are captured and launched here
   size_t arena_bytes = 0;
   std::unordered_map<uint64_t, Scene> scenes;
+  int batch_graph = 0;
+  std::string graph_sig;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
   bool timing = false;
   hipEvent_t ev[kStages + 1] = {};
   bool ev_recorded = false;
+  int ev_marks = 0;
   int pack_block = 256;
-  int small_texels = 64;
+  int small_texels = 256;
+  int uf_link_init = 1;
   int32_t* check_flag = nullptr;  // device int for index validation
 };
 
@@ -112,34 +122,57 @@ int fa_create(const fa_config* cfg_in, fa_ctx** out_ctx) {
   const size_t tiles = T / kTriTile + 2;
   const size_t sort_tiles = C / kSortTile + 2;
   struct Part { void** p; size_t bytes; };
-  Work& w = ctx->w;
-  std::vector<Part> parts = {
-      {(void**)&w.clip, sizeof(float4) * V},   {(void**)&w.parent, 4 * T},
-      {(void**)&w.vmin, 4 * V},                {(void**)&w.cov, 4 * V},
-      {(void**)&w.tile_count, 4 * tiles},      {(void**)&w.tile_off, 4 * tiles},
-      {(void**)&w.accum, 16 * C},              {(void**)&w.keys_a, 4 * C},
-      {(void**)&w.vals_a, 4 * C},              {(void**)&w.keys_b, 4 * C},
-      {(void**)&w.vals_b, 4 * C},              {(void**)&w.hist, 4 * kRadix * sort_tiles},
-      {(void**)&w.sorted_wh, 8 * C},           {(void**)&w.cand_x, 8 * J * C},
-      {(void**)&w.cand_ab, 4 * J * C},         {(void**)&w.cand_y, 4 * J * C},
-      {(void**)&w.cand_tab, 4 * kCandStride * J}, {(void**)&w.big, 8 * T},
-      {(void**)&w.pack_charts, sizeof(fa_chart) * C},
-      {(void**)&w.state, sizeof(FrameState)},  {(void**)&ctx->check_flag, 4}};
-  size_t total = 0;
-  for (auto& p : parts) total += align_up(p.bytes);
-  if (hipMalloc(&ctx->arena, total) != hipSuccess) {
-    delete ctx;
-    return FA_ERR_OUT_OF_MEMORY;
+  ctx->slots.resize(cfg.max_views);
+  for (int v = 0; v < cfg.max_views; ++v) {
+    Work& w = ctx->slots[v];
+    std::vector<Part> parts = {
+        {(void**)&w.clip, sizeof(float4) * V},   {(void**)&w.parent, 4 * T},
+        {(void**)&w.vmin, 4 * V},                {(void**)&w.cov, 4 * V},
+        {(void**)&w.tile_count, 4 * tiles},      {(void**)&w.tile_off, 4 * tiles},
+        {(void**)&w.tile_vis, 4 * tiles},
+        {(void**)&w.accum, 16 * C},              {(void**)&w.keys_a, 4 * C},
+        {(void**)&w.vals_a, 4 * C},              {(void**)&w.keys_b, 4 * C},
+        {(void**)&w.vals_b, 4 * C},              {(void**)&w.hist, 4 * kRadix * sort_tiles},
+        {(void**)&w.sorted_wh, 8 * C},           {(void**)&w.cand_x, 8 * J * C},
+        {(void**)&w.cand_ab, 4 * J * C},         {(void**)&w.cand_y, 4 * J * C},
+        {(void**)&w.cand_tab, 4 * kCandStride * J},
+        {(void**)&w.big, 16 * std::min<size_t>(2 * T, size_t(1) << 24)},
+        {(void**)&w.big_counter, 8}, {(void**)&w.partial, 8 * kCountGrid},
+        {(void**)&w.pack_charts, sizeof(fa_chart) * C},
+        {(void**)&w.state, sizeof(FrameState)}};
+    size_t total = 0;
+    for (auto& p : parts) total += align_up(p.bytes);
+    void* arena = nullptr;
+    if (hipMalloc(&arena, total) != hipSuccess) {
+      fa_destroy(ctx);
+      return FA_ERR_OUT_OF_MEMORY;
+    }
+    ctx->arenas.push_back(arena);
+    ctx->arena_bytes += total;
+    char* base = static_cast<char*>(arena);
+    for (auto& p : parts) {
+      *p.p = base;
+      base += align_up(p.bytes);
+    }
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      fa_destroy(ctx);
+      return FA_ERR_DEVICE;
+    }
+    ctx->slot_streams.push_back(s);
+    ctx->slot_join.push_back(e);
   }
-  ctx->arena_bytes = total;
-  char* base = static_cast<char*>(ctx->arena);
-  for (auto& p : parts) {
-    *p.p = base;
-    base += align_up(p.bytes);
+  if (hipMalloc(&ctx->check_flag, 4) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_done, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    fa_destroy(ctx);
+    return FA_ERR_DEVICE;
   }
   if (pack_kernel_attributes(2 * cfg.max_atlas * (int)sizeof(int32_t)) != hipSuccess) {
-    (void)hipFree(ctx->arena);
-    delete ctx;
+    fa_destroy(ctx);
     return FA_ERR_DEVICE;
   }
   for (int i = 0; i <= kStages; ++i) (void)hipEventCreate(&ctx->ev[i]);
@@ -150,11 +183,20 @@ int fa_create(const fa_config* cfg_in, fa_ctx** out_ctx) {
 void fa_destroy(fa_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->cfg.device);
+  (void)hipDeviceSynchronize();
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
   for (auto& kv : ctx->scenes) (void)hipFree(kv.second.nbr);
   ctx->scenes.clear();
   for (int i = 0; i <= kStages; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
-  (void)hipFree(ctx->arena);
+  for (hipStream_t s : ctx->slot_streams) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : ctx->slot_join) (void)hipEventDestroy(e);
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_done) (void)hipEventDestroy(ctx->ev_done);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  for (void* a : ctx->arenas) (void)hipFree(a);
+  if (ctx->check_flag) (void)hipFree(ctx->check_flag);
   delete ctx;
 }
 
@@ -275,38 +317,39 @@ static int frame_params(const fa_ctx* ctx, const fa_camera* cam, int32_t atlas, 
   return FA_OK;
 }
 
-static inline void mark(fa_ctx* ctx, int i, hipStream_t st) {
-  if (ctx->timing) (void)hipEventRecord(ctx->ev[i], st);
-}
 
-static int run_frame(fa_ctx* ctx, const fa_mesh* mesh, Scene* sc, const uint8_t* visible,
-                     const FrameParams& p, fa_atlas_out* out, hipStream_t st) {
-  const Work& w = ctx->w;
+static int run_frame(fa_ctx* ctx, const Work& w, const fa_mesh* mesh, Scene* sc,
+                     const uint8_t* visible, const FrameParams& p, const fa_atlas_out* out,
+                     hipStream_t st) {
   const int64_t T = mesh->num_triangles, V = mesh->num_vertices;
   int32_t* cov = out->chart_of_vert ? out->chart_of_vert : w.cov;
   hipError_t e = hipSuccess;
   auto ok = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
-  mark(ctx, 0, st);
-  ok(launch_frame_init(w, st));
-  ok(launch_clip(mesh->positions, V, p, w, cov, st));
+  // per-kernel events: prologue, uf_hook, uf_vertex_hook, uf_flatten, scan_tiles,
+  // assign_roots, gather_boxes, sizes_order, pack, select_place, uv, occ_fill,
+  // occ_small, occ_big, occ_count, meta
+  Marker mk;
+  if (ctx->timing) { mk.ev = ctx->ev; mk.cap = kStages + 1; }
+  mk(st);
+  ok(launch_prologue(mesh->positions, V, visible, sc->nbr, T, p, w, cov, ctx->uf_link_init, st));
+  mk(st);
   ok(launch_charts(visible, mesh->indices, sc->nbr, T, p, w, out->chart_of_tri, cov, out->charts,
-                   st));
-  mark(ctx, 1, st);
-  ok(launch_chart_sizes(p, w, out->charts, st));
-  mark(ctx, 2, st);
-  ok(launch_order(p, w, out->charts, st));
-  mark(ctx, 3, st);
+                   mk, st));
+  ok(launch_order(p, w, out->charts, 1, st));
+  mk(st);
   ok(launch_pack(p, w, ctx->pack_block, st));
+  mk(st);
   ok(launch_select_place(p, w, out->charts, out->candidates, st));
-  mark(ctx, 4, st);
+  mk(st);
   if (out->uv) ok(launch_uv(V, p, w, cov, out->charts, out->uv, st));
-  mark(ctx, 5, st);
+  mk(st);
   if (out->occupancy)
     ok(launch_occupancy(mesh->indices, T, p, w, out->chart_of_tri, out->charts, out->occupancy,
-                        ctx->small_texels, st));
-  ok(launch_meta(p, w, out->meta, st));
-  mark(ctx, 6, st);
-  ctx->ev_recorded = ctx->timing;
+                        ctx->small_texels, mk, st));
+  ok(launch_meta(p, w, out->meta, out->occupancy != nullptr, st));
+  mk(st);
+  ctx->ev_marks = mk.n;
+  ctx->ev_recorded = ctx->timing && mk.n == kStages + 1;
   return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
 }
 
@@ -325,7 +368,33 @@ int fa_build_atlas(fa_ctx* ctx, const fa_mesh* mesh, const uint8_t* visible,
   Scene* sc = nullptr;
   rc = get_scene(ctx, mesh, st, &sc);
   if (rc) return rc;
-  return run_frame(ctx, mesh, sc, visible, p, out, st);
+  return run_frame(ctx, ctx->slots[0], mesh, sc, visible, p, out, st);
+}
+
+// Views run concurrently, view i on scratch slot i % max_views and that
+// slot's stream, forked from and joined back into the caller's stream. With
+// the batch-graph knob, the forked work is captured once into a hipGraph
+// (keyed by every byte of the descriptors) and replayed as one launch.
+static int enqueue_views(fa_ctx* ctx, const fa_mesh* mesh, Scene* sc, int32_t n,
+                         const fa_view* views, const std::vector<FrameParams>& ps,
+                         hipStream_t origin) {
+  const int S = std::min<int>(n, (int)ctx->slots.size());
+  if (hipEventRecord(ctx->ev_fork, origin) != hipSuccess) return FA_ERR_DEVICE;
+  for (int k = 0; k < S; ++k)
+    if (hipStreamWaitEvent(ctx->slot_streams[k], ctx->ev_fork, 0) != hipSuccess)
+      return FA_ERR_DEVICE;
+  for (int i = 0; i < n; ++i) {
+    const int k = i % S;
+    int rc = run_frame(ctx, ctx->slots[k], mesh, sc, views[i].visible, ps[i], &views[i].out,
+                       ctx->slot_streams[k]);
+    if (rc) return rc;
+  }
+  for (int k = 0; k < S; ++k) {
+    if (hipEventRecord(ctx->slot_join[k], ctx->slot_streams[k]) != hipSuccess ||
+        hipStreamWaitEvent(origin, ctx->slot_join[k], 0) != hipSuccess)
+      return FA_ERR_DEVICE;
+  }
+  return FA_OK;
 }
 
 int fa_build_atlas_batch(fa_ctx* ctx, const fa_mesh* mesh, int32_t n, const fa_view* views,
@@ -340,16 +409,55 @@ int fa_build_atlas_batch(fa_ctx* ctx, const fa_mesh* mesh, int32_t n, const fa_v
     rc = frame_params(ctx, &v.cam, v.atlas_size, v.texel_per_pixel, &ps[i]);
     if (rc) return rc;
   }
+  if (n == 0) return FA_OK;
   if (hipSetDevice(ctx->cfg.device) != hipSuccess) return FA_ERR_DEVICE;
   hipStream_t st = (hipStream_t)stream;
   Scene* sc = nullptr;
   rc = get_scene(ctx, mesh, st, &sc);
   if (rc) return rc;
-  for (int i = 0; i < n; ++i) {
-    fa_atlas_out o = views[i].out;
-    rc = run_frame(ctx, mesh, sc, views[i].visible, ps[i], &o, st);
-    if (rc) return rc;
+  const bool timing = ctx->timing;
+  ctx->timing = false;  // no stage events inside a batch
+  if (!ctx->batch_graph) {
+    rc = enqueue_views(ctx, mesh, sc, n, views, ps, st);
+    ctx->timing = timing;
+    return rc;
   }
+  std::string sig(reinterpret_cast<const char*>(mesh), sizeof(fa_mesh));
+  sig.append(reinterpret_cast<const char*>(views), sizeof(fa_view) * (size_t)n);
+  sig.append(reinterpret_cast<const char*>(&ctx->pack_block), sizeof(int) * 3);
+  if (!ctx->graph_exec || sig != ctx->graph_sig) {
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    ctx->graph_sig.clear();
+    if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      ctx->timing = timing;
+      return FA_ERR_DEVICE;
+    }
+    rc = enqueue_views(ctx, mesh, sc, n, views, ps, ctx->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+    ctx->timing = timing;
+    if (rc || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc ? rc : FA_ERR_DEVICE;
+    }
+    if (hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      ctx->graph_exec = nullptr;
+      return FA_ERR_DEVICE;
+    }
+    ctx->graph = g;
+    ctx->graph_sig = sig;
+  }
+  ctx->timing = timing;
+  if (hipEventRecord(ctx->ev_fork, st) != hipSuccess ||
+      hipStreamWaitEvent(ctx->cap_stream, ctx->ev_fork, 0) != hipSuccess ||
+      hipGraphLaunch(ctx->graph_exec, ctx->cap_stream) != hipSuccess ||
+      hipEventRecord(ctx->ev_done, ctx->cap_stream) != hipSuccess ||
+      hipStreamWaitEvent(st, ctx->ev_done, 0) != hipSuccess)
+    return FA_ERR_DEVICE;
   return FA_OK;
 }
 
@@ -362,18 +470,52 @@ int fa_pack_boxes(fa_ctx* ctx, const float* sizes, int32_t n, int32_t atlas_size
   if (rc) return rc;
   if (hipSetDevice(ctx->cfg.device) != hipSuccess) return FA_ERR_DEVICE;
   hipStream_t st = (hipStream_t)stream;
-  const Work& w = ctx->w;
+  const Work& w = ctx->slots[0];
   fa_chart* charts = w.pack_charts;
   hipError_t e = hipSuccess;
   auto ok = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
-  ok(launch_frame_init(w, st));
   ok(launch_pack_prepare(sizes, n, p, w, charts, st));
-  ok(launch_order(p, w, charts, st));
+  ok(launch_order(p, w, charts, 0, st));
   ok(launch_pack(p, w, ctx->pack_block, st));
   ok(launch_select_place(p, w, charts, candidates, st));
   ok(launch_pack_emit(n, charts, placements, w, st));
-  ok(launch_meta(p, w, meta, st));
+  ok(launch_meta(p, w, meta, 0, st));
   return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+
+int fa_set_tuning(fa_ctx* ctx, int knob, int value) {
+  if (!ctx) return FA_ERR_INVALID_ARG;
+  switch (knob) {
+    case FA_TUNE_PACK_BLOCK:
+      if (value != 256 && value != 512 && value != 1024) return FA_ERR_INVALID_ARG;
+      ctx->pack_block = value;
+      return FA_OK;
+    case FA_TUNE_OCC_SMALL_TEXELS:
+      if (value < 0 || value > 4096) return FA_ERR_INVALID_ARG;
+      ctx->small_texels = value;
+      return FA_OK;
+    case FA_TUNE_UF_LINK_INIT:
+      if (value != 0 && value != 1) return FA_ERR_INVALID_ARG;
+      ctx->uf_link_init = value;
+      return FA_OK;
+    case FA_TUNE_BATCH_GRAPH:
+      if (value != 0 && value != 1) return FA_ERR_INVALID_ARG;
+      ctx->batch_graph = value;
+      return FA_OK;
+    default:
+      return FA_ERR_INVALID_ARG;
+  }
+}
+
+int fa_get_tuning(fa_ctx* ctx, int knob) {
+  if (!ctx) return -1;
+  switch (knob) {
+    case FA_TUNE_PACK_BLOCK: return ctx->pack_block;
+    case FA_TUNE_OCC_SMALL_TEXELS: return ctx->small_texels;
+    case FA_TUNE_UF_LINK_INIT: return ctx->uf_link_init;
+    case FA_TUNE_BATCH_GRAPH: return ctx->batch_graph;
+    default: return -1;
+  }
 }
 
 int fa_set_stage_timing(fa_ctx* ctx, int enable) {

@@ -2,42 +2,13 @@
 //   clip transform, union-find charts (Appendix "GPU Union Find", Alg. 1),
 //   root compaction, per-triangle conservative boxes (Sec. "Computing Bounding
 //   Boxes of Projected Visible Sub-Charts") reduced per chart, chart sizes.
+#include <algorithm>
 #include <climits>
 
 #include "fa_internal.h"
 
 namespace fa {
 namespace {
-
-// ---------------------------------------------------------------------------
-// clip transform: clip = M (x, y, z, 1)^T, each row summed left to right
-// ---------------------------------------------------------------------------
-__global__ void k_clip(const float* __restrict__ pos, int64_t V, FrameParams p,
-                       float4* __restrict__ clip, int32_t* __restrict__ vmin,
-                       int32_t* __restrict__ cov) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= V) return;
-  const float x = pos[3 * v], y = pos[3 * v + 1], z = pos[3 * v + 2];
-  float r[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    float acc = p.M[4 * i] * x;
-    acc = acc + p.M[4 * i + 1] * y;
-    acc = acc + p.M[4 * i + 2] * z;
-    r[i] = acc + p.M[4 * i + 3];
-  }
-  clip[v] = make_float4(r[0], r[1], r[2], r[3]);
-  vmin[v] = INT_MAX;
-  cov[v] = -1;
-}
-
-__global__ void k_frame_init(FrameState* st) {
-  if (threadIdx.x == 0) {
-    FrameState s = {};
-    s.status = FA_OK;
-    *st = s;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // union-find over visible triangles. parent[x] <= x always holds; a root has
@@ -74,27 +45,66 @@ __device__ __forceinline__ void uf_join(int32_t* parent, int u, int v) {
   }
 }
 
-// Init: every visible triangle points at the smallest of itself and its
-// visible edge neighbours (Alg. 1, first loop).
-__global__ void k_uf_init(const uint8_t* __restrict__ vis, const int32_t* __restrict__ nbr,
-                          int64_t T, int32_t* __restrict__ parent) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Prologue of a frame: frame state, clip transform of every vertex
+// (clip = M (x, y, z, 1)^T, rows summed left to right), per-vertex scratch, and
+// the union-find start of every triangle. Blocks [0, vblocks) handle
+// vertices, the rest triangles. With link_neighbours a visible triangle starts
+// linked to the smallest of itself and its visible edge neighbours (Alg. 1,
+// first loop); otherwise it starts as its own root (same final labels).
+__global__ void k_prologue(const float* __restrict__ pos, int64_t V, FrameParams p,
+                           float4* __restrict__ clip, int32_t* __restrict__ vmin,
+                           int32_t* __restrict__ cov, const uint8_t* __restrict__ vis,
+                           const int32_t* __restrict__ nbr, int64_t T,
+                           int32_t* __restrict__ parent, int link_neighbours, unsigned vblocks,
+                           FrameState* st, unsigned long long* big_counter) {
+  if (blockIdx.x < vblocks) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      FrameState s = {};
+      s.status = FA_OK;
+      *st = s;
+      *big_counter = 0ull;
+    }
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const float x = pos[3 * v], y = pos[3 * v + 1], z = pos[3 * v + 2];
+    float r[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float acc = p.M[4 * i] * x;
+      acc = acc + p.M[4 * i + 1] * y;
+      acc = acc + p.M[4 * i + 2] * z;
+      r[i] = acc + p.M[4 * i + 3];
+    }
+    clip[v] = make_float4(r[0], r[1], r[2], r[3]);
+    vmin[v] = INT_MAX;
+    cov[v] = -1;
+    return;
+  }
+  const int64_t t = (int64_t)(blockIdx.x - vblocks) * blockDim.x + threadIdx.x;
   if (t >= T) return;
   if (!vis[t]) { parent[t] = -1; return; }
-  int p = (int)t;
+  int q = (int)t;
+  if (link_neighbours) {
 #pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    int n = nbr[3 * t + e];
-    if (n >= 0 && vis[n]) p = min(p, n);
+    for (int e = 0; e < 3; ++e) {
+      const int n = nbr[3 * t + e];
+      if (n >= 0 && vis[n]) q = min(q, n);
+    }
   }
-  parent[t] = p;
+  parent[t] = q;
 }
 
-// Hook: join across every shared edge once (u < v) (Alg. 1, second loop).
+// Hook across every shared edge once (u < v) (Alg. 1, second loop) and record
+// for every vertex the smallest visible triangle using it. The record only has
+// to name some triangle of the charts meeting at the vertex; the smallest
+// triangle serves as well as its root does in Alg. 1's third loop.
 __global__ void k_uf_hook(const uint8_t* __restrict__ vis, const int32_t* __restrict__ nbr,
-                          int64_t T, int32_t* parent) {
+                          const int32_t* __restrict__ idx, int64_t T, int32_t* parent,
+                          int32_t* __restrict__ vmin) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= T || !vis[t]) return;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) atomicMin(&vmin[idx[3 * t + e]], (int)t);
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     int n = nbr[3 * t + e];
@@ -102,19 +112,8 @@ __global__ void k_uf_hook(const uint8_t* __restrict__ vis, const int32_t* __rest
   }
 }
 
-// Vertex minimum: every vertex records the smallest root among its visible
-// triangles (Alg. 1, third loop).
-__global__ void k_uf_vertex_min(const uint8_t* __restrict__ vis, const int32_t* __restrict__ idx,
-                                int64_t T, int32_t* parent, int32_t* __restrict__ vmin) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= T || !vis[t]) return;
-  int r = uf_root(parent, (int)t);
-#pragma unroll
-  for (int e = 0; e < 3; ++e) atomicMin(&vmin[idx[3 * t + e]], r);
-}
-
-// Vertex hook: join every visible triangle with the recorded root of each of
-// its vertices, merging charts that share only a vertex.
+// Vertex hook: join every visible triangle with the recorded triangle of each
+// of its vertices, merging charts that share only a vertex.
 __global__ void k_uf_vertex_hook(const uint8_t* __restrict__ vis, const int32_t* __restrict__ idx,
                                  int64_t T, int32_t* parent, const int32_t* __restrict__ vmin) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -129,7 +128,8 @@ __global__ void k_uf_vertex_hook(const uint8_t* __restrict__ vis, const int32_t*
 // Flatten every visible triangle to its root and count roots per tile of
 // kTriTile consecutive triangles.
 __global__ void k_uf_flatten_count(const uint8_t* __restrict__ vis, int64_t T, int32_t* parent,
-                                   uint32_t* __restrict__ tile_count, FrameState* st) {
+                                   uint32_t* __restrict__ tile_count,
+                                   uint32_t* __restrict__ tile_vis) {
   __shared__ uint32_t sh[kBlock / kWave];
   const int64_t base = (int64_t)blockIdx.x * kTriTile + (int64_t)threadIdx.x * 4;
   uint32_t roots = 0, visible = 0;
@@ -147,24 +147,30 @@ __global__ void k_uf_flatten_count(const uint8_t* __restrict__ vis, int64_t T, i
   uint32_t vs = block_sum<uint32_t>(visible, sh);
   if (threadIdx.x == 0) {
     tile_count[blockIdx.x] = rs;
-    atomicAdd(&st->visible, (unsigned long long)vs);
+    tile_vis[blockIdx.x] = vs;
   }
 }
 
 // Exclusive scan of the per-tile root counts (one workgroup); C = total.
-__global__ void k_scan_tiles(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ off,
-                             int64_t ntiles, int32_t max_charts, FrameState* st) {
+__global__ void k_scan_tiles(const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ vis_cnt,
+                             uint32_t* __restrict__ off, int64_t ntiles, int32_t max_charts,
+                             FrameState* st) {
   __shared__ uint32_t sh[1024 / kWave];
+  __shared__ unsigned long long shv[1024 / kWave];
   uint32_t run = 0;
+  unsigned long long nvis = 0;
   for (int64_t b0 = 0; b0 < ntiles; b0 += blockDim.x) {
     int64_t b = b0 + threadIdx.x;
     uint32_t v = b < ntiles ? cnt[b] : 0;
+    nvis += b < ntiles ? vis_cnt[b] : 0;
     uint32_t tot;
     uint32_t inc = block_incl_scan<uint32_t>(v, sh, &tot);
     if (b < ntiles) off[b] = run + inc - v;
     run += tot;
   }
+  nvis = block_sum<unsigned long long>(nvis, shv);
   if (threadIdx.x == 0) {
+    st->visible = nvis;
     st->num_charts = (int32_t)run;
     if ((int64_t)run > (int64_t)max_charts) st->status = FA_ERR_CAPACITY;
   }
@@ -330,126 +336,128 @@ __device__ __forceinline__ bool triangle_ndc_box(const float4& a, const float4& 
 }
 
 // Gather: chart of every visible triangle and its vertices, and the chart's
-// box as the union of its triangles' boxes. Lanes of one wave that belong to
-// the same chart are reduced in registers before one lane issues the atomics.
-__global__ void k_gather_boxes(const uint8_t* __restrict__ vis, const int32_t* __restrict__ idx,
-                               int64_t T, const int32_t* __restrict__ parent,
-                               const float4* __restrict__ clip, int32_t* cot,
-                               int32_t* __restrict__ cov, uint32_t* __restrict__ accum,
-                               uint32_t flags, const FrameState* __restrict__ st) {
-  if (st->status != FA_OK) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = t < T;
-  const bool visible = valid && vis[t];
-  int c = -1;
-  bool has = false;
-  float4 box = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (visible) {
-    c = cot[parent[t]];
-    const int i0 = idx[3 * t], i1 = idx[3 * t + 1], i2 = idx[3 * t + 2];
-    cov[i0] = c;
-    cov[i1] = c;
-    cov[i2] = c;
-    has = triangle_ndc_box(clip[i0], clip[i1], clip[i2], !(flags & FA_FLAG_NO_SIDE_CLIP), box);
-  }
-  if (valid) cot[t] = c;
-  const uint32_t e0 = ord_of(box.x), e1 = ord_of(box.y), e2 = ord_of(box.z), e3 = ord_of(box.w);
-  unsigned long long todo = __ballot(has);
-  while (todo) {
-    const int leader = __ffsll((long long)todo) - 1;
-    const int cl = __shfl(c, leader, kWave);
-    const bool mine = has && c == cl;
-    const unsigned long long grp = __ballot(mine);
-    uint32_t a0 = wave_min<uint32_t>(mine ? e0 : 0xFFFFFFFFu);
-    uint32_t a1 = wave_min<uint32_t>(mine ? e1 : 0xFFFFFFFFu);
-    uint32_t a2 = wave_max<uint32_t>(mine ? e2 : 0u);
-    uint32_t a3 = wave_max<uint32_t>(mine ? e3 : 0u);
-    if (lane_id() == leader) {
-      atomicMin(&accum[4 * cl + 0], a0);
-      atomicMin(&accum[4 * cl + 1], a1);
-      atomicMax(&accum[4 * cl + 2], a2);
-      atomicMax(&accum[4 * cl + 3], a3);
-    }
-    todo &= ~grp;
-  }
-}
+// box as the union of its triangles' boxes. Each thread handles kGatherItems
+// triangles; lanes of a wave with the same chart are reduced in registers,
+// then merged into a small per-workgroup table in LDS, and only the table is
+// flushed with global atomics (large charts would otherwise serialize on
+// their four accumulator words).
+constexpr int kGatherItems = 8;
+constexpr int kSlots = 64;
 
-// Chart frame and target size: viewport transform of the NDC box times the
-// rate, orientation (taller than wide) and the 13-bit height key.
-__global__ void k_chart_sizes(FrameParams p, const uint32_t* __restrict__ accum,
-                              fa_chart* __restrict__ charts, uint32_t* __restrict__ keys,
-                              int32_t* __restrict__ vals, const FrameState* __restrict__ st) {
+__global__ __launch_bounds__(kBlock) void k_gather_boxes(
+    const uint8_t* __restrict__ vis, const int32_t* __restrict__ idx, int64_t T,
+    const int32_t* __restrict__ parent, const float4* __restrict__ clip, int32_t* cot,
+    int32_t* __restrict__ cov, uint32_t* __restrict__ accum, uint32_t flags,
+    const FrameState* __restrict__ st) {
+  __shared__ int32_t skey[kSlots];
+  __shared__ uint32_t sbox[kSlots][4];
   if (st->status != FA_OK) return;
-  const int C = st->num_charts;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= C) return;
-  const uint4 e = reinterpret_cast<const uint4*>(accum)[c];
-  float x0 = 0.0f, y0 = 0.0f, x1 = 0.0f, y1 = 0.0f;
-  if (e.z != 0u) {
-    x0 = float_of(e.x);
-    y0 = float_of(e.y);
-    x1 = float_of(e.z);
-    y1 = float_of(e.w);
+  for (int i = threadIdx.x; i < kSlots; i += blockDim.x) {
+    skey[i] = -1;
+    sbox[i][0] = sbox[i][1] = 0xFFFFFFFFu;
+    sbox[i][2] = sbox[i][3] = 0u;
   }
-  x0 = x0 + 0.0f; y0 = y0 + 0.0f; x1 = x1 + 0.0f; y1 = y1 + 0.0f;
-  const float halfW = 0.5f * (float)p.W, halfH = 0.5f * (float)p.H;
-  const float tw = ((x1 - x0) * halfW) * p.rate;
-  const float th = ((y1 - y0) * halfH) * p.rate;
-  const int rot = tw > th ? 1 : 0;
-  const float bw = rot ? th : tw, bh = rot ? tw : th;
-  const int key = min((int)ceilf(bh), kKeyCap);
-  fa_chart& ch = charts[c];
-  ch.ndc_box[0] = x0; ch.ndc_box[1] = y0; ch.ndc_box[2] = x1; ch.ndc_box[3] = y1;
-  ch.target_w = tw; ch.target_h = th;
-  ch.oriented_w = bw; ch.oriented_h = bh;
-  ch.rotated = rot;
-  ch.key = key;
-  keys[c] = (uint32_t)(kKeyCap - key);
-  vals[c] = c;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * (kBlock * kGatherItems);
+  for (int k = 0; k < kGatherItems; ++k) {
+    const int64_t t = base + (int64_t)k * kBlock + threadIdx.x;
+    const bool valid = t < T;
+    const bool visible = valid && vis[t];
+    int c = -1;
+    bool has = false;
+    float4 box = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (visible) {
+      c = cot[parent[t]];
+      const int i0 = idx[3 * t], i1 = idx[3 * t + 1], i2 = idx[3 * t + 2];
+      cov[i0] = c;
+      cov[i1] = c;
+      cov[i2] = c;
+      has = triangle_ndc_box(clip[i0], clip[i1], clip[i2], !(flags & FA_FLAG_NO_SIDE_CLIP), box);
+    }
+    if (valid) cot[t] = c;
+    const uint32_t e0 = ord_of(box.x), e1 = ord_of(box.y), e2 = ord_of(box.z), e3 = ord_of(box.w);
+    unsigned long long todo = __ballot(has);
+    while (todo) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const int cl = __shfl(c, leader, kWave);
+      const bool mine = has && c == cl;
+      const unsigned long long grp = __ballot(mine);
+      const uint32_t a0 = wave_min<uint32_t>(mine ? e0 : 0xFFFFFFFFu);
+      const uint32_t a1 = wave_min<uint32_t>(mine ? e1 : 0xFFFFFFFFu);
+      const uint32_t a2 = wave_max<uint32_t>(mine ? e2 : 0u);
+      const uint32_t a3 = wave_max<uint32_t>(mine ? e3 : 0u);
+      if (lane_id() == leader) {
+        int h = cl & (kSlots - 1), slot = -1;
+        for (int probe = 0; probe < kSlots; ++probe) {
+          const int prev = atomicCAS(&skey[h], -1, cl);
+          if (prev == -1 || prev == cl) { slot = h; break; }
+          h = (h + 1) & (kSlots - 1);
+        }
+        if (slot >= 0) {
+          atomicMin(&sbox[slot][0], a0);
+          atomicMin(&sbox[slot][1], a1);
+          atomicMax(&sbox[slot][2], a2);
+          atomicMax(&sbox[slot][3], a3);
+        } else {
+          atomicMin(&accum[4 * cl + 0], a0);
+          atomicMin(&accum[4 * cl + 1], a1);
+          atomicMax(&accum[4 * cl + 2], a2);
+          atomicMax(&accum[4 * cl + 3], a3);
+        }
+      }
+      todo &= ~grp;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kSlots; i += blockDim.x) {
+    const int cl = skey[i];
+    if (cl < 0) continue;
+    atomicMin(&accum[4 * cl + 0], sbox[i][0]);
+    atomicMin(&accum[4 * cl + 1], sbox[i][1]);
+    atomicMax(&accum[4 * cl + 2], sbox[i][2]);
+    atomicMax(&accum[4 * cl + 3], sbox[i][3]);
+  }
 }
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 }  // namespace
 
-hipError_t launch_frame_init(const Work& w, hipStream_t st) {
-  k_frame_init<<<1, 64, 0, st>>>(w.state);
-  return hipGetLastError();
-}
-
-hipError_t launch_clip(const float* pos, int64_t V, const FrameParams& p, const Work& w,
-                       int32_t* cov, hipStream_t st) {
-  if (V > 0) k_clip<<<grid_for(V, kBlock), kBlock, 0, st>>>(pos, V, p, w.clip, w.vmin, cov);
+hipError_t launch_prologue(const float* pos, int64_t V, const uint8_t* vis, const int32_t* nbr,
+                           int64_t T, const FrameParams& p, const Work& w, int32_t* cov,
+                           int uf_link_init, hipStream_t st) {
+  const unsigned vb = std::max(1u, grid_for(V, kBlock));
+  k_prologue<<<vb + grid_for(T, kBlock), kBlock, 0, st>>>(pos, V, p, w.clip, w.vmin, cov, vis, nbr,
+                                                          T, w.parent, uf_link_init, vb, w.state,
+                                                          w.big_counter);
   return hipGetLastError();
 }
 
 hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* nbr, int64_t T,
                          const FrameParams& p, const Work& w, int32_t* cot, int32_t* cov,
-                         fa_chart* charts, hipStream_t st) {
+                         fa_chart* charts, Marker& mk, hipStream_t st) {
   const int64_t ntiles = (T + kTriTile - 1) / kTriTile;
   if (T > 0) {
     const unsigned g = grid_for(T, kBlock);
-    k_uf_init<<<g, kBlock, 0, st>>>(vis, nbr, T, w.parent);
-    k_uf_hook<<<g, kBlock, 0, st>>>(vis, nbr, T, w.parent);
-    k_uf_vertex_min<<<g, kBlock, 0, st>>>(vis, idx, T, w.parent, w.vmin);
+    k_uf_hook<<<g, kBlock, 0, st>>>(vis, nbr, idx, T, w.parent, w.vmin);
+    mk(st);
     k_uf_vertex_hook<<<g, kBlock, 0, st>>>(vis, idx, T, w.parent, w.vmin);
+    mk(st);
     k_uf_flatten_count<<<(unsigned)ntiles, kBlock, 0, st>>>(vis, T, w.parent, w.tile_count,
-                                                            w.state);
+                                                            w.tile_vis);
   }
-  k_scan_tiles<<<1, 1024, 0, st>>>(w.tile_count, w.tile_off, ntiles, p.max_charts, w.state);
+  mk(st);
+  k_scan_tiles<<<1, 1024, 0, st>>>(w.tile_count, w.tile_vis, w.tile_off, ntiles, p.max_charts,
+                                   w.state);
+  mk(st);
   if (T > 0) {
     k_assign_roots<<<(unsigned)ntiles, kBlock, 0, st>>>(vis, T, w.parent, w.tile_off, cot, charts,
                                                         w.accum, w.state);
-    k_gather_boxes<<<grid_for(T, kBlock), kBlock, 0, st>>>(vis, idx, T, w.parent, w.clip, cot, cov,
-                                                           w.accum, p.flags, w.state);
+    mk(st);
+    k_gather_boxes<<<grid_for(T, kBlock * kGatherItems), kBlock, 0, st>>>(
+        vis, idx, T, w.parent, w.clip, cot, cov, w.accum, p.flags, w.state);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_chart_sizes(const FrameParams& p, const Work& w, fa_chart* charts,
-                              hipStream_t st) {
-  k_chart_sizes<<<grid_for(p.max_charts, kBlock), kBlock, 0, st>>>(p, w.accum, charts, w.keys_a,
-                                                                   w.vals_a, w.state);
+  mk(st);
   return hipGetLastError();
 }
 

@@ -189,50 +189,66 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
   }
 }
 
-// Largest effective scale j/L_j among fitting candidates (ties -> larger j).
-__global__ void k_select(FrameParams p, const int32_t* __restrict__ cand_tab, FrameState* st,
-                         int32_t* __restrict__ cand_out) {
-  if (threadIdx.x < p.J && cand_out) {
-    const int32_t* t = cand_tab + threadIdx.x * kCandStride;
-    int32_t* o = cand_out + 4 * threadIdx.x;
-    if (st->status == FA_OK) { o[0] = t[0]; o[1] = t[1]; o[2] = t[2]; o[3] = t[3]; }
-    else { o[0] = 0; o[1] = 0; o[2] = 0; o[3] = 0; }
-  }
-  if (threadIdx.x != 0 || st->status != FA_OK) return;
-  int best = 0;
-  long long bestL = 1;
-  for (int j = 1; j <= p.J; ++j) {
-    const int32_t* t = cand_tab + (j - 1) * kCandStride;
-    if (!t[0]) continue;
-    const long long L = t[2];
-    if (best == 0 || (long long)j * bestL >= (long long)best * L) {
-      best = j;
-      bestL = L;
-    }
-  }
-  st->jstar = best;
-  if (!best) {
-    st->status = FA_ERR_NOFIT;
-    return;
-  }
-  const int32_t* t = cand_tab + (best - 1) * kCandStride;
-  st->layout_w = t[2];
-  st->layout_h = t[3];
-  st->rows = t[4];
-  st->s_star = (float)best / (float)p.J;
-  st->q_star = (float)p.omega / (float)t[2];
+// Selection and placement in one kernel: every workgroup reduces the J
+// candidate records (one lane per candidate) to the largest effective scale
+// j/L_j among fitting candidates (ties -> larger j), workgroup 0 publishes it,
+// then every thread places one chart from the chosen candidate.
+__device__ __forceinline__ bool sel_better(int j1, int L1, int j2, int L2) {
+  if (j1 == 0) return false;
+  if (j2 == 0) return true;
+  const long long a = (long long)j1 * L2, b = (long long)j2 * L1;
+  return a > b || (a == b && j1 > j2);
 }
 
-// Final placement of every chart from the chosen candidate.
-__global__ void k_place(FrameParams p, const int32_t* __restrict__ order,
-                        const long long* __restrict__ cand_x, const uint32_t* __restrict__ cand_ab,
-                        const int32_t* __restrict__ cand_y, int64_t stride,
-                        fa_chart* __restrict__ charts, const FrameState* __restrict__ st) {
-  if (st->status != FA_OK) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= st->num_charts) return;
-  const int jm = st->jstar - 1;
-  const int L = st->layout_w;
+__global__ __launch_bounds__(kBlock) void k_select_place(
+    FrameParams p, const int32_t* __restrict__ cand_tab, FrameState* st,
+    int32_t* __restrict__ cand_out, const int32_t* __restrict__ order,
+    const long long* __restrict__ cand_x, const uint32_t* __restrict__ cand_ab,
+    const int32_t* __restrict__ cand_y, int64_t stride, fa_chart* __restrict__ charts) {
+  __shared__ int sj, sL;
+  const bool ok = st->status == FA_OK;
+  const int C = st->num_charts;
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid < p.J && cand_out) {
+    const int32_t* t = cand_tab + tid * kCandStride;
+    int32_t* o = cand_out + 4 * tid;
+    o[0] = ok ? t[0] : 0; o[1] = ok ? t[1] : 0; o[2] = ok ? t[2] : 0; o[3] = ok ? t[3] : 0;
+  }
+  if (!ok) return;
+  if (blockIdx.x > 0 && (int64_t)blockIdx.x * kBlock >= C) return;
+  if (tid < kWave) {
+    int j = 0, L = 1, H = 0, rows = 0;
+    if (tid < p.J) {
+      const int32_t* t = cand_tab + tid * kCandStride;
+      if (t[0]) { j = tid + 1; L = t[2]; H = t[3]; rows = t[4]; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const int oj = __shfl_xor(j, o, kWave), oL = __shfl_xor(L, o, kWave);
+      const int oH = __shfl_xor(H, o, kWave), orows = __shfl_xor(rows, o, kWave);
+      if (sel_better(oj, oL, j, L)) { j = oj; L = oL; H = oH; rows = orows; }
+    }
+    if (tid == 0) {
+      sj = j;
+      sL = L;
+      if (blockIdx.x == 0) {
+        st->jstar = j;
+        if (!j) {
+          st->status = FA_ERR_NOFIT;
+        } else {
+          st->layout_w = L;
+          st->layout_h = H;
+          st->rows = rows;
+          st->s_star = (float)j / (float)p.J;
+          st->q_star = (float)p.omega / (float)L;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int jm = sj - 1, L = sL;
+  const int i = blockIdx.x * kBlock + tid;
+  if (jm < 0 || i >= C) return;
   const long long Xi = cand_x[(int64_t)jm * stride + i];
   const uint32_t ab = cand_ab[(int64_t)jm * stride + i];
   const int a = (int)(ab & 0xFFFFu), b = (int)(ab >> 16);
@@ -246,11 +262,20 @@ __global__ void k_place(FrameParams p, const int32_t* __restrict__ order,
 }
 
 // ---- packer-only entry: box sizes in, placements out ---------------------
+__global__ void k_pack_state(FrameState* st, unsigned long long* big_counter, int32_t n) {
+  if (threadIdx.x == 0) {
+    FrameState s = {};
+    s.status = FA_OK;
+    s.num_charts = n;
+    *st = s;
+    *big_counter = 0ull;
+  }
+}
+
 __global__ void k_pack_prepare(const float* __restrict__ sizes, int32_t n,
                                fa_chart* __restrict__ charts, uint32_t* __restrict__ keys,
                                int32_t* __restrict__ vals, FrameState* st) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c == 0) st->num_charts = n;
   if (c >= n) return;
   const float tw = sizes[2 * c], th = sizes[2 * c + 1];
   const float lim = 16777216.0f;  // 2^24 texels
@@ -316,17 +341,19 @@ hipError_t launch_pack(const FrameParams& p, const Work& w, int block, hipStream
 
 hipError_t launch_select_place(const FrameParams& p, const Work& w, fa_chart* charts,
                                int32_t* cand_out, hipStream_t st) {
-  k_select<<<1, kMaxScales, 0, st>>>(p, w.cand_tab, w.state, cand_out);
-  k_place<<<(unsigned)((p.max_charts + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-      p, w.vals_a, w.cand_x, w.cand_ab, w.cand_y, p.max_charts, charts, w.state);
+  k_select_place<<<(unsigned)((p.max_charts + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+      p, w.cand_tab, w.state, cand_out, w.vals_a, w.cand_x, w.cand_ab, w.cand_y, p.max_charts,
+      charts);
   return hipGetLastError();
 }
 
 hipError_t launch_pack_prepare(const float* sizes, int32_t n, const FrameParams& p, const Work& w,
                                fa_chart* charts, hipStream_t st) {
   (void)p;
-  k_pack_prepare<<<(unsigned)((n + kBlock - 1) / kBlock) + 1, kBlock, 0, st>>>(
-      sizes, n, charts, w.keys_a, w.vals_a, w.state);
+  k_pack_state<<<1, 64, 0, st>>>(w.state, w.big_counter, n);
+  if (n > 0)
+    k_pack_prepare<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        sizes, n, charts, w.keys_a, w.vals_a, w.state);
   return hipGetLastError();
 }
 

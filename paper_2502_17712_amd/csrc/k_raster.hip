@@ -117,36 +117,57 @@ __device__ __forceinline__ int32_t snap(float u) {
   return (int32_t)__builtin_rintf(fminf(fmaxf(u * 256.0f, -lim), lim));
 }
 
-// Footprint of fan triangle f (0 or 1) of visible triangle t; false when it
-// claims nothing.
-__device__ bool footprint(int64_t t, int f, const int32_t* __restrict__ idx,
-                          const float4* __restrict__ clip, const int32_t* __restrict__ cot,
-                          const fa_chart* __restrict__ charts, const FrameParams& p,
-                          const FrameState& st, Footprint& fp) {
+// The near-clipped polygon of visible triangle t mapped to snapped atlas
+// coordinates (1/256 texel); n = 0 when the triangle claims nothing.
+struct SnapPoly {
+  int64_t u[4], v[4];
+  int n;
+  int chart;
+};
+
+__device__ __forceinline__ void snap_polygon(int64_t t, const int32_t* __restrict__ idx,
+                                             const float4* __restrict__ clip,
+                                             const int32_t* __restrict__ cot,
+                                             const fa_chart* __restrict__ charts,
+                                             const FrameParams& p, const FrameState& st,
+                                             SnapPoly& sp) {
+  sp.n = 0;
   const int c = cot[t];
-  if (c < 0) return false;
+  sp.chart = c;
+  if (c < 0) return;
   const float4 a = clip[idx[3 * t]], b = clip[idx[3 * t + 1]], cc = clip[idx[3 * t + 2]];
   if (outside<0>(a, b, cc) || outside<1>(a, b, cc) || outside<2>(a, b, cc) ||
       outside<3>(a, b, cc) || outside<4>(a, b, cc) || outside<5>(a, b, cc))
-    return false;
+    return;
   float4 poly[4];
   int n;
   if (pd<4>(a) < 0.0f || pd<4>(b) < 0.0f || pd<4>(cc) < 0.0f) {
     n = near_clip(a, b, cc, poly);
   } else {
-    poly[0] = a; poly[1] = b; poly[2] = cc; n = 3;
+    poly[0] = a; poly[1] = b; poly[2] = cc; poly[3] = cc; n = 3;
   }
-  if (f + 2 >= n) return false;
   for (int k = 0; k < n; ++k)
-    if (!(poly[k].w > 0.0f)) return false;
-  const fa_chart& ch = charts[c];
-  const ChartXform m = chart_xform(ch, p, st);
-  const float2 u0 = to_atlas(m, poly[0].x, poly[0].y, poly[0].w);
-  const float2 u1 = to_atlas(m, poly[f + 1].x, poly[f + 1].y, poly[f + 1].w);
-  const float2 u2 = to_atlas(m, poly[f + 2].x, poly[f + 2].y, poly[f + 2].w);
-  fp.ax = snap(u0.x); fp.ay = snap(u0.y);
-  fp.bx = snap(u1.x); fp.by = snap(u1.y);
-  fp.cx = snap(u2.x); fp.cy = snap(u2.y);
+    if (!(poly[k].w > 0.0f)) return;
+  const ChartXform m = chart_xform(charts[c], p, st);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k < n) {
+      const float2 q = to_atlas(m, poly[k].x, poly[k].y, poly[k].w);
+      sp.u[k] = snap(q.x);
+      sp.v[k] = snap(q.y);
+    }
+  }
+  sp.n = n;
+}
+
+// Fan triangle f (0 or 1) of a snapped polygon: vertices 0, f+1, f+2.
+__device__ __forceinline__ bool fan_footprint(const SnapPoly& sp, int f, const fa_chart& ch,
+                                              const FrameParams& p, const FrameState& st,
+                                              Footprint& fp) {
+  if (f + 2 >= sp.n) return false;
+  fp.ax = sp.u[0]; fp.ay = sp.v[0];
+  fp.bx = sp.u[f + 1]; fp.by = sp.v[f + 1];
+  fp.cx = sp.u[f + 2]; fp.cy = sp.v[f + 2];
   fp.area = (fp.bx - fp.ax) * (fp.cy - fp.ay) - (fp.by - fp.ay) * (fp.cx - fp.ax);
   if (fp.area == 0) return false;
   // texel range of the placed box: 2*x*omega <= (2t+1)*L < 2*(x+w)*omega
@@ -164,8 +185,20 @@ __device__ bool footprint(int64_t t, int f, const int32_t* __restrict__ idx,
   hi_y = min(hi_y, min(om - 1, floor_div64(vmax - 128, 256)));
   if (lo_x > hi_x || lo_y > hi_y) return false;
   fp.tx0 = (int)lo_x; fp.tx1 = (int)hi_x; fp.ty0 = (int)lo_y; fp.ty1 = (int)hi_y;
-  fp.chart = c;
+  fp.chart = sp.chart;
   return true;
+}
+
+__device__ __forceinline__ bool footprint(int64_t t, int f, const int32_t* __restrict__ idx,
+                                          const float4* __restrict__ clip,
+                                          const int32_t* __restrict__ cot,
+                                          const fa_chart* __restrict__ charts,
+                                          const FrameParams& p, const FrameState& st,
+                                          Footprint& fp) {
+  SnapPoly sp;
+  snap_polygon(t, idx, clip, cot, charts, p, st, sp);
+  if (sp.n == 0) return false;
+  return fan_footprint(sp, f, charts[sp.chart], p, st, fp);
 }
 
 __device__ __forceinline__ bool covers(const Footprint& fp, int tx, int ty) {
@@ -183,50 +216,140 @@ __global__ void k_occ_fill(int4* __restrict__ occ, int64_t n4, const FrameState*
     occ[i] = neg;
 }
 
+// Texel tests of a small footprint by one thread. When every snapped vertex
+// lies within 2^13 units of the first one, all edge functions at texel
+// centres of the (clipped) range fit in 32 bits.
+__device__ __forceinline__ void raster_thread(const Footprint& fp, int32_t* __restrict__ occ,
+                                              int omega) {
+  const int64_t du = max(llabs(fp.bx - fp.ax), llabs(fp.cx - fp.ax));
+  const int64_t dv = max(llabs(fp.by - fp.ay), llabs(fp.cy - fp.ay));
+  const int64_t ox = 256 * (int64_t)fp.tx0 + 128 - fp.ax, oy = 256 * (int64_t)fp.ty0 + 128 - fp.ay;
+  const bool narrow = du < 8192 && dv < 8192 && llabs(ox) < 8192 && llabs(oy) < 8192 &&
+                      (fp.tx1 - fp.tx0) < 32 && (fp.ty1 - fp.ty0) < 32;
+  if (narrow) {
+    // coordinates relative to vertex a: |values| < 2^14 * 2^14 * 2
+    const int bx = (int)(fp.bx - fp.ax), by = (int)(fp.by - fp.ay);
+    const int cx = (int)(fp.cx - fp.ax), cy = (int)(fp.cy - fp.ay);
+    const bool pos = fp.area > 0;
+    for (int ty = fp.ty0; ty <= fp.ty1; ++ty) {
+      const int py = (int)(256 * (int64_t)ty + 128 - fp.ay);
+      for (int tx = fp.tx0; tx <= fp.tx1; ++tx) {
+        const int px = (int)(256 * (int64_t)tx + 128 - fp.ax);
+        const int e0 = bx * py - by * px;
+        const int e1 = (cx - bx) * (py - by) - (cy - by) * (px - bx);
+        const int e2 = (0 - cx) * (py - cy) - (0 - cy) * (px - cx);
+        const bool in = pos ? (e0 >= 0 && e1 >= 0 && e2 >= 0) : (e0 <= 0 && e1 <= 0 && e2 <= 0);
+        if (in) occ[(int64_t)ty * omega + tx] = fp.chart;
+      }
+    }
+    return;
+  }
+  for (int ty = fp.ty0; ty <= fp.ty1; ++ty)
+    for (int tx = fp.tx0; tx <= fp.tx1; ++tx)
+      if (covers(fp, tx, ty)) occ[(int64_t)ty * omega + tx] = fp.chart;
+}
+
+constexpr int kOccTile = 16;                   // queued footprints are cut into 16x16 tiles
+constexpr unsigned long long kSlotShift = 40;  // queue counter: footprints << 40 | tiles
+
 __global__ void k_occ_small(const int32_t* __restrict__ idx, int64_t T, FrameParams p,
                             const float4* __restrict__ clip, const int32_t* __restrict__ cot,
                             const fa_chart* __restrict__ charts, int32_t* __restrict__ occ,
-                            uint32_t* __restrict__ big, int small_texels, FrameState* stp) {
+                            ulonglong2* __restrict__ big, uint32_t big_cap, int small_texels,
+                            unsigned long long* __restrict__ big_counter,
+                            const FrameState* __restrict__ stp) {
   const FrameState st = *stp;
   if (st.status != FA_OK) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= T) return;
+  if (t >= T || cot[t] < 0) return;
+  SnapPoly sp;
+  snap_polygon(t, idx, clip, cot, charts, p, st, sp);
+  if (sp.n == 0) return;
+  const fa_chart& ch = charts[sp.chart];
   for (int f = 0; f < 2; ++f) {
     Footprint fp;
-    if (!footprint(t, f, idx, clip, cot, charts, p, st, fp)) continue;
+    if (!fan_footprint(sp, f, ch, p, st, fp)) continue;
     const int nx = fp.tx1 - fp.tx0 + 1, ny = fp.ty1 - fp.ty0 + 1;
     if ((int64_t)nx * ny > small_texels) {
-      const uint32_t slot = atomicAdd(&stp->big_count, 1u);
-      big[slot] = (uint32_t)(2 * t + f);
-      continue;
+      const uint32_t tx_n = (uint32_t)((nx + kOccTile - 1) / kOccTile);
+      const uint32_t nt = tx_n * (uint32_t)((ny + kOccTile - 1) / kOccTile);
+      const unsigned long long old =
+          atomicAdd(big_counter, (1ull << kSlotShift) | (unsigned long long)nt);
+      const unsigned long long slot = old >> kSlotShift;
+      if (slot < big_cap) {
+        // x: footprint code | tiles across << 32; y: first tile | tiles << 40
+        big[slot] = make_ulonglong2(
+            (unsigned long long)(2 * t + f) | ((unsigned long long)tx_n << 32),
+            (old & ((1ull << kSlotShift) - 1)) | ((unsigned long long)nt << kSlotShift));
+        continue;
+      }
     }
-    for (int ty = fp.ty0; ty <= fp.ty1; ++ty)
-      for (int tx = fp.tx0; tx <= fp.tx1; ++tx)
-        if (covers(fp, tx, ty)) occ[(int64_t)ty * p.omega + tx] = fp.chart;
+    raster_thread(fp, occ, p.omega);
   }
 }
 
-__global__ void k_occ_big(const int32_t* __restrict__ idx, FrameParams p,
-                          const float4* __restrict__ clip, const int32_t* __restrict__ cot,
-                          const fa_chart* __restrict__ charts, int32_t* __restrict__ occ,
-                          const uint32_t* __restrict__ big, const FrameState* __restrict__ stp) {
+// Queued footprints: their concatenated 16x16 tiles are split evenly over all
+// waves of the grid; a wave finds its first footprint by binary search over
+// the (increasing) first-tile indices and walks forward, 4 texels per lane.
+__global__ __launch_bounds__(kBlock) void k_occ_big(
+    const int32_t* __restrict__ idx, FrameParams p, const float4* __restrict__ clip,
+    const int32_t* __restrict__ cot, const fa_chart* __restrict__ charts,
+    int32_t* __restrict__ occ, const ulonglong2* __restrict__ big, uint32_t big_cap,
+    const unsigned long long* __restrict__ big_counter, const FrameState* __restrict__ stp) {
   const FrameState st = *stp;
   if (st.status != FA_OK) return;
-  for (uint32_t e = blockIdx.x; e < st.big_count; e += gridDim.x) {
-    const uint32_t code = big[e];
-    Footprint fp;
-    if (!footprint((int64_t)(code >> 1), (int)(code & 1u), idx, clip, cot, charts, p, st, fp))
-      continue;
-    const int nx = fp.tx1 - fp.tx0 + 1;
-    const int64_t total = (int64_t)nx * (fp.ty1 - fp.ty0 + 1);
-    for (int64_t k = threadIdx.x; k < total; k += blockDim.x) {
-      const int ty = fp.ty0 + (int)(k / nx), tx = fp.tx0 + (int)(k % nx);
-      if (covers(fp, tx, ty)) occ[(int64_t)ty * p.omega + tx] = fp.chart;
+  const unsigned long long ctr = *big_counter;
+  const uint32_t nent = (uint32_t)min<unsigned long long>(ctr >> kSlotShift, big_cap);
+  if (nent == 0) return;
+  constexpr unsigned long long kLow = (1ull << kSlotShift) - 1;
+  const ulonglong2 lastv = big[nent - 1];
+  const uint64_t total = (lastv.y & kLow) + (lastv.y >> kSlotShift);
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
+  const uint64_t wid = (uint64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  const uint64_t per = (total + nwaves - 1) / nwaves;
+  const uint64_t k0 = wid * per, k1 = min<uint64_t>(total, k0 + per);
+  if (k0 >= k1) return;
+  uint32_t lo = 0, hi = nent - 1;  // last entry whose first tile <= k0
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) / 2;
+    if ((big[mid].y & kLow) <= k0) lo = mid; else hi = mid - 1;
+  }
+  uint32_t e = lo;
+  ulonglong2 ent = big[e];
+  uint64_t base = ent.y & kLow, nt = ent.y >> kSlotShift;
+  uint32_t code = (uint32_t)ent.x, tiles_x = (uint32_t)(ent.x >> 32);
+  Footprint fp;
+  bool ok = footprint((int64_t)(code >> 1), (int)(code & 1u), idx, clip, cot, charts, p, st, fp);
+  const int lane = lane_id();
+  for (uint64_t k = k0; k < k1; ++k) {
+    bool moved = false;
+    while (k >= base + nt) {
+      ent = big[++e];
+      base = ent.y & kLow;
+      nt = ent.y >> kSlotShift;
+      code = (uint32_t)ent.x;
+      tiles_x = (uint32_t)(ent.x >> 32);
+      moved = true;
+    }
+    if (moved)
+      ok = footprint((int64_t)(code >> 1), (int)(code & 1u), idx, clip, cot, charts, p, st, fp);
+    if (!ok) continue;
+    const uint32_t tt = (uint32_t)(k - base);
+    const int ox = fp.tx0 + kOccTile * (int)(tt % tiles_x);
+    const int oy = fp.ty0 + kOccTile * (int)(tt / tiles_x);
+#pragma unroll
+    for (int q = 0; q < kOccTile * kOccTile / kWave; ++q) {
+      const int i = lane + q * kWave;
+      const int tx = ox + (i % kOccTile), ty = oy + (i / kOccTile);
+      if (tx <= fp.tx1 && ty <= fp.ty1 && covers(fp, tx, ty))
+        occ[(int64_t)ty * p.omega + tx] = fp.chart;
     }
   }
 }
 
-__global__ void k_occ_count(const int4* __restrict__ occ, int64_t n4, FrameState* st) {
+// Occupied texels: per-block partial counts (no global atomics).
+__global__ void k_occ_count(const int4* __restrict__ occ, int64_t n4,
+                            unsigned long long* __restrict__ partial) {
   __shared__ unsigned long long sh[kBlock / kWave];
   unsigned long long cnt = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
@@ -235,12 +358,21 @@ __global__ void k_occ_count(const int4* __restrict__ occ, int64_t n4, FrameState
     cnt += (v.x >= 0) + (v.y >= 0) + (v.z >= 0) + (v.w >= 0);
   }
   cnt = block_sum<unsigned long long>(cnt, sh);
-  if (threadIdx.x == 0 && cnt) atomicAdd(&st->occupied, cnt);
+  if (threadIdx.x == 0) partial[blockIdx.x] = cnt;
 }
 
-__global__ void k_meta(FrameParams p, const FrameState* __restrict__ stp,
+// Frame record for the caller; sums the occupancy partial counts when the
+// occupancy map was built.
+__global__ void k_meta(FrameParams p, FrameState* stp,
+                       const unsigned long long* __restrict__ big_counter,
+                       const unsigned long long* __restrict__ partial, int npartial,
                        fa_atlas_meta* __restrict__ meta) {
+  __shared__ unsigned long long sh[kBlock / kWave];
+  unsigned long long occ = 0;
+  for (int i = threadIdx.x; i < npartial; i += blockDim.x) occ += partial[i];
+  occ = block_sum<unsigned long long>(occ, sh);
   if (threadIdx.x != 0) return;
+  if (npartial && stp->status == FA_OK) stp->occupied = occ;
   const FrameState st = *stp;
   fa_atlas_meta m;
   m.status = st.status;
@@ -255,7 +387,7 @@ __global__ void k_meta(FrameParams p, const FrameState* __restrict__ stp,
   m.rate = p.rate;
   m.occupied_texels = (int64_t)st.occupied;
   m.visible_triangles = (int64_t)st.visible;
-  m.reserved = 0;
+  m.large_tiles = (int64_t)(*big_counter & ((1ull << 40) - 1));
   *meta = m;
 }
 
@@ -271,21 +403,29 @@ hipError_t launch_uv(const int64_t V, const FrameParams& p, const Work& w, const
 
 hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
                             const int32_t* cot, const fa_chart* charts, int32_t* occ,
-                            int small_texels, hipStream_t st) {
+                            int small_texels, Marker& mk, hipStream_t st) {
   const int64_t n4 = (int64_t)p.omega * p.omega / 4;
   const unsigned fill_grid = (unsigned)std::min<int64_t>((n4 + kBlock - 1) / kBlock, 4096);
   k_occ_fill<<<fill_grid, kBlock, 0, st>>>(reinterpret_cast<int4*>(occ), n4, w.state);
+  mk(st);
+  const uint32_t cap = (uint32_t)std::min<int64_t>(2 * std::max<int64_t>(T, 1), 1 << 24);
   if (T > 0) {
     k_occ_small<<<(unsigned)((T + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-        idx, T, p, w.clip, cot, charts, occ, w.big, small_texels, w.state);
-    k_occ_big<<<2048, kBlock, 0, st>>>(idx, p, w.clip, cot, charts, occ, w.big, w.state);
+        idx, T, p, w.clip, cot, charts, occ, w.big, cap, small_texels, w.big_counter, w.state);
+    mk(st);
+    k_occ_big<<<kOccBigGrid, kBlock, 0, st>>>(idx, p, w.clip, cot, charts, occ, w.big, cap,
+                                              w.big_counter, w.state);
   }
-  k_occ_count<<<fill_grid, kBlock, 0, st>>>(reinterpret_cast<const int4*>(occ), n4, w.state);
+  mk(st);
+  k_occ_count<<<kCountGrid, kBlock, 0, st>>>(reinterpret_cast<const int4*>(occ), n4, w.partial);
+  mk(st);
   return hipGetLastError();
 }
 
-hipError_t launch_meta(const FrameParams& p, const Work& w, fa_atlas_meta* meta, hipStream_t st) {
-  k_meta<<<1, 64, 0, st>>>(p, w.state, meta);
+hipError_t launch_meta(const FrameParams& p, const Work& w, fa_atlas_meta* meta,
+                       int with_occupancy, hipStream_t st) {
+  k_meta<<<1, kBlock, 0, st>>>(p, w.state, w.big_counter, w.partial,
+                               with_occupancy ? kCountGrid : 0, meta);
   return hipGetLastError();
 }
 

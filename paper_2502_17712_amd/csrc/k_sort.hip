@@ -34,24 +34,30 @@ __global__ void k_radix_hist(const K* __restrict__ keys, const int32_t* __restri
   for (int d = threadIdx.x; d < kRadix; d += blockDim.x) hist[(int64_t)d * ntiles + b] = h[d];
 }
 
-// Exclusive scan of the digit-major histogram (one workgroup). Each thread
-// owns a contiguous segment: sum, block scan of the sums, then write.
-__global__ void k_radix_scan(uint32_t* __restrict__ hist, const int32_t* __restrict__ n_dev,
-                             int64_t n_host) {
+// Exclusive scan of the digit-major histogram (one workgroup of 1024): chunks
+// of 4 consecutive words per thread, a block scan per chunk, running total.
+__global__ __launch_bounds__(1024) void k_radix_scan(uint32_t* __restrict__ hist,
+                                                     const int32_t* __restrict__ n_dev,
+                                                     int64_t n_host) {
   __shared__ uint32_t sh[1024 / kWave];
   const int64_t n = n_dev ? min((int64_t)*n_dev, n_host) : n_host;
   const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
   const int64_t total = ntiles * kRadix;
-  const int64_t seg = (total + blockDim.x - 1) / blockDim.x;
-  const int64_t s0 = min(total, (int64_t)threadIdx.x * seg), s1 = min(total, s0 + seg);
-  uint32_t sum = 0;
-  for (int64_t i = s0; i < s1; ++i) sum += hist[i];
-  uint32_t tot;
-  uint32_t run = block_incl_scan<uint32_t>(sum, sh, &tot) - sum;
-  for (int64_t i = s0; i < s1; ++i) {
-    uint32_t v = hist[i];
-    hist[i] = run;
-    run += v;
+  uint32_t run = 0;
+  for (int64_t c0 = 0; c0 < total; c0 += 4 * (int64_t)blockDim.x) {
+    const int64_t i0 = c0 + 4 * (int64_t)threadIdx.x;
+    uint32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = i0 + k < total ? hist[i0 + k] : 0u;
+    const uint32_t mine = v[0] + v[1] + v[2] + v[3];
+    uint32_t tot;
+    uint32_t pre = run + block_incl_scan<uint32_t>(mine, sh, &tot) - mine;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (i0 + k < total) hist[i0 + k] = pre;
+      pre += v[k];
+    }
+    run += tot;
   }
 }
 
@@ -168,17 +174,124 @@ __global__ void k_edge_runs(const unsigned long long* __restrict__ keys,
 }
 
 // ---------------------------------------------------------------------------
-// per-frame order
+// per-frame chart sizes and order, one workgroup of 1024 threads
 // ---------------------------------------------------------------------------
-__global__ void k_sorted_sizes(const int32_t* __restrict__ order, fa_chart* __restrict__ charts,
-                               float2* __restrict__ wh, const FrameState* __restrict__ st) {
+// Chart frame and target size (Sec. bounding boxes, last paragraph; Sec.
+// fixed shading rate): the union of the triangles' NDC boxes (all empty ->
+// zero box, -0 -> +0), viewport transform times the rate, rotation so the box
+// is at least as tall as wide (Sec. "Box Ordering…"), 13-bit height key.
+__device__ __forceinline__ void chart_size(const FrameParams& p, const uint4 e, fa_chart& ch,
+                                           uint32_t& key_out) {
+  float x0 = 0.0f, y0 = 0.0f, x1 = 0.0f, y1 = 0.0f;
+  if (e.z != 0u) {
+    x0 = float_of(e.x);
+    y0 = float_of(e.y);
+    x1 = float_of(e.z);
+    y1 = float_of(e.w);
+  }
+  x0 = x0 + 0.0f; y0 = y0 + 0.0f; x1 = x1 + 0.0f; y1 = y1 + 0.0f;
+  const float halfW = 0.5f * (float)p.W, halfH = 0.5f * (float)p.H;
+  const float tw = ((x1 - x0) * halfW) * p.rate;
+  const float th = ((y1 - y0) * halfH) * p.rate;
+  const int rot = tw > th ? 1 : 0;
+  const float bw = rot ? th : tw, bh = rot ? tw : th;
+  const int key = min((int)ceilf(bh), kKeyCap);
+  ch.ndc_box[0] = x0; ch.ndc_box[1] = y0; ch.ndc_box[2] = x1; ch.ndc_box[3] = y1;
+  ch.target_w = tw; ch.target_h = th;
+  ch.oriented_w = bw; ch.oriented_h = bh;
+  ch.rotated = rot;
+  ch.key = key;
+  key_out = (uint32_t)(kKeyCap - key);
+}
+
+// Sizes (when from_accum) and the stable order by (height desc, chart asc):
+// two 8-bit LSD radix passes over the 13-bit keys in one workgroup, items
+// ranked 1024 at a time (ballot matching inside a wave, per-wave digit counts
+// across the 16 waves), then the sorted oriented sizes for the packer.
+constexpr int kOrderThreads = 1024;
+
+__global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
+    FrameParams p, const uint32_t* __restrict__ accum, fa_chart* __restrict__ charts,
+    uint32_t* __restrict__ keys_a, int32_t* __restrict__ vals_a, uint32_t* __restrict__ keys_b,
+    int32_t* __restrict__ vals_b, float2* __restrict__ sorted_wh, int from_accum,
+    const FrameState* __restrict__ st) {
+  constexpr int NW = kOrderThreads / kWave;
+  __shared__ uint32_t base[kRadix];
+  __shared__ uint32_t wcnt[NW][kRadix];
+  __shared__ uint32_t sh[NW];
   if (st->status != FA_OK) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= st->num_charts) return;
-  const int c = order[i];
-  fa_chart& ch = charts[c];
-  wh[i] = make_float2(ch.oriented_w, ch.oriented_h);
-  ch.order_rank = i;
+  const int C = min(st->num_charts, p.max_charts);
+  const int tid = threadIdx.x, w = tid / kWave;
+  if (from_accum) {
+    for (int c = tid; c < C; c += kOrderThreads) {
+      uint32_t key;
+      chart_size(p, reinterpret_cast<const uint4*>(accum)[c], charts[c], key);
+      keys_a[c] = key;
+      vals_a[c] = c;
+    }
+    __syncthreads();
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    const int shift = kRadixBits * pass;
+    const uint32_t* kin = pass ? keys_b : keys_a;
+    const int32_t* vin = pass ? vals_b : vals_a;
+    uint32_t* kout = pass ? keys_a : keys_b;
+    int32_t* vout = pass ? vals_a : vals_b;
+    if (tid < kRadix) base[tid] = 0;
+    __syncthreads();
+    for (int c = tid; c < C; c += kOrderThreads) atomicAdd(&base[(kin[c] >> shift) & (kRadix - 1)], 1u);
+    __syncthreads();
+    {
+      const uint32_t v = tid < kRadix ? base[tid] : 0u;
+      uint32_t tot;
+      const uint32_t ex = block_incl_scan<uint32_t>(v, sh, &tot) - v;
+      if (tid < kRadix) base[tid] = ex;
+    }
+    for (int c0 = 0; c0 < C; c0 += kOrderThreads) {
+      uint32_t* flat = &wcnt[0][0];
+#pragma unroll
+      for (int k = 0; k < NW * kRadix / kOrderThreads; ++k) flat[tid + k * kOrderThreads] = 0u;
+      __syncthreads();
+      const int i = c0 + tid;
+      const bool valid = i < C;
+      const uint32_t key = valid ? kin[i] : 0u;
+      const uint32_t d = (key >> shift) & (kRadix - 1);
+      unsigned long long m = __ballot(valid);
+#pragma unroll
+      for (int bit = 0; bit < kRadixBits; ++bit) {
+        const bool on = (d >> bit) & 1u;
+        const unsigned long long bb = __ballot(on);
+        m &= on ? bb : ~bb;
+      }
+      const unsigned long long below = m & lanes_below();
+      const uint32_t rank = (uint32_t)__popcll(below);
+      if (valid && below == 0) wcnt[w][d] = (uint32_t)__popcll(m);
+      __syncthreads();
+      if (tid < kRadix) {
+        uint32_t run = base[tid];
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+          const uint32_t c = wcnt[k][tid];
+          wcnt[k][tid] = run;
+          run += c;
+        }
+        base[tid] = run;
+      }
+      __syncthreads();
+      if (valid) {
+        const uint32_t pos = wcnt[w][d] + rank;
+        kout[pos] = key;
+        vout[pos] = vin[i];
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < C; i += kOrderThreads) {
+    const int c = vals_a[i];
+    fa_chart& ch = charts[c];
+    sorted_wh[i] = make_float2(ch.oriented_w, ch.oriented_h);
+    ch.order_rank = i;
+  }
 }
 
 }  // namespace
@@ -205,14 +318,10 @@ hipError_t launch_adjacency(const int32_t* idx, int64_t T, int64_t V, const AdjT
   return hipGetLastError();
 }
 
-hipError_t launch_order(const FrameParams& p, const Work& w, fa_chart* charts, hipStream_t st) {
-  bool in_b = false;
-  hipError_t e = radix_sort<uint32_t>(w.keys_a, w.vals_a, w.keys_b, w.vals_b, w.hist,
-                                      &w.state->num_charts, p.max_charts, 13, st, &in_b);
-  if (e != hipSuccess) return e;
-  // 13 bits take two passes, so the sorted order is back in keys_a / vals_a
-  k_sorted_sizes<<<(unsigned)((p.max_charts + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-      in_b ? w.vals_b : w.vals_a, charts, w.sorted_wh, w.state);
+hipError_t launch_order(const FrameParams& p, const Work& w, fa_chart* charts, int from_accum,
+                        hipStream_t st) {
+  k_sizes_order<<<1, kOrderThreads, 0, st>>>(p, w.accum, charts, w.keys_a, w.vals_a, w.keys_b,
+                                             w.vals_b, w.sorted_wh, from_accum, w.state);
   return hipGetLastError();
 }
 

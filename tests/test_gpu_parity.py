@@ -148,6 +148,23 @@ def test_city_frames_more():
         compare(g, oracle.build_frame(f, want_occupancy=False), occupancy=False)
 
 
+@pytest.mark.parametrize("knob,value", [(1, 512), (1, 1024), (2, 0), (2, 16), (2, 1024),
+                                        (3, 0)])
+def test_tuning_knobs_do_not_change_results(knob, value):
+    fa = _fa()
+    ctx = ctx_for()
+    old = ctx.get_tuning(knob)
+    ctx.set_tuning(knob, value)
+    try:
+        for f in (scenes.orbit_frame(21), scenes.city_frame(5)):
+            g = run_gpu(f, ctx)
+            compare(g, oracle.build_frame(f))
+    finally:
+        ctx.set_tuning(knob, old)
+    with pytest.raises(fa.FastAtlasError):
+        ctx.set_tuning(knob, {1: 3, 2: -1, 3: 3}[knob])
+
+
 # ---------------------------------------------------------------------------
 def _random_mesh(rng, T, V):
     idx = rng.integers(0, V, size=(T, 3)).astype(np.int32)
@@ -290,3 +307,114 @@ def test_batch_equals_single():
     torch.cuda.synchronize()
     for f, o in zip(frames, outs):
         compare(o.to_numpy(), oracle.build_frame(f))
+
+
+def _orbit_batch_frames():
+    return [scenes.orbit_frame(k, atlas_size=om, rate=r)
+            for k, om, r in ((5, 1024, 1.0), (33, 2048, 0.5), (61, 512, 2.0), (90, 1024, 1.0),
+                             (100, 256, 0.5), (118, 4096, 2.0))]
+
+
+_MULTI = {}
+
+
+def _multi_ctx():
+    if "c" not in _MULTI:
+        f = scenes.orbit_frame(0)
+        _MULTI["c"] = _fa().Context(f.num_triangles, f.num_vertices, max_charts=8192,
+                                    max_atlas=4096, max_views=4)
+    return _MULTI["c"]
+
+
+def test_batch_concurrent_slots():
+    ctx = _multi_ctx()
+    frames = _orbit_batch_frames()
+    mesh = mesh_for(frames[0])
+    outs = [ctx.outputs(mesh, f.atlas_size) for f in frames]
+    vis = [torch.as_tensor(f.visible).cuda() for f in frames]
+    print("[gpu] batch of 6 views on 4 slots", flush=True)
+    ctx.build_atlas_batch(mesh, [(vis[i], f.view_proj, f.width, f.height, f.atlas_size, f.rate)
+                                 for i, f in enumerate(frames)], outs)
+    torch.cuda.synchronize()
+    for f, o in zip(frames, outs):
+        compare(o.to_numpy(), oracle.build_frame(f))
+
+
+def test_batch_graph_replays():
+    fa = _fa()
+    ctx = _multi_ctx()
+    ctx.set_tuning(fa.FA_TUNE_BATCH_GRAPH, 1)
+    try:
+        frames = _orbit_batch_frames()[:5]
+        mesh = mesh_for(frames[0])
+        outs = [ctx.outputs(mesh, f.atlas_size) for f in frames]
+        vis = [torch.as_tensor(f.visible).cuda() for f in frames]
+        desc = [(vis[i], f.view_proj, f.width, f.height, f.atlas_size, f.rate)
+                for i, f in enumerate(frames)]
+        want = [oracle.build_frame(f) for f in frames]
+        other = scenes.orbit_frame(7)
+        for rep in range(3):
+            print(f"[gpu] batch graph replay {rep}", flush=True)
+            for o in outs:  # poison every output so a stale replay cannot pass
+                for t in (o.chart_of_tri, o.chart_of_vert, o.occupancy, o.candidates):
+                    t.fill_(-7)
+                o.uv.fill_(-7.0)
+                o.charts.fill_(-7)
+                o.meta.fill_(-7)
+            ctx.build_atlas_batch(mesh, desc, outs)
+            # eager work between replays
+            g = run_gpu(other, ctx)
+            junk = torch.randn(1 << 20, device="cuda").sum()
+            torch.cuda.synchronize()
+            assert torch.isfinite(junk)
+            for o, r in zip(outs, want):
+                compare(o.to_numpy(), r)
+        compare(g, oracle.build_frame(other))
+    finally:
+        ctx.set_tuning(fa.FA_TUNE_BATCH_GRAPH, 0)
+
+
+def test_serve_mix_equals_alone():
+    """Continuous batching: each request's results are identical alone and in
+    the mix (many requests in flight on 4 slots, uneven sizes)."""
+    import paper_2502_17712_amd as fa
+    from paper_2502_17712_amd import serve
+    from synth import requests as rq
+    meshes_np = {k: v for k, v in rq.scene_meshes().items() if k != "city"}
+    meshes = {k: fa.Mesh(p, t, key) for k, (p, t, key) in meshes_np.items()}
+    pools = {"grid": rq.pose_pool("grid", 4, seed=1), "orbit": rq.pose_pool("orbit", 4, seed=2)}
+    stream = rq.poisson_stream(5000.0, 24, pools, clients=8, seed=3)
+    vis = {(s, i): torch.as_tensor(pools[s][i].visible).cuda() for s in pools
+           for i in range(len(pools[s]))}
+    reqs = []
+    for rid, (a, c, s, i, om, r) in enumerate(stream):
+        pz = pools[s][i]
+        reqs.append(serve.Request(rid, s, vis[(s, i)], pz.view_proj, pz.width, pz.height, om, r,
+                                  arrival=a * 0.05, client=c))
+    print("[gpu] serve mix of 24 requests on 4 slots", flush=True)
+    srv = serve.Server(meshes, slots=4, hbm_budget=2 << 30, max_charts=8192, max_atlas=4096)
+    res = {r.rid: r for r in srv.run(reqs, keep_outputs=True)}
+    srv.close()
+    alone = fa.Context(max(m.num_triangles for m in meshes.values()),
+                       max(m.num_vertices for m in meshes.values()), max_charts=8192,
+                       max_atlas=4096)
+    for q in reqs:
+        mesh = meshes[q.scene]
+        o = alone.build_atlas(mesh, q.visible, q.view_proj, q.width, q.height, q.atlas_size,
+                              q.rate)
+        torch.cuda.synchronize()
+        a, b = o.to_numpy(), res[q.rid].out.to_numpy()
+        for k in ("chart_of_tri", "chart_of_vert", "occupancy", "candidates"):
+            assert np.array_equal(a[k], b[k]), (q.rid, k)
+        assert np.array_equal(a["charts"], b["charts"])
+        assert np.array_equal(bits(a["uv"]), bits(b["uv"]))
+        assert a["meta"] == b["meta"]
+    # back-pressure: a budget that holds one request at a time still serves all
+    srv = serve.Server(meshes, slots=4, hbm_budget=serve.output_bytes(
+        max(m.num_triangles for m in meshes.values()), max(m.num_vertices for m in meshes.values()),
+        8192, 4096, 64), max_charts=8192, max_atlas=4096)
+    out = srv.run(reqs[:8])
+    srv.close()
+    assert sorted(r.rid for r in out) == list(range(8))
+    for r in out:
+        assert r.meta["status"] == 0
