@@ -42,18 +42,18 @@ def kernel_bytes(name, T, V, Tv, Vv, C, J, omega, occupied):
     """Algorithmic bytes of one launch of a kernel (what it must read and write
     at minimum); the per-unit figures are listed in the design doc."""
     per = {
-        "prologue": V * (12 + 16 + 4 + 4) + T * (1 + 4) + Tv * 12,
-        "uf_hook": T * 1 + Tv * (12 + 12 + 4),
-        "uf_vertex_hook": T * 1 + Tv * (12 + 12),
-        "uf_flatten": T * 1 + Tv * 8,
-        "gather_boxes": T * (1 + 4) + Tv * (12 + 48 + 12 + 4),
+        "prologue": V * (12 + 16 + 4 + 4) + T * (1 + 4) + Tv * (12 + 4 + 4),
+        "uf_hook_vertex_min": Tv * (4 + 12 + 3 + 4 + 12 + 12),
+        "uf_vertex_hook": Tv * (4 + 12 + 12 + 4),
+        "uf_flatten": Tv * (4 + 4 + 4),
+        "assign_roots": Tv * (4 + 4) + C * (4 + 4 + 16),
+        "gather_boxes": Tv * (4 + 4 + 4 + 12 + 48 + 12) + C * 16,
         "sizes_order": C * (16 + 64 + 8 + 16),
         "pack": J * C * (8 + 16),
         "select_place": C * (16 + 16),
         "uv": V * (16 + 4 + 8) + C * 64,
         "occ_fill": omega * omega * 4,
-        "occ_small": T * 4 + Tv * (12 + 48) + occupied * 4,
-        "occ_big": occupied * 4,
+        "occ_small": Tv * (4 + 4 + 12 + 48) + occupied * 4,
         "occ_count": omega * omega * 4,
     }
     return per.get(name)
@@ -72,9 +72,22 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=4)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=1000.0)
     ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run 4 plain device copies of 256 MiB (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel(), "copies": 4}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
               "run with --gpus 1", file=sys.stderr)
@@ -167,32 +180,85 @@ def main():
                     "unit": "GB/s", "frac": (ach / HBM_PEAK_GBS) if ach else None,
                     "traffic": None, "kernel_ms": stages[dom], "algorithmic_bytes": kb}
 
+    # secondary workloads: the small and medium scenes, other rates on the large one
+    def time_frames(ctx_, mesh_, frs, reps=3):
+        vs = [torch.as_tensor(f.visible).to(dev) for f in frs]
+        outs_ = {om: ctx_.outputs(mesh_, om) for om in {f.atlas_size for f in frs}}
+        for f, v in zip(frs, vs):
+            ctx_.build_atlas(mesh_, v, f.view_proj, f.width, f.height, f.atlas_size, f.rate,
+                             out=outs_[f.atlas_size], stream=stream)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            for f, v in zip(frs, vs):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                ctx_.build_atlas(mesh_, v, f.view_proj, f.width, f.height, f.atlas_size, f.rate,
+                                 out=outs_[f.atlas_size], stream=stream)
+                b.record(stream)
+                ts.append((a, b))
+        torch.cuda.synchronize()
+        per_ = np.array([a.elapsed_time(b) for a, b in ts])
+        return dict(mean_ms=float(per_.mean()), p50_ms=float(np.percentile(per_, 50)),
+                    p99_ms=float(np.percentile(per_, 99)), frames=len(frs))
+    secondary = {}
+    if not args.no_secondary:
+        g0 = scenes.grid_frame(0)
+        sctx = fa.Context(T, V, max_charts=65536, max_atlas=4096)
+        for knob_ in (fa.FA_TUNE_OCC_SMALL_TEXELS, fa.FA_TUNE_UF_LINK_INIT,
+                      fa.FA_TUNE_UF_EDGE_HOOKS, fa.FA_TUNE_PACK_BLOCK):
+            sctx.set_tuning(knob_, ctx.get_tuning(knob_))
+        secondary["grid8k_1280x720_atlas1024"] = time_frames(
+            sctx, fa.Mesh(g0.positions, g0.indices, g0.scene_key),
+            [scenes.grid_frame(s) for s in range(64)])
+        o0 = scenes.orbit_frame(0)
+        secondary["orbit86k_1920x1080_atlas2048"] = time_frames(
+            sctx, fa.Mesh(o0.positions, o0.indices, o0.scene_key),
+            [scenes.orbit_frame(k) for k in range(120)])
+        for r_ in (0.5, 2.0):
+            secondary[f"city2m_3840x2160_atlas4096_rate{r_}"] = time_frames(
+                ctx, mesh, [scenes.city_frame(k, rate=r_) for k in range(0, 32, 8)])
+        sctx.close()
+        log("secondary:", json.dumps(secondary))
+
     # batched views vs the plain per-view path
     batch = None
     if not args.no_batch:
         views = scenes.batch_views(16)
-        bouts = [ctx.outputs(mesh, v.atlas_size) for v in views]
+        bctx = fa.Context(T, V, max_charts=65536, max_atlas=4096, max_views=8)
+        for knob_ in (fa.FA_TUNE_OCC_SMALL_TEXELS, fa.FA_TUNE_UF_LINK_INIT,
+                      fa.FA_TUNE_UF_EDGE_HOOKS, fa.FA_TUNE_PACK_BLOCK):
+            bctx.set_tuning(knob_, ctx.get_tuning(knob_))
+        bouts = [bctx.outputs(mesh, v.atlas_size) for v in views]
         bvis = [torch.as_tensor(v.visible).to(dev) for v in views]
         desc = [(bvis[i], v.view_proj, v.width, v.height, v.atlas_size, v.rate)
                 for i, v in enumerate(views)]
-        for _ in range(2):
-            ctx.build_atlas_batch(mesh, desc, bouts, stream=stream)
-        torch.cuda.synchronize()
         reps = 10
-        w1 = time.perf_counter()
-        for _ in range(reps):
-            ctx.build_atlas_batch(mesh, desc, bouts, stream=stream)
-        torch.cuda.synchronize()
-        tb = (time.perf_counter() - w1) / reps
-        w2 = time.perf_counter()
-        for _ in range(reps):
+
+        def timed(fn):
+            for _ in range(2):
+                fn()
+            torch.cuda.synchronize()
+            w_ = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - w_) / reps
+
+        def plain():
             for i, v in enumerate(views):
-                ctx.build_atlas(mesh, bvis[i], v.view_proj, v.width, v.height, v.atlas_size,
-                                v.rate, out=bouts[i], stream=stream)
-        torch.cuda.synchronize()
-        tp = (time.perf_counter() - w2) / reps
-        batch = dict(views=16, batched_views_per_s=16 / tb, plain_views_per_s=16 / tp,
-                     speedup=tp / tb)
+                bctx.build_atlas(mesh, bvis[i], v.view_proj, v.width, v.height, v.atlas_size,
+                                 v.rate, out=bouts[i], stream=stream)
+        tp = timed(plain)
+        bctx.set_tuning(fa.FA_TUNE_BATCH_GRAPH, 0)
+        tb = timed(lambda: bctx.build_atlas_batch(mesh, desc, bouts, stream=stream))
+        bctx.set_tuning(fa.FA_TUNE_BATCH_GRAPH, 1)
+        tg = timed(lambda: bctx.build_atlas_batch(mesh, desc, bouts, stream=stream))
+        bctx.close()
+        batch = dict(views=16, slots=8, plain_views_per_s=16 / tp,
+                     batched_views_per_s=16 / min(tb, tg),
+                     batched_streams_views_per_s=16 / tb, batched_graph_views_per_s=16 / tg,
+                     speedup=tp / min(tb, tg))
 
     # served: continuous batching over the three scenes vs one-at-a-time FIFO
     served = None
@@ -216,10 +282,9 @@ def main():
         served = {}
         for slots in (8, 1):
             srv = serve.Server(smeshes, slots=slots, hbm_budget=16 << 30, max_atlas=4096,
-                               tuning={fa.FA_TUNE_OCC_SMALL_TEXELS:
-                                       ctx.get_tuning(fa.FA_TUNE_OCC_SMALL_TEXELS),
-                                       fa.FA_TUNE_UF_LINK_INIT:
-                                       ctx.get_tuning(fa.FA_TUNE_UF_LINK_INIT)})
+                               tuning={k_: ctx.get_tuning(k_) for k_ in (
+                                   fa.FA_TUNE_OCC_SMALL_TEXELS, fa.FA_TUNE_UF_LINK_INIT,
+                                   fa.FA_TUNE_UF_EDGE_HOOKS, fa.FA_TUNE_PACK_BLOCK)})
             srv.run(make_reqs(args.serve_rate, 64))  # warm-up
             reqs = make_reqs(args.serve_rate, args.serve_requests)
             w3 = time.perf_counter()
@@ -273,6 +338,7 @@ def main():
         "frame_hbm_roofline_frac": B / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "batch": batch,
         "served": served,
+        "secondary": secondary,
         "cpu_baseline": cpu,
         "roofline": roofline,
     }

@@ -194,27 +194,32 @@ int fa_pack_boxes(fa_ctx* ctx, const float* sizes, int32_t n, int32_t atlas_size
 /* Performance knobs of one context. Every accepted value produces identical
  * results; only the speed changes (an autotuner may pick any of them).
  *   FA_TUNE_PACK_BLOCK        threads per candidate packing: 256, 512, 1024
- *   FA_TUNE_OCC_SMALL_TEXELS  footprints up to this many texels are
- *                             rasterized by one thread (0..4096)
+ *   FA_TUNE_OCC_SMALL_TEXELS  footprints (bounding rectangle in texels) up to
+ *                             this many texels are rasterized by one thread,
+ *                             larger ones by whole waves (0..4096)
  *   FA_TUNE_UF_LINK_INIT      1: a triangle starts linked to its smallest
  *                             visible edge neighbour (Alg. 1); 0: to itself
+ *   FA_TUNE_UF_EDGE_HOOKS     1: join across shared edges, then across shared
+ *                             vertices (Alg. 1); 0: vertices only (every
+ *                             shared edge is a shared vertex: same charts)
  *   FA_TUNE_BATCH_GRAPH       1: fa_build_atlas_batch captures its views into
  *                             a hipGraph once per distinct set of view
  *                             descriptors and replays it (one launch); 0: off
  * fa_set_tuning returns FA_ERR_INVALID_ARG for unknown knobs or values;
  * fa_get_tuning returns the current value or -1. */
 enum { FA_TUNE_PACK_BLOCK = 1, FA_TUNE_OCC_SMALL_TEXELS = 2, FA_TUNE_UF_LINK_INIT = 3,
-       FA_TUNE_BATCH_GRAPH = 4 };
+       FA_TUNE_BATCH_GRAPH = 4, FA_TUNE_UF_EDGE_HOOKS = 5 };
 int fa_set_tuning(fa_ctx* ctx, int knob, int value);
 int fa_get_tuning(fa_ctx* ctx, int knob);
 
 /* Per-kernel timing: when enabled, fa_build_atlas (with uv and occupancy
  * outputs) records an event after each of its 16 kernels; fa_stage_times
  * (after the stream completed) fills up to n floats with milliseconds for, in
- * order: prologue (state, clip transform, union-find start), uf_hook,
- * uf_vertex_hook, uf_flatten, scan_tiles, assign_roots, gather_boxes,
- * sizes_order, pack, select_place, uv, occ_fill, occ_small, occ_big,
- * occ_count, meta; it returns the number filled (0 if none recorded).
+ * order: prologue (state, clip transform, union-find start, compaction of the
+ * visible triangles), uf_hook_vertex_min, uf_vertex_hook, uf_flatten,
+ * scan_tiles, assign_roots, gather_boxes, sizes_order, pack, select_place, uv,
+ * occ_fill, occ_small, occ_big, occ_count, meta; it returns the number filled
+ * (0 if none recorded).
  * Enabling costs a little host time and device idle time between kernels. */
 int fa_set_stage_timing(fa_ctx* ctx, int enable);
 int fa_stage_times(fa_ctx* ctx, float* ms_host, int n);

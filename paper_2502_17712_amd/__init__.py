@@ -25,6 +25,7 @@ FA_OK, FA_ERR_INVALID_ARG, FA_ERR_OUT_OF_MEMORY, FA_ERR_CAPACITY = 0, 1, 2, 3
 FA_ERR_NOFIT, FA_ERR_DEVICE, FA_ERR_UNSUPPORTED = 4, 5, 6
 FA_FLAG_NO_SIDE_CLIP = 1
 FA_TUNE_PACK_BLOCK, FA_TUNE_OCC_SMALL_TEXELS, FA_TUNE_UF_LINK_INIT, FA_TUNE_BATCH_GRAPH = 1, 2, 3, 4
+FA_TUNE_UF_EDGE_HOOKS = 5
 
 
 class fa_config(ctypes.Structure):
@@ -115,9 +116,9 @@ fa_get_tuning = _lib.fa_get_tuning
 fa_set_stage_timing = _lib.fa_set_stage_timing
 fa_stage_times = _lib.fa_stage_times
 
-STAGES = ["prologue", "uf_hook", "uf_vertex_hook", "uf_flatten", "scan_tiles", "assign_roots",
-          "gather_boxes", "sizes_order", "pack", "select_place", "uv", "occ_fill", "occ_small",
-          "occ_big", "occ_count", "meta"]
+STAGES = ["prologue", "uf_hook_vertex_min", "uf_vertex_hook", "uf_flatten", "scan_tiles",
+          "assign_roots", "gather_boxes", "sizes_order", "pack", "select_place", "uv",
+          "occ_fill", "occ_small", "occ_big", "occ_count", "meta"]
 
 
 class FastAtlasError(RuntimeError):

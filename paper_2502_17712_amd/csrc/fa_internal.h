@@ -23,6 +23,7 @@ constexpr int kMaxAtlas = 8192;
 constexpr int kCountGrid = 1024;     // blocks of the occupancy count
 constexpr int kOccBigGrid = 2048;    // blocks of the large-footprint raster
 
+
 // Device-resident results of one frame that later stages read (kept on the
 // device so that no stage needs a host round trip).
 struct FrameState {
@@ -34,10 +35,9 @@ struct FrameState {
   int32_t rows;
   float s_star;       // j*/J
   float q_star;       // omega/L*
-  uint32_t pad0;
-  uint32_t pad1;
+  int32_t visible;    // visible triangles (length of the visible list)
+  int32_t pad;
   unsigned long long occupied;
-  unsigned long long visible;
 };
 
 // Per-frame constants passed by value.
@@ -49,6 +49,7 @@ struct FrameParams {
   int32_t J, gutter, min_box;
   uint32_t flags;
   int32_t max_charts;
+  int32_t edge_hooks;  // run the edge-hook pass of the union-find
 };
 
 // Scratch buffers of one context (sized by the capacities).
@@ -71,6 +72,8 @@ struct Work {
   uint32_t* cand_ab;     // [J][max_charts] a | b << 16
   int32_t* cand_y;       // [J][max_charts]
   int32_t* cand_tab;     // [J][kCandStride] fit, m, L, H, rows
+  int32_t* vlist;        // [T] visible triangles in ascending order
+  uint32_t* tile_voff;   // [T/kTriTile + 1] visible-list offset of each triangle tile
   ulonglong2* big;       // [min(2T, 2^24)] large occupancy footprints
   unsigned long long* big_counter; // [1] queued footprints << 40 | queued tiles
   unsigned long long* partial;     // [kCountGrid] per-block partial counts
@@ -201,7 +204,7 @@ struct Marker {
 
 hipError_t launch_prologue(const float* pos, int64_t V, const uint8_t* vis, const int32_t* nbr,
                            int64_t T, const FrameParams& p, const Work& w, int32_t* cov,
-                           int uf_link_init, hipStream_t st);
+                           int32_t* cot, int uf_link_init, hipStream_t st);
 hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* nbr, int64_t T,
                          const FrameParams& p, const Work& w, int32_t* cot, int32_t* cov,
                          fa_chart* charts, Marker& mk, hipStream_t st);
@@ -215,6 +218,7 @@ hipError_t launch_uv(const int64_t V, const FrameParams& p, const Work& w, const
 hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
                             const int32_t* cot, const fa_chart* charts, int32_t* occ,
                             int small_texels, Marker& mk, hipStream_t st);
+unsigned visible_grid(int64_t T);  // blocks of the kernels that walk the visible list
 hipError_t launch_meta(const FrameParams& p, const Work& w, fa_atlas_meta* meta,
                        int with_occupancy, hipStream_t st);
 

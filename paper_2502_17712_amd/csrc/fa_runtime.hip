@@ -57,6 +57,7 @@ struct fa_ctx {
   int pack_block = 256;
   int small_texels = 256;
   int uf_link_init = 1;
+  int uf_edge_hooks = 1;
   int32_t* check_flag = nullptr;  // device int for index validation
 };
 
@@ -136,8 +137,9 @@ int fa_create(const fa_config* cfg_in, fa_ctx** out_ctx) {
         {(void**)&w.sorted_wh, 8 * C},           {(void**)&w.cand_x, 8 * J * C},
         {(void**)&w.cand_ab, 4 * J * C},         {(void**)&w.cand_y, 4 * J * C},
         {(void**)&w.cand_tab, 4 * kCandStride * J},
+        {(void**)&w.vlist, 4 * T},               {(void**)&w.tile_voff, 4 * tiles},
         {(void**)&w.big, 16 * std::min<size_t>(2 * T, size_t(1) << 24)},
-        {(void**)&w.big_counter, 8}, {(void**)&w.partial, 8 * kCountGrid},
+        {(void**)&w.big_counter, 8},             {(void**)&w.partial, 8 * kCountGrid},
         {(void**)&w.pack_charts, sizeof(fa_chart) * C},
         {(void**)&w.state, sizeof(FrameState)}};
     size_t total = 0;
@@ -314,6 +316,7 @@ static int frame_params(const fa_ctx* ctx, const fa_camera* cam, int32_t atlas, 
   p->min_box = ctx->cfg.min_box;
   p->flags = ctx->cfg.flags;
   p->max_charts = ctx->cfg.max_charts;
+  p->edge_hooks = ctx->uf_edge_hooks;
   return FA_OK;
 }
 
@@ -331,7 +334,8 @@ static int run_frame(fa_ctx* ctx, const Work& w, const fa_mesh* mesh, Scene* sc,
   Marker mk;
   if (ctx->timing) { mk.ev = ctx->ev; mk.cap = kStages + 1; }
   mk(st);
-  ok(launch_prologue(mesh->positions, V, visible, sc->nbr, T, p, w, cov, ctx->uf_link_init, st));
+  ok(launch_prologue(mesh->positions, V, visible, sc->nbr, T, p, w, cov, out->chart_of_tri,
+                     ctx->uf_link_init, st));
   mk(st);
   ok(launch_charts(visible, mesh->indices, sc->nbr, T, p, w, out->chart_of_tri, cov, out->charts,
                    mk, st));
@@ -502,6 +506,10 @@ int fa_set_tuning(fa_ctx* ctx, int knob, int value) {
       if (value != 0 && value != 1) return FA_ERR_INVALID_ARG;
       ctx->batch_graph = value;
       return FA_OK;
+    case FA_TUNE_UF_EDGE_HOOKS:
+      if (value != 0 && value != 1) return FA_ERR_INVALID_ARG;
+      ctx->uf_edge_hooks = value;
+      return FA_OK;
     default:
       return FA_ERR_INVALID_ARG;
   }
@@ -514,6 +522,7 @@ int fa_get_tuning(fa_ctx* ctx, int knob) {
     case FA_TUNE_OCC_SMALL_TEXELS: return ctx->small_texels;
     case FA_TUNE_UF_LINK_INIT: return ctx->uf_link_init;
     case FA_TUNE_BATCH_GRAPH: return ctx->batch_graph;
+    case FA_TUNE_UF_EDGE_HOOKS: return ctx->uf_edge_hooks;
     default: return -1;
   }
 }

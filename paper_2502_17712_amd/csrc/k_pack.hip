@@ -21,6 +21,11 @@
 namespace fa {
 namespace {
 
+// Candidates of frames with at most kPackLds charts keep their prefix sums
+// and sizes in LDS next to the frontline, so the sequential row loop never
+// waits on global memory.
+constexpr int kPackLds = 4096;
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
                                              const FrameState* __restrict__ st, FrameParams p,
@@ -28,7 +33,7 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
                                              uint32_t* __restrict__ cand_ab,
                                              int32_t* __restrict__ cand_y,
                                              int32_t* __restrict__ cand_tab, int64_t stride) {
-  extern __shared__ int32_t F[];  // [2 * omega]
+  extern __shared__ int32_t F[];  // [2 * omega] frontline, then the LDS copies of X and AB
   __shared__ uint32_t marker[NT];
   __shared__ int32_t bx[NT], ba[NT], bb[NT], ym[NT];
   __shared__ long long sh64[NT / kWave];
@@ -41,8 +46,11 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
   const int tid = threadIdx.x, w = tid / kWave;
   const int C = st->num_charts;
   const int omega = p.omega, lg = p.log2omega;
-  long long* X = cand_x + (int64_t)(j - 1) * stride;
-  uint32_t* AB = cand_ab + (int64_t)(j - 1) * stride;
+  long long* Xg = cand_x + (int64_t)(j - 1) * stride;
+  uint32_t* ABg = cand_ab + (int64_t)(j - 1) * stride;
+  const bool in_lds = C <= kPackLds;
+  long long* X = in_lds ? reinterpret_cast<long long*>(F + 2 * omega) : Xg;
+  uint32_t* AB = in_lds ? reinterpret_cast<uint32_t*>(F + 2 * omega + 2 * kPackLds) : ABg;
   int32_t* Y = cand_y + (int64_t)(j - 1) * stride;
   int32_t* tab = cand_tab + (j - 1) * kCandStride;
   const float s = (float)j / (float)p.J;
@@ -66,10 +74,14 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
     const long long Xi = run + incl - a;
     run += tot;
     if (i < C) {
-      X[i] = Xi;
+      Xg[i] = Xi;
       if (a > 2 * omega || b > 2 * omega) bad = 1;  // cannot fit: m > omega or H > L
       const uint32_t ca = (uint32_t)min(a, 2 * omega + 1), cb = (uint32_t)min(b, 2 * omega + 1);
-      AB[i] = ca | (cb << 16);
+      ABg[i] = ca | (cb << 16);
+      if (in_lds) {
+        X[i] = Xi;
+        AB[i] = ca | (cb << 16);
+      }
       mloc = max(mloc, (Xi & (long long)(omega - 1)) + a - omega);
     }
   }
@@ -262,13 +274,12 @@ __global__ __launch_bounds__(kBlock) void k_select_place(
 }
 
 // ---- packer-only entry: box sizes in, placements out ---------------------
-__global__ void k_pack_state(FrameState* st, unsigned long long* big_counter, int32_t n) {
+__global__ void k_pack_state(FrameState* st, int32_t n) {
   if (threadIdx.x == 0) {
     FrameState s = {};
     s.status = FA_OK;
     s.num_charts = n;
     *st = s;
-    *big_counter = 0ull;
   }
 }
 
@@ -313,7 +324,8 @@ __global__ void k_pack_emit(int32_t n, const fa_chart* __restrict__ charts,
 
 }  // namespace
 
-hipError_t pack_kernel_attributes(int max_dyn_bytes) {
+hipError_t pack_kernel_attributes(int max_frontline_bytes) {
+  const int max_dyn_bytes = max_frontline_bytes + kPackLds * 12;
   hipError_t e = hipFuncSetAttribute((const void*)k_pack<256>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn_bytes);
   if (e != hipSuccess) return e;
@@ -325,7 +337,7 @@ hipError_t pack_kernel_attributes(int max_dyn_bytes) {
 }
 
 hipError_t launch_pack(const FrameParams& p, const Work& w, int block, hipStream_t st) {
-  const size_t dyn = (size_t)2 * p.omega * sizeof(int32_t);
+  const size_t dyn = (size_t)2 * p.omega * sizeof(int32_t) + (size_t)kPackLds * 12;
   const int64_t stride = p.max_charts;
   if (block == 1024)
     k_pack<1024><<<p.J, 1024, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab, w.cand_y,
@@ -350,7 +362,7 @@ hipError_t launch_select_place(const FrameParams& p, const Work& w, fa_chart* ch
 hipError_t launch_pack_prepare(const float* sizes, int32_t n, const FrameParams& p, const Work& w,
                                fa_chart* charts, hipStream_t st) {
   (void)p;
-  k_pack_state<<<1, 64, 0, st>>>(w.state, w.big_counter, n);
+  k_pack_state<<<1, 64, 0, st>>>(w.state, n);
   if (n > 0)
     k_pack_prepare<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(
         sizes, n, charts, w.keys_a, w.vals_a, w.state);

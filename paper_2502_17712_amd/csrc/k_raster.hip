@@ -252,39 +252,57 @@ __device__ __forceinline__ void raster_thread(const Footprint& fp, int32_t* __re
 constexpr int kOccTile = 16;                   // queued footprints are cut into 16x16 tiles
 constexpr unsigned long long kSlotShift = 40;  // queue counter: footprints << 40 | tiles
 
-__global__ void k_occ_small(const int32_t* __restrict__ idx, int64_t T, FrameParams p,
-                            const float4* __restrict__ clip, const int32_t* __restrict__ cot,
-                            const fa_chart* __restrict__ charts, int32_t* __restrict__ occ,
-                            ulonglong2* __restrict__ big, uint32_t big_cap, int small_texels,
+__global__ void k_occ_small(const int32_t* __restrict__ idx, const int32_t* __restrict__ vlist,
+                            FrameParams p, const float4* __restrict__ clip,
+                            const int32_t* __restrict__ cot, const fa_chart* __restrict__ charts,
+                            int32_t* __restrict__ occ, ulonglong2* __restrict__ big,
+                            uint32_t big_cap, int small_texels,
                             unsigned long long* __restrict__ big_counter,
                             const FrameState* __restrict__ stp) {
   const FrameState st = *stp;
   if (st.status != FA_OK) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= T || cot[t] < 0) return;
-  SnapPoly sp;
-  snap_polygon(t, idx, clip, cot, charts, p, st, sp);
-  if (sp.n == 0) return;
-  const fa_chart& ch = charts[sp.chart];
-  for (int f = 0; f < 2; ++f) {
-    Footprint fp;
-    if (!fan_footprint(sp, f, ch, p, st, fp)) continue;
-    const int nx = fp.tx1 - fp.tx0 + 1, ny = fp.ty1 - fp.ty0 + 1;
-    if ((int64_t)nx * ny > small_texels) {
-      const uint32_t tx_n = (uint32_t)((nx + kOccTile - 1) / kOccTile);
-      const uint32_t nt = tx_n * (uint32_t)((ny + kOccTile - 1) / kOccTile);
-      const unsigned long long old =
-          atomicAdd(big_counter, (1ull << kSlotShift) | (unsigned long long)nt);
-      const unsigned long long slot = old >> kSlotShift;
-      if (slot < big_cap) {
-        // x: footprint code | tiles across << 32; y: first tile | tiles << 40
-        big[slot] = make_ulonglong2(
-            (unsigned long long)(2 * t + f) | ((unsigned long long)tx_n << 32),
-            (old & ((1ull << kSlotShift) - 1)) | ((unsigned long long)nt << kSlotShift));
-        continue;
+  const int nv = st.visible;
+  constexpr unsigned long long kLow = (1ull << kSlotShift) - 1;
+  for (int i0 = blockIdx.x * blockDim.x; i0 < nv; i0 += gridDim.x * blockDim.x) {
+    const int i = i0 + threadIdx.x;
+    const bool valid = i < nv;
+    SnapPoly sp;
+    sp.n = 0;
+    sp.chart = -1;
+    if (valid) snap_polygon(vlist[i], idx, clip, cot, charts, p, st, sp);
+    for (int f = 0; f < 2; ++f) {
+      Footprint fp;
+      const bool ok = sp.n > 0 && fan_footprint(sp, f, charts[sp.chart], p, st, fp);
+      int nx = 0, ny = 0;
+      if (ok) {
+        nx = fp.tx1 - fp.tx0 + 1;
+        ny = fp.ty1 - fp.ty0 + 1;
       }
+      const bool want = ok && (int64_t)nx * ny > small_texels;
+      bool queued = false;
+      const unsigned long long qm = __ballot(want);
+      if (qm) {
+        // one atomic per wave: lanes take consecutive queue slots and tiles
+        const uint32_t tx_n = want ? (uint32_t)((nx + kOccTile - 1) / kOccTile) : 0u;
+        const uint32_t nt = want ? tx_n * (uint32_t)((ny + kOccTile - 1) / kOccTile) : 0u;
+        const uint32_t before = wave_incl_scan<uint32_t>(nt) - nt;
+        const uint32_t all = __shfl(before + nt, kWave - 1, kWave);
+        const int leader = __ffsll((long long)qm) - 1;
+        unsigned long long old = 0;
+        if (lane_id() == leader)
+          old = atomicAdd(big_counter, ((unsigned long long)__popcll(qm) << kSlotShift) | all);
+        old = __shfl(old, leader, kWave);
+        const unsigned long long slot = (old >> kSlotShift) + __popcll(qm & lanes_below());
+        if (want && slot < big_cap) {
+          // x: footprint code | tiles across << 32; y: first tile | tiles << 40
+          big[slot] = make_ulonglong2(
+              (unsigned long long)(2 * (int64_t)vlist[i] + f) | ((unsigned long long)tx_n << 32),
+              ((old & kLow) + before) | ((unsigned long long)nt << kSlotShift));
+          queued = true;
+        }
+      }
+      if (ok && !queued) raster_thread(fp, occ, p.omega);
     }
-    raster_thread(fp, occ, p.omega);
   }
 }
 
@@ -410,8 +428,9 @@ hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p,
   mk(st);
   const uint32_t cap = (uint32_t)std::min<int64_t>(2 * std::max<int64_t>(T, 1), 1 << 24);
   if (T > 0) {
-    k_occ_small<<<(unsigned)((T + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-        idx, T, p, w.clip, cot, charts, occ, w.big, cap, small_texels, w.big_counter, w.state);
+    k_occ_small<<<visible_grid(T), kBlock, 0, st>>>(idx, w.vlist, p, w.clip, cot, charts, occ,
+                                                    w.big, cap, small_texels, w.big_counter,
+                                                    w.state);
     mk(st);
     k_occ_big<<<kOccBigGrid, kBlock, 0, st>>>(idx, p, w.clip, cot, charts, occ, w.big, cap,
                                               w.big_counter, w.state);

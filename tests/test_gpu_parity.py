@@ -149,7 +149,7 @@ def test_city_frames_more():
 
 
 @pytest.mark.parametrize("knob,value", [(1, 512), (1, 1024), (2, 0), (2, 16), (2, 1024),
-                                        (3, 0)])
+                                        (3, 0), (5, 0)])
 def test_tuning_knobs_do_not_change_results(knob, value):
     fa = _fa()
     ctx = ctx_for()
@@ -162,7 +162,7 @@ def test_tuning_knobs_do_not_change_results(knob, value):
     finally:
         ctx.set_tuning(knob, old)
     with pytest.raises(fa.FastAtlasError):
-        ctx.set_tuning(knob, {1: 3, 2: -1, 3: 3}[knob])
+        ctx.set_tuning(knob, {1: 3, 2: -1, 3: 3, 5: 2}[knob])
 
 
 # ---------------------------------------------------------------------------
