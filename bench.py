@@ -43,7 +43,9 @@ def kernel_bytes(name, T, V, Tv, Vv, C, J, omega, occupied):
     at minimum); the per-unit figures are listed in the design doc."""
     per = {
         "prologue": V * (12 + 16 + 4 + 4) + T * (1 + 4) + Tv * (12 + 4 + 4),
-        "uf_hook_vertex_min": Tv * (4 + 12 + 3 + 4 + 12 + 12),
+        "vis_compact": T * 1 + Tv * 4,
+        "uf_hook": Tv * (4 + 12 + 3 + 4),
+        "uf_vertex_min": Tv * (4 + 4 + 12 + 12),
         "uf_vertex_hook": Tv * (4 + 12 + 12 + 4),
         "uf_flatten": Tv * (4 + 4 + 4),
         "assign_roots": Tv * (4 + 4) + C * (4 + 4 + 16),
@@ -73,7 +75,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--serve-rate", type=float, default=1000.0)
+    ap.add_argument("--serve-rate", type=float, nargs="+", default=[60.0, 250.0, 1000.0, 2000.0])
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 4 plain device copies of 256 MiB (counter calibration)")
@@ -95,6 +97,8 @@ def main():
 
     import torch
     import paper_2502_17712_amd as fa
+    TUNED = (fa.FA_TUNE_OCC_SMALL_TEXELS, fa.FA_TUNE_OCC_LANE_TEXELS, fa.FA_TUNE_UF_LINK_INIT,
+             fa.FA_TUNE_UF_EDGE_HOOKS, fa.FA_TUNE_PACK_BLOCK)
     from synth import scenes
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -147,6 +151,65 @@ def main():
     per = np.array([a.elapsed_time(b) for a, b in evs])
     meta = fa.parse_meta(out.meta)
     assert meta["status"] == fa.FA_OK, meta
+
+    # the same frames without the occupancy output (UVs and placements only)
+    out_nocc = ctx.outputs(mesh, args.atlas, occupancy=False)
+    for k in range(8):
+        f = frames[k % len(frames)]
+        ctx.build_atlas(mesh, vis[k % len(frames)], f.view_proj, f.width, f.height,
+                        f.atlas_size, f.rate, out=out_nocc, stream=stream)
+    evn = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(len(frames) * 2)]
+    for k, (a_, b_) in enumerate(evn):
+        f = frames[k % len(frames)]
+        a_.record(stream)
+        ctx.build_atlas(mesh, vis[k % len(frames)], f.view_proj, f.width, f.height,
+                        f.atlas_size, f.rate, out=out_nocc, stream=stream)
+        b_.record(stream)
+    torch.cuda.synchronize()
+    ms_nocc = float(np.mean([a_.elapsed_time(b_) for a_, b_ in evn]))
+    del out_nocc
+
+    # plain device copy bandwidth on this GPU (context for the roofline)
+    cpa = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    cpb = torch.empty_like(cpa)
+    cpa.fill_(1)
+    cpb.copy_(cpa)
+    c0_, c1_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0_.record(stream)
+    for _ in range(5):
+        cpb.copy_(cpa)
+    c1_.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * cpa.numel() / (c0_.elapsed_time(c1_) * 1e-3) / 1e9
+    del cpa, cpb
+
+    # the visible-triangle pass on the device (coarse depth buffer), alone and
+    # followed by the atlas of the same frame
+    vbuf = torch.empty(T, dtype=torch.uint8, device=dev)
+    for f in frames[:4]:
+        ctx.visibility(mesh, f.view_proj, f.width, f.height, f.eye, f.near, f.coarse, out=vbuf,
+                       stream=stream)
+    torch.cuda.synchronize()
+    evv = []
+    for k in range(len(frames) * 2):
+        f = frames[k % len(frames)]
+        a_, m_, b_ = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        a_.record(stream)
+        ctx.visibility(mesh, f.view_proj, f.width, f.height, f.eye, f.near, f.coarse, out=vbuf,
+                       stream=stream)
+        m_.record(stream)
+        ctx.build_atlas(mesh, vbuf, f.view_proj, f.width, f.height, f.atlas_size, f.rate,
+                        out=out, stream=stream)
+        b_.record(stream)
+        evv.append((a_, m_, b_))
+    torch.cuda.synchronize()
+    visibility = dict(coarse=frames[0].coarse,
+                      visibility_ms=float(np.mean([a_.elapsed_time(m_) for a_, m_, _ in evv])),
+                      visibility_plus_atlas_ms=float(np.mean([a_.elapsed_time(b_)
+                                                              for a_, _, b_ in evv])))
+    assert torch.equal(vbuf.cpu(), torch.as_tensor(frames[(len(evv) - 1) % len(frames)].visible))
+    del vbuf
 
     # per-kernel live times (separate pass with an event after every kernel)
     ctx.set_stage_timing(True)
@@ -205,8 +268,7 @@ def main():
     if not args.no_secondary:
         g0 = scenes.grid_frame(0)
         sctx = fa.Context(T, V, max_charts=65536, max_atlas=4096)
-        for knob_ in (fa.FA_TUNE_OCC_SMALL_TEXELS, fa.FA_TUNE_UF_LINK_INIT,
-                      fa.FA_TUNE_UF_EDGE_HOOKS, fa.FA_TUNE_PACK_BLOCK):
+        for knob_ in TUNED:
             sctx.set_tuning(knob_, ctx.get_tuning(knob_))
         secondary["grid8k_1280x720_atlas1024"] = time_frames(
             sctx, fa.Mesh(g0.positions, g0.indices, g0.scene_key),
@@ -226,8 +288,7 @@ def main():
     if not args.no_batch:
         views = scenes.batch_views(16)
         bctx = fa.Context(T, V, max_charts=65536, max_atlas=4096, max_views=8)
-        for knob_ in (fa.FA_TUNE_OCC_SMALL_TEXELS, fa.FA_TUNE_UF_LINK_INIT,
-                      fa.FA_TUNE_UF_EDGE_HOOKS, fa.FA_TUNE_PACK_BLOCK):
+        for knob_ in TUNED:
             bctx.set_tuning(knob_, ctx.get_tuning(knob_))
         bouts = [bctx.outputs(mesh, v.atlas_size) for v in views]
         bvis = [torch.as_tensor(v.visible).to(dev) for v in views]
@@ -272,28 +333,41 @@ def main():
         svis = {(s, i): torch.as_tensor(pools[s][i].visible).to(dev) for s in pools
                 for i in range(len(pools[s]))}
 
-        def make_reqs(lam, n):
+        def make_reqs(lam, n, device_vis=False):
             out_ = []
             for rid, (a, c, s, i, om, r) in enumerate(rq.poisson_stream(lam, n, pools, seed=7)):
                 pz = pools[s][i]
-                out_.append(serve.Request(rid, s, svis[(s, i)], pz.view_proj, pz.width,
-                                          pz.height, om, r, arrival=a, client=c))
+                out_.append(serve.Request(rid, s, None if device_vis else svis[(s, i)],
+                                          pz.view_proj, pz.width, pz.height, om, r, arrival=a,
+                                          client=c, eye=tuple(pz.eye), near=pz.near,
+                                          coarse=pz.coarse))
             return out_
         served = {}
         for slots in (8, 1):
             srv = serve.Server(smeshes, slots=slots, hbm_budget=16 << 30, max_atlas=4096,
-                               tuning={k_: ctx.get_tuning(k_) for k_ in (
-                                   fa.FA_TUNE_OCC_SMALL_TEXELS, fa.FA_TUNE_UF_LINK_INIT,
-                                   fa.FA_TUNE_UF_EDGE_HOOKS, fa.FA_TUNE_PACK_BLOCK)})
-            srv.run(make_reqs(args.serve_rate, 64))  # warm-up
-            reqs = make_reqs(args.serve_rate, args.serve_requests)
-            w3 = time.perf_counter()
-            res_ = srv.run(reqs)
-            wall3 = time.perf_counter() - w3
+                               tuning={k_: ctx.get_tuning(k_) for k_ in TUNED})
+            srv.run(make_reqs(max(args.serve_rate), 64))  # warm-up
+            kind = "continuous" if slots > 1 else "fifo"
+            served[kind] = {}
+            for lam in args.serve_rate:
+                reqs = make_reqs(lam, min(args.serve_requests, int(lam * 5) + 64))
+                w3 = time.perf_counter()
+                res_ = srv.run(reqs)
+                wall3 = time.perf_counter() - w3
+                assert all(r.meta["status"] == 0 for r in res_)
+                served[kind][f"{lam:g}"] = dict(slots=slots, offered_req_per_s=lam,
+                                                 **serve.summarize(res_, wall3))
+            if slots > 1:
+                # the same stream with the visible sets computed on the device
+                lam = max(args.serve_rate)
+                reqs = make_reqs(lam, args.serve_requests, device_vis=True)
+                w3 = time.perf_counter()
+                res_ = srv.run(reqs)
+                wall3 = time.perf_counter() - w3
+                assert all(r.meta["status"] == 0 for r in res_)
+                served["continuous_device_visibility"] = {f"{lam:g}": dict(
+                    slots=slots, offered_req_per_s=lam, **serve.summarize(res_, wall3))}
             srv.close()
-            assert all(r.meta["status"] == 0 for r in res_)
-            served["continuous" if slots > 1 else "fifo"] = dict(
-                slots=slots, offered_req_per_s=args.serve_rate, **serve.summarize(res_, wall3))
         log("served:", json.dumps(served))
 
     # CPU oracle on a bounded sample of the same workload
@@ -336,6 +410,14 @@ def main():
         "large_tiles": meta["large_tiles"],
         "algorithmic_bytes_per_frame": B,
         "frame_hbm_roofline_frac": B / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "no_occupancy": {"ms_per_frame": ms_nocc,
+                         "algorithmic_bytes": B - 4.0 * args.atlas * args.atlas,
+                         "hbm_roofline_frac": (B - 4.0 * args.atlas * args.atlas)
+                         / (ms_nocc * 1e-3) / (HBM_PEAK_GBS * 1e9)},
+        "dependent_phases": len(stages),
+        "pack_rows_at_chosen_scale": meta["rows"],
+        "copy_gbs": copy_gbs,
+        "device_visibility": visibility,
         "batch": batch,
         "served": served,
         "secondary": secondary,

@@ -165,6 +165,27 @@ int fa_scene_adjacency(fa_ctx* ctx, const fa_mesh* mesh, int32_t* nbr_out, void*
 /* Drop the resident adjacency of one scene (no work may be in flight). */
 int fa_scene_evict(fa_ctx* ctx, uint64_t scene_key);
 
+/* Visible triangles of a view (App. "Detecting Visible Triangles": a depth
+ * pre-pass, then every triangle's samples are tested against the depth buffer
+ * with "less or equal" and the triangles that pass are marked). float64.
+ * A triangle is a candidate iff it faces the eye, (b-a) x (c-a) . (eye-a) > 0
+ * with positions a, b, c, and no clip plane (-w <= x, y, z <= w, clip =
+ * view_proj * (x, y, z, 1)) has all three vertices outside. coarse = 0:
+ * visible = candidate. coarse = k > 0: a depth buffer of (W/k) x (H/k)
+ * samples at pixel centres (x right, y down) is filled by the candidates whose
+ * three w exceed near_w, with the NDC z interpolated by edge-function
+ * weights; such a candidate stays visible iff it covers no sample or one of
+ * its samples has z <= depth + 1e-6; candidates crossing the near plane stay
+ * visible. eye: world-space camera position (3 doubles, host); near_w: w at
+ * the near plane (> 0). visible: device [T], written 0/1. Uses the context's
+ * visibility scratch; the first call at a larger coarse grid allocates it
+ * (later calls with grids up to that size allocate nothing). Errors:
+ * FA_ERR_INVALID_ARG (null pointers, bad sizes, coarse outside 0..64,
+ * non-finite camera, near_w <= 0, out-of-range indices), FA_ERR_CAPACITY
+ * (mesh larger than the context). */
+int fa_visibility(fa_ctx* ctx, const fa_mesh* mesh, const fa_camera* cam, const double* eye,
+                  double near_w, int32_t coarse, uint8_t* visible, void* stream);
+
 /* Atlas one frame: charts, boxes, order, J-candidate packing, selection,
  * per-vertex UVs and (if out->occupancy) the atlas occupancy map.
  * visible: [T] 0/1. atlas_size: power of two, 16 <= atlas_size <= max_atlas.
@@ -194,32 +215,39 @@ int fa_pack_boxes(fa_ctx* ctx, const float* sizes, int32_t n, int32_t atlas_size
 /* Performance knobs of one context. Every accepted value produces identical
  * results; only the speed changes (an autotuner may pick any of them).
  *   FA_TUNE_PACK_BLOCK        threads per candidate packing: 256, 512, 1024
- *   FA_TUNE_OCC_SMALL_TEXELS  footprints (bounding rectangle in texels) up to
- *                             this many texels are rasterized by one thread,
- *                             larger ones by whole waves (0..4096)
+ *   FA_TUNE_OCC_SMALL_TEXELS  footprints (texel range of a fan triangle) of
+ *                             more texels are queued and cut into 16x16
+ *                             tiles shared by all waves (0..4096)
+ *   FA_TUNE_OCC_LANE_TEXELS   footprints up to this many texels are
+ *                             rasterized by one lane; larger ones (up to
+ *                             FA_TUNE_OCC_SMALL_TEXELS) by their wave (0..4096)
  *   FA_TUNE_UF_LINK_INIT      1: a triangle starts linked to its smallest
  *                             visible edge neighbour (Alg. 1); 0: to itself
+ *                             (used when FA_TUNE_UF_EDGE_HOOKS is 0 or 1)
  *   FA_TUNE_UF_EDGE_HOOKS     1: join across shared edges, then across shared
- *                             vertices (Alg. 1); 0: vertices only (every
- *                             shared edge is a shared vertex: same charts)
+ *                             vertices (Alg. 1); 2 (default): shared edges
+ *                             inside tiles of 2048 visible triangles joined in
+ *                             LDS first, then vertices; 0: vertices only
+ *                             (every shared edge is a shared vertex: the
+ *                             charts are the same for all three)
  *   FA_TUNE_BATCH_GRAPH       1: fa_build_atlas_batch captures its views into
  *                             a hipGraph once per distinct set of view
  *                             descriptors and replays it (one launch); 0: off
  * fa_set_tuning returns FA_ERR_INVALID_ARG for unknown knobs or values;
  * fa_get_tuning returns the current value or -1. */
 enum { FA_TUNE_PACK_BLOCK = 1, FA_TUNE_OCC_SMALL_TEXELS = 2, FA_TUNE_UF_LINK_INIT = 3,
-       FA_TUNE_BATCH_GRAPH = 4, FA_TUNE_UF_EDGE_HOOKS = 5 };
+       FA_TUNE_BATCH_GRAPH = 4, FA_TUNE_UF_EDGE_HOOKS = 5, FA_TUNE_OCC_LANE_TEXELS = 6 };
 int fa_set_tuning(fa_ctx* ctx, int knob, int value);
 int fa_get_tuning(fa_ctx* ctx, int knob);
 
 /* Per-kernel timing: when enabled, fa_build_atlas (with uv and occupancy
- * outputs) records an event after each of its 16 kernels; fa_stage_times
+ * outputs) records an event after each of its 19 kernels; fa_stage_times
  * (after the stream completed) fills up to n floats with milliseconds for, in
- * order: prologue (state, clip transform, union-find start, compaction of the
- * visible triangles), uf_hook_vertex_min, uf_vertex_hook, uf_flatten,
- * scan_tiles, assign_roots, gather_boxes, sizes_order, pack, select_place, uv,
- * occ_fill, occ_small, occ_big, occ_count, meta; it returns the number filled
- * (0 if none recorded).
+ * order: prologue (state, clip transform, union-find start), vis_scan,
+ * vis_compact (list of the visible triangles), uf_hook, uf_vertex_min,
+ * uf_vertex_hook, uf_flatten, chart_scan, assign_roots, gather_boxes,
+ * sizes_order, pack, select_place, uv, occ_fill, occ_small, occ_big,
+ * occ_count, meta; it returns the number filled (0 if none recorded).
  * Enabling costs a little host time and device idle time between kernels. */
 int fa_set_stage_timing(fa_ctx* ctx, int enable);
 int fa_stage_times(fa_ctx* ctx, float* ms_host, int n);

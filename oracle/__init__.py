@@ -61,6 +61,7 @@ def lib():
         L.oracle_occupancy.argtypes = [P, P, P, P, i64, P, P, P, P, P, P, P, i32, i32, f32, i32,
                                        i32, i32, i64, i32, P]
         L.oracle_occupancy.restype = i64
+        L.oracle_visibility.argtypes = [P, i64, P, i64, P, P, ctypes.c_double, i32, i32, i32, P]
         _lib = L
     return _lib
 
@@ -82,6 +83,18 @@ def clip(positions, view_proj):
     M = _c(view_proj, np.float32).ravel()
     out = np.empty((pos.shape[0], 4), np.float32)
     lib().oracle_clip(_p(pos), pos.shape[0], _p(M), _p(out))
+    return out
+
+
+def visibility(positions, indices, view_proj, eye, near, width, height, coarse=0):
+    """Visible triangles of a view (App. "Detecting Visible Triangles"): uint8 [T]."""
+    pos = _c(positions, np.float32)
+    idx = _c(indices, np.int32)
+    M = _c(view_proj, np.float32).ravel()
+    e = _c(np.asarray(eye, np.float64), np.float64)
+    out = np.empty(idx.shape[0], np.uint8)
+    lib().oracle_visibility(_p(pos), pos.shape[0], _p(idx), idx.shape[0], _p(M), _p(e),
+                            float(near), int(width), int(height), int(coarse), _p(out))
     return out
 
 

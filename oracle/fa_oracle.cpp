@@ -16,8 +16,9 @@
 //
 // Parity status per step:
 //   adjacency, clip, charts, per-triangle boxes, chart frames, order, fold,
-//   push, select, UV, occupancy: pinned by independent tests (brute force,
-//   closed forms, exact double clipping, invariants); see tests/test_oracle_*.
+//   push, select, UV, occupancy, visibility: pinned by independent tests
+//   (brute force, closed forms, exact double clipping, invariants, an
+//   independent vectorized implementation); see tests/test_oracle_*.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -523,6 +524,110 @@ int64_t oracle_occupancy(const float* clip, const int32_t* idx, const uint8_t* n
   int64_t cnt = 0;
   for (int64_t i = 0; i < N; ++i) cnt += occ[i] >= 0;
   return cnt;
+}
+
+// ---------------------------------------------------------------------------
+// V   visible triangles of a view (App. "Detecting Visible Triangles": a depth
+// pre-pass fills a depth buffer, a second pass tests every triangle's samples
+// against it with "less or equal" and marks the triangles that pass).
+// Readings: float64 throughout; a triangle is a candidate iff it faces the eye
+// ((b-a) x (c-a) . (eye-a) > 0) and no clip plane has all three vertices
+// outside; with coarse = k > 0 the depth buffer has (W/k) x (H/k) samples at
+// pixel centres, only candidates with every w > near_w write it (their
+// depth is the NDC z interpolated with edge-function weights), and such a
+// triangle stays visible iff it covers no sample (it cannot be proven hidden:
+// the conservative side) or one covered sample has z <= D + 1e-6; candidates
+// crossing the near plane stay visible. coarse = 0: candidates only.
+// ---------------------------------------------------------------------------
+void oracle_visibility(const float* pos, int64_t V, const int32_t* idx, int64_t T,
+                       const float* Mf, const double* eye, double near_w, int32_t W, int32_t H,
+                       int32_t coarse, uint8_t* vis) {
+  double M[16];
+  for (int i = 0; i < 16; ++i) M[i] = (double)Mf[i];
+  std::vector<double> c(4 * (size_t)V);
+  for (int64_t v = 0; v < V; ++v) {
+    const double x = pos[3 * v], y = pos[3 * v + 1], z = pos[3 * v + 2];
+    for (int i = 0; i < 4; ++i)
+      c[4 * v + i] = ((M[4 * i] * x + M[4 * i + 1] * y) + M[4 * i + 2] * z) + M[4 * i + 3];
+  }
+  std::vector<uint8_t> occluder(T, 0);
+  for (int64_t t = 0; t < T; ++t) {
+    const int64_t i0 = idx[3 * t], i1 = idx[3 * t + 1], i2 = idx[3 * t + 2];
+    double a[3], b[3], d[3];
+    for (int k = 0; k < 3; ++k) {
+      const double q0 = pos[3 * i0 + k], q1 = pos[3 * i1 + k], q2 = pos[3 * i2 + k];
+      a[k] = q1 - q0;
+      b[k] = q2 - q0;
+      d[k] = eye[k] - q0;
+    }
+    const double n0 = a[1] * b[2] - a[2] * b[1];
+    const double n1 = a[2] * b[0] - a[0] * b[2];
+    const double n2 = a[0] * b[1] - a[1] * b[0];
+    const bool front = ((n0 * d[0] + n1 * d[1]) + n2 * d[2]) > 0.0;
+    bool outside = false;
+    for (int pl = 0; pl < 6 && !outside; ++pl) {
+      const int k = pl / 2;  // x, y, z
+      const double sgn = (pl % 2 == 0) ? 1.0 : -1.0;
+      int out = 0;
+      for (int e = 0; e < 3; ++e) {
+        const int64_t v = idx[3 * t + e];
+        const double w = c[4 * v + 3], u = c[4 * v + k];
+        const double dist = sgn > 0 ? w + u : w - u;
+        out += dist < 0.0;
+      }
+      outside = out == 3;
+    }
+    vis[t] = (front && !outside) ? 1 : 0;
+    occluder[t] = vis[t] && c[4 * i0 + 3] > near_w && c[4 * i1 + 3] > near_w &&
+                  c[4 * i2 + 3] > near_w;
+  }
+  if (coarse <= 0) return;
+  const int64_t Wc = W / coarse, Hc = H / coarse;
+  if (Wc <= 0 || Hc <= 0) return;
+  std::vector<double> D((size_t)(Wc * Hc), INFINITY);
+  // screen position of a vertex in coarse pixels (x right, y down) and NDC z
+  auto screen = [&](int64_t v, double* X, double* Y, double* Z) {
+    const double w = c[4 * v + 3];
+    *X = ((c[4 * v + 0] / w) * 0.5 + 0.5) * (double)Wc;
+    *Y = (0.5 - (c[4 * v + 1] / w) * 0.5) * (double)Hc;
+    *Z = c[4 * v + 2] / w;
+  };
+  // visit every sample centre covered by triangle t: fn(pixel, depth)
+  auto covered = [&](int64_t t, auto&& fn) {
+    double X[3], Y[3], Z[3];
+    for (int e = 0; e < 3; ++e) screen(idx[3 * t + e], &X[e], &Y[e], &Z[e]);
+    const double xmin = std::min({X[0], X[1], X[2]}), xmax = std::max({X[0], X[1], X[2]});
+    const double ymin = std::min({Y[0], Y[1], Y[2]}), ymax = std::max({Y[0], Y[1], Y[2]});
+    const int64_t ix0 = (int64_t)std::min(std::max(std::ceil(xmin - 0.5), 0.0), (double)(Wc - 1));
+    const int64_t ix1 = (int64_t)std::min(std::max(std::floor(xmax - 0.5), -1.0), (double)(Wc - 1));
+    const int64_t iy0 = (int64_t)std::min(std::max(std::ceil(ymin - 0.5), 0.0), (double)(Hc - 1));
+    const int64_t iy1 = (int64_t)std::min(std::max(std::floor(ymax - 0.5), -1.0), (double)(Hc - 1));
+    for (int64_t py = iy0; py <= iy1; ++py) {
+      for (int64_t px = ix0; px <= ix1; ++px) {
+        const double cx = (double)px + 0.5, cy = (double)py + 0.5;
+        const double e0 = (X[2] - X[1]) * (cy - Y[1]) - (Y[2] - Y[1]) * (cx - X[1]);
+        const double e1 = (X[0] - X[2]) * (cy - Y[2]) - (Y[0] - Y[2]) * (cx - X[2]);
+        const double e2 = (X[1] - X[0]) * (cy - Y[0]) - (Y[1] - Y[0]) * (cx - X[0]);
+        const double area = (e0 + e1) + e2;
+        const bool in = area != 0.0 && ((e0 >= 0 && e1 >= 0 && e2 >= 0) ||
+                                        (e0 <= 0 && e1 <= 0 && e2 <= 0));
+        if (!in) continue;
+        const double z = ((e0 * Z[0] + e1 * Z[1]) + e2 * Z[2]) / area;
+        fn(py * Wc + px, z);
+      }
+    }
+  };
+  for (int64_t t = 0; t < T; ++t)
+    if (occluder[t]) covered(t, [&](int64_t pix, double z) { D[pix] = std::min(D[pix], z); });
+  for (int64_t t = 0; t < T; ++t) {
+    if (!occluder[t]) continue;
+    bool any = false, pass = false;
+    covered(t, [&](int64_t pix, double z) {
+      any = true;
+      if (z <= D[pix] + 1e-6) pass = true;
+    });
+    vis[t] = (!any || pass) ? 1 : 0;
+  }
 }
 
 }  // extern "C"

@@ -13,7 +13,8 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_float, c_int, c_int32, c_int64, c_uint32, c_uint64, c_void_p
+from ctypes import (POINTER, c_double, c_float, c_int, c_int32, c_int64, c_uint32, c_uint64,
+                    c_void_p)
 
 import numpy as np
 import torch
@@ -25,7 +26,7 @@ FA_OK, FA_ERR_INVALID_ARG, FA_ERR_OUT_OF_MEMORY, FA_ERR_CAPACITY = 0, 1, 2, 3
 FA_ERR_NOFIT, FA_ERR_DEVICE, FA_ERR_UNSUPPORTED = 4, 5, 6
 FA_FLAG_NO_SIDE_CLIP = 1
 FA_TUNE_PACK_BLOCK, FA_TUNE_OCC_SMALL_TEXELS, FA_TUNE_UF_LINK_INIT, FA_TUNE_BATCH_GRAPH = 1, 2, 3, 4
-FA_TUNE_UF_EDGE_HOOKS = 5
+FA_TUNE_UF_EDGE_HOOKS, FA_TUNE_OCC_LANE_TEXELS = 5, 6
 
 
 class fa_config(ctypes.Structure):
@@ -68,7 +69,7 @@ assert CHART_DTYPE.itemsize == 64 and META_DTYPE.itemsize == 64
 
 EXPORTS = ["fa_create", "fa_destroy", "fa_status_string", "fa_scene_adjacency", "fa_scene_evict",
            "fa_build_atlas", "fa_build_atlas_batch", "fa_pack_boxes", "fa_set_tuning",
-           "fa_get_tuning", "fa_set_stage_timing", "fa_stage_times"]
+           "fa_get_tuning", "fa_set_stage_timing", "fa_stage_times", "fa_visibility"]
 
 
 def _load():
@@ -93,9 +94,11 @@ def _load():
     lib.fa_get_tuning.argtypes = [c_void_p, c_int]
     lib.fa_set_stage_timing.argtypes = [c_void_p, c_int]
     lib.fa_stage_times.argtypes = [c_void_p, POINTER(c_float), c_int]
+    lib.fa_visibility.argtypes = [c_void_p, POINTER(fa_mesh), POINTER(fa_camera),
+                                  POINTER(c_double), c_double, c_int32, c_void_p, c_void_p]
     for n in ("fa_scene_adjacency", "fa_scene_evict", "fa_build_atlas", "fa_build_atlas_batch",
               "fa_pack_boxes", "fa_set_tuning", "fa_get_tuning", "fa_set_stage_timing",
-              "fa_stage_times"):
+              "fa_stage_times", "fa_visibility"):
         getattr(lib, n).restype = c_int
     return lib
 
@@ -115,10 +118,11 @@ fa_set_tuning = _lib.fa_set_tuning
 fa_get_tuning = _lib.fa_get_tuning
 fa_set_stage_timing = _lib.fa_set_stage_timing
 fa_stage_times = _lib.fa_stage_times
+fa_visibility = _lib.fa_visibility
 
-STAGES = ["prologue", "uf_hook_vertex_min", "uf_vertex_hook", "uf_flatten", "scan_tiles",
-          "assign_roots", "gather_boxes", "sizes_order", "pack", "select_place", "uv",
-          "occ_fill", "occ_small", "occ_big", "occ_count", "meta"]
+STAGES = ["prologue", "vis_scan", "vis_compact", "uf_hook", "uf_vertex_min", "uf_vertex_hook",
+          "uf_flatten", "chart_scan", "assign_roots", "gather_boxes", "sizes_order", "pack",
+          "select_place", "uv", "occ_fill", "occ_small", "occ_big", "occ_count", "meta"]
 
 
 class FastAtlasError(RuntimeError):
@@ -249,6 +253,17 @@ class Context:
         _check(fa_scene_adjacency(self.h, ctypes.byref(mesh.c), _ptr(nbr), _stream_handle(stream)),
                "fa_scene_adjacency")
         return nbr
+
+    def visibility(self, mesh: Mesh, view_proj, width, height, eye, near, coarse=0, out=None,
+                   stream=None):
+        """Visible triangles of a view on the device: uint8 [T] (see fa_visibility)."""
+        if out is None:
+            out = torch.empty(mesh.num_triangles, dtype=torch.uint8, device="cuda")
+        cam = make_camera(view_proj, width, height)
+        e = (c_double * 3)(*[float(x) for x in eye])
+        _check(fa_visibility(self.h, ctypes.byref(mesh.c), ctypes.byref(cam), e, float(near),
+                             int(coarse), _ptr(out), _stream_handle(stream)), "fa_visibility")
+        return out
 
     def build_atlas(self, mesh: Mesh, visible, view_proj, width, height, atlas_size, rate,
                     out: AtlasOutputs = None, stream=None):

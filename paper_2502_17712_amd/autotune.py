@@ -12,17 +12,19 @@ import json
 
 import torch
 
-from . import (FA_TUNE_OCC_SMALL_TEXELS, FA_TUNE_PACK_BLOCK, FA_TUNE_UF_EDGE_HOOKS,
-               FA_TUNE_UF_LINK_INIT, AtlasOutputs, Context)
+from . import (FA_TUNE_OCC_LANE_TEXELS, FA_TUNE_OCC_SMALL_TEXELS, FA_TUNE_PACK_BLOCK,
+               FA_TUNE_UF_EDGE_HOOKS, FA_TUNE_UF_LINK_INIT, AtlasOutputs, Context)
 
 KNOBS = {
     FA_TUNE_OCC_SMALL_TEXELS: [64, 128, 256, 512, 1024],
+    FA_TUNE_OCC_LANE_TEXELS: [8, 16, 32, 64, 128],
     FA_TUNE_UF_LINK_INIT: [1, 0],
-    FA_TUNE_UF_EDGE_HOOKS: [1, 0],
+    FA_TUNE_UF_EDGE_HOOKS: [2, 1, 0],
     FA_TUNE_PACK_BLOCK: [256, 512, 1024],
 }
 NAMES = {FA_TUNE_PACK_BLOCK: "pack_block", FA_TUNE_OCC_SMALL_TEXELS: "occ_small_texels",
-         FA_TUNE_UF_LINK_INIT: "uf_link_init", FA_TUNE_UF_EDGE_HOOKS: "uf_edge_hooks"}
+         FA_TUNE_UF_LINK_INIT: "uf_link_init", FA_TUNE_UF_EDGE_HOOKS: "uf_edge_hooks",
+         FA_TUNE_OCC_LANE_TEXELS: "occ_lane_texels"}
 
 
 def _snapshot(out: AtlasOutputs):

@@ -21,7 +21,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfastatlas.so")
 
-SOURCES = ["k_charts.hip", "k_sort.hip", "k_pack.hip", "k_raster.hip", "fa_runtime.hip"]
+SOURCES = ["k_charts.hip", "k_sort.hip", "k_pack.hip", "k_raster.hip", "k_visibility.hip",
+           "fa_runtime.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -40,6 +40,15 @@ struct FrameState {
   unsigned long long occupied;
 };
 
+// Constants of one visibility pass, passed by value (float64).
+struct VisParams {
+  double M[16];   // view_proj, row-major
+  double eye[3];  // camera position
+  double near_w;  // w at the near plane
+  int32_t Wc, Hc; // depth-buffer samples per row and column
+  int32_t coarse; // 0: facing and frustum only
+};
+
 // Per-frame constants passed by value.
 struct FrameParams {
   float M[16];
@@ -49,7 +58,7 @@ struct FrameParams {
   int32_t J, gutter, min_box;
   uint32_t flags;
   int32_t max_charts;
-  int32_t edge_hooks;  // run the edge-hook pass of the union-find
+  int32_t edge_hooks;  // edge hooks of the union-find: 0 none, 1 global, 2 per tile in LDS
 };
 
 // Scratch buffers of one context (sized by the capacities).
@@ -78,6 +87,9 @@ struct Work {
   unsigned long long* big_counter; // [1] queued footprints << 40 | queued tiles
   unsigned long long* partial;     // [kCountGrid] per-block partial counts
   fa_chart* pack_charts; // [max_charts] chart records of the packer-only entry
+  int32_t* cand_rs;      // [J][max_charts + 1] row starts of each candidate (frames above
+                         // the LDS capacity of the packer)
+  int4* chart_tex;       // [max_charts] texel range of each placed box (lo_x, hi_x, lo_y, hi_y)
   FrameState* state;     // [1]
 };
 
@@ -204,7 +216,7 @@ struct Marker {
 
 hipError_t launch_prologue(const float* pos, int64_t V, const uint8_t* vis, const int32_t* nbr,
                            int64_t T, const FrameParams& p, const Work& w, int32_t* cov,
-                           int32_t* cot, int uf_link_init, hipStream_t st);
+                           int32_t* cot, int uf_init, Marker& mk, hipStream_t st);
 hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* nbr, int64_t T,
                          const FrameParams& p, const Work& w, int32_t* cot, int32_t* cov,
                          fa_chart* charts, Marker& mk, hipStream_t st);
@@ -217,8 +229,11 @@ hipError_t launch_uv(const int64_t V, const FrameParams& p, const Work& w, const
                      const fa_chart* charts, float* uv, hipStream_t st);
 hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
                             const int32_t* cot, const fa_chart* charts, int32_t* occ,
-                            int small_texels, Marker& mk, hipStream_t st);
+                            int small_texels, int lane_texels, Marker& mk, hipStream_t st);
 unsigned visible_grid(int64_t T);  // blocks of the kernels that walk the visible list
+hipError_t launch_visibility(const float* pos, const int32_t* idx, int64_t T, const VisParams& q,
+                             int32_t* occl, uint32_t* count, unsigned long long* depth,
+                             uint8_t* vis, hipStream_t st);
 hipError_t launch_meta(const FrameParams& p, const Work& w, fa_atlas_meta* meta,
                        int with_occupancy, hipStream_t st);
 

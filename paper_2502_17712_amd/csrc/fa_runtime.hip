@@ -22,7 +22,7 @@ struct Scene {
   int64_t T = 0, V = 0;
 };
 
-enum { kStages = 16 };
+enum { kStages = 19 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -56,9 +56,16 @@ struct fa_ctx {
   int ev_marks = 0;
   int pack_block = 256;
   int small_texels = 256;
+  int lane_texels = 32;
   int uf_link_init = 1;
-  int uf_edge_hooks = 1;
+  int uf_edge_hooks = 2;
   int32_t* check_flag = nullptr;  // device int for index validation
+  // visibility pass scratch: occluder list [max_triangles] + its counter, and
+  // a depth buffer that grows to the largest grid asked for
+  int32_t* vis_list = nullptr;
+  uint32_t* vis_count = nullptr;
+  unsigned long long* vis_depth = nullptr;
+  int64_t vis_depth_cap = 0;
 };
 
 namespace {
@@ -140,7 +147,8 @@ int fa_create(const fa_config* cfg_in, fa_ctx** out_ctx) {
         {(void**)&w.vlist, 4 * T},               {(void**)&w.tile_voff, 4 * tiles},
         {(void**)&w.big, 16 * std::min<size_t>(2 * T, size_t(1) << 24)},
         {(void**)&w.big_counter, 8},             {(void**)&w.partial, 8 * kCountGrid},
-        {(void**)&w.pack_charts, sizeof(fa_chart) * C},
+        {(void**)&w.pack_charts, sizeof(fa_chart) * C}, {(void**)&w.chart_tex, 16 * C},
+        {(void**)&w.cand_rs, 4 * J * (C + 1)},
         {(void**)&w.state, sizeof(FrameState)}};
     size_t total = 0;
     for (auto& p : parts) total += align_up(p.bytes);
@@ -199,6 +207,9 @@ void fa_destroy(fa_ctx* ctx) {
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   for (void* a : ctx->arenas) (void)hipFree(a);
   if (ctx->check_flag) (void)hipFree(ctx->check_flag);
+  if (ctx->vis_list) (void)hipFree(ctx->vis_list);
+  if (ctx->vis_count) (void)hipFree(ctx->vis_count);
+  if (ctx->vis_depth) (void)hipFree(ctx->vis_depth);
   delete ctx;
 }
 
@@ -282,6 +293,55 @@ int fa_scene_adjacency(fa_ctx* ctx, const fa_mesh* mesh, int32_t* nbr_out, void*
   return FA_OK;
 }
 
+int fa_visibility(fa_ctx* ctx, const fa_mesh* mesh, const fa_camera* cam, const double* eye,
+                  double near_w, int32_t coarse, uint8_t* visible, void* stream) {
+  if (!ctx || !cam || !eye) return FA_ERR_INVALID_ARG;
+  int rc = check_mesh(ctx, mesh);
+  if (rc) return rc;
+  if (!visible && mesh->num_triangles > 0) return FA_ERR_INVALID_ARG;
+  if (cam->width < 1 || cam->width > 16384 || cam->height < 1 || cam->height > 16384)
+    return FA_ERR_INVALID_ARG;
+  if (coarse < 0 || coarse > 64 || !(near_w > 0.0) || !std::isfinite(near_w))
+    return FA_ERR_INVALID_ARG;
+  VisParams q{};
+  for (int i = 0; i < 16; ++i) {
+    if (!std::isfinite(cam->view_proj[i])) return FA_ERR_INVALID_ARG;
+    q.M[i] = (double)cam->view_proj[i];
+  }
+  for (int k = 0; k < 3; ++k) {
+    if (!std::isfinite(eye[k])) return FA_ERR_INVALID_ARG;
+    q.eye[k] = eye[k];
+  }
+  q.near_w = near_w;
+  q.Wc = coarse > 0 ? cam->width / coarse : 0;
+  q.Hc = coarse > 0 ? cam->height / coarse : 0;
+  q.coarse = (q.Wc > 0 && q.Hc > 0) ? coarse : 0;
+  if (hipSetDevice(ctx->cfg.device) != hipSuccess) return FA_ERR_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  Scene* sc = nullptr;  // validates the indices once per scene
+  rc = get_scene(ctx, mesh, st, &sc);
+  if (rc) return rc;
+  if (!ctx->vis_list) {
+    const size_t T = (size_t)std::max<int64_t>(ctx->cfg.max_triangles, 1);
+    if (hipMalloc(&ctx->vis_list, 4 * T) != hipSuccess ||
+        hipMalloc(&ctx->vis_count, 4) != hipSuccess)
+      return FA_ERR_OUT_OF_MEMORY;
+  }
+  const int64_t nd = (int64_t)q.Wc * q.Hc;
+  if (nd > ctx->vis_depth_cap) {
+    (void)hipStreamSynchronize(st);
+    if (ctx->vis_depth) (void)hipFree(ctx->vis_depth);
+    ctx->vis_depth = nullptr;
+    ctx->vis_depth_cap = 0;
+    if (hipMalloc(&ctx->vis_depth, 8 * (size_t)nd) != hipSuccess) return FA_ERR_OUT_OF_MEMORY;
+    ctx->vis_depth_cap = nd;
+  }
+  if (launch_visibility(mesh->positions, mesh->indices, mesh->num_triangles, q, ctx->vis_list,
+                        ctx->vis_count, ctx->vis_depth, visible, st) != hipSuccess)
+    return FA_ERR_DEVICE;
+  return FA_OK;
+}
+
 int fa_scene_evict(fa_ctx* ctx, uint64_t scene_key) {
   if (!ctx) return FA_ERR_INVALID_ARG;
   auto it = ctx->scenes.find(scene_key);
@@ -328,15 +388,12 @@ static int run_frame(fa_ctx* ctx, const Work& w, const fa_mesh* mesh, Scene* sc,
   int32_t* cov = out->chart_of_vert ? out->chart_of_vert : w.cov;
   hipError_t e = hipSuccess;
   auto ok = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
-  // per-kernel events: prologue, uf_hook, uf_vertex_hook, uf_flatten, scan_tiles,
-  // assign_roots, gather_boxes, sizes_order, pack, select_place, uv, occ_fill,
-  // occ_small, occ_big, occ_count, meta
+  // one event after every kernel (names in order: fa_stage_times)
   Marker mk;
   if (ctx->timing) { mk.ev = ctx->ev; mk.cap = kStages + 1; }
   mk(st);
   ok(launch_prologue(mesh->positions, V, visible, sc->nbr, T, p, w, cov, out->chart_of_tri,
-                     ctx->uf_link_init, st));
-  mk(st);
+                     p.edge_hooks == 2 ? 0 : (ctx->uf_link_init ? 2 : 1), mk, st));
   ok(launch_charts(visible, mesh->indices, sc->nbr, T, p, w, out->chart_of_tri, cov, out->charts,
                    mk, st));
   ok(launch_order(p, w, out->charts, 1, st));
@@ -349,7 +406,7 @@ static int run_frame(fa_ctx* ctx, const Work& w, const fa_mesh* mesh, Scene* sc,
   mk(st);
   if (out->occupancy)
     ok(launch_occupancy(mesh->indices, T, p, w, out->chart_of_tri, out->charts, out->occupancy,
-                        ctx->small_texels, mk, st));
+                        ctx->small_texels, ctx->lane_texels, mk, st));
   ok(launch_meta(p, w, out->meta, out->occupancy != nullptr, st));
   mk(st);
   ctx->ev_marks = mk.n;
@@ -507,8 +564,12 @@ int fa_set_tuning(fa_ctx* ctx, int knob, int value) {
       ctx->batch_graph = value;
       return FA_OK;
     case FA_TUNE_UF_EDGE_HOOKS:
-      if (value != 0 && value != 1) return FA_ERR_INVALID_ARG;
+      if (value < 0 || value > 2) return FA_ERR_INVALID_ARG;
       ctx->uf_edge_hooks = value;
+      return FA_OK;
+    case FA_TUNE_OCC_LANE_TEXELS:
+      if (value < 0 || value > 4096) return FA_ERR_INVALID_ARG;
+      ctx->lane_texels = value;
       return FA_OK;
     default:
       return FA_ERR_INVALID_ARG;
@@ -523,6 +584,7 @@ int fa_get_tuning(fa_ctx* ctx, int knob) {
     case FA_TUNE_UF_LINK_INIT: return ctx->uf_link_init;
     case FA_TUNE_BATCH_GRAPH: return ctx->batch_graph;
     case FA_TUNE_UF_EDGE_HOOKS: return ctx->uf_edge_hooks;
+    case FA_TUNE_OCC_LANE_TEXELS: return ctx->lane_texels;
     default: return -1;
   }
 }

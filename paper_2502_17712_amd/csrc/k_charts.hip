@@ -54,15 +54,16 @@ __device__ __forceinline__ void uf_join(int32_t* parent, int u, int v) {
 // (clip = M (x, y, z, 1)^T, rows summed left to right), per-vertex scratch,
 // chart_of_tri = -1, the union-find start of every visible triangle and the
 // visible count of every tile of kTriTile triangles. Blocks [0, vblocks)
-// handle vertices, the rest triangle tiles. With link_neighbours a visible
-// triangle starts linked to the smallest of itself and its visible edge
-// neighbours (Alg. 1, first loop); otherwise as its own root (same labels).
+// handle vertices, the rest triangle tiles. uf_init 2: a visible triangle
+// starts linked to the smallest of itself and its visible edge neighbours
+// (Alg. 1, first loop); 1: as its own root (same labels); 0: not written (a
+// later pass writes it).
 __global__ void k_prologue(const float* __restrict__ pos, int64_t V, FrameParams p,
                            float4* __restrict__ clip, int32_t* __restrict__ vmin,
                            int32_t* __restrict__ cov, const uint8_t* __restrict__ vis,
                            const int32_t* __restrict__ nbr, int64_t T,
                            int32_t* __restrict__ parent, int32_t* __restrict__ cot,
-                           uint32_t* __restrict__ tile_vis, int link_neighbours,
+                           uint32_t* __restrict__ tile_vis, int uf_init,
                            unsigned vblocks, FrameState* st,
                            unsigned long long* __restrict__ big_counter) {
   __shared__ uint32_t sh[kBlock / kWave];
@@ -100,14 +101,14 @@ __global__ void k_prologue(const float* __restrict__ pos, int64_t V, FrameParams
     if (!vis[t]) continue;
     ++nv;
     int q = (int)t;
-    if (link_neighbours) {
+    if (uf_init == 2) {
 #pragma unroll
       for (int e = 0; e < 3; ++e) {
         const int n = nbr[3 * t + e];
         if (n >= 0 && vis[n]) q = min(q, n);
       }
     }
-    parent[t] = q;
+    if (uf_init) parent[t] = q;
   }
   nv = block_sum<uint32_t>(nv, sh);
   if (threadIdx.x == 0) tile_vis[tile] = nv;
@@ -171,6 +172,78 @@ __global__ void k_uf_hook(const uint8_t* __restrict__ vis, const int32_t* __rest
       if (n > t && vis[n]) uf_join(parent, t, n);
     }
   }
+}
+
+// Edge hooks inside one tile of kUfTile consecutive entries of the visible
+// list, in LDS: entries are local indices (ascending with the triangle index),
+// a shared edge whose other triangle lies in the tile joins the two local sets
+// (larger local root hooked below the smaller by compare-and-swap). Then every
+// entry's parent becomes the smallest triangle of its local set, which is a
+// valid union-find start for the vertex passes; edges leaving the tile are
+// shared vertices too, so those passes complete the charts.
+constexpr int kUfTile = 2048;
+constexpr int kUfThreads = 512;
+
+__device__ __forceinline__ int lds_get(int* a, int i) {
+  return __hip_atomic_load(&a[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_put(int* a, int i, int v) {
+  __hip_atomic_store(&a[i], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ int lds_root(int* lp, int x) {
+  int p = lds_get(lp, x);
+  while (p != x) {  // path splitting
+    const int gp = lds_get(lp, p);
+    if (gp != p) lds_put(lp, x, gp);
+    x = p;
+    p = gp;
+  }
+  return x;
+}
+__device__ __forceinline__ void lds_join(int* lp, int a, int b) {
+  int ra = lds_root(lp, a), rb = lds_root(lp, b);
+  while (ra != rb) {
+    if (ra > rb) { const int s = ra; ra = rb; rb = s; }
+    const int old = atomicCAS(&lp[rb], rb, ra);
+    if (old == rb) return;
+    rb = lds_root(lp, old);
+  }
+}
+
+__global__ __launch_bounds__(kUfThreads) void k_uf_local(const uint8_t* __restrict__ vis,
+                                                         const int32_t* __restrict__ nbr,
+                                                         const int32_t* __restrict__ vlist,
+                                                         int32_t* __restrict__ parent,
+                                                         const FrameState* __restrict__ st) {
+  __shared__ int lv[kUfTile];
+  __shared__ int lp[kUfTile];
+  const int nv = st->visible;
+  const int64_t s0 = (int64_t)blockIdx.x * kUfTile;
+  if (s0 >= nv) return;
+  const int cnt = (int)min<int64_t>(kUfTile, nv - s0);
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    lv[i] = vlist[s0 + i];
+    lp[i] = i;
+  }
+  __syncthreads();
+  const int last = lv[cnt - 1];
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const int t = lv[i];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const int n = nbr[3 * (int64_t)t + e];
+      if (n > t && n <= last && vis[n]) {
+        int lo = i + 1, hi = cnt - 1;  // n is in lv[lo..hi]
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (lv[mid] < n) lo = mid + 1; else hi = mid;
+        }
+        lds_join(lp, i, lo);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) parent[lv[i]] = lv[lds_root(lp, i)];
 }
 
 // Vertex minimum (Alg. 1, third loop): every visible triangle is compressed
@@ -394,11 +467,13 @@ __device__ __forceinline__ bool triangle_ndc_box(const float4& a, const float4& 
 
 // Gather: chart of every visible triangle and its vertices, and the chart's
 // box as the union of its triangles' boxes. Each thread handles kGatherItems
-// entries of the visible list; lanes of a wave with the same chart are
-// reduced in registers, then merged into a small per-workgroup table in LDS,
-// and only the table is flushed with global atomics (large charts would
-// otherwise serialize on their four accumulator words).
-constexpr int kGatherItems = 8;
+// entries of the visible list, issuing the dependent loads of all its entries
+// level by level (list, root, chart and indices, clip vertices) so that their
+// latencies overlap; lanes of a wave with the same chart are reduced in
+// registers, then merged into a small per-workgroup table in LDS, and only the
+// table is flushed with global atomics (large charts would otherwise
+// serialize on their four accumulator words).
+constexpr int kGatherItems = 4;
 constexpr int kSlots = 64;
 
 __global__ __launch_bounds__(kBlock) void k_gather_boxes(
@@ -418,21 +493,38 @@ __global__ __launch_bounds__(kBlock) void k_gather_boxes(
     sbox[i][2] = sbox[i][3] = 0u;
   }
   __syncthreads();
+  int tv[kGatherItems], cv[kGatherItems], vi[kGatherItems][3];
+  float4 q[kGatherItems][3];
+#pragma unroll
   for (int k = 0; k < kGatherItems; ++k) {
     const int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
-    const bool valid = i < nv;
-    int c = -1;
+    tv[k] = i < nv ? vlist[i] : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < kGatherItems; ++k) cv[k] = tv[k] >= 0 ? parent[tv[k]] : 0;
+#pragma unroll
+  for (int k = 0; k < kGatherItems; ++k) {
+    const int t = max(tv[k], 0);
+    cv[k] = tv[k] >= 0 ? cot[cv[k]] : -1;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) vi[k][e] = tv[k] >= 0 ? idx[3 * (int64_t)t + e] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kGatherItems; ++k)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) q[k][e] = clip[vi[k][e]];
+#pragma unroll
+  for (int k = 0; k < kGatherItems; ++k) {
+    const bool valid = tv[k] >= 0;
+    const int c = cv[k];
     bool has = false;
     float4 box = make_float4(0.f, 0.f, 0.f, 0.f);
     if (valid) {
-      const int t = vlist[i];
-      c = cot[parent[t]];
-      cot[t] = c;
-      const int i0 = idx[3 * (int64_t)t], i1 = idx[3 * (int64_t)t + 1], i2 = idx[3 * (int64_t)t + 2];
-      cov[i0] = c;
-      cov[i1] = c;
-      cov[i2] = c;
-      has = triangle_ndc_box(clip[i0], clip[i1], clip[i2], !(flags & FA_FLAG_NO_SIDE_CLIP), box);
+      cot[tv[k]] = c;
+      cov[vi[k][0]] = c;
+      cov[vi[k][1]] = c;
+      cov[vi[k][2]] = c;
+      has = triangle_ndc_box(q[k][0], q[k][1], q[k][2], !(flags & FA_FLAG_NO_SIDE_CLIP), box);
     }
     const uint32_t e0 = ord_of(box.x), e1 = ord_of(box.y), e2 = ord_of(box.z), e3 = ord_of(box.w);
     unsigned long long todo = __ballot(has);
@@ -488,15 +580,18 @@ unsigned visible_grid(int64_t T) {
 
 hipError_t launch_prologue(const float* pos, int64_t V, const uint8_t* vis, const int32_t* nbr,
                            int64_t T, const FrameParams& p, const Work& w, int32_t* cov,
-                           int32_t* cot, int uf_link_init, hipStream_t st) {
+                           int32_t* cot, int uf_init, Marker& mk, hipStream_t st) {
   const unsigned vb = std::max(1u, grid_for(V, kBlock));
   const unsigned tt = grid_for(T, kTriTile);
   k_prologue<<<vb + tt, kBlock, 0, st>>>(pos, V, p, w.clip, w.vmin, cov, vis, nbr, T, w.parent,
-                                         cot, w.tile_vis, uf_link_init, vb, w.state,
+                                         cot, w.tile_vis, uf_init, vb, w.state,
                                          w.big_counter);
+  mk(st);
   k_scan_counts<<<1, 1024, 0, st>>>(w.tile_vis, w.tile_voff, nullptr, T, &w.state->visible, -1,
                                     w.state);
+  mk(st);
   if (T > 0) k_vis_compact<<<tt, kBlock, 0, st>>>(vis, T, w.tile_voff, w.vlist);
+  mk(st);
   return hipGetLastError();
 }
 
@@ -506,12 +601,21 @@ hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* 
   const unsigned g = visible_grid(T);
   const unsigned vt = std::max(1u, grid_for(T, kTriTile));
   if (T > 0) {
-    if (p.edge_hooks) k_uf_hook<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, w.state);
+    if (p.edge_hooks == 1)
+      k_uf_hook<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, w.state);
+    else if (p.edge_hooks == 2)
+      k_uf_local<<<std::max(1u, grid_for(T, kUfTile)), kUfThreads, 0, st>>>(vis, nbr, w.vlist,
+                                                                            w.parent, w.state);
+    mk(st);
     k_uf_vertex_min<<<g, kBlock, 0, st>>>(idx, w.vlist, w.parent, w.vmin, w.state);
     mk(st);
     k_uf_vertex_hook<<<g, kBlock, 0, st>>>(idx, w.vlist, w.parent, w.vmin, w.state);
     mk(st);
     k_uf_flatten_count<<<vt, kBlock, 0, st>>>(w.vlist, w.parent, w.tile_count, w.state);
+  } else {
+    mk(st);
+    mk(st);
+    mk(st);
   }
   mk(st);
   k_scan_counts<<<1, 1024, 0, st>>>(w.tile_count, w.tile_off, &w.state->visible, T,
@@ -523,6 +627,8 @@ hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* 
     mk(st);
     k_gather_boxes<<<grid_for(T, kBlock * kGatherItems), kBlock, 0, st>>>(
         w.vlist, idx, w.parent, w.clip, cot, cov, w.accum, p.flags, w.state);
+  } else {
+    mk(st);
   }
   mk(st);
   return hipGetLastError();

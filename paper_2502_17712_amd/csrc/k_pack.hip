@@ -32,18 +32,18 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
                                              long long* __restrict__ cand_x,
                                              uint32_t* __restrict__ cand_ab,
                                              int32_t* __restrict__ cand_y,
+                                             int32_t* __restrict__ cand_rs,
                                              int32_t* __restrict__ cand_tab, int64_t stride) {
-  extern __shared__ int32_t F[];  // [2 * omega] frontline, then the LDS copies of X and AB
-  __shared__ uint32_t marker[NT];
-  __shared__ int32_t bx[NT], ba[NT], bb[NT], ym[NT];
+  // [2 * omega] frontline, then the LDS copies of X, AB and the row starts
+  extern __shared__ int32_t F[];
   __shared__ long long sh64[NT / kWave];
   __shared__ int32_t sh32[NT / kWave];
-  __shared__ uint32_t shu[NT / kWave];
-  __shared__ int32_t Hsh;
+  __shared__ int32_t Hsh[2];
+  constexpr int NW = NT / kWave;
 
   if (st->status != FA_OK) return;
   const int j = blockIdx.x + 1;
-  const int tid = threadIdx.x, w = tid / kWave;
+  const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
   const int C = st->num_charts;
   const int omega = p.omega, lg = p.log2omega;
   long long* Xg = cand_x + (int64_t)(j - 1) * stride;
@@ -51,6 +51,7 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
   const bool in_lds = C <= kPackLds;
   long long* X = in_lds ? reinterpret_cast<long long*>(F + 2 * omega) : Xg;
   uint32_t* AB = in_lds ? reinterpret_cast<uint32_t*>(F + 2 * omega + 2 * kPackLds) : ABg;
+  int32_t* RS = in_lds ? F + 2 * omega + 3 * kPackLds : cand_rs + (int64_t)(j - 1) * (stride + 1);
   int32_t* Y = cand_y + (int64_t)(j - 1) * stride;
   int32_t* tab = cand_tab + (j - 1) * kCandStride;
   const float s = (float)j / (float)p.J;
@@ -100,103 +101,53 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
   }
   const int L = omega + (int)m;
 
-  // ---- push ----------------------------------------------------------------
+  // ---- row starts: first box of every non-empty row, in order --------------
+  int nr = 0;
+  for (int base = 0; base < C; base += NT) {
+    const int i = base + tid;
+    const int first = (i < C && (i == 0 || (X[i] >> lg) != (X[i - 1] >> lg))) ? 1 : 0;
+    int tot;
+    const int incl = block_incl_scan<int>(first, sh32, &tot);
+    if (first) RS[nr + incl - 1] = i;
+    nr += tot;
+  }
+  if (tid == 0) RS[nr] = C;
   for (int c = tid; c < L; c += NT) F[c] = 0;
-  marker[tid] = 0u;
-  if (tid == 0) Hsh = 0;
-  const int K = (L + NT - 1) / NT;  // columns per thread
-  const int c0 = tid * K, c1 = min(c0 + K, L);
+  if (tid < 2) Hsh[tid] = 0;
   __syncthreads();
 
-  long long sidx = 0;
-  uint32_t seq = 0;
-  while (sidx < C) {
-    const long long r = X[sidx] >> lg;
-    const long long row_end = (r + 1) << lg;
+  // ---- push: row by row; the boxes of a row have disjoint spans, so each
+  // wave takes whole boxes (a strided read-max, then a strided write) and
+  // one barrier per row orders the rows. The height test reads a slot that
+  // no wave can touch again before every wave has read it.
+  int Hw = 0;
+  for (int rr = 0; rr < nr; ++rr) {
+    const int s0 = RS[rr], s1 = RS[rr + 1];
+    const long long r = X[s0] >> lg;
     const bool right = (r % 3) != 0;
-    const long long i = sidx + tid;
-    long long Xi = 0;
-    bool inrow = false;
-    if (i < C) {
-      Xi = X[i];
-      inrow = Xi < row_end;
-    }
-    const int n = __syncthreads_count(inrow);
-    ++seq;
-    if (inrow) {
-      const uint32_t ab = AB[i];
+    for (int k = s0 + w; k < s1; k += NW) {
+      const long long Xk = X[k];
+      const uint32_t ab = AB[k];
       const int a = (int)(ab & 0xFFFFu), b = (int)(ab >> 16);
-      const int o = (int)(Xi - (r << lg));
+      const int o = (int)(Xk - (r << lg));
       const int x = right ? L - o - a : o;
-      bx[tid] = x;
-      ba[tid] = a;
-      bb[tid] = b;
-      ym[tid] = 0;
-      const int ci = (x + K - 1) / K;
-      if (ci < NT) atomicMax(&marker[ci], (seq << 12) | (uint32_t)(right ? 4095 - tid : tid));
+      int mx = 0;
+      for (int c = x + lane; c < x + a; c += kWave) mx = max(mx, F[c]);
+      const int y = wave_max<int>(mx);
+      for (int c = x + lane; c < x + a; c += kWave) F[c] = y + b;
+      if (lane == 0) Y[k] = y;
+      Hw = max(Hw, y + b);
     }
+    if (lane == 0) atomicMax(&Hsh[rr & 1], Hw);
     __syncthreads();
-    // box covering column c0: tagged inclusive max-scan of the start markers
-    uint32_t mk = wave_incl_max_scan<uint32_t>(marker[tid]);
-    if (lane_id() == kWave - 1) shu[w] = mk;
-    __syncthreads();
-    for (int k = 0; k < w; ++k) mk = max(mk, shu[k]);
-    const int step = right ? -1 : 1;
-    int k0;
-    if ((mk >> 12) == seq) {
-      const int lo = (int)(mk & 4095u);
-      k0 = right ? 4095 - lo : lo;
-    } else {
-      k0 = right ? n - 1 : 0;
-    }
-    {  // reads: per-box maximum of the frontline
-      int kk = k0;
-      bool ok = kk >= 0 && kk < n;
-      int bxk = ok ? bx[kk] : 0, bek = ok ? bxk + ba[kk] : 0;
-      int cur = -1;
-      for (int c = c0; c < c1; ++c) {
-        while (ok && c >= bek) {
-          if (cur >= 0) atomicMax(&ym[kk], cur);
-          cur = -1;
-          kk += step;
-          ok = kk >= 0 && kk < n;
-          if (ok) { bxk = bx[kk]; bek = bxk + ba[kk]; }
-        }
-        if (!ok) break;
-        if (c >= bxk) cur = max(cur, F[c]);
-      }
-      if (ok && cur >= 0) atomicMax(&ym[kk], cur);
-    }
-    __syncthreads();
-    {  // writes: raise the spans
-      int kk = k0;
-      bool ok = kk >= 0 && kk < n;
-      int bxk = ok ? bx[kk] : 0, bek = ok ? bxk + ba[kk] : 0;
-      int top = ok ? ym[kk] + bb[kk] : 0;
-      for (int c = c0; c < c1; ++c) {
-        while (ok && c >= bek) {
-          kk += step;
-          ok = kk >= 0 && kk < n;
-          if (ok) { bxk = bx[kk]; bek = bxk + ba[kk]; top = ym[kk] + bb[kk]; }
-        }
-        if (!ok) break;
-        if (c >= bxk) F[c] = top;
-      }
-    }
-    if (inrow) {
-      const int y = ym[tid];
-      Y[i] = y;
-      atomicMax(&Hsh, y + bb[tid]);
-    }
-    __syncthreads();
-    sidx += n;
-    if (Hsh > L) break;
+    if (Hsh[rr & 1] > L) break;
   }
   if (tid == 0) {
-    tab[0] = Hsh <= L ? 1 : 0;
+    const int H = nr > 0 ? max(Hsh[0], Hsh[1]) : 0;
+    tab[0] = H <= L ? 1 : 0;
     tab[1] = (int32_t)m;
     tab[2] = L;
-    tab[3] = Hsh;
+    tab[3] = H;
     tab[4] = (int32_t)min(rows, (long long)INT_MAX);
   }
 }
@@ -216,7 +167,8 @@ __global__ __launch_bounds__(kBlock) void k_select_place(
     FrameParams p, const int32_t* __restrict__ cand_tab, FrameState* st,
     int32_t* __restrict__ cand_out, const int32_t* __restrict__ order,
     const long long* __restrict__ cand_x, const uint32_t* __restrict__ cand_ab,
-    const int32_t* __restrict__ cand_y, int64_t stride, fa_chart* __restrict__ charts) {
+    const int32_t* __restrict__ cand_y, int64_t stride, fa_chart* __restrict__ charts,
+    int4* __restrict__ chart_tex) {
   __shared__ int sj, sL;
   const bool ok = st->status == FA_OK;
   const int C = st->num_charts;
@@ -267,10 +219,20 @@ __global__ __launch_bounds__(kBlock) void k_select_place(
   const long long r = Xi >> p.log2omega;
   const int o = (int)(Xi - (r << p.log2omega));
   fa_chart& ch = charts[order[i]];
-  ch.x = (r % 3 == 0) ? o : L - o - a;
-  ch.y = cand_y[(int64_t)jm * stride + i];
+  const int x = (r % 3 == 0) ? o : L - o - a, y = cand_y[(int64_t)jm * stride + i];
+  ch.x = x;
+  ch.y = y;
   ch.w = a;
   ch.h = b;
+  if (chart_tex) {
+    // texels t whose centre lies in the box: 2 x omega <= (2t+1) L < 2 (x+w) omega
+    const int64_t om = p.omega, L2 = 2 * (int64_t)L;
+    chart_tex[order[i]] = make_int4(
+        (int)ceil_div64(2 * (int64_t)x * om - L, L2),
+        (int)ceil_div64(2 * ((int64_t)x + a) * om - L, L2) - 1,
+        (int)ceil_div64(2 * (int64_t)y * om - L, L2),
+        (int)ceil_div64(2 * ((int64_t)y + b) * om - L, L2) - 1);
+  }
 }
 
 // ---- packer-only entry: box sizes in, placements out ---------------------
@@ -325,7 +287,7 @@ __global__ void k_pack_emit(int32_t n, const fa_chart* __restrict__ charts,
 }  // namespace
 
 hipError_t pack_kernel_attributes(int max_frontline_bytes) {
-  const int max_dyn_bytes = max_frontline_bytes + kPackLds * 12;
+  const int max_dyn_bytes = max_frontline_bytes + kPackLds * 16 + 4;
   hipError_t e = hipFuncSetAttribute((const void*)k_pack<256>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn_bytes);
   if (e != hipSuccess) return e;
@@ -337,17 +299,17 @@ hipError_t pack_kernel_attributes(int max_frontline_bytes) {
 }
 
 hipError_t launch_pack(const FrameParams& p, const Work& w, int block, hipStream_t st) {
-  const size_t dyn = (size_t)2 * p.omega * sizeof(int32_t) + (size_t)kPackLds * 12;
+  const size_t dyn = (size_t)2 * p.omega * sizeof(int32_t) + (size_t)kPackLds * 16 + 4;
   const int64_t stride = p.max_charts;
   if (block == 1024)
     k_pack<1024><<<p.J, 1024, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab, w.cand_y,
-                                         w.cand_tab, stride);
+                                         w.cand_rs, w.cand_tab, stride);
   else if (block == 512)
     k_pack<512><<<p.J, 512, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab, w.cand_y,
-                                       w.cand_tab, stride);
+                                       w.cand_rs, w.cand_tab, stride);
   else
     k_pack<256><<<p.J, 256, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab, w.cand_y,
-                                       w.cand_tab, stride);
+                                       w.cand_rs, w.cand_tab, stride);
   return hipGetLastError();
 }
 
@@ -355,7 +317,7 @@ hipError_t launch_select_place(const FrameParams& p, const Work& w, fa_chart* ch
                                int32_t* cand_out, hipStream_t st) {
   k_select_place<<<(unsigned)((p.max_charts + kBlock - 1) / kBlock), kBlock, 0, st>>>(
       p, w.cand_tab, w.state, cand_out, w.vals_a, w.cand_x, w.cand_ab, w.cand_y, p.max_charts,
-      charts);
+      charts, w.chart_tex);
   return hipGetLastError();
 }
 

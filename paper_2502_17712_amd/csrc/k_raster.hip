@@ -8,8 +8,8 @@
 // c's visible triangles mapped to the atlas (near-clipped when the triangle
 // crosses the near plane), snapped to 1/256 texel with round-to-nearest-even,
 // fan-triangulated from the first vertex, edges inclusive. Small footprints
-// are rasterized by one thread; large ones are queued and rasterized by a
-// whole workgroup each.
+// are rasterized by one lane, medium ones by their wave, large ones are queued
+// and cut into 16x16 tiles shared by all waves.
 #include <algorithm>
 
 #include "fa_internal.h"
@@ -66,10 +66,11 @@ __global__ void k_uv(int64_t V, FrameParams p, const float4* __restrict__ clip,
 // occupancy
 // ---------------------------------------------------------------------------
 struct Footprint {
-  int64_t ax, ay, bx, by, cx, cy;  // snapped vertices (1/256 texel)
-  int64_t area;
-  int tx0, tx1, ty0, ty1;          // inclusive texel range to test (may be empty)
+  int32_t ax, ay;          // vertex a (1/256 texel)
+  int32_t bx, by, cx, cy;  // vertices b and c relative to a
+  int tx0, tx1, ty0, ty1;  // inclusive texel range to test (non-empty)
   int chart;
+  int neg;                 // signed area < 0
 };
 
 template <int P>
@@ -118,9 +119,9 @@ __device__ __forceinline__ int32_t snap(float u) {
 }
 
 // The near-clipped polygon of visible triangle t mapped to snapped atlas
-// coordinates (1/256 texel); n = 0 when the triangle claims nothing.
+// coordinates (1/256 texel, |value| <= 2^28); n = 0 when it claims nothing.
 struct SnapPoly {
-  int64_t u[4], v[4];
+  int32_t u[4], v[4];
   int n;
   int chart;
 };
@@ -160,31 +161,30 @@ __device__ __forceinline__ void snap_polygon(int64_t t, const int32_t* __restric
   sp.n = n;
 }
 
-// Fan triangle f (0 or 1) of a snapped polygon: vertices 0, f+1, f+2.
-__device__ __forceinline__ bool fan_footprint(const SnapPoly& sp, int f, const fa_chart& ch,
-                                              const FrameParams& p, const FrameState& st,
+// Fan triangle f (0 or 1) of a snapped polygon: vertices 0, f+1, f+2, with
+// its texel range: texel centres (256 t + 128) inside the bounding box of the
+// snapped triangle and inside the chart's placed box (`box` = lo_x, hi_x,
+// lo_y, hi_y, the exact integer membership range of the box).
+__device__ __forceinline__ bool fan_footprint(const SnapPoly& sp, int f, const int4 box, int omega,
                                               Footprint& fp) {
   if (f + 2 >= sp.n) return false;
-  fp.ax = sp.u[0]; fp.ay = sp.v[0];
-  fp.bx = sp.u[f + 1]; fp.by = sp.v[f + 1];
-  fp.cx = sp.u[f + 2]; fp.cy = sp.v[f + 2];
-  fp.area = (fp.bx - fp.ax) * (fp.cy - fp.ay) - (fp.by - fp.ay) * (fp.cx - fp.ax);
-  if (fp.area == 0) return false;
-  // texel range of the placed box: 2*x*omega <= (2t+1)*L < 2*(x+w)*omega
-  const int64_t om = p.omega, L = st.layout_w;
-  int64_t lo_x = ceil_div64(2 * (int64_t)ch.x * om - L, 2 * L);
-  int64_t hi_x = ceil_div64(2 * ((int64_t)ch.x + ch.w) * om - L, 2 * L) - 1;
-  int64_t lo_y = ceil_div64(2 * (int64_t)ch.y * om - L, 2 * L);
-  int64_t hi_y = ceil_div64(2 * ((int64_t)ch.y + ch.h) * om - L, 2 * L) - 1;
-  // texel centres 256*t + 128 inside the bounding box of the snapped triangle
-  const int64_t umin = min(fp.ax, min(fp.bx, fp.cx)), umax = max(fp.ax, max(fp.bx, fp.cx));
-  const int64_t vmin = min(fp.ay, min(fp.by, fp.cy)), vmax = max(fp.ay, max(fp.by, fp.cy));
-  lo_x = max(lo_x, max((int64_t)0, floor_div64(umin - 128 + 255, 256)));
-  hi_x = min(hi_x, min(om - 1, floor_div64(umax - 128, 256)));
-  lo_y = max(lo_y, max((int64_t)0, floor_div64(vmin - 128 + 255, 256)));
-  hi_y = min(hi_y, min(om - 1, floor_div64(vmax - 128, 256)));
+  const int32_t ax = sp.u[0], ay = sp.v[0];
+  const int32_t ub = sp.u[f + 1], vb = sp.v[f + 1], uc = sp.u[f + 2], vc = sp.v[f + 2];
+  fp.ax = ax; fp.ay = ay;
+  fp.bx = ub - ax; fp.by = vb - ay;
+  fp.cx = uc - ax; fp.cy = vc - ay;
+  const int64_t area = (int64_t)fp.bx * fp.cy - (int64_t)fp.by * fp.cx;
+  if (area == 0) return false;
+  fp.neg = area < 0;
+  const int32_t umin = min(ax, min(ub, uc)), umax = max(ax, max(ub, uc));
+  const int32_t vmin = min(ay, min(vb, vc)), vmax = max(ay, max(vb, vc));
+  // ceil((x - 128) / 256) and floor((x - 128) / 256) as arithmetic shifts
+  const int lo_x = max(box.x, max(0, (umin + 127) >> 8));
+  const int hi_x = min(box.y, min(omega - 1, (umax - 128) >> 8));
+  const int lo_y = max(box.z, max(0, (vmin + 127) >> 8));
+  const int hi_y = min(box.w, min(omega - 1, (vmax - 128) >> 8));
   if (lo_x > hi_x || lo_y > hi_y) return false;
-  fp.tx0 = (int)lo_x; fp.tx1 = (int)hi_x; fp.ty0 = (int)lo_y; fp.ty1 = (int)hi_y;
+  fp.tx0 = lo_x; fp.tx1 = hi_x; fp.ty0 = lo_y; fp.ty1 = hi_y;
   fp.chart = sp.chart;
   return true;
 }
@@ -193,20 +193,46 @@ __device__ __forceinline__ bool footprint(int64_t t, int f, const int32_t* __res
                                           const float4* __restrict__ clip,
                                           const int32_t* __restrict__ cot,
                                           const fa_chart* __restrict__ charts,
+                                          const int4* __restrict__ chart_tex,
                                           const FrameParams& p, const FrameState& st,
                                           Footprint& fp) {
   SnapPoly sp;
   snap_polygon(t, idx, clip, cot, charts, p, st, sp);
   if (sp.n == 0) return false;
-  return fan_footprint(sp, f, charts[sp.chart], p, st, fp);
+  return fan_footprint(sp, f, chart_tex[sp.chart], p.omega, fp);
 }
 
-__device__ __forceinline__ bool covers(const Footprint& fp, int tx, int ty) {
-  const int64_t px = 256 * (int64_t)tx + 128, py = 256 * (int64_t)ty + 128;
-  const int64_t e0 = (fp.bx - fp.ax) * (py - fp.ay) - (fp.by - fp.ay) * (px - fp.ax);
-  const int64_t e1 = (fp.cx - fp.bx) * (py - fp.by) - (fp.cy - fp.by) * (px - fp.bx);
-  const int64_t e2 = (fp.ax - fp.cx) * (py - fp.cy) - (fp.ay - fp.cy) * (px - fp.cx);
-  return fp.area > 0 ? (e0 >= 0 && e1 >= 0 && e2 >= 0) : (e0 <= 0 && e1 <= 0 && e2 <= 0);
+// The three edge functions at the centre of texel (tx, ty), exact in 64-bit
+// integers (inputs within 2^31, products within 2^61), negated when the
+// triangle is clockwise so that "covered" is always "all three >= 0":
+//   e0 = (b-a) x (p-a), e1 = (c-b) x (p-b), e2 = (a-c) x (p-c).
+struct Edges {
+  int64_t e0, e1, e2;
+};
+__device__ __forceinline__ Edges edges_at(const Footprint& fp, int tx, int ty) {
+  const int32_t px = 256 * tx + 128 - fp.ax, py = 256 * ty + 128 - fp.ay;
+  Edges e;
+  e.e0 = (int64_t)fp.bx * py - (int64_t)fp.by * px;
+  e.e1 = (int64_t)(fp.cx - fp.bx) * (py - fp.by) - (int64_t)(fp.cy - fp.by) * (px - fp.bx);
+  e.e2 = (int64_t)fp.cy * px - (int64_t)fp.cx * py;
+  if (fp.neg) { e.e0 = -e.e0; e.e1 = -e.e1; e.e2 = -e.e2; }
+  return e;
+}
+// change of the edge functions per texel step in x and in y
+__device__ __forceinline__ Edges step_x(const Footprint& fp) {
+  const int64_t s = fp.neg ? -256 : 256;
+  return Edges{-s * fp.by, -s * (fp.cy - fp.by), s * fp.cy};
+}
+__device__ __forceinline__ Edges step_y(const Footprint& fp) {
+  const int64_t s = fp.neg ? -256 : 256;
+  return Edges{s * fp.bx, s * (fp.cx - fp.bx), -s * fp.cx};
+}
+__device__ __forceinline__ bool inside(const Edges& e) { return (e.e0 | e.e1 | e.e2) >= 0; }
+__device__ __forceinline__ void add(Edges& e, const Edges& d) {
+  e.e0 += d.e0; e.e1 += d.e1; e.e2 += d.e2;
+}
+__device__ __forceinline__ Edges madd(const Edges& a, int64_t k, const Edges& b) {
+  return Edges{a.e0 + k * b.e0, a.e1 + k * b.e1, a.e2 + k * b.e2};
 }
 
 __global__ void k_occ_fill(int4* __restrict__ occ, int64_t n4, const FrameState* __restrict__ st) {
@@ -216,49 +242,69 @@ __global__ void k_occ_fill(int4* __restrict__ occ, int64_t n4, const FrameState*
     occ[i] = neg;
 }
 
-// Texel tests of a small footprint by one thread. When every snapped vertex
-// lies within 2^13 units of the first one, all edge functions at texel
-// centres of the (clipped) range fit in 32 bits.
-__device__ __forceinline__ void raster_thread(const Footprint& fp, int32_t* __restrict__ occ,
-                                              int omega) {
-  const int64_t du = max(llabs(fp.bx - fp.ax), llabs(fp.cx - fp.ax));
-  const int64_t dv = max(llabs(fp.by - fp.ay), llabs(fp.cy - fp.ay));
-  const int64_t ox = 256 * (int64_t)fp.tx0 + 128 - fp.ax, oy = 256 * (int64_t)fp.ty0 + 128 - fp.ay;
-  const bool narrow = du < 8192 && dv < 8192 && llabs(ox) < 8192 && llabs(oy) < 8192 &&
-                      (fp.tx1 - fp.tx0) < 32 && (fp.ty1 - fp.ty0) < 32;
-  if (narrow) {
-    // coordinates relative to vertex a: |values| < 2^14 * 2^14 * 2
-    const int bx = (int)(fp.bx - fp.ax), by = (int)(fp.by - fp.ay);
-    const int cx = (int)(fp.cx - fp.ax), cy = (int)(fp.cy - fp.ay);
-    const bool pos = fp.area > 0;
-    for (int ty = fp.ty0; ty <= fp.ty1; ++ty) {
-      const int py = (int)(256 * (int64_t)ty + 128 - fp.ay);
-      for (int tx = fp.tx0; tx <= fp.tx1; ++tx) {
-        const int px = (int)(256 * (int64_t)tx + 128 - fp.ax);
-        const int e0 = bx * py - by * px;
-        const int e1 = (cx - bx) * (py - by) - (cy - by) * (px - bx);
-        const int e2 = (0 - cx) * (py - cy) - (0 - cy) * (px - cx);
-        const bool in = pos ? (e0 >= 0 && e1 >= 0 && e2 >= 0) : (e0 <= 0 && e1 <= 0 && e2 <= 0);
-        if (in) occ[(int64_t)ty * omega + tx] = fp.chart;
-      }
+// All texels of a footprint by one lane, row by row, edge functions stepped.
+__device__ __forceinline__ void raster_lane(const Footprint& fp, int32_t* __restrict__ occ,
+                                            int omega) {
+  Edges r = edges_at(fp, fp.tx0, fp.ty0);
+  const Edges dx = step_x(fp), dy = step_y(fp);
+  for (int ty = fp.ty0; ty <= fp.ty1; ++ty) {
+    int32_t* row = occ + (int64_t)ty * omega;
+    Edges e = r;
+    for (int tx = fp.tx0; tx <= fp.tx1; ++tx) {
+      if (inside(e)) row[tx] = fp.chart;
+      add(e, dx);
     }
-    return;
+    add(r, dy);
   }
-  for (int ty = fp.ty0; ty <= fp.ty1; ++ty)
-    for (int tx = fp.tx0; tx <= fp.tx1; ++tx)
-      if (covers(fp, tx, ty)) occ[(int64_t)ty * omega + tx] = fp.chart;
+}
+
+__device__ __forceinline__ int rl(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+// All texels of lane src's footprint by the whole wave: lane k takes texels
+// k, k+64, ... of the range in row-major order.
+__device__ __forceinline__ void raster_wave(const Footprint& mine, int src,
+                                            int32_t* __restrict__ occ, int omega) {
+  Footprint fp;
+  fp.ax = rl(mine.ax, src); fp.ay = rl(mine.ay, src);
+  fp.bx = rl(mine.bx, src); fp.by = rl(mine.by, src);
+  fp.cx = rl(mine.cx, src); fp.cy = rl(mine.cy, src);
+  fp.tx0 = rl(mine.tx0, src); fp.tx1 = rl(mine.tx1, src);
+  fp.ty0 = rl(mine.ty0, src); fp.ty1 = rl(mine.ty1, src);
+  fp.chart = rl(mine.chart, src); fp.neg = rl(mine.neg, src);
+  const int nx = fp.tx1 - fp.tx0 + 1, n = nx * (fp.ty1 - fp.ty0 + 1);
+  const int lane = lane_id();
+  int col = lane % nx, row = lane / nx;
+  const int dcol = kWave % nx, drow = kWave / nx;
+  const Edges dx = step_x(fp), dy = step_y(fp);
+  const Edges adv = madd(madd(Edges{0, 0, 0}, drow, dy), dcol, dx);  // one stride of 64
+  const Edges wrap = madd(dy, -(int64_t)nx, dx);                        // next row, first column
+  Edges e = edges_at(fp, fp.tx0 + col, fp.ty0 + row);
+  for (int k = lane; k < n; k += kWave) {
+    if (inside(e)) occ[(int64_t)(fp.ty0 + row) * omega + fp.tx0 + col] = fp.chart;
+    col += dcol;
+    row += drow;
+    add(e, adv);
+    if (col >= nx) {
+      col -= nx;
+      row += 1;
+      add(e, wrap);
+    }
+  }
 }
 
 constexpr int kOccTile = 16;                   // queued footprints are cut into 16x16 tiles
 constexpr unsigned long long kSlotShift = 40;  // queue counter: footprints << 40 | tiles
 
-__global__ void k_occ_small(const int32_t* __restrict__ idx, const int32_t* __restrict__ vlist,
-                            FrameParams p, const float4* __restrict__ clip,
-                            const int32_t* __restrict__ cot, const fa_chart* __restrict__ charts,
-                            int32_t* __restrict__ occ, ulonglong2* __restrict__ big,
-                            uint32_t big_cap, int small_texels,
-                            unsigned long long* __restrict__ big_counter,
-                            const FrameState* __restrict__ stp) {
+// Occupancy of the visible triangles. Per fan footprint (texel range of n
+// texels): n <= lane_texels by its own lane; lane_texels < n <= small_texels
+// by its whole wave; larger ones are queued (one atomic per wave) for k_occ_big.
+__global__ __launch_bounds__(kBlock) void k_occ_small(
+    const int32_t* __restrict__ idx, const int32_t* __restrict__ vlist, FrameParams p,
+    const float4* __restrict__ clip, const int32_t* __restrict__ cot,
+    const fa_chart* __restrict__ charts, const int4* __restrict__ chart_tex,
+    int32_t* __restrict__ occ, ulonglong2* __restrict__ big, uint32_t big_cap, int small_texels,
+    int lane_texels, unsigned long long* __restrict__ big_counter,
+    const FrameState* __restrict__ stp) {
   const FrameState st = *stp;
   if (st.status != FA_OK) return;
   const int nv = st.visible;
@@ -269,20 +315,19 @@ __global__ void k_occ_small(const int32_t* __restrict__ idx, const int32_t* __re
     SnapPoly sp;
     sp.n = 0;
     sp.chart = -1;
-    if (valid) snap_polygon(vlist[i], idx, clip, cot, charts, p, st, sp);
+    const int t = valid ? vlist[i] : 0;
+    if (valid) snap_polygon(t, idx, clip, cot, charts, p, st, sp);
     for (int f = 0; f < 2; ++f) {
       Footprint fp;
-      const bool ok = sp.n > 0 && fan_footprint(sp, f, charts[sp.chart], p, st, fp);
-      int nx = 0, ny = 0;
-      if (ok) {
-        nx = fp.tx1 - fp.tx0 + 1;
-        ny = fp.ty1 - fp.ty0 + 1;
-      }
-      const bool want = ok && (int64_t)nx * ny > small_texels;
+      const bool ok = sp.n > 0 && fan_footprint(sp, f, chart_tex[sp.chart], p.omega, fp);
+      if (!__ballot(ok)) continue;
+      const int n = ok ? (fp.tx1 - fp.tx0 + 1) * (fp.ty1 - fp.ty0 + 1) : 0;
+      const bool want = ok && n > small_texels;
       bool queued = false;
       const unsigned long long qm = __ballot(want);
       if (qm) {
         // one atomic per wave: lanes take consecutive queue slots and tiles
+        const int nx = fp.tx1 - fp.tx0 + 1, ny = fp.ty1 - fp.ty0 + 1;
         const uint32_t tx_n = want ? (uint32_t)((nx + kOccTile - 1) / kOccTile) : 0u;
         const uint32_t nt = want ? tx_n * (uint32_t)((ny + kOccTile - 1) / kOccTile) : 0u;
         const uint32_t before = wave_incl_scan<uint32_t>(nt) - nt;
@@ -296,23 +341,27 @@ __global__ void k_occ_small(const int32_t* __restrict__ idx, const int32_t* __re
         if (want && slot < big_cap) {
           // x: footprint code | tiles across << 32; y: first tile | tiles << 40
           big[slot] = make_ulonglong2(
-              (unsigned long long)(2 * (int64_t)vlist[i] + f) | ((unsigned long long)tx_n << 32),
+              (unsigned long long)(2 * (int64_t)t + f) | ((unsigned long long)tx_n << 32),
               ((old & kLow) + before) | ((unsigned long long)nt << kSlotShift));
           queued = true;
         }
       }
-      if (ok && !queued) raster_thread(fp, occ, p.omega);
+      const bool coop = ok && !queued && n > lane_texels;
+      if (ok && !queued && !coop) raster_lane(fp, occ, p.omega);
+      for (unsigned long long cm = __ballot(coop); cm; cm &= cm - 1)
+        raster_wave(fp, __ffsll((long long)cm) - 1, occ, p.omega);
     }
   }
 }
 
 // Queued footprints: their concatenated 16x16 tiles are split evenly over all
-// waves of the grid; a wave finds its first footprint by binary search over
+// waves of the grid; a wave finds its first footprint by a 64-way search over
 // the (increasing) first-tile indices and walks forward, 4 texels per lane.
 __global__ __launch_bounds__(kBlock) void k_occ_big(
     const int32_t* __restrict__ idx, FrameParams p, const float4* __restrict__ clip,
     const int32_t* __restrict__ cot, const fa_chart* __restrict__ charts,
-    int32_t* __restrict__ occ, const ulonglong2* __restrict__ big, uint32_t big_cap,
+    const int4* __restrict__ chart_tex, int32_t* __restrict__ occ,
+    const ulonglong2* __restrict__ big, uint32_t big_cap,
     const unsigned long long* __restrict__ big_counter, const FrameState* __restrict__ stp) {
   const FrameState st = *stp;
   if (st.status != FA_OK) return;
@@ -327,18 +376,26 @@ __global__ __launch_bounds__(kBlock) void k_occ_big(
   const uint64_t per = (total + nwaves - 1) / nwaves;
   const uint64_t k0 = wid * per, k1 = min<uint64_t>(total, k0 + per);
   if (k0 >= k1) return;
-  uint32_t lo = 0, hi = nent - 1;  // last entry whose first tile <= k0
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi + 1) / 2;
-    if ((big[mid].y & kLow) <= k0) lo = mid; else hi = mid - 1;
+  const int lane = lane_id();
+  // last entry whose first tile <= k0; entry 0 starts at tile 0
+  uint32_t lo = 0, hi = nent;
+  while (hi - lo > 1) {
+    const uint32_t step = (hi - lo + kWave - 1) / kWave;
+    const uint32_t probe = lo + (uint32_t)lane * step;
+    const bool le = probe < hi && (big[probe].y & kLow) <= k0;
+    const int cnt = __popcll(__ballot(le));
+    lo += (uint32_t)(cnt - 1) * step;
+    hi = min(hi, lo + step);
   }
   uint32_t e = lo;
   ulonglong2 ent = big[e];
   uint64_t base = ent.y & kLow, nt = ent.y >> kSlotShift;
   uint32_t code = (uint32_t)ent.x, tiles_x = (uint32_t)(ent.x >> 32);
   Footprint fp;
-  bool ok = footprint((int64_t)(code >> 1), (int)(code & 1u), idx, clip, cot, charts, p, st, fp);
-  const int lane = lane_id();
+  bool ok = footprint((int64_t)(code >> 1), (int)(code & 1u), idx, clip, cot, charts, chart_tex,
+                      p, st, fp);
+  const int lx = lane % kOccTile, ly = lane / kOccTile;
+  constexpr int kRows = kWave / kOccTile;
   for (uint64_t k = k0; k < k1; ++k) {
     bool moved = false;
     while (k >= base + nt) {
@@ -350,17 +407,19 @@ __global__ __launch_bounds__(kBlock) void k_occ_big(
       moved = true;
     }
     if (moved)
-      ok = footprint((int64_t)(code >> 1), (int)(code & 1u), idx, clip, cot, charts, p, st, fp);
+      ok = footprint((int64_t)(code >> 1), (int)(code & 1u), idx, clip, cot, charts, chart_tex,
+                     p, st, fp);
     if (!ok) continue;
     const uint32_t tt = (uint32_t)(k - base);
-    const int ox = fp.tx0 + kOccTile * (int)(tt % tiles_x);
-    const int oy = fp.ty0 + kOccTile * (int)(tt / tiles_x);
+    const int tx = fp.tx0 + kOccTile * (int)(tt % tiles_x) + lx;
+    const int ty0 = fp.ty0 + kOccTile * (int)(tt / tiles_x) + ly;
+    Edges ev = edges_at(fp, tx, ty0);
+    const Edges dy = madd(Edges{0, 0, 0}, kRows, step_y(fp));
 #pragma unroll
-    for (int q = 0; q < kOccTile * kOccTile / kWave; ++q) {
-      const int i = lane + q * kWave;
-      const int tx = ox + (i % kOccTile), ty = oy + (i / kOccTile);
-      if (tx <= fp.tx1 && ty <= fp.ty1 && covers(fp, tx, ty))
-        occ[(int64_t)ty * p.omega + tx] = fp.chart;
+    for (int q = 0; q < kOccTile / kRows; ++q) {
+      const int ty = ty0 + q * kRows;
+      if (tx <= fp.tx1 && ty <= fp.ty1 && inside(ev)) occ[(int64_t)ty * p.omega + tx] = fp.chart;
+      add(ev, dy);
     }
   }
 }
@@ -421,19 +480,21 @@ hipError_t launch_uv(const int64_t V, const FrameParams& p, const Work& w, const
 
 hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
                             const int32_t* cot, const fa_chart* charts, int32_t* occ,
-                            int small_texels, Marker& mk, hipStream_t st) {
+                            int small_texels, int lane_texels, Marker& mk, hipStream_t st) {
   const int64_t n4 = (int64_t)p.omega * p.omega / 4;
   const unsigned fill_grid = (unsigned)std::min<int64_t>((n4 + kBlock - 1) / kBlock, 4096);
   k_occ_fill<<<fill_grid, kBlock, 0, st>>>(reinterpret_cast<int4*>(occ), n4, w.state);
   mk(st);
   const uint32_t cap = (uint32_t)std::min<int64_t>(2 * std::max<int64_t>(T, 1), 1 << 24);
   if (T > 0) {
-    k_occ_small<<<visible_grid(T), kBlock, 0, st>>>(idx, w.vlist, p, w.clip, cot, charts, occ,
-                                                    w.big, cap, small_texels, w.big_counter,
-                                                    w.state);
+    k_occ_small<<<visible_grid(T), kBlock, 0, st>>>(idx, w.vlist, p, w.clip, cot, charts,
+                                                    w.chart_tex, occ, w.big, cap, small_texels,
+                                                    lane_texels, w.big_counter, w.state);
     mk(st);
-    k_occ_big<<<kOccBigGrid, kBlock, 0, st>>>(idx, p, w.clip, cot, charts, occ, w.big, cap,
-                                              w.big_counter, w.state);
+    k_occ_big<<<kOccBigGrid, kBlock, 0, st>>>(idx, p, w.clip, cot, charts, w.chart_tex, occ,
+                                              w.big, cap, w.big_counter, w.state);
+  } else {
+    mk(st);
   }
   mk(st);
   k_occ_count<<<kCountGrid, kBlock, 0, st>>>(reinterpret_cast<const int4*>(occ), n4, w.partial);

@@ -1,7 +1,9 @@
 """Continuous-batching request server over the atlasing library.
 
 Requests (scene, camera, visible set, atlas size, rate) arrive over time from
-many clients. The server owns `slots` execution slots; each slot is a library
+many clients. A request either brings its visible set or leaves it to the
+device: then the slot runs the visible-triangle pass (fa_visibility) on the
+request's camera first, so the whole request stays on the GPU. The server owns `slots` execution slots; each slot is a library
 context (its own scratch and resident scene adjacency) bound to its own HIP
 stream. A request is admitted as soon as it has arrived, a slot is free and
 its output memory fits in the HBM budget; admitted requests run concurrently
@@ -29,7 +31,7 @@ from . import AtlasOutputs, Context, Mesh, parse_meta
 class Request:
     rid: int
     scene: str
-    visible: torch.Tensor      # uint8 [T] on the device
+    visible: torch.Tensor | None  # uint8 [T] on the device, or None: computed on the device
     view_proj: np.ndarray      # float32 [16]
     width: int
     height: int
@@ -37,6 +39,9 @@ class Request:
     rate: float
     arrival: float = 0.0       # seconds after the start of the run
     client: int = 0
+    eye: tuple = (0.0, 0.0, 0.0)  # camera position (device visibility)
+    near: float = 0.1             # w at the near plane (device visibility)
+    coarse: int = 8               # coarse depth-buffer factor (device visibility)
 
 
 @dataclasses.dataclass
@@ -73,7 +78,9 @@ class Server:
             stream = torch.cuda.Stream()
             for m in meshes.values():  # scene adjacency stays resident per slot
                 ctx.adjacency(m, stream=stream)
-            self.slots.append((ctx, stream))
+            with torch.cuda.stream(stream):
+                vis_buf = torch.empty(T, dtype=torch.uint8, device="cuda")
+            self.slots.append((ctx, stream, vis_buf))
         torch.cuda.synchronize()
         self.budget = int(hbm_budget)
 
@@ -103,11 +110,16 @@ class Server:
                     break
                 pending.popleft()
                 k = free.pop()
-                ctx, stream = self.slots[k]
+                ctx, stream, vis_buf = self.slots[k]
                 mesh = self.meshes[r.scene]
                 with torch.cuda.stream(stream):
                     out = ctx.outputs(mesh, r.atlas_size)
-                    ctx.build_atlas(mesh, r.visible, r.view_proj, r.width, r.height,
+                    vis = r.visible
+                    if vis is None:
+                        vis = ctx.visibility(mesh, r.view_proj, r.width, r.height, r.eye,
+                                             r.near, r.coarse, out=vis_buf[:mesh.num_triangles],
+                                             stream=stream)
+                    ctx.build_atlas(mesh, vis, r.view_proj, r.width, r.height,
                                     r.atlas_size, r.rate, out=out, stream=stream)
                     ev = torch.cuda.Event()
                     ev.record(stream)
@@ -136,7 +148,7 @@ class Server:
         return results
 
     def close(self):
-        for ctx, _ in self.slots:
+        for ctx, _, _ in self.slots:
             ctx.close()
         self.slots = []
 

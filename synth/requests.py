@@ -25,6 +25,9 @@ class Pose:
     width: int
     height: int
     visible: np.ndarray
+    eye: np.ndarray = None   # camera position
+    near: float = 0.0        # w at the near plane
+    coarse: int = 0          # coarse depth-buffer factor of `visible`
 
 
 def scene_meshes():
@@ -49,17 +52,20 @@ def pose_pool(name, n, seed=0):
             eye = 2.5 * np.array([np.cos(el) * np.cos(yaw), np.cos(el) * np.sin(yaw), np.sin(el)])
             cam = scenes.make_camera(eye, (0, 0, 0), W, H, 0.05, 100.0)
             vis = scenes.visible_set(pos, tris, cam)
+            coarse = 0
         elif name == "orbit":
             pos, tris, th0 = scenes._cached("orbit", lambda: scenes.scene_orbit(1))
             th = th0 + 2 * np.pi * int(rng.integers(0, 120)) / 120.0
             eye = np.array([6 * np.cos(th), 6 * np.sin(th), 2.0])
             cam = scenes.make_camera(eye, (0, 0, 0), W, H, 0.05, 100.0)
             vis = scenes.visible_set(pos, tris, cam)
+            coarse = 0
         else:
             pos, tris = scenes.city_scene()
             cam = scenes.city_camera(4000 + seed * 1000 + k, int(rng.integers(0, 32)), W, H)
             vis = scenes.visible_set(pos, tris, cam, coarse_occlusion=True)
-        out.append(Pose(name, cam.view_proj, W, H, vis))
+            coarse = 8
+        out.append(Pose(name, cam.view_proj, W, H, vis, cam.eye, cam.near, coarse))
     return out
 
 

@@ -341,8 +341,12 @@ def make_camera(eye, target, width, height, near, far, up=(0, 0, 1)):
 # visibility (input generation; float64)
 # --------------------------------------------------------------------------
 def _clip64(pos, cam):
+    # elementwise, in a fixed order ((m0 x + m1 y) + m2 z) + m3 per row, so the
+    # result does not depend on a BLAS kernel's summation order or FMA use
     M = cam.view_proj.astype(np.float64).reshape(4, 4)
-    return pos.astype(np.float64) @ M[:, :3].T + M[:, 3]
+    p = pos.astype(np.float64)
+    x, y, z = p[:, 0:1], p[:, 1:2], p[:, 2:3]
+    return ((x * M[:, 0] + y * M[:, 1]) + z * M[:, 2]) + M[:, 3]
 
 
 def visible_set(pos, tris, cam, coarse_occlusion=False):
@@ -350,7 +354,11 @@ def visible_set(pos, tris, cam, coarse_occlusion=False):
     (optionally) not hidden behind a (W/8)x(H/8) coarse depth buffer."""
     p = pos.astype(np.float64)
     p0, p1, p2 = p[tris[:, 0]], p[tris[:, 1]], p[tris[:, 2]]
-    front = (np.cross(p1 - p0, p2 - p0) * (cam.eye - p0)).sum(1) > 0
+    a, b, d = p1 - p0, p2 - p0, cam.eye - p0
+    n0 = a[:, 1] * b[:, 2] - a[:, 2] * b[:, 1]
+    n1 = a[:, 2] * b[:, 0] - a[:, 0] * b[:, 2]
+    n2 = a[:, 0] * b[:, 1] - a[:, 1] * b[:, 0]
+    front = ((n0 * d[:, 0] + n1 * d[:, 1]) + n2 * d[:, 2]) > 0
     c = _clip64(pos, cam)
     cx, cy, cz, cw = c[:, 0], c[:, 1], c[:, 2], c[:, 3]
     outside_all = np.zeros(tris.shape[0], bool)
@@ -428,6 +436,9 @@ class Frame:
     atlas_size: int
     rate: float
     scene_key: int
+    eye: np.ndarray = None  # float64 [3], camera position (visibility input)
+    near: float = 0.0       # near-plane distance (w at the near plane)
+    coarse: int = 0         # coarse depth-buffer factor of the visible set (0: none)
 
     @property
     def num_triangles(self):
@@ -463,7 +474,7 @@ def grid_frame(seed: int, atlas_size: int = 1024, rate: float = 1.0) -> Frame:
     cam = make_camera(eye, (0, 0, 0), 1280, 720, 0.05, 100.0)
     vis = visible_set(pos, tris, cam)
     return Frame(f"grid8k/seed{seed}", pos, tris, vis, cam.view_proj, 1280, 720,
-                 atlas_size, rate, 1000 + seed)
+                 atlas_size, rate, 1000 + seed, cam.eye, cam.near, 0)
 
 
 def orbit_frame(frame: int, atlas_size: int = 2048, rate: float = 1.0) -> Frame:
@@ -474,7 +485,7 @@ def orbit_frame(frame: int, atlas_size: int = 2048, rate: float = 1.0) -> Frame:
     cam = make_camera(eye, (0, 0, 0), 1920, 1080, 0.05, 100.0)
     vis = visible_set(pos, tris, cam)
     return Frame(f"orbit86k/f{frame}", pos, tris, vis, cam.view_proj, 1920, 1080,
-                 atlas_size, rate, 2001)
+                 atlas_size, rate, 2001, cam.eye, cam.near, 0)
 
 
 def city_scene():
@@ -500,7 +511,7 @@ def city_frame(frame: int = 0, rate: float = 1.0, atlas_size: int = 4096,
     cam = city_camera(seed, frame, width, height)
     vis = visible_set(pos, tris, cam, coarse_occlusion=True)
     return Frame(f"city2m/s{seed}f{frame}", pos, tris, vis, cam.view_proj, width, height,
-                 atlas_size, rate, 3002)
+                 atlas_size, rate, 3002, cam.eye, cam.near, 8)
 
 
 _RES = [(1280, 720), (1920, 1080), (2560, 1440), (3840, 2160)]
@@ -518,5 +529,6 @@ def batch_views(n: int = 16, base_seed: int = 3000):
         r = [0.5, 1.0, 2.0][int(rng.integers(0, 3))]
         cam = city_camera(base_seed + i, 0, W, H)
         vis = visible_set(pos, tris, cam, coarse_occlusion=True)
-        views.append(Frame(f"city2m/view{i}", pos, tris, vis, cam.view_proj, W, H, om, r, 3002))
+        views.append(Frame(f"city2m/view{i}", pos, tris, vis, cam.view_proj, W, H, om, r, 3002,
+                           cam.eye, cam.near, 8))
     return views

@@ -149,7 +149,7 @@ def test_city_frames_more():
 
 
 @pytest.mark.parametrize("knob,value", [(1, 512), (1, 1024), (2, 0), (2, 16), (2, 1024),
-                                        (3, 0), (5, 0)])
+                                        (2, 4096), (3, 0), (5, 0), (5, 1), (6, 0), (6, 1), (6, 4096)])
 def test_tuning_knobs_do_not_change_results(knob, value):
     fa = _fa()
     ctx = ctx_for()
@@ -162,7 +162,7 @@ def test_tuning_knobs_do_not_change_results(knob, value):
     finally:
         ctx.set_tuning(knob, old)
     with pytest.raises(fa.FastAtlasError):
-        ctx.set_tuning(knob, {1: 3, 2: -1, 3: 3, 5: 2}[knob])
+        ctx.set_tuning(knob, {1: 3, 2: -1, 3: 3, 5: 3, 6: 4097}[knob])
 
 
 # ---------------------------------------------------------------------------
@@ -292,6 +292,22 @@ def test_deterministic_repeats():
             assert np.array_equal(o[k], outs[0][k])
         assert np.array_equal(o["charts"], outs[0]["charts"])
         assert np.array_equal(bits(o["uv"]), bits(outs[0]["uv"]))
+
+
+def test_stage_timing_one_event_per_kernel():
+    fa = _fa()
+    f = scenes.orbit_frame(7)
+    ctx = ctx_for()
+    ctx.set_stage_timing(True)
+    try:
+        g = run_gpu(f, ctx)
+        st = ctx.stage_times()
+    finally:
+        ctx.set_stage_timing(False)
+    assert list(st) == fa.STAGES and len(st) == 19
+    assert all(v >= 0.0 for v in st.values())
+    # timing changes nothing
+    compare(g, oracle.build_frame(f))
 
 
 def test_batch_equals_single():
