@@ -75,6 +75,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-dual", action="store_true")
     ap.add_argument("--serve-rate", type=float, nargs="+", default=[60.0, 250.0, 1000.0, 2000.0])
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -211,6 +212,23 @@ def main():
     assert torch.equal(vbuf.cpu(), torch.as_tensor(frames[(len(evv) - 1) % len(frames)].visible))
     del vbuf
 
+    # temporal reuse over the frame sequence, a key frame every 10 frames
+    fr_re, ms_re = [], []
+    for k in range(len(frames)):
+        if k % 10 == 0:
+            key_f, key_v = frames[k], vis[k]
+            continue
+        a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a_.record(stream)
+        _, reused_ = ctx.reuse_flags(mesh, key_f.view_proj, key_v, vis[k], stream=stream)
+        b_.record(stream)
+        torch.cuda.synchronize()
+        ms_re.append(a_.elapsed_time(b_))
+        fr_re.append(int(reused_.item()) / max(1, int(frames[k].visible.sum())))
+    reuse = dict(key_interval=10, mean_reused_fraction=float(np.mean(fr_re)) if fr_re else None,
+                 min_reused_fraction=float(np.min(fr_re)) if fr_re else None,
+                 flags_ms=float(np.mean(ms_re)) if ms_re else None)
+
     # per-kernel live times (separate pass with an event after every kernel)
     ctx.set_stage_timing(True)
     stage_acc = {}
@@ -282,6 +300,44 @@ def main():
                 ctx, mesh, [scenes.city_frame(k, rate=r_) for k in range(0, 32, 8)])
         sctx.close()
         log("secondary:", json.dumps(secondary))
+
+    # dual atlas: an 8K full-rate atlas and its 1K companion (same packing)
+    dual = None
+    if not args.no_dual:
+        dctx = fa.Context(T, V, max_charts=65536, max_atlas=8192, gutter=8)
+        for knob_ in TUNED:
+            dctx.set_tuning(knob_, ctx.get_tuning(knob_))
+        dfr = [scenes.city_frame(k, rate=args.rate, atlas_size=8192) for k in range(0, 32, 8)]
+        dvis = [torch.as_tensor(f.visible).to(dev) for f in dfr]
+        dout = dctx.outputs(mesh, 8192)
+        dlow = torch.empty((1024, 1024), dtype=torch.int32, device=dev)
+
+        def dual_step(k, both):
+            f = dfr[k % len(dfr)]
+            if both:
+                dctx.build_dual_atlas(mesh, dvis[k % len(dfr)], f.view_proj, f.width, f.height,
+                                      8192, f.rate, 3, out=dout, occupancy_low=dlow,
+                                      stream=stream)
+            else:
+                dctx.build_atlas(mesh, dvis[k % len(dfr)], f.view_proj, f.width, f.height, 8192,
+                                 f.rate, out=dout, stream=stream)
+        res_d = {}
+        for both in (False, True):
+            for k in range(4):
+                dual_step(k, both)
+            evd = []
+            for k in range(16):
+                a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a_.record(stream)
+                dual_step(k, both)
+                b_.record(stream)
+                evd.append((a_, b_))
+            torch.cuda.synchronize()
+            res_d["dual_ms" if both else "single_8k_ms"] = float(
+                np.mean([a_.elapsed_time(b_) for a_, b_ in evd]))
+        dual = dict(atlas=8192, low_atlas=1024, gutter=8, frames=len(dfr), **res_d)
+        del dout, dlow
+        dctx.close()
 
     # batched views vs the plain per-view path
     batch = None
@@ -418,6 +474,8 @@ def main():
         "pack_rows_at_chosen_scale": meta["rows"],
         "copy_gbs": copy_gbs,
         "device_visibility": visibility,
+        "temporal_reuse": reuse,
+        "dual_atlas": dual,
         "batch": batch,
         "served": served,
         "secondary": secondary,

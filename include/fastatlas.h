@@ -186,6 +186,19 @@ int fa_scene_evict(fa_ctx* ctx, uint64_t scene_key);
 int fa_visibility(fa_ctx* ctx, const fa_mesh* mesh, const fa_camera* cam, const double* eye,
                   double near_w, int32_t coarse, uint8_t* visible, void* stream);
 
+/* Temporal reuse classification (Sec. "Temporal Reuse"): after a key frame
+ * whose atlas was shaded in full, a later frame only re-shades triangles that
+ * are newly visible or were partially visible in the key frame (a vertex with
+ * max(|x|, |y|) >= w in the key frame's clip space, float32, clip =
+ * key_cam->view_proj * (x, y, z, 1) summed left to right); the rest reuse the
+ * key frame's shading. flags: device [T], 0 = not visible now, 1 = reuse,
+ * 2 = shade. key_visible, visible: device [T] 0/1. reused: device int64 [1]
+ * receiving the number of 1 flags, or NULL. Errors: FA_ERR_INVALID_ARG (null
+ * pointers, non-finite camera, out-of-range indices), FA_ERR_CAPACITY. */
+int fa_reuse_flags(fa_ctx* ctx, const fa_mesh* mesh, const fa_camera* key_cam,
+                   const uint8_t* key_visible, const uint8_t* visible, uint8_t* flags,
+                   int64_t* reused, void* stream);
+
 /* Atlas one frame: charts, boxes, order, J-candidate packing, selection,
  * per-vertex UVs and (if out->occupancy) the atlas occupancy map.
  * visible: [T] 0/1. atlas_size: power of two, 16 <= atlas_size <= max_atlas.
@@ -193,6 +206,23 @@ int fa_visibility(fa_ctx* ctx, const fa_mesh* mesh, const fa_camera* cam, const 
 int fa_build_atlas(fa_ctx* ctx, const fa_mesh* mesh, const uint8_t* visible,
                    const fa_camera* cam, int32_t atlas_size, float texel_per_pixel,
                    fa_atlas_out* out, void* stream);
+
+/* Atlas one frame as fa_build_atlas, plus the occupancy of the same packing
+ * in a low-resolution companion atlas of side atlas_size >> low_shift (App.
+ * "Depth-of-Field" and "Foveated Rendering": one packing serves a full-rate
+ * atlas and a reduced-rate one, its coordinates scaled by 2^-low_shift per
+ * axis; the caller's UVs for it are uv * 2^-low_shift). occupancy_low: device
+ * [(atlas_size >> low_shift)^2], the same definition as the occupancy map
+ * with omega = atlas_size >> low_shift (meta->occupied_texels stays the
+ * full-rate count). To keep charts apart in the low atlas, configure a gutter
+ * of at least 2^low_shift texels (charts whose triangles leave the view can
+ * still reach their box edge). low_shift: 1..6, atlas_size >> low_shift >= 16.
+ * Errors as fa_build_atlas, plus FA_ERR_INVALID_ARG for a bad low_shift or a
+ * null occupancy_low. */
+int fa_build_dual_atlas(fa_ctx* ctx, const fa_mesh* mesh, const uint8_t* visible,
+                        const fa_camera* cam, int32_t atlas_size, float texel_per_pixel,
+                        int32_t low_shift, fa_atlas_out* out, int32_t* occupancy_low,
+                        void* stream);
 
 /* Atlas n views of one mesh (views: host array of n descriptors, each with its
  * own visibility, camera, atlas size, rate and outputs). Views run
@@ -227,7 +257,8 @@ int fa_pack_boxes(fa_ctx* ctx, const float* sizes, int32_t n, int32_t atlas_size
  *   FA_TUNE_UF_EDGE_HOOKS     1: join across shared edges, then across shared
  *                             vertices (Alg. 1); 2 (default): shared edges
  *                             inside tiles of 2048 visible triangles joined in
- *                             LDS first, then vertices; 0: vertices only
+ *                             LDS first, then the edges between tiles, then
+ *                             vertices; 0: vertices only
  *                             (every shared edge is a shared vertex: the
  *                             charts are the same for all three)
  *   FA_TUNE_BATCH_GRAPH       1: fa_build_atlas_batch captures its views into

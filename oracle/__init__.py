@@ -62,6 +62,11 @@ def lib():
                                        i32, i32, i64, i32, P]
         L.oracle_occupancy.restype = i64
         L.oracle_visibility.argtypes = [P, i64, P, i64, P, P, ctypes.c_double, i32, i32, i32, P]
+        L.oracle_reuse_flags.argtypes = [P, i64, P, i64, P, P, P, P]
+        L.oracle_profiles.argtypes = [P, P, P, P, i64, P, P, P, P, i32, i32, f32, f32, i32, P, P,
+                                      P, i64, P, P]
+        L.oracle_candidate_fp.argtypes = [P, P, P, P, i64, i32, P, P, P]
+        L.oracle_reuse_flags.restype = i64
         _lib = L
     return _lib
 
@@ -96,6 +101,20 @@ def visibility(positions, indices, view_proj, eye, near, width, height, coarse=0
     lib().oracle_visibility(_p(pos), pos.shape[0], _p(idx), idx.shape[0], _p(M), _p(e),
                             float(near), int(width), int(height), int(coarse), _p(out))
     return out
+
+
+def reuse_flags(positions, indices, key_view_proj, key_visible, visible):
+    """Temporal reuse classification (Sec. "Temporal Reuse"): (flags uint8 [T]
+    with 0 not visible / 1 reuse / 2 shade, number reused)."""
+    pos = _c(positions, np.float32)
+    idx = _c(indices, np.int32)
+    M = _c(key_view_proj, np.float32).ravel()
+    kv = _c(key_visible, np.uint8)
+    v = _c(visible, np.uint8)
+    out = np.empty(idx.shape[0], np.uint8)
+    n = lib().oracle_reuse_flags(_p(pos), pos.shape[0], _p(idx), idx.shape[0], _p(M), _p(kv),
+                                 _p(v), _p(out))
+    return out, int(n)
 
 
 def adjacency(indices):
@@ -159,6 +178,56 @@ def candidate(sbw, sbh, j, J, omega, gutter=1, min_box=2):
                 x=x, y=y, a=a, b=b)
 
 
+def profiles(clip_c, indices, nonempty, chart_of_tri, frame, target, oriented, rotated, W, H,
+             rate, s, gutter, a, b, prof_off):
+    """Footprint profiles (top, bottom rows per box column) of every chart at
+    scale s; a, b, prof_off are chart-indexed; returns (top, bottom)."""
+    C = a.shape[0]
+    total = int((prof_off + a).max()) if C else 0
+    top = np.empty(total, np.int32)
+    bot = np.empty(total, np.int32)
+    idx = _c(indices, np.int32)
+    lib().oracle_profiles(_p(_c(clip_c, np.float32)), _p(idx), _p(_c(nonempty, np.uint8)),
+                          _p(_c(chart_of_tri, np.int32)), idx.shape[0], _p(_c(frame, np.float32)),
+                          _p(_c(target, np.float32)), _p(_c(oriented, np.float32)),
+                          _p(_c(rotated, np.int32)), int(W), int(H), float(rate), float(s),
+                          int(gutter), _p(_c(a, np.int32)), _p(_c(b, np.int32)),
+                          _p(_c(prof_off, np.int64)), C, _p(top), _p(bot))
+    return top, bot
+
+
+def candidate_fp(a_o, top, bot, poff_o, omega):
+    """Footprint-aware push of one candidate (inputs in packing order)."""
+    C = a_o.shape[0]
+    x = np.empty(C, np.int32)
+    y = np.empty(C, np.int32)
+    out = np.zeros(5, np.int64)
+    lib().oracle_candidate_fp(_p(_c(a_o, np.int32)), _p(top), _p(bot), _p(_c(poff_o, np.int64)),
+                              C, int(omega), _p(x), _p(y), _p(out))
+    return dict(fit=bool(out[0]), m=int(out[1]), L=int(out[2]), H=int(out[3]), rows=int(out[4]),
+                x=x, y=y)
+
+
+def footprint_candidate(clip_c, idx, ne, cot, frame, target, oriented, rot, W, H, rate, j, J,
+                        omega, gutter, order_, box_cd):
+    """Candidate j with the footprint-aware push; sizes from the box candidate."""
+    a_o, b_o = box_cd["a"], box_cd["b"]
+    C = a_o.shape[0]
+    poff_o = np.zeros(C, np.int64)
+    if C:
+        poff_o[1:] = np.cumsum(a_o[:-1].astype(np.int64))
+    a = np.empty(C, np.int32)
+    b = np.empty(C, np.int32)
+    poff = np.empty(C, np.int64)
+    a[order_], b[order_], poff[order_] = a_o, b_o, poff_o
+    s = np.float32(j) / np.float32(J)
+    top, bot = profiles(clip_c, idx, ne, cot, frame, target, oriented, rot, W, H, rate, s, gutter,
+                        a, b, poff)
+    fp = candidate_fp(a_o, top, bot, poff_o, omega)
+    fp.update(a=a_o, b=b_o, top=top, bot=bot, prof_off=poff, H_box=box_cd["H"])
+    return fp
+
+
 def select(cand_table):
     ct = _c(cand_table, np.int64)
     return int(lib().oracle_select(_p(ct), ct.shape[0]))
@@ -169,9 +238,14 @@ def select(cand_table):
 # ---------------------------------------------------------------------------
 def build_atlas(positions, indices, visible, view_proj, width, height, atlas_size, rate,
                 J=64, gutter=1, min_box=2, side_clip=True, want_occupancy=True,
-                want_adjacency=False):
+                want_adjacency=False, low_shift=0, footprint=False):
     """Run every step on one frame. Returns a dict of all intermediate and
-    final results (per-chart arrays are indexed by chart index)."""
+    final results (per-chart arrays are indexed by chart index). low_shift = k
+    > 0 adds the occupancy of the same packing scaled into an atlas of side
+    omega / 2^k (App. "Depth-of-Field" and "Foveated Rendering": the low
+    resolution atlas reuses the packing, coordinates scaled per axis).
+    footprint=True packs with the footprint-aware push (per-column profiles
+    of each chart's footprint instead of its full box)."""
     pos = _c(positions, np.float32)
     idx = _c(indices, np.int32)
     vis = _c(visible, np.uint8)
@@ -198,6 +272,9 @@ def build_atlas(positions, indices, visible, view_proj, width, height, atlas_siz
     cands = []
     for j in range(1, J + 1):
         cd = candidate(sbw, sbh, j, J, omega, gutter, min_box)
+        if footprint:
+            cd = footprint_candidate(r["clip"], idx, ne, cot, frame, target, oriented, rot, W, H,
+                                     rate, j, J, omega, gutter, o, cd)
         cands.append(cd)
         table[j - 1] = [cd["fit"], cd["m"], cd["L"], cd["H"], cd["rows"]]
     r["cand"] = table
@@ -228,6 +305,13 @@ def build_atlas(positions, indices, visible, view_proj, width, height, atlas_siz
                                    _p(rot), _p(px), _p(py), _p(pa), _p(pb), W, H, float(rate), js,
                                    J, omega, L, gutter, _p(occ))
         r.update(occupancy=occ, occupied=int(n))
+    if low_shift:
+        ol = omega >> int(low_shift)
+        occ_l = np.empty((ol, ol), np.int32)
+        n = lib().oracle_occupancy(_p(clip_c), _p(idx), _p(ne), _p(cot), T, _p(frame), _p(target),
+                                   _p(rot), _p(px), _p(py), _p(pa), _p(pb), W, H, float(rate), js,
+                                   J, ol, L, gutter, _p(occ_l))
+        r.update(occupancy_low=occ_l, occupied_low=int(n))
     return r
 
 

@@ -16,7 +16,7 @@
 //
 // Parity status per step:
 //   adjacency, clip, charts, per-triangle boxes, chart frames, order, fold,
-//   push, select, UV, occupancy, visibility: pinned by independent tests
+//   push, select, UV, occupancy, visibility, reuse flags: pinned by independent tests
 //   (brute force, closed forms, exact double clipping, invariants, an
 //   independent vectorized implementation); see tests/test_oracle_*.
 #include <algorithm>
@@ -628,6 +628,205 @@ void oracle_visibility(const float* pos, int64_t V, const int32_t* idx, int64_t 
     });
     vis[t] = (!any || pass) ? 1 : 0;
   }
+}
+
+// ---------------------------------------------------------------------------
+// R   temporal reuse classification (Sec. "Temporal Reuse"): a key frame's
+// atlas is shaded in full; a later frame re-shades only triangles that are
+// newly visible (visible now, not in the key frame) or were partially visible
+// in the key frame (some vertex with max(|x|, |y|) >= w in the key frame's
+// clip space, i.e. part of it was off screen and never shaded). Every other
+// visible triangle reuses the key frame's shading.
+// flags[t] = 0 not visible now, 1 reuse, 2 shade. Clip coordinates follow O1
+// (float32, fixed order). Returns the number of reused triangles.
+// ---------------------------------------------------------------------------
+int64_t oracle_reuse_flags(const float* pos, int64_t V, const int32_t* idx, int64_t T,
+                           const float* key_M, const uint8_t* key_vis, const uint8_t* vis,
+                           uint8_t* flags) {
+  std::vector<float> kc(4 * (size_t)V);
+  oracle_clip(pos, V, key_M, kc.data());
+  int64_t reused = 0;
+  for (int64_t t = 0; t < T; ++t) {
+    if (!vis[t]) { flags[t] = 0; continue; }
+    bool partial = false;
+    for (int e = 0; e < 3; ++e) {
+      const float* q = &kc[4 * (size_t)idx[3 * t + e]];
+      if (std::max(std::fabs(q[0]), std::fabs(q[1])) >= q[3]) partial = true;
+    }
+    const bool reuse = key_vis[t] && !partial;
+    flags[t] = reuse ? 1 : 2;
+    reused += reuse;
+  }
+  return reused;
+}
+
+// ---------------------------------------------------------------------------
+// FP  footprint-aware push: an extension of the box push (Sec. "Box Packing")
+// for non-rectangular charts. Each chart contributes per-column profiles
+// (top, bottom row) of its footprint instead of its full box, so a chart can
+// rise into the empty corners under its neighbours in the frontline.
+//
+// Profiles of chart c at scale s (box a x b): every triangle of c with a
+// non-empty box (the near-clipped polygon as in O10, all w > 0) is mapped to
+// box-local layout coordinates (g + lx*s, g + ly*s) (lx, ly as in O9) and
+// clipped to the chart frame [g, g + bw*s] x [g, g + bh*s]; for each column
+// strip [k, k+1) overlapping it, the polygon is cut to the strip (inside
+// endpoint first, t = (x_line - A.x) / (B.x - A.x)) and its y-range, clamped
+// to the frame, covers rows floor(ylo) .. ceil(yhi) - 1 (at least one row).
+// The union over triangles is dilated by g columns and rows (the gutter) and
+// clamped to the box. Empty columns: top = INT32_MAX, bottom = -1.
+// ---------------------------------------------------------------------------
+namespace {
+struct P2 { float x, y; };
+
+int cut_vertical(const P2* in, int n, float xl, bool keep_right, P2* out) {
+  int m = 0;
+  for (int i = 0; i < n; ++i) {
+    const P2 S = in[i], E = in[(i + 1) % n];
+    const bool iS = keep_right ? S.x >= xl : S.x <= xl;
+    const bool iE = keep_right ? E.x >= xl : E.x <= xl;
+    if (iS != iE) {
+      const P2 A = iS ? S : E, B = iS ? E : S;
+      const float t = (xl - A.x) / (B.x - A.x);
+      out[m++] = P2{xl, A.y + t * (B.y - A.y)};
+    }
+    if (iE) out[m++] = E;
+  }
+  return m;
+}
+}  // namespace
+
+void oracle_profiles(const float* clip, const int32_t* idx, const uint8_t* nonempty,
+                     const int32_t* chart_of_tri, int64_t T, const float* frame,
+                     const float* target, const float* oriented, const int32_t* rotated,
+                     int32_t W, int32_t H, float rate, float s, int32_t gutter,
+                     const int32_t* box_a, const int32_t* box_b, const int64_t* prof_off,
+                     int64_t C, int32_t* top, int32_t* bot) {
+  int64_t total = 0;
+  for (int64_t c = 0; c < C; ++c) total = std::max(total, prof_off[c] + box_a[c]);
+  std::vector<int32_t> rt(total, INT32_MAX), rb(total, -1);
+  const float g = (float)gutter;
+  for (int64_t t = 0; t < T; ++t) {
+    if (!nonempty[t]) continue;
+    const int32_t c = chart_of_tri[t];
+    V4 tri[3] = {load_clip(clip, idx[3 * t]), load_clip(clip, idx[3 * t + 1]),
+                 load_clip(clip, idx[3 * t + 2])};
+    V4 poly[4];
+    int n = 3;
+    const bool cross_near = plane_dist(tri[0], PN) < 0.0f || plane_dist(tri[1], PN) < 0.0f ||
+                            plane_dist(tri[2], PN) < 0.0f;
+    if (cross_near) n = clip_one_plane(tri, 3, PN, poly);
+    else for (int k = 0; k < 3; ++k) poly[k] = tri[k];
+    bool ok = n >= 3;
+    for (int k = 0; k < n; ++k) ok = ok && poly[k].w > 0.0f;
+    if (!ok) continue;
+    const float x0 = frame[4 * c], y1 = frame[4 * c + 3], tw = target[2 * c];
+    const float halfW = 0.5f * (float)W, halfH = 0.5f * (float)H;
+    P2 P[4];
+    for (int k = 0; k < n; ++k) {
+      const float nx = poly[k].x / poly[k].w, ny = poly[k].y / poly[k].w;
+      const float px = ((nx - x0) * halfW) * rate;
+      const float py = ((y1 - ny) * halfH) * rate;
+      const float lx = rotated[c] ? py : px;
+      const float ly = rotated[c] ? (tw - px) : py;
+      P[k] = P2{g + lx * s, g + ly * s};
+    }
+    const float fx1 = g + oriented[2 * c] * s, fy1 = g + oriented[2 * c + 1] * s;
+    float xmin = P[0].x, xmax = P[0].x;
+    for (int k = 1; k < n; ++k) { xmin = std::min(xmin, P[k].x); xmax = std::max(xmax, P[k].x); }
+    const float xl = std::max(xmin, g), xr = std::min(xmax, fx1);
+    if (!(xl <= xr)) continue;
+    const int k0 = (int)std::floor(xl);
+    int k1 = (int)std::ceil(xr) - 1;
+    if (k1 < k0) k1 = k0;
+    for (int k = k0; k <= k1; ++k) {
+      const float sl = std::max((float)k, g), sr = std::min((float)(k + 1), fx1);
+      P2 A[6], B[6];
+      const int na = cut_vertical(P, n, sl, true, A);
+      const int nb = na ? cut_vertical(A, na, sr, false, B) : 0;
+      if (nb == 0) continue;
+      float ymin = B[0].y, ymax = B[0].y;
+      for (int q = 1; q < nb; ++q) { ymin = std::min(ymin, B[q].y); ymax = std::max(ymax, B[q].y); }
+      const float ylo = std::max(ymin, g), yhi = std::min(ymax, fy1);
+      if (!(ylo <= yhi)) continue;
+      const int r0 = (int)std::floor(ylo);
+      int r1 = (int)std::ceil(yhi) - 1;
+      if (r1 < r0) r1 = r0;
+      const int64_t at = prof_off[c] + k;
+      rt[at] = std::min(rt[at], r0);
+      rb[at] = std::max(rb[at], r1);
+    }
+  }
+  for (int64_t c = 0; c < C; ++c) {
+    const int a = box_a[c], b = box_b[c];
+    for (int k = 0; k < a; ++k) {
+      int tmin = INT32_MAX, bmax = -1;
+      for (int d = std::max(0, k - gutter); d <= std::min(a - 1, k + gutter); ++d) {
+        tmin = std::min(tmin, rt[prof_off[c] + d]);
+        bmax = std::max(bmax, rb[prof_off[c] + d]);
+      }
+      if (bmax < 0) {
+        top[prof_off[c] + k] = INT32_MAX;
+        bot[prof_off[c] + k] = -1;
+      } else {
+        top[prof_off[c] + k] = std::max(0, tmin - gutter);
+        bot[prof_off[c] + k] = std::min(b - 1, bmax + gutter);
+      }
+    }
+  }
+}
+
+// Candidate j with footprint profiles (inputs in packing order): sizes, fold,
+// overflow and mirrored rows exactly as O7; the push reads, per box, y =
+// max(0, max over its non-empty columns of F[x+k] - top[k]), then sets
+// F[x+k] = y + bottom[k] + 1 on those columns (all reads of a row before its
+// writes). H = max F; fit iff m <= omega and H <= L.
+void oracle_candidate_fp(const int32_t* a, const int32_t* top, const int32_t* bot,
+                         const int64_t* poff, int64_t C, int32_t omega, int32_t* x, int32_t* y,
+                         int64_t* out) {
+  int log2w = 0;
+  while ((1 << log2w) < omega) ++log2w;
+  std::vector<int64_t> X(C), row(C), off(C);
+  int64_t run = 0, m = 0;
+  for (int64_t i = 0; i < C; ++i) {
+    X[i] = run;
+    run += a[i];
+    row[i] = X[i] >> log2w;
+    off[i] = X[i] & (int64_t)(omega - 1);
+    m = std::max(m, off[i] + a[i] - omega);
+  }
+  const int64_t L = omega + m;
+  out[1] = m;
+  out[2] = L;
+  out[4] = C ? row[C - 1] + 1 : 0;
+  if (m > omega) {
+    out[0] = 0;
+    out[3] = -1;
+    for (int64_t i = 0; i < C; ++i) x[i] = y[i] = 0;
+    return;
+  }
+  for (int64_t i = 0; i < C; ++i)
+    x[i] = (int32_t)((row[i] % 3 == 0) ? off[i] : L - off[i] - a[i]);
+  std::vector<int64_t> F(L, 0);
+  int64_t i = 0;
+  while (i < C) {
+    int64_t e = i;
+    while (e < C && row[e] == row[i]) ++e;
+    for (int64_t k = i; k < e; ++k) {
+      int64_t yy = 0;
+      for (int q = 0; q < a[k]; ++q)
+        if (bot[poff[k] + q] >= 0) yy = std::max(yy, F[x[k] + q] - top[poff[k] + q]);
+      y[k] = (int32_t)yy;
+    }
+    for (int64_t k = i; k < e; ++k)
+      for (int q = 0; q < a[k]; ++q)
+        if (bot[poff[k] + q] >= 0) F[x[k] + q] = y[k] + bot[poff[k] + q] + 1;
+    i = e;
+  }
+  int64_t Hm = 0;
+  for (int64_t c = 0; c < L; ++c) Hm = std::max(Hm, F[c]);
+  out[3] = Hm;
+  out[0] = Hm <= L ? 1 : 0;
 }
 
 }  // extern "C"

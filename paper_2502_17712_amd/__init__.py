@@ -69,7 +69,8 @@ assert CHART_DTYPE.itemsize == 64 and META_DTYPE.itemsize == 64
 
 EXPORTS = ["fa_create", "fa_destroy", "fa_status_string", "fa_scene_adjacency", "fa_scene_evict",
            "fa_build_atlas", "fa_build_atlas_batch", "fa_pack_boxes", "fa_set_tuning",
-           "fa_get_tuning", "fa_set_stage_timing", "fa_stage_times", "fa_visibility"]
+           "fa_get_tuning", "fa_set_stage_timing", "fa_stage_times", "fa_visibility",
+           "fa_reuse_flags", "fa_build_dual_atlas"]
 
 
 def _load():
@@ -96,9 +97,14 @@ def _load():
     lib.fa_stage_times.argtypes = [c_void_p, POINTER(c_float), c_int]
     lib.fa_visibility.argtypes = [c_void_p, POINTER(fa_mesh), POINTER(fa_camera),
                                   POINTER(c_double), c_double, c_int32, c_void_p, c_void_p]
+    lib.fa_reuse_flags.argtypes = [c_void_p, POINTER(fa_mesh), POINTER(fa_camera), c_void_p,
+                                   c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.fa_build_dual_atlas.argtypes = [c_void_p, POINTER(fa_mesh), c_void_p, POINTER(fa_camera),
+                                        c_int32, c_float, c_int32, POINTER(fa_atlas_out),
+                                        c_void_p, c_void_p]
     for n in ("fa_scene_adjacency", "fa_scene_evict", "fa_build_atlas", "fa_build_atlas_batch",
               "fa_pack_boxes", "fa_set_tuning", "fa_get_tuning", "fa_set_stage_timing",
-              "fa_stage_times", "fa_visibility"):
+              "fa_stage_times", "fa_visibility", "fa_reuse_flags", "fa_build_dual_atlas"):
         getattr(lib, n).restype = c_int
     return lib
 
@@ -119,6 +125,8 @@ fa_get_tuning = _lib.fa_get_tuning
 fa_set_stage_timing = _lib.fa_set_stage_timing
 fa_stage_times = _lib.fa_stage_times
 fa_visibility = _lib.fa_visibility
+fa_reuse_flags = _lib.fa_reuse_flags
+fa_build_dual_atlas = _lib.fa_build_dual_atlas
 
 STAGES = ["prologue", "vis_scan", "vis_compact", "uf_hook", "uf_vertex_min", "uf_vertex_hook",
           "uf_flatten", "chart_scan", "assign_roots", "gather_boxes", "sizes_order", "pack",
@@ -264,6 +272,33 @@ class Context:
         _check(fa_visibility(self.h, ctypes.byref(mesh.c), ctypes.byref(cam), e, float(near),
                              int(coarse), _ptr(out), _stream_handle(stream)), "fa_visibility")
         return out
+
+    def reuse_flags(self, mesh: Mesh, key_view_proj, key_visible, visible, stream=None):
+        """Temporal reuse flags (0 not visible, 1 reuse, 2 shade) and the reused count
+        (a device int64 tensor), see fa_reuse_flags."""
+        flags = torch.empty(mesh.num_triangles, dtype=torch.uint8, device="cuda")
+        reused = torch.empty(1, dtype=torch.int64, device="cuda")
+        cam = make_camera(key_view_proj, 1, 1)
+        _check(fa_reuse_flags(self.h, ctypes.byref(mesh.c), ctypes.byref(cam), _ptr(key_visible),
+                              _ptr(visible), _ptr(flags), _ptr(reused), _stream_handle(stream)),
+               "fa_reuse_flags")
+        return flags, reused
+
+    def build_dual_atlas(self, mesh: Mesh, visible, view_proj, width, height, atlas_size, rate,
+                         low_shift, out: AtlasOutputs = None, occupancy_low=None, stream=None):
+        """fa_build_dual_atlas: returns (outputs, low-resolution occupancy map)."""
+        if out is None:
+            out = self.outputs(mesh, atlas_size)
+        if occupancy_low is None:
+            ol = int(atlas_size) >> int(low_shift)
+            occupancy_low = torch.empty((ol, ol), dtype=torch.int32, device="cuda")
+        cam = make_camera(view_proj, width, height)
+        oc = out.c()
+        _check(fa_build_dual_atlas(self.h, ctypes.byref(mesh.c), _ptr(visible), ctypes.byref(cam),
+                                   int(atlas_size), float(rate), int(low_shift), ctypes.byref(oc),
+                                   _ptr(occupancy_low), _stream_handle(stream)),
+               "fa_build_dual_atlas")
+        return out, occupancy_low
 
     def build_atlas(self, mesh: Mesh, visible, view_proj, width, height, atlas_size, rate,
                     out: AtlasOutputs = None, stream=None):

@@ -49,6 +49,11 @@ struct VisParams {
   int32_t coarse; // 0: facing and frustum only
 };
 
+// Key-frame camera of the temporal reuse classification (float32).
+struct KeyClip {
+  float M[16];
+};
+
 // Per-frame constants passed by value.
 struct FrameParams {
   float M[16];
@@ -230,7 +235,17 @@ hipError_t launch_uv(const int64_t V, const FrameParams& p, const Work& w, const
 hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
                             const int32_t* cot, const fa_chart* charts, int32_t* occ,
                             int small_texels, int lane_texels, Marker& mk, hipStream_t st);
+// Occupancy of the frame's packing drawn into an atlas of side p.omega (a
+// scaled copy of the frame's atlas): box ranges for that side, then the
+// occupancy kernels.
+hipError_t launch_occupancy_scaled(const int32_t* idx, int64_t T, const FrameParams& p,
+                                   const Work& w, const int32_t* cot, const fa_chart* charts,
+                                   int32_t* occ, int small_texels, int lane_texels,
+                                   hipStream_t st);
 unsigned visible_grid(int64_t T);  // blocks of the kernels that walk the visible list
+hipError_t launch_reuse_flags(const float* pos, const int32_t* idx, int64_t T, const KeyClip& kc,
+                              const uint8_t* key_vis, const uint8_t* vis, uint8_t* flags,
+                              unsigned long long* reused, hipStream_t st);
 hipError_t launch_visibility(const float* pos, const int32_t* idx, int64_t T, const VisParams& q,
                              int32_t* occl, uint32_t* count, unsigned long long* depth,
                              uint8_t* vis, hipStream_t st);

@@ -342,6 +342,30 @@ int fa_visibility(fa_ctx* ctx, const fa_mesh* mesh, const fa_camera* cam, const 
   return FA_OK;
 }
 
+int fa_reuse_flags(fa_ctx* ctx, const fa_mesh* mesh, const fa_camera* key_cam,
+                   const uint8_t* key_visible, const uint8_t* visible, uint8_t* flags,
+                   int64_t* reused, void* stream) {
+  if (!ctx || !key_cam) return FA_ERR_INVALID_ARG;
+  int rc = check_mesh(ctx, mesh);
+  if (rc) return rc;
+  if (mesh->num_triangles > 0 && (!key_visible || !visible || !flags)) return FA_ERR_INVALID_ARG;
+  KeyClip kc{};
+  for (int i = 0; i < 16; ++i) {
+    if (!std::isfinite(key_cam->view_proj[i])) return FA_ERR_INVALID_ARG;
+    kc.M[i] = key_cam->view_proj[i];
+  }
+  if (hipSetDevice(ctx->cfg.device) != hipSuccess) return FA_ERR_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  Scene* sc = nullptr;  // validates the indices once per scene
+  rc = get_scene(ctx, mesh, st, &sc);
+  if (rc) return rc;
+  if (launch_reuse_flags(mesh->positions, mesh->indices, mesh->num_triangles, kc, key_visible,
+                         visible, flags, reinterpret_cast<unsigned long long*>(reused),
+                         st) != hipSuccess)
+    return FA_ERR_DEVICE;
+  return FA_OK;
+}
+
 int fa_scene_evict(fa_ctx* ctx, uint64_t scene_key) {
   if (!ctx) return FA_ERR_INVALID_ARG;
   auto it = ctx->scenes.find(scene_key);
@@ -430,6 +454,36 @@ int fa_build_atlas(fa_ctx* ctx, const fa_mesh* mesh, const uint8_t* visible,
   rc = get_scene(ctx, mesh, st, &sc);
   if (rc) return rc;
   return run_frame(ctx, ctx->slots[0], mesh, sc, visible, p, out, st);
+}
+
+int fa_build_dual_atlas(fa_ctx* ctx, const fa_mesh* mesh, const uint8_t* visible,
+                        const fa_camera* cam, int32_t atlas_size, float texel_per_pixel,
+                        int32_t low_shift, fa_atlas_out* out, int32_t* occupancy_low,
+                        void* stream) {
+  if (!ctx || !visible || !cam || !out || !occupancy_low) return FA_ERR_INVALID_ARG;
+  if (!out->chart_of_tri || !out->charts || !out->meta) return FA_ERR_INVALID_ARG;
+  if (low_shift < 1 || low_shift > 6 || (atlas_size >> low_shift) < 16) return FA_ERR_INVALID_ARG;
+  int rc = check_mesh(ctx, mesh);
+  if (rc) return rc;
+  FrameParams p;
+  rc = frame_params(ctx, cam, atlas_size, texel_per_pixel, &p);
+  if (rc) return rc;
+  if (hipSetDevice(ctx->cfg.device) != hipSuccess) return FA_ERR_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  Scene* sc = nullptr;
+  rc = get_scene(ctx, mesh, st, &sc);
+  if (rc) return rc;
+  const Work& w = ctx->slots[0];
+  rc = run_frame(ctx, w, mesh, sc, visible, p, out, st);
+  if (rc) return rc;
+  FrameParams pl = p;
+  pl.omega = atlas_size >> low_shift;
+  pl.log2omega = p.log2omega - low_shift;
+  if (launch_occupancy_scaled(mesh->indices, mesh->num_triangles, pl, w, out->chart_of_tri,
+                              out->charts, occupancy_low, ctx->small_texels, ctx->lane_texels,
+                              st) != hipSuccess)
+    return FA_ERR_DEVICE;
+  return FA_OK;
 }
 
 // Views run concurrently, view i on scratch slot i % max_views and that

@@ -160,16 +160,19 @@ __global__ void k_vis_compact(const uint8_t* __restrict__ vis, int64_t T,
 }
 
 // Hook across every shared edge once (u < v) (Alg. 1, second loop).
+// With tile > 0 only edges leaving the entry's tile of `tile` consecutive
+// list entries are hooked (the others were joined inside the tile).
 __global__ void k_uf_hook(const uint8_t* __restrict__ vis, const int32_t* __restrict__ nbr,
-                          const int32_t* __restrict__ vlist, int32_t* parent,
+                          const int32_t* __restrict__ vlist, int32_t* parent, int tile,
                           const FrameState* __restrict__ st) {
   const int nv = st->visible;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
     const int t = vlist[i];
+    const int last = tile > 0 ? vlist[min(nv, (i / tile + 1) * tile) - 1] : -1;
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
       const int n = nbr[3 * (int64_t)t + e];
-      if (n > t && vis[n]) uf_join(parent, t, n);
+      if (n > t && n > last && vis[n]) uf_join(parent, t, n);
     }
   }
 }
@@ -601,11 +604,13 @@ hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* 
   const unsigned g = visible_grid(T);
   const unsigned vt = std::max(1u, grid_for(T, kTriTile));
   if (T > 0) {
-    if (p.edge_hooks == 1)
-      k_uf_hook<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, w.state);
-    else if (p.edge_hooks == 2)
+    if (p.edge_hooks == 1) {
+      k_uf_hook<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, 0, w.state);
+    } else if (p.edge_hooks == 2) {
       k_uf_local<<<std::max(1u, grid_for(T, kUfTile)), kUfThreads, 0, st>>>(vis, nbr, w.vlist,
                                                                             w.parent, w.state);
+      k_uf_hook<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, kUfTile, w.state);
+    }
     mk(st);
     k_uf_vertex_min<<<g, kBlock, 0, st>>>(idx, w.vlist, w.parent, w.vmin, w.state);
     mk(st);

@@ -32,7 +32,7 @@ __device__ __forceinline__ ChartXform chart_xform(const fa_chart& ch, const Fram
   m.halfH = 0.5f * (float)p.H;
   m.rate = p.rate;
   m.s = st.s_star;
-  m.q = st.q_star;
+  m.q = (float)p.omega / (float)st.layout_w;  // omega/L (the atlas side being drawn)
   m.ox = (float)(ch.x + p.gutter);
   m.oy = (float)(ch.y + p.gutter);
   m.rot = ch.rotated;
@@ -500,6 +500,36 @@ hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p,
   k_occ_count<<<kCountGrid, kBlock, 0, st>>>(reinterpret_cast<const int4*>(occ), n4, w.partial);
   mk(st);
   return hipGetLastError();
+}
+
+namespace {
+// Texel range of every placed box for an atlas of side p.omega (the same exact
+// integer membership test as at placement), and an empty large-footprint
+// queue: the start of an occupancy pass at another atlas side.
+__global__ void k_chart_tex(FrameParams p, const fa_chart* __restrict__ charts,
+                            int4* __restrict__ chart_tex, unsigned long long* __restrict__ big_counter,
+                            const FrameState* __restrict__ stp) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c == 0) *big_counter = 0ull;
+  const FrameState st = *stp;
+  if (st.status != FA_OK || c >= st.num_charts) return;
+  const fa_chart& ch = charts[c];
+  const int64_t om = p.omega, L = st.layout_w, L2 = 2 * L;
+  chart_tex[c] = make_int4((int)ceil_div64(2 * (int64_t)ch.x * om - L, L2),
+                           (int)ceil_div64(2 * ((int64_t)ch.x + ch.w) * om - L, L2) - 1,
+                           (int)ceil_div64(2 * (int64_t)ch.y * om - L, L2),
+                           (int)ceil_div64(2 * ((int64_t)ch.y + ch.h) * om - L, L2) - 1);
+}
+}  // namespace
+
+hipError_t launch_occupancy_scaled(const int32_t* idx, int64_t T, const FrameParams& p,
+                                   const Work& w, const int32_t* cot, const fa_chart* charts,
+                                   int32_t* occ, int small_texels, int lane_texels,
+                                   hipStream_t st) {
+  k_chart_tex<<<(unsigned)((p.max_charts + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+      p, charts, w.chart_tex, w.big_counter, w.state);
+  Marker none;
+  return launch_occupancy(idx, T, p, w, cot, charts, occ, small_texels, lane_texels, none, st);
 }
 
 hipError_t launch_meta(const FrameParams& p, const Work& w, fa_atlas_meta* meta,

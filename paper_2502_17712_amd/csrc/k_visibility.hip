@@ -223,7 +223,64 @@ __global__ __launch_bounds__(kBlock) void k_vis_depth(const float* __restrict__ 
   }
 }
 
+// Temporal reuse classification (Sec. "Temporal Reuse"): 0 not visible now,
+// 1 reuse the key frame's shading, 2 shade (newly visible, or some vertex had
+// max(|x|, |y|) >= w in the key frame's clip space, float32 as the atlas path
+// computes it). One atomic per wave counts the reused triangles.
+__global__ void k_zero64(unsigned long long* p) { *p = 0ull; }
+
+__global__ __launch_bounds__(kBlock) void k_reuse_flags(
+    const float* __restrict__ pos, const int32_t* __restrict__ idx, int64_t T, KeyClip kc,
+    const uint8_t* __restrict__ key_vis, const uint8_t* __restrict__ vis,
+    uint8_t* __restrict__ flags, unsigned long long* __restrict__ reused) {
+  for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x; b0 < T;
+       b0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = b0 + threadIdx.x;
+    bool reuse = false;
+    if (t < T) {
+      uint8_t f = 0;
+      if (vis[t]) {
+        bool partial = false;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          const int64_t v = idx[3 * t + e];
+          const float x = pos[3 * v], y = pos[3 * v + 1], z = pos[3 * v + 2];
+          float r[4];
+#pragma unroll
+          for (int i = 0; i < 4; i += 1) {
+            if (i == 2) { r[i] = 0.0f; continue; }  // z is not needed
+            float acc = kc.M[4 * i] * x;
+            acc = acc + kc.M[4 * i + 1] * y;
+            acc = acc + kc.M[4 * i + 2] * z;
+            r[i] = acc + kc.M[4 * i + 3];
+          }
+          if (fmaxf(fabsf(r[0]), fabsf(r[1])) >= r[3]) partial = true;
+        }
+        reuse = key_vis[t] != 0 && !partial;
+        f = reuse ? 1 : 2;
+      }
+      flags[t] = f;
+    }
+    if (reused) {
+      const unsigned long long m = __ballot(reuse);
+      if (m && lane_id() == __ffsll((long long)m) - 1)
+        atomicAdd(reused, (unsigned long long)__popcll(m));
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_reuse_flags(const float* pos, const int32_t* idx, int64_t T, const KeyClip& kc,
+                              const uint8_t* key_vis, const uint8_t* vis, uint8_t* flags,
+                              unsigned long long* reused, hipStream_t st) {
+  if (reused) k_zero64<<<1, 1, 0, st>>>(reused);
+  if (T > 0) {
+    const unsigned g = (unsigned)std::min<int64_t>((T + kBlock - 1) / kBlock, 8192);
+    k_reuse_flags<<<g, kBlock, 0, st>>>(pos, idx, T, kc, key_vis, vis, flags, reused);
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_visibility(const float* pos, const int32_t* idx, int64_t T, const VisParams& q,
                              int32_t* occl, uint32_t* count, unsigned long long* depth,

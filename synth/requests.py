@@ -45,7 +45,8 @@ def pose_pool(name, n, seed=0):
     for k in range(n):
         W, H = RES[int(rng.integers(0, 4))]
         if name == "grid":
-            f = scenes.grid_frame(int(rng.integers(0, 64)))
+            # the served grid scene (scene_meshes), seen from a seeded yaw
+            f = scenes.grid_frame(0)
             pos, tris = f.positions, f.indices
             el = np.radians(45.0)
             yaw = rng.uniform(0, 2 * np.pi)

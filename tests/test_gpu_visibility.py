@@ -179,3 +179,19 @@ def test_serve_device_visibility_equals_precomputed():
         for k in ("chart_of_tri", "chart_of_vert", "occupancy", "candidates"):
             assert np.array_equal(a[k], b[k]), (rid, k)
         assert a["meta"] == b["meta"]
+
+
+@pytest.mark.parametrize("key,frames", [(10, (11, 14, 19)), (0, (0, 3))])
+def test_reuse_flags(key, frames):
+    kf = scenes.orbit_frame(key)
+    ctx = _ctx()
+    m = _mesh(kf)
+    kvis = torch.as_tensor(kf.visible).cuda()
+    for k in frames:
+        f = scenes.orbit_frame(k)
+        print(f"[gpu] reuse flags key {key} frame {k}", flush=True)
+        flags, reused = ctx.reuse_flags(m, kf.view_proj, kvis, torch.as_tensor(f.visible).cuda())
+        torch.cuda.synchronize()
+        ref, n = oracle.reuse_flags(f.positions, f.indices, kf.view_proj, kf.visible, f.visible)
+        assert np.array_equal(flags.cpu().numpy(), ref)
+        assert int(reused.item()) == n
