@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "atlas ms/frame (2M tris, 4K view); batched views/s vs plain; p99 latency"
 HBM_PEAK_GBS = 8000.0
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def log(*a):
@@ -42,7 +43,7 @@ def kernel_bytes(name, T, V, Tv, Vv, C, J, omega, occupied):
     """Algorithmic bytes of one launch of a kernel (what it must read and write
     at minimum); the per-unit figures are listed in the design doc."""
     per = {
-        "prologue": V * (12 + 16 + 4 + 4) + T * (1 + 4) + Tv * (12 + 4 + 4),
+        "prologue": V * (12 + 16 + 4 + 4) + T * (1 + 4),
         "vis_compact": T * 1 + Tv * 4,
         "uf_hook": Tv * (4 + 12 + 3 + 4),
         "uf_vertex_min": Tv * (4 + 4 + 12 + 12),
@@ -56,102 +57,40 @@ def kernel_bytes(name, T, V, Tv, Vv, C, J, omega, occupied):
         "uv": V * (16 + 4 + 8) + C * 64,
         "occ_fill": omega * omega * 4,
         "occ_small": Tv * (4 + 4 + 12 + 48) + occupied * 4,
+        # the two occupancy raster kernels are one job split by footprint size:
+        # geometry of every visible triangle read once, every covered texel
+        # written once
+        "occ_small+occ_big": Tv * (4 + 4 + 12 + 48) + occupied * 4,
         "occ_count": omega * omega * 4,
     }
     return per.get(name)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=32)
-    ap.add_argument("--frames", type=int, default=32, help="distinct orbit frames")
-    ap.add_argument("--rate", type=float, default=1.0)
-    ap.add_argument("--atlas", type=int, default=4096)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--cpu-frames", type=int, default=4)
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--no-dual", action="store_true")
-    ap.add_argument("--serve-rate", type=float, nargs="+", default=[60.0, 250.0, 1000.0, 2000.0])
-    ap.add_argument("--serve-requests", type=int, default=1000)
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only run 4 plain device copies of 256 MiB (counter calibration)")
-    args = ap.parse_args()
-    if args.calibrate_copy:
-        import torch
-        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
-        a.fill_(1)
-        for _ in range(4):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": a.numel(), "copies": 4}))
-        return
-    if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current sources of that kernel; else None."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", "traffic_occ_raster_city4k.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel") != kernel:
+        return None
+    for name in ("k_raster.hip", "fa_internal.h"):
+        src = os.path.join(HERE, "paper_2502_17712_amd", "csrc", name)
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get(f"sha256 {name}"):
+            return None
+    return float(fields["hbm_bytes_per_launch"])
 
+
+def extras(args, ctx, mesh, frames, vis, out, stream, dev, T):
+    """No-occupancy frame time, device copy bandwidth, the device visibility
+    pass and temporal reuse on the benchmark frames."""
     import torch
-    import paper_2502_17712_amd as fa
-    TUNED = (fa.FA_TUNE_OCC_SMALL_TEXELS, fa.FA_TUNE_OCC_LANE_TEXELS, fa.FA_TUNE_UF_LINK_INIT,
-             fa.FA_TUNE_UF_EDGE_HOOKS, fa.FA_TUNE_PACK_BLOCK)
-    from synth import scenes
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    t0 = time.time()
-    pos, tris = scenes.city_scene()
-    frames = [scenes.city_frame(f, rate=args.rate, atlas_size=args.atlas)
-              for f in range(0, 32, max(1, 32 // args.frames))][: args.frames]
-    log(f"generated {len(frames)} frames in {time.time() - t0:.1f}s; T={tris.shape[0]} "
-        f"V={pos.shape[0]}")
-    T, V = tris.shape[0], pos.shape[0]
-    ctx = fa.Context(T, V, max_charts=65536, max_atlas=args.atlas)
-    mesh = fa.Mesh(pos, tris, frames[0].scene_key)
-    vis = [torch.as_tensor(f.visible).to(dev) for f in frames]
-    out = ctx.outputs(mesh, args.atlas)
-    stream = torch.cuda.current_stream()
-
-    # per-scene adjacency (resident afterwards), timed on its own
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    ctx.adjacency(mesh)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    adjacency_ms = e0.elapsed_time(e1)
-
-    def step(k):
-        f = frames[k % len(frames)]
-        ctx.build_atlas(mesh, vis[k % len(frames)], f.view_proj, f.width, f.height,
-                        f.atlas_size, f.rate, out=out, stream=stream)
-
-    tuning = None
-    if not args.no_autotune:
-        from paper_2502_17712_amd import autotune
-        tuning = autotune.tune(ctx, lambda: step(0), out)
-        log("autotune:", json.dumps(tuning))
-    for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    for k in range(args.steps):
-        evs[k][0].record(stream)
-        step(k)
-        evs[k][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    per = np.array([a.elapsed_time(b) for a, b in evs])
-    meta = fa.parse_meta(out.meta)
-    assert meta["status"] == fa.FA_OK, meta
 
     # the same frames without the occupancy output (UVs and placements only)
     out_nocc = ctx.outputs(mesh, args.atlas, occupancy=False)
@@ -228,6 +167,108 @@ def main():
     reuse = dict(key_interval=10, mean_reused_fraction=float(np.mean(fr_re)) if fr_re else None,
                  min_reused_fraction=float(np.min(fr_re)) if fr_re else None,
                  flags_ms=float(np.mean(ms_re)) if ms_re else None)
+    return ms_nocc, copy_gbs, visibility, reuse
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=32)
+    ap.add_argument("--frames", type=int, default=32, help="distinct orbit frames")
+    ap.add_argument("--rate", type=float, default=1.0)
+    ap.add_argument("--atlas", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--cpu-frames", type=int, default=4)
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the knobs on the first frame first (default: library defaults)")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-dual", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the no-occupancy, copy, visibility and reuse measurements")
+    ap.add_argument("--serve-rate", type=float, nargs="+", default=[60.0, 250.0, 1000.0, 2000.0])
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run 4 plain device copies of 256 MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel(), "copies": 4}))
+        return
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2502_17712_amd as fa
+    TUNED = (fa.FA_TUNE_OCC_SMALL_TEXELS, fa.FA_TUNE_OCC_LANE_TEXELS, fa.FA_TUNE_UF_LINK_INIT,
+             fa.FA_TUNE_UF_EDGE_HOOKS, fa.FA_TUNE_PACK_BLOCK)
+    from synth import scenes
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    pos, tris = scenes.city_scene()
+    frames = [scenes.city_frame(f, rate=args.rate, atlas_size=args.atlas)
+              for f in range(0, 32, max(1, 32 // args.frames))][: args.frames]
+    log(f"generated {len(frames)} frames in {time.time() - t0:.1f}s; T={tris.shape[0]} "
+        f"V={pos.shape[0]}")
+    T, V = tris.shape[0], pos.shape[0]
+    ctx = fa.Context(T, V, max_charts=65536, max_atlas=args.atlas)
+    mesh = fa.Mesh(pos, tris, frames[0].scene_key)
+    vis = [torch.as_tensor(f.visible).to(dev) for f in frames]
+    out = ctx.outputs(mesh, args.atlas)
+    stream = torch.cuda.current_stream()
+
+    # per-scene adjacency (resident afterwards), timed on its own
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.adjacency(mesh)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    adjacency_ms = e0.elapsed_time(e1)
+
+    def step(k):
+        f = frames[k % len(frames)]
+        ctx.build_atlas(mesh, vis[k % len(frames)], f.view_proj, f.width, f.height,
+                        f.atlas_size, f.rate, out=out, stream=stream)
+
+    tuning = None
+    if args.autotune:
+        from paper_2502_17712_amd import autotune
+        tuning = autotune.tune(ctx, lambda: step(0), out)
+        log("autotune:", json.dumps(tuning))
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for k in range(args.steps):
+        evs[k][0].record(stream)
+        step(k)
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    per = np.array([a.elapsed_time(b) for a, b in evs])
+    meta = fa.parse_meta(out.meta)
+    assert meta["status"] == fa.FA_OK, meta
+
+    ms_nocc = copy_gbs = visibility = reuse = None
+    if not args.no_extras:
+        ms_nocc, copy_gbs, visibility, reuse = extras(args, ctx, mesh, frames, vis, out, stream,
+                                                      dev, T)
 
     # per-kernel live times (separate pass with an event after every kernel)
     ctx.set_stage_timing(True)
@@ -252,14 +293,19 @@ def main():
     Tv, Vv, C = (float(np.mean([s[i] for s in stats])) for i in range(3))
     B = algorithmic_bytes(T, V, Tv, Vv, C, 64, args.atlas)
     occupied = float(meta["occupied_texels"])
-    dom = max(stages, key=stages.get) if stages else None
+    # the dominant kernel; the two occupancy raster kernels count as one
+    timed = {k: v for k, v in stages.items() if k not in ("occ_small", "occ_big")}
+    if "occ_small" in stages:
+        timed["occ_small+occ_big"] = stages["occ_small"] + stages.get("occ_big", 0.0)
+    dom = max(timed, key=timed.get) if timed else None
     roofline = None
     if dom is not None:
         kb = kernel_bytes(dom, T, V, Tv, Vv, C, 64, args.atlas, occupied)
-        ach = kb / (stages[dom] * 1e-3) / 1e9 if kb else None
+        ach = kb / (timed[dom] * 1e-3) / 1e9 if kb else None
         roofline = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": (ach / HBM_PEAK_GBS) if ach else None,
-                    "traffic": None, "kernel_ms": stages[dom], "algorithmic_bytes": kb}
+                    "traffic": measured_traffic(dom), "kernel_ms": timed[dom],
+                    "algorithmic_bytes": kb}
 
     # secondary workloads: the small and medium scenes, other rates on the large one
     def time_frames(ctx_, mesh_, frs, reps=3):
@@ -466,10 +512,10 @@ def main():
         "large_tiles": meta["large_tiles"],
         "algorithmic_bytes_per_frame": B,
         "frame_hbm_roofline_frac": B / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
-        "no_occupancy": {"ms_per_frame": ms_nocc,
-                         "algorithmic_bytes": B - 4.0 * args.atlas * args.atlas,
-                         "hbm_roofline_frac": (B - 4.0 * args.atlas * args.atlas)
-                         / (ms_nocc * 1e-3) / (HBM_PEAK_GBS * 1e9)},
+        "no_occupancy": None if ms_nocc is None else {
+            "ms_per_frame": ms_nocc, "algorithmic_bytes": B - 4.0 * args.atlas * args.atlas,
+            "hbm_roofline_frac": (B - 4.0 * args.atlas * args.atlas) / (ms_nocc * 1e-3)
+            / (HBM_PEAK_GBS * 1e9)},
         "dependent_phases": len(stages),
         "pack_rows_at_chosen_scale": meta["rows"],
         "copy_gbs": copy_gbs,

@@ -54,9 +54,9 @@ struct fa_ctx {
   hipEvent_t ev[kStages + 1] = {};
   bool ev_recorded = false;
   int ev_marks = 0;
-  int pack_block = 256;
+  int pack_block = 1024;
   int small_texels = 256;
-  int lane_texels = 32;
+  int lane_texels = 64;
   int uf_link_init = 1;
   int uf_edge_hooks = 2;
   int32_t* check_flag = nullptr;  // device int for index validation

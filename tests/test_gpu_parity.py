@@ -148,7 +148,7 @@ def test_city_frames_more():
         compare(g, oracle.build_frame(f, want_occupancy=False), occupancy=False)
 
 
-@pytest.mark.parametrize("knob,value", [(1, 512), (1, 1024), (2, 0), (2, 16), (2, 1024),
+@pytest.mark.parametrize("knob,value", [(1, 256), (1, 512), (2, 0), (2, 16), (2, 1024),
                                         (2, 4096), (3, 0), (5, 0), (5, 1), (6, 0), (6, 1), (6, 4096)])
 def test_tuning_knobs_do_not_change_results(knob, value):
     fa = _fa()
