@@ -177,6 +177,47 @@ __global__ void k_uf_hook(const uint8_t* __restrict__ vis, const int32_t* __rest
   }
 }
 
+// Edges between tiles, after the LDS pass: an edge (t, n) joins the sets of
+// parent[t] and parent[n] (ancestors of t and n). Lanes of a wave whose edges
+// name the same pair of parents keep only the lowest lane, so a pair that many
+// edges along a tile border share is hooked once per wave instead of every
+// lane contending for the same root.
+__global__ void k_uf_cross(const uint8_t* __restrict__ vis, const int32_t* __restrict__ nbr,
+                           const int32_t* __restrict__ vlist, int32_t* parent, int tile,
+                           const FrameState* __restrict__ st) {
+  const int nv = st->visible;
+  const int lane = lane_id();
+  for (int i0 = blockIdx.x * blockDim.x; i0 < nv; i0 += gridDim.x * blockDim.x) {
+    const int i = i0 + threadIdx.x;
+    const bool valid = i < nv;
+    const int t = valid ? vlist[i] : 0;
+    const int last = valid ? vlist[min(nv, (i / tile + 1) * tile) - 1] : 0;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const int n = valid ? nbr[3 * (int64_t)t + e] : -1;
+      bool want = valid && n > last && vis[n];
+      int a = 0, b = 0;
+      if (want) {
+        a = parent[t];
+        b = parent[n];
+        if (a > b) { const int s = a; a = b; b = s; }
+        want = a != b;
+      }
+      // keep the lowest lane of every distinct (a, b)
+      unsigned long long todo = __ballot(want);
+      bool keep = false;
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int la = __shfl(a, leader, kWave), lb = __shfl(b, leader, kWave);
+        const bool same = want && a == la && b == lb;
+        if (lane == leader) keep = true;
+        todo &= ~__ballot(same);
+      }
+      if (keep) uf_join(parent, a, b);
+    }
+  }
+}
+
 // Edge hooks inside one tile of kUfTile consecutive entries of the visible
 // list, in LDS: entries are local indices (ascending with the triangle index),
 // a shared edge whose other triangle lies in the tile joins the two local sets
@@ -609,7 +650,7 @@ hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* 
     } else if (p.edge_hooks == 2) {
       k_uf_local<<<std::max(1u, grid_for(T, kUfTile)), kUfThreads, 0, st>>>(vis, nbr, w.vlist,
                                                                             w.parent, w.state);
-      k_uf_hook<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, kUfTile, w.state);
+      k_uf_cross<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, kUfTile, w.state);
     }
     mk(st);
     k_uf_vertex_min<<<g, kBlock, 0, st>>>(idx, w.vlist, w.parent, w.vmin, w.state);

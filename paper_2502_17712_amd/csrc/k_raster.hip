@@ -327,10 +327,9 @@ __global__ __launch_bounds__(kBlock) void k_occ_small(
       const unsigned long long qm = __ballot(want);
       if (qm) {
         // one atomic per wave: lanes take consecutive queue slots and tiles
-        // tiles on the atlas's 16x16 grid, so each tile row is one aligned 64 B line
-        const uint32_t tx_n = want ? (uint32_t)(fp.tx1 / kOccTile - fp.tx0 / kOccTile + 1) : 0u;
-        const uint32_t nt =
-            want ? tx_n * (uint32_t)(fp.ty1 / kOccTile - fp.ty0 / kOccTile + 1) : 0u;
+        const int nx = fp.tx1 - fp.tx0 + 1, ny = fp.ty1 - fp.ty0 + 1;
+        const uint32_t tx_n = want ? (uint32_t)((nx + kOccTile - 1) / kOccTile) : 0u;
+        const uint32_t nt = want ? tx_n * (uint32_t)((ny + kOccTile - 1) / kOccTile) : 0u;
         const uint32_t before = wave_incl_scan<uint32_t>(nt) - nt;
         const uint32_t all = __shfl(before + nt, kWave - 1, kWave);
         const int leader = __ffsll((long long)qm) - 1;
@@ -355,8 +354,8 @@ __global__ __launch_bounds__(kBlock) void k_occ_small(
   }
 }
 
-// Queued footprints: the cells of the atlas's 16x16 grid that each one's texel
-// range touches, concatenated, are split evenly over all waves of the grid; a wave finds its first footprint by a 64-way search over
+// Queued footprints: their texel ranges cut into 16x16 tiles, concatenated,
+// are split evenly over all waves of the grid; a wave finds its first footprint by a 64-way search over
 // the (increasing) first-tile indices and walks forward, 4 texels per lane.
 __global__ __launch_bounds__(kBlock) void k_occ_big(
     const int32_t* __restrict__ idx, FrameParams p, const float4* __restrict__ clip,
@@ -412,15 +411,14 @@ __global__ __launch_bounds__(kBlock) void k_occ_big(
                      p, st, fp);
     if (!ok) continue;
     const uint32_t tt = (uint32_t)(k - base);
-    const int tx = (fp.tx0 / kOccTile + (int)(tt % tiles_x)) * kOccTile + lx;
-    const int ty0 = (fp.ty0 / kOccTile + (int)(tt / tiles_x)) * kOccTile + ly;
+    const int tx = fp.tx0 + kOccTile * (int)(tt % tiles_x) + lx;
+    const int ty0 = fp.ty0 + kOccTile * (int)(tt / tiles_x) + ly;
     Edges ev = edges_at(fp, tx, ty0);
     const Edges dy = madd(Edges{0, 0, 0}, kRows, step_y(fp));
 #pragma unroll
     for (int q = 0; q < kOccTile / kRows; ++q) {
       const int ty = ty0 + q * kRows;
-      if (tx >= fp.tx0 && tx <= fp.tx1 && ty >= fp.ty0 && ty <= fp.ty1 && inside(ev))
-        occ[(int64_t)ty * p.omega + tx] = fp.chart;
+      if (tx <= fp.tx1 && ty <= fp.ty1 && inside(ev)) occ[(int64_t)ty * p.omega + tx] = fp.chart;
       add(ev, dy);
     }
   }

@@ -434,3 +434,24 @@ def test_serve_mix_equals_alone():
     assert sorted(r.rid for r in out) == list(range(8))
     for r in out:
         assert r.meta["status"] == 0
+
+
+@pytest.mark.parametrize("link,hooks", [(0, 0), (0, 1), (0, 2), (1, 0), (1, 1), (1, 2)])
+def test_union_find_modes_all_combinations(link, hooks):
+    """Every (start link, edge-hook mode) pair gives the oracle's charts, frame
+    after frame (the charts do not depend on how the union-find gets there)."""
+    ctx = ctx_for()
+    old = (ctx.get_tuning(3), ctx.get_tuning(5))
+    ctx.set_tuning(3, link)
+    ctx.set_tuning(5, hooks)
+    try:
+        for fr in (0, 16):
+            f = scenes.city_frame(fr)
+            r = oracle.build_frame(f, want_occupancy=False)
+            for rep in range(3):
+                g = run_gpu(f, ctx, occupancy=False)
+                assert np.array_equal(g["chart_of_tri"], r["chart_of_tri"]), (fr, rep)
+                assert np.array_equal(g["chart_of_vert"], r["chart_of_vert"]), (fr, rep)
+    finally:
+        ctx.set_tuning(3, old[0])
+        ctx.set_tuning(5, old[1])
