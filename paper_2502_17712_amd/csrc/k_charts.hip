@@ -17,17 +17,33 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // union-find over visible triangles. parent[x] <= x always holds; a root has
-// parent[x] == x. Path halving stores are agent-scope atomics so they stay
-// coherent with the hooking compare-and-swaps across the chip's L2 caches.
+// parent[x] == x. The eight XCDs have separate L2 caches: a plain load may
+// return a value another XCD has since replaced. Inside a join that is
+// harmless (values only move towards the root, and the compare-and-swap sees
+// the current value), so joins walk with plain loads. Every read whose value
+// is used as the answer (the vertex minima, the final root of a triangle, the
+// root test) is an agent-scope atomic load, and every write of parent[] an
+// agent-scope atomic store; with plain loads there a stale line could show a
+// hooked root as a root and split a chart.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int aload(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void astore(int32_t* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// EXACT: coherent loads (the result is used as the current root);
+// otherwise plain loads (a join re-checks with its compare-and-swap).
+template <bool EXACT>
 __device__ __forceinline__ int uf_root(int32_t* parent, int x) {
-  int cur = parent[x];
+  int cur = EXACT ? aload(&parent[x]) : parent[x];
   if (cur == x) return x;
   int prev = x;
   for (;;) {
-    int nxt = parent[cur];
+    int nxt = EXACT ? aload(&parent[cur]) : parent[cur];
     if (nxt >= cur) return cur;  // parent[cur] == cur
-    __hip_atomic_store(&parent[prev], nxt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    astore(&parent[prev], nxt);
     prev = cur;
     cur = nxt;
   }
@@ -36,7 +52,7 @@ __device__ __forceinline__ int uf_root(int32_t* parent, int x) {
 // Join the trees of u and v: the larger root is hooked below the smaller one
 // with a compare-and-swap; on failure continue from the value that won.
 __device__ __forceinline__ void uf_join(int32_t* parent, int u, int v) {
-  int ru = uf_root(parent, u), rv = uf_root(parent, v);
+  int ru = uf_root<false>(parent, u), rv = uf_root<false>(parent, v);
   while (ru != rv) {
     if (ru < rv) {
       int old = atomicCAS(&parent[rv], rv, ru);
@@ -86,7 +102,7 @@ __global__ void k_prologue(const float* __restrict__ pos, int64_t V, FrameParams
       r[i] = acc + p.M[4 * i + 3];
     }
     clip[v] = make_float4(r[0], r[1], r[2], r[3]);
-    vmin[v] = INT_MAX;
+    astore(&vmin[v], INT_MAX);
     cov[v] = -1;
     return;
   }
@@ -108,7 +124,7 @@ __global__ void k_prologue(const float* __restrict__ pos, int64_t V, FrameParams
         if (n >= 0 && vis[n]) q = min(q, n);
       }
     }
-    if (uf_init) parent[t] = q;
+    if (uf_init) astore(&parent[t], q);
   }
   nv = block_sum<uint32_t>(nv, sh);
   if (threadIdx.x == 0) tile_vis[tile] = nv;
@@ -198,8 +214,8 @@ __global__ void k_uf_cross(const uint8_t* __restrict__ vis, const int32_t* __res
       bool want = valid && n > last && vis[n];
       int a = 0, b = 0;
       if (want) {
-        a = parent[t];
-        b = parent[n];
+        a = aload(&parent[t]);
+        b = aload(&parent[n]);
         if (a > b) { const int s = a; a = b; b = s; }
         want = a != b;
       }
@@ -287,20 +303,23 @@ __global__ __launch_bounds__(kUfThreads) void k_uf_local(const uint8_t* __restri
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < cnt; i += blockDim.x) parent[lv[i]] = lv[lds_root(lp, i)];
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x)
+    astore(&parent[lv[i]], lv[lds_root(lp, i)]);
 }
 
 // Vertex minimum (Alg. 1, third loop): every visible triangle is compressed
-// to its current root and every vertex records the smallest root among its
-// visible triangles. The compression keeps the vertex hook's walks short.
+// to the root it reaches (an ancestor in any case) and every vertex records
+// the smallest of these among its visible triangles; the vertex hook then
+// joins every triangle of the vertex with that one value, read coherently.
+// The compression keeps the vertex hook's walks short.
 __global__ void k_uf_vertex_min(const int32_t* __restrict__ idx,
                                 const int32_t* __restrict__ vlist, int32_t* parent,
                                 int32_t* __restrict__ vmin, const FrameState* __restrict__ st) {
   const int nv = st->visible;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
     const int t = vlist[i];
-    const int r = uf_root(parent, t);
-    if (r != t) __hip_atomic_store(&parent[t], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int r = uf_root<false>(parent, t);
+    if (r != t) astore(&parent[t], r);
 #pragma unroll
     for (int e = 0; e < 3; ++e) atomicMin(&vmin[idx[3 * (int64_t)t + e]], r);
   }
@@ -317,7 +336,7 @@ __global__ void k_uf_vertex_hook(const int32_t* __restrict__ idx,
     const int t = vlist[i];
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
-      const int m = vmin[idx[3 * (int64_t)t + e]];
+      const int m = aload(&vmin[idx[3 * (int64_t)t + e]]);
       if (m != t) uf_join(parent, t, m);
     }
   }
@@ -338,8 +357,8 @@ __global__ void k_uf_flatten_count(const int32_t* __restrict__ vlist, int32_t* p
     const int64_t i = base + k;
     if (i < nv) {
       const int t = vlist[i];
-      const int r = uf_root(parent, t);
-      parent[t] = r;
+      const int r = uf_root<true>(parent, t);
+      astore(&parent[t], r);
       roots += (r == t);
     }
   }
@@ -367,7 +386,7 @@ __global__ void k_assign_roots(const int32_t* __restrict__ vlist,
   for (int k = 0; k < 4; ++k) {
     const int64_t i = base + k;
     tv[k] = i < nv ? vlist[i] : -1;
-    root[k] = tv[k] >= 0 && parent[tv[k]] == tv[k];
+    root[k] = tv[k] >= 0 && aload(&parent[tv[k]]) == tv[k];
     mine += root[k];
   }
   uint32_t tot;
@@ -545,7 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_boxes(
     tv[k] = i < nv ? vlist[i] : -1;
   }
 #pragma unroll
-  for (int k = 0; k < kGatherItems; ++k) cv[k] = tv[k] >= 0 ? parent[tv[k]] : 0;
+  for (int k = 0; k < kGatherItems; ++k) cv[k] = tv[k] >= 0 ? aload(&parent[tv[k]]) : 0;
 #pragma unroll
   for (int k = 0; k < kGatherItems; ++k) {
     const int t = max(tv[k], 0);

@@ -355,8 +355,9 @@ __global__ __launch_bounds__(kBlock) void k_occ_small(
 }
 
 // Queued footprints: their texel ranges cut into 16x16 tiles, concatenated,
-// are split evenly over all waves of the grid; a wave finds its first footprint by a 64-way search over
-// the (increasing) first-tile indices and walks forward, 4 texels per lane.
+// are split evenly over all waves of the grid; a wave finds its first
+// footprint by a 64-way search over the (increasing) first-tile indices and
+// walks forward, 4 texels per lane.
 __global__ __launch_bounds__(kBlock) void k_occ_big(
     const int32_t* __restrict__ idx, FrameParams p, const float4* __restrict__ clip,
     const int32_t* __restrict__ cot, const fa_chart* __restrict__ charts,
@@ -387,40 +388,63 @@ __global__ __launch_bounds__(kBlock) void k_occ_big(
     lo += (uint32_t)(cnt - 1) * step;
     hi = min(hi, lo + step);
   }
-  uint32_t e = lo;
-  ulonglong2 ent = big[e];
-  uint64_t base = ent.y & kLow, nt = ent.y >> kSlotShift;
-  uint32_t code = (uint32_t)ent.x, tiles_x = (uint32_t)(ent.x >> 32);
-  Footprint fp;
-  bool ok = footprint((int64_t)(code >> 1), (int)(code & 1u), idx, clip, cot, charts, chart_tex,
-                      p, st, fp);
+  // The wave's footprints are set up 64 at a time, one per lane (their
+  // dependent loads overlap), then rasterized one after another with the
+  // footprint broadcast from its lane.
   const int lx = lane % kOccTile, ly = lane / kOccTile;
   constexpr int kRows = kWave / kOccTile;
-  for (uint64_t k = k0; k < k1; ++k) {
-    bool moved = false;
-    while (k >= base + nt) {
-      ent = big[++e];
+  for (uint32_t e0 = lo; e0 < nent;) {
+    const uint32_t my = e0 + (uint32_t)lane;
+    uint64_t base = 0, nt = 0;
+    uint32_t tiles_x = 1;
+    bool mine = false, ok = false;
+    Footprint f;
+    f.ax = f.ay = f.bx = f.by = f.cx = f.cy = 0;
+    f.tx0 = f.tx1 = f.ty0 = f.ty1 = f.chart = f.neg = 0;
+    if (my < nent) {
+      const ulonglong2 ent = big[my];
       base = ent.y & kLow;
       nt = ent.y >> kSlotShift;
-      code = (uint32_t)ent.x;
       tiles_x = (uint32_t)(ent.x >> 32);
-      moved = true;
+      mine = base < k1;
+      if (mine) {
+        const uint32_t code = (uint32_t)ent.x;
+        ok = footprint((int64_t)(code >> 1), (int)(code & 1u), idx, clip, cot, charts, chart_tex,
+                       p, st, f);
+      }
     }
-    if (moved)
-      ok = footprint((int64_t)(code >> 1), (int)(code & 1u), idx, clip, cot, charts, chart_tex,
-                     p, st, fp);
-    if (!ok) continue;
-    const uint32_t tt = (uint32_t)(k - base);
-    const int tx = fp.tx0 + kOccTile * (int)(tt % tiles_x) + lx;
-    const int ty0 = fp.ty0 + kOccTile * (int)(tt / tiles_x) + ly;
-    Edges ev = edges_at(fp, tx, ty0);
-    const Edges dy = madd(Edges{0, 0, 0}, kRows, step_y(fp));
+    const int cnt = __popcll(__ballot(mine));  // entries start in order: a prefix of lanes
+    for (int j = 0; j < cnt; ++j) {
+      if (!rl((int)ok, j)) continue;
+      Footprint fp;
+      fp.ax = rl(f.ax, j); fp.ay = rl(f.ay, j);
+      fp.bx = rl(f.bx, j); fp.by = rl(f.by, j);
+      fp.cx = rl(f.cx, j); fp.cy = rl(f.cy, j);
+      fp.tx0 = rl(f.tx0, j); fp.tx1 = rl(f.tx1, j);
+      fp.ty0 = rl(f.ty0, j); fp.ty1 = rl(f.ty1, j);
+      fp.chart = rl(f.chart, j); fp.neg = rl(f.neg, j);
+      const uint64_t bj = ((uint64_t)(uint32_t)rl((int)(uint32_t)(base >> 32), j) << 32) |
+                          (uint32_t)rl((int)(uint32_t)base, j);
+      const uint64_t nj = (uint64_t)(uint32_t)rl((int)(uint32_t)nt, j);
+      const uint32_t txj = (uint32_t)rl((int)tiles_x, j);
+      const uint64_t t0 = (k0 > bj ? k0 : bj) - bj;
+      const uint64_t t1 = (k1 < bj + nj ? k1 : bj + nj) - bj;
+      const Edges dy = madd(Edges{0, 0, 0}, kRows, step_y(fp));
+      for (uint64_t tt = t0; tt < t1; ++tt) {
+        const int tx = fp.tx0 + kOccTile * (int)(tt % txj) + lx;
+        const int ty0 = fp.ty0 + kOccTile * (int)(tt / txj) + ly;
+        Edges ev = edges_at(fp, tx, ty0);
 #pragma unroll
-    for (int q = 0; q < kOccTile / kRows; ++q) {
-      const int ty = ty0 + q * kRows;
-      if (tx <= fp.tx1 && ty <= fp.ty1 && inside(ev)) occ[(int64_t)ty * p.omega + tx] = fp.chart;
-      add(ev, dy);
+        for (int q = 0; q < kOccTile / kRows; ++q) {
+          const int ty = ty0 + q * kRows;
+          if (tx <= fp.tx1 && ty <= fp.ty1 && inside(ev))
+            occ[(int64_t)ty * p.omega + tx] = fp.chart;
+          add(ev, dy);
+        }
+      }
     }
+    if (cnt < kWave) break;
+    e0 += kWave;
   }
 }
 
