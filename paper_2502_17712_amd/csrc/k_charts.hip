@@ -17,14 +17,11 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // union-find over visible triangles. parent[x] <= x always holds; a root has
-// parent[x] == x. The eight XCDs have separate L2 caches: a plain load may
-// return a value another XCD has since replaced. Inside a join that is
-// harmless (values only move towards the root, and the compare-and-swap sees
-// the current value), so joins walk with plain loads. Every read whose value
-// is used as the answer (the vertex minima, the final root of a triangle, the
-// root test) is an agent-scope atomic load, and every write of parent[] an
-// agent-scope atomic store; with plain loads there a stale line could show a
-// hooked root as a root and split a chart.
+// parent[x] == x. The eight XCDs have separate L2 caches and parent[] is
+// rewritten every frame, so a plain load can return another XCD's or an
+// earlier frame's value; a path-halving store built on such a value can undo
+// a hook. Every read of parent[] and of the vertex minima is therefore an
+// agent-scope atomic load and every write an agent-scope atomic store.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int aload(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -33,15 +30,12 @@ __device__ __forceinline__ void astore(int32_t* p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// EXACT: coherent loads (the result is used as the current root);
-// otherwise plain loads (a join re-checks with its compare-and-swap).
-template <bool EXACT>
 __device__ __forceinline__ int uf_root(int32_t* parent, int x) {
-  int cur = EXACT ? aload(&parent[x]) : parent[x];
+  int cur = aload(&parent[x]);
   if (cur == x) return x;
   int prev = x;
   for (;;) {
-    int nxt = EXACT ? aload(&parent[cur]) : parent[cur];
+    int nxt = aload(&parent[cur]);
     if (nxt >= cur) return cur;  // parent[cur] == cur
     astore(&parent[prev], nxt);
     prev = cur;
@@ -52,7 +46,7 @@ __device__ __forceinline__ int uf_root(int32_t* parent, int x) {
 // Join the trees of u and v: the larger root is hooked below the smaller one
 // with a compare-and-swap; on failure continue from the value that won.
 __device__ __forceinline__ void uf_join(int32_t* parent, int u, int v) {
-  int ru = uf_root<false>(parent, u), rv = uf_root<false>(parent, v);
+  int ru = uf_root(parent, u), rv = uf_root(parent, v);
   while (ru != rv) {
     if (ru < rv) {
       int old = atomicCAS(&parent[rv], rv, ru);
@@ -308,17 +302,15 @@ __global__ __launch_bounds__(kUfThreads) void k_uf_local(const uint8_t* __restri
 }
 
 // Vertex minimum (Alg. 1, third loop): every visible triangle is compressed
-// to the root it reaches (an ancestor in any case) and every vertex records
-// the smallest of these among its visible triangles; the vertex hook then
-// joins every triangle of the vertex with that one value, read coherently.
-// The compression keeps the vertex hook's walks short.
+// to its current root and every vertex records the smallest root among its
+// visible triangles. The compression keeps the vertex hook's walks short.
 __global__ void k_uf_vertex_min(const int32_t* __restrict__ idx,
                                 const int32_t* __restrict__ vlist, int32_t* parent,
                                 int32_t* __restrict__ vmin, const FrameState* __restrict__ st) {
   const int nv = st->visible;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
     const int t = vlist[i];
-    const int r = uf_root<false>(parent, t);
+    const int r = uf_root(parent, t);
     if (r != t) astore(&parent[t], r);
 #pragma unroll
     for (int e = 0; e < 3; ++e) atomicMin(&vmin[idx[3 * (int64_t)t + e]], r);
@@ -334,16 +326,23 @@ __global__ void k_uf_vertex_hook(const int32_t* __restrict__ idx,
   const int nv = st->visible;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
     const int t = vlist[i];
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-      const int m = aload(&vmin[idx[3 * (int64_t)t + e]]);
-      if (m != t) uf_join(parent, t, m);
-    }
+    const int m0 = aload(&vmin[idx[3 * (int64_t)t]]), m1 = aload(&vmin[idx[3 * (int64_t)t + 1]]);
+    const int m2 = aload(&vmin[idx[3 * (int64_t)t + 2]]);
+    // parent[t] is an ancestor of t (its root at the vertex minimum): a vertex
+    // whose minimum equals it needs no join, which skips almost every one
+    const int pt = aload(&parent[t]);
+    if (m0 != pt) uf_join(parent, pt, m0);
+    if (m1 != pt && m1 != m0) uf_join(parent, pt, m1);
+    if (m2 != pt && m2 != m0 && m2 != m1) uf_join(parent, pt, m2);
   }
 }
 
 // Flatten every visible triangle to its root and count roots per tile of
-// kTriTile consecutive entries of the visible list.
+// kTriTile consecutive entries of the visible list. The walk here only reads:
+// a path-halving store by one thread (parent[x] = a grandparent it read
+// earlier) could land after another thread has set parent[x] to the root and
+// leave x pointing at a non-root, which the later stages would read as the
+// chart's root.
 __global__ void k_uf_flatten_count(const int32_t* __restrict__ vlist, int32_t* parent,
                                    uint32_t* __restrict__ tile_count,
                                    const FrameState* __restrict__ st) {
@@ -357,8 +356,12 @@ __global__ void k_uf_flatten_count(const int32_t* __restrict__ vlist, int32_t* p
     const int64_t i = base + k;
     if (i < nv) {
       const int t = vlist[i];
-      const int r = uf_root<true>(parent, t);
-      astore(&parent[t], r);
+      int r = t, up = aload(&parent[t]);
+      while (up != r) {
+        r = up;
+        up = aload(&parent[r]);
+      }
+      if (r != t) astore(&parent[t], r);
       roots += (r == t);
     }
   }

@@ -253,7 +253,7 @@ __global__ void k_pack_prepare(const float* __restrict__ sizes, int32_t n,
   const float tw = sizes[2 * c], th = sizes[2 * c + 1];
   const float lim = 16777216.0f;  // 2^24 texels
   if (!(tw >= 0.0f && tw <= lim && th >= 0.0f && th <= lim)) {
-    atomicExch(&st->status, (int32_t)FA_ERR_INVALID_ARG);
+    st->status = FA_ERR_INVALID_ARG;  // every writer stores the same value
     return;
   }
   const int rot = tw > th ? 1 : 0;

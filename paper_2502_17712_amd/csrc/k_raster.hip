@@ -297,17 +297,30 @@ constexpr unsigned long long kSlotShift = 40;  // queue counter: footprints << 4
 
 // Occupancy of the visible triangles. Per fan footprint (texel range of n
 // texels): n <= lane_texels by its own lane; lane_texels < n <= small_texels
-// by its whole wave; larger ones are queued (one atomic per wave) for k_occ_big.
-__global__ __launch_bounds__(kBlock) void k_occ_small(
+// by its whole wave; larger ones are queued for k_occ_big. Both fans of every
+// triangle are set up first and the queue is reserved with one atomic per
+// workgroup and step (a single counter serializes at about 12 ns per atomic);
+// the rasterization after it runs without barriers.
+constexpr int kOccSmallBlock = 256;
+
+__device__ __forceinline__ uint32_t tiles_of(const Footprint& fp, uint32_t* tiles_x) {
+  *tiles_x = (uint32_t)((fp.tx1 - fp.tx0 + kOccTile) / kOccTile);
+  return *tiles_x * (uint32_t)((fp.ty1 - fp.ty0 + kOccTile) / kOccTile);
+}
+
+__global__ __launch_bounds__(kOccSmallBlock) void k_occ_small(
     const int32_t* __restrict__ idx, const int32_t* __restrict__ vlist, FrameParams p,
     const float4* __restrict__ clip, const int32_t* __restrict__ cot,
     const fa_chart* __restrict__ charts, const int4* __restrict__ chart_tex,
     int32_t* __restrict__ occ, ulonglong2* __restrict__ big, uint32_t big_cap, int small_texels,
     int lane_texels, unsigned long long* __restrict__ big_counter,
     const FrameState* __restrict__ stp) {
+  __shared__ uint32_t wcnt[kOccSmallBlock / kWave], wtil[kOccSmallBlock / kWave];
+  __shared__ unsigned long long bbase;
   const FrameState st = *stp;
   if (st.status != FA_OK) return;
   const int nv = st.visible;
+  const int lane = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
   constexpr unsigned long long kLow = (1ull << kSlotShift) - 1;
   for (int i0 = blockIdx.x * blockDim.x; i0 < nv; i0 += gridDim.x * blockDim.x) {
     const int i = i0 + threadIdx.x;
@@ -317,40 +330,65 @@ __global__ __launch_bounds__(kBlock) void k_occ_small(
     sp.chart = -1;
     const int t = valid ? vlist[i] : 0;
     if (valid) snap_polygon(t, idx, clip, cot, charts, p, st, sp);
-    for (int f = 0; f < 2; ++f) {
-      Footprint fp;
-      const bool ok = sp.n > 0 && fan_footprint(sp, f, chart_tex[sp.chart], p.omega, fp);
-      if (!__ballot(ok)) continue;
-      const int n = ok ? (fp.tx1 - fp.tx0 + 1) * (fp.ty1 - fp.ty0 + 1) : 0;
-      const bool want = ok && n > small_texels;
-      bool queued = false;
-      const unsigned long long qm = __ballot(want);
-      if (qm) {
-        // one atomic per wave: lanes take consecutive queue slots and tiles
-        const int nx = fp.tx1 - fp.tx0 + 1, ny = fp.ty1 - fp.ty0 + 1;
-        const uint32_t tx_n = want ? (uint32_t)((nx + kOccTile - 1) / kOccTile) : 0u;
-        const uint32_t nt = want ? tx_n * (uint32_t)((ny + kOccTile - 1) / kOccTile) : 0u;
-        const uint32_t before = wave_incl_scan<uint32_t>(nt) - nt;
-        const uint32_t all = __shfl(before + nt, kWave - 1, kWave);
-        const int leader = __ffsll((long long)qm) - 1;
-        unsigned long long old = 0;
-        if (lane_id() == leader)
-          old = atomicAdd(big_counter, ((unsigned long long)__popcll(qm) << kSlotShift) | all);
-        old = __shfl(old, leader, kWave);
-        const unsigned long long slot = (old >> kSlotShift) + __popcll(qm & lanes_below());
-        if (want && slot < big_cap) {
-          // x: footprint code | tiles across << 32; y: first tile | tiles << 40
-          big[slot] = make_ulonglong2(
-              (unsigned long long)(2 * (int64_t)t + f) | ((unsigned long long)tx_n << 32),
-              ((old & kLow) + before) | ((unsigned long long)nt << kSlotShift));
-          queued = true;
-        }
-      }
-      const bool coop = ok && !queued && n > lane_texels;
-      if (ok && !queued && !coop) raster_lane(fp, occ, p.omega);
-      for (unsigned long long cm = __ballot(coop); cm; cm &= cm - 1)
-        raster_wave(fp, __ffsll((long long)cm) - 1, occ, p.omega);
+    Footprint fa, fb;
+    const int4 box = sp.n > 0 ? chart_tex[sp.chart] : make_int4(0, -1, 0, -1);
+    const bool oka = sp.n > 0 && fan_footprint(sp, 0, box, p.omega, fa);
+    const bool okb = sp.n > 3 && fan_footprint(sp, 1, box, p.omega, fb);
+    const int na = oka ? (fa.tx1 - fa.tx0 + 1) * (fa.ty1 - fa.ty0 + 1) : 0;
+    const int nb = okb ? (fb.tx1 - fb.tx0 + 1) * (fb.ty1 - fb.ty0 + 1) : 0;
+    const bool wa = oka && na > small_texels, wb = okb && nb > small_texels;
+    uint32_t txa = 0, txb = 0;
+    const uint32_t nta = wa ? tiles_of(fa, &txa) : 0u, ntb = wb ? tiles_of(fb, &txb) : 0u;
+    // queue order: wave-major, then lane, fan a before fan b
+    const uint32_t mine = (uint32_t)wa + (uint32_t)wb, mine_t = nta + ntb;
+    const uint32_t c_in = wave_incl_scan<uint32_t>(mine) - mine;
+    const uint32_t t_in = wave_incl_scan<uint32_t>(mine_t) - mine_t;
+    if (lane == kWave - 1) {
+      wcnt[w] = c_in + mine;
+      wtil[w] = t_in + mine_t;
     }
+    __syncthreads();
+    uint32_t c_before = 0, t_before = 0, c_all = 0, t_all = 0;
+    for (int k = 0; k < nw; ++k) {
+      const uint32_t c = wcnt[k], tl = wtil[k];
+      if (k < w) {
+        c_before += c;
+        t_before += tl;
+      }
+      c_all += c;
+      t_all += tl;
+    }
+    if (threadIdx.x == 0 && c_all)
+      bbase = atomicAdd(big_counter, ((unsigned long long)c_all << kSlotShift) | t_all);
+    __syncthreads();
+    bool qa = false, qb = false;
+    if (c_all) {
+      const unsigned long long old = bbase;
+      unsigned long long slot = (old >> kSlotShift) + c_before + c_in;
+      unsigned long long tile = (old & kLow) + t_before + t_in;
+      // x: footprint code | tiles across << 32; y: first tile | tiles << 40
+      if (wa && slot < big_cap) {
+        big[slot] = make_ulonglong2((unsigned long long)(2 * (int64_t)t) |
+                                        ((unsigned long long)txa << 32),
+                                    tile | ((unsigned long long)nta << kSlotShift));
+        qa = true;
+      }
+      slot += wa;
+      tile += nta;
+      if (wb && slot < big_cap) {
+        big[slot] = make_ulonglong2((unsigned long long)(2 * (int64_t)t + 1) |
+                                        ((unsigned long long)txb << 32),
+                                    tile | ((unsigned long long)ntb << kSlotShift));
+        qb = true;
+      }
+    }
+    const bool ca = oka && !qa && na > lane_texels, cb = okb && !qb && nb > lane_texels;
+    if (oka && !qa && !ca) raster_lane(fa, occ, p.omega);
+    if (okb && !qb && !cb) raster_lane(fb, occ, p.omega);
+    for (unsigned long long cm = __ballot(ca); cm; cm &= cm - 1)
+      raster_wave(fa, __ffsll((long long)cm) - 1, occ, p.omega);
+    for (unsigned long long cm = __ballot(cb); cm; cm &= cm - 1)
+      raster_wave(fb, __ffsll((long long)cm) - 1, occ, p.omega);
   }
 }
 
@@ -366,7 +404,8 @@ __global__ __launch_bounds__(kBlock) void k_occ_big(
     const unsigned long long* __restrict__ big_counter, const FrameState* __restrict__ stp) {
   const FrameState st = *stp;
   if (st.status != FA_OK) return;
-  const unsigned long long ctr = *big_counter;
+  const unsigned long long ctr =
+      __hip_atomic_load(big_counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const uint32_t nent = (uint32_t)min<unsigned long long>(ctr >> kSlotShift, big_cap);
   if (nent == 0) return;
   constexpr unsigned long long kLow = (1ull << kSlotShift) - 1;
@@ -488,7 +527,9 @@ __global__ void k_meta(FrameParams p, FrameState* stp,
   m.rate = p.rate;
   m.occupied_texels = (int64_t)st.occupied;
   m.visible_triangles = (int64_t)st.visible;
-  m.large_tiles = (int64_t)(*big_counter & ((1ull << 40) - 1));
+  m.large_tiles = (int64_t)(__hip_atomic_load(big_counter, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT) &
+                            ((1ull << 40) - 1));
   *meta = m;
 }
 
@@ -511,9 +552,9 @@ hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p,
   mk(st);
   const uint32_t cap = (uint32_t)std::min<int64_t>(2 * std::max<int64_t>(T, 1), 1 << 24);
   if (T > 0) {
-    k_occ_small<<<visible_grid(T), kBlock, 0, st>>>(idx, w.vlist, p, w.clip, cot, charts,
-                                                    w.chart_tex, occ, w.big, cap, small_texels,
-                                                    lane_texels, w.big_counter, w.state);
+    k_occ_small<<<visible_grid(T), kOccSmallBlock, 0, st>>>(idx, w.vlist, p, w.clip, cot, charts, w.chart_tex,
+                                               occ, w.big, cap, small_texels, lane_texels,
+                                               w.big_counter, w.state);
     mk(st);
     k_occ_big<<<kOccBigGrid, kBlock, 0, st>>>(idx, p, w.clip, cot, charts, w.chart_tex, occ,
                                               w.big, cap, w.big_counter, w.state);

@@ -225,7 +225,14 @@ __global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
   if (from_accum) {
     for (int c = tid; c < C; c += kOrderThreads) {
       uint32_t key;
-      chart_size(p, reinterpret_cast<const uint4*>(accum)[c], charts[c], key);
+      // the box words were reduced with atomics (possibly on other XCDs):
+      // read them with agent-scope loads, not through a maybe-stale L2 line
+      uint4 box;
+      box.x = __hip_atomic_load(&accum[4 * c + 0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      box.y = __hip_atomic_load(&accum[4 * c + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      box.z = __hip_atomic_load(&accum[4 * c + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      box.w = __hip_atomic_load(&accum[4 * c + 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      chart_size(p, box, charts[c], key);
       keys_a[c] = key;
       vals_a[c] = c;
     }

@@ -41,6 +41,12 @@ __device__ __forceinline__ double dval(unsigned long long k) {
   return __longlong_as_double((long long)b);
 }
 
+// the depth buffer and the occluder count are produced by atomics (possibly
+// on other XCDs): read them with agent-scope loads
+__device__ __forceinline__ unsigned long long dload(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ void k_vis_clear(unsigned long long* __restrict__ depth, int64_t n,
                             uint32_t* __restrict__ count) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *count = 0u;
@@ -50,11 +56,22 @@ __global__ void k_vis_clear(unsigned long long* __restrict__ depth, int64_t n,
     depth[i] = inf;
 }
 
-__global__ __launch_bounds__(kBlock) void k_vis_cull(const float* __restrict__ pos,
-                                                     const int32_t* __restrict__ idx, int64_t T,
-                                                     VisParams q, uint8_t* __restrict__ vis,
-                                                     int32_t* __restrict__ occl,
-                                                     uint32_t* __restrict__ count) {
+// Candidates and occluders. Occluders are gathered per workgroup in LDS and
+// appended to the global list with one atomic per full buffer (a single
+// counter serializes at about 12 ns per atomic).
+constexpr int kCullBlock = 1024;
+constexpr int kCullBuf = 8192;
+
+__global__ __launch_bounds__(kCullBlock) void k_vis_cull(const float* __restrict__ pos,
+                                                         const int32_t* __restrict__ idx,
+                                                         int64_t T, VisParams q,
+                                                         uint8_t* __restrict__ vis,
+                                                         int32_t* __restrict__ occl,
+                                                         uint32_t* __restrict__ count) {
+  __shared__ int32_t buf[kCullBuf];
+  __shared__ uint32_t sh[kCullBlock / kWave];
+  __shared__ uint32_t gbase;
+  uint32_t fill = 0;  // entries in buf (block-uniform)
   for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x; b0 < T;
        b0 += (int64_t)gridDim.x * blockDim.x) {
     const int64_t t = b0 + threadIdx.x;
@@ -85,15 +102,24 @@ __global__ __launch_bounds__(kBlock) void k_vis_cull(const float* __restrict__ p
       vis[t] = cand ? 1 : 0;
       occluder = q.coarse > 0 && cand && c0.w > q.near_w && c1.w > q.near_w && c2.w > q.near_w;
     }
-    // one atomic per wave appends the wave's occluders
-    const unsigned long long m = __ballot(occluder);
-    if (m) {
-      const int leader = __ffsll((long long)m) - 1;
-      uint32_t base = 0;
-      if (lane_id() == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
-      base = __shfl(base, leader, kWave);
-      if (occluder) occl[base + __popcll(m & lanes_below())] = (int32_t)t;
+    uint32_t tot;
+    const uint32_t one = occluder ? 1u : 0u;
+    const uint32_t at = block_incl_scan<uint32_t>(one, sh, &tot) - one;
+    if (fill + tot > (uint32_t)kCullBuf) {  // flush the full buffer first
+      if (threadIdx.x == 0) gbase = atomicAdd(count, fill);
+      __syncthreads();
+      for (uint32_t k = threadIdx.x; k < fill; k += blockDim.x) occl[gbase + k] = buf[k];
+      __syncthreads();
+      fill = 0;
     }
+    if (occluder) buf[fill + at] = (int32_t)t;
+    fill += tot;
+  }
+  __syncthreads();
+  if (fill) {
+    if (threadIdx.x == 0) gbase = atomicAdd(count, fill);
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < fill; k += blockDim.x) occl[gbase + k] = buf[k];
   }
 }
 
@@ -166,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_vis_depth(const float* __restrict__ 
                                                       const uint32_t* __restrict__ count,
                                                       unsigned long long* __restrict__ depth,
                                                       uint8_t* __restrict__ vis) {
-  const int n_occ = (int)*count;
+  const int n_occ = (int)__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const int lane = lane_id();
   for (int b0 = blockIdx.x * blockDim.x; b0 < n_occ; b0 += gridDim.x * blockDim.x) {
     const int i = b0 + threadIdx.x;
@@ -189,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_vis_depth(const float* __restrict__ 
         const int64_t pix = (int64_t)py * q.Wc + px;
         if (MARK) {
           any = true;
-          if (z <= dval(depth[pix]) + 1e-6) pass = true;
+          if (z <= dval(dload(&depth[pix])) + 1e-6) pass = true;
         } else {
           atomicMin(&depth[pix], dkey(z));
         }
@@ -207,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_vis_depth(const float* __restrict__ 
           const int64_t pix = (int64_t)(w.iy0 + k / wnx) * q.Wc + (w.ix0 + k % wnx);
           if (MARK) {
             wany = true;
-            if (z <= dval(depth[pix]) + 1e-6) wpass = true;
+            if (z <= dval(dload(&depth[pix])) + 1e-6) wpass = true;
           } else {
             atomicMin(&depth[pix], dkey(z));
           }
@@ -289,8 +315,8 @@ hipError_t launch_visibility(const float* pos, const int32_t* idx, int64_t T, co
   const unsigned cg = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nd + kBlock - 1) / kBlock, 1024));
   k_vis_clear<<<cg, kBlock, 0, st>>>(depth, nd, count);
   if (T == 0) return hipGetLastError();
-  const unsigned g = (unsigned)std::min<int64_t>((T + kBlock - 1) / kBlock, 8192);
-  k_vis_cull<<<g, kBlock, 0, st>>>(pos, idx, T, q, vis, occl, count);
+  const unsigned g = (unsigned)std::min<int64_t>((T + kCullBlock - 1) / kCullBlock, 256);
+  k_vis_cull<<<g, kCullBlock, 0, st>>>(pos, idx, T, q, vis, occl, count);
   if (q.coarse > 0) {
     const unsigned og = visible_grid(T);
     k_vis_depth<false><<<og, kBlock, 0, st>>>(pos, idx, q, occl, count, depth, vis);
