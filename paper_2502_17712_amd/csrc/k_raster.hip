@@ -552,9 +552,9 @@ hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p,
   mk(st);
   const uint32_t cap = (uint32_t)std::min<int64_t>(2 * std::max<int64_t>(T, 1), 1 << 24);
   if (T > 0) {
-    k_occ_small<<<visible_grid(T), kOccSmallBlock, 0, st>>>(idx, w.vlist, p, w.clip, cot, charts, w.chart_tex,
-                                               occ, w.big, cap, small_texels, lane_texels,
-                                               w.big_counter, w.state);
+    k_occ_small<<<visible_grid(T), kOccSmallBlock, 0, st>>>(
+        idx, w.vlist, p, w.clip, cot, charts, w.chart_tex, occ, w.big, cap, small_texels,
+        lane_texels, w.big_counter, w.state);
     mk(st);
     k_occ_big<<<kOccBigGrid, kBlock, 0, st>>>(idx, p, w.clip, cot, charts, w.chart_tex, occ,
                                               w.big, cap, w.big_counter, w.state);
