@@ -247,10 +247,12 @@ int fa_pack_boxes(fa_ctx* ctx, const float* sizes, int32_t n, int32_t atlas_size
  *   FA_TUNE_PACK_BLOCK        threads per candidate packing: 256, 512, 1024
  *   FA_TUNE_OCC_SMALL_TEXELS  footprints (texel range of a fan triangle) of
  *                             more texels are queued and cut into 16x16
- *                             tiles shared by all waves (0..4096)
+ *                             tiles shared by all waves (0..4096, default 64)
  *   FA_TUNE_OCC_LANE_TEXELS   footprints up to this many texels are
- *                             rasterized by one lane; larger ones (up to
- *                             FA_TUNE_OCC_SMALL_TEXELS) by their wave (0..4096)
+ *                             rasterized by one lane (scattered stores);
+ *                             larger ones (up to FA_TUNE_OCC_SMALL_TEXELS)
+ *                             by their wave, 64 texels per step with
+ *                             coalesced stores (0..4096, default 64)
  *   FA_TUNE_UF_LINK_INIT      1: a triangle starts linked to its smallest
  *                             visible edge neighbour (Alg. 1); 0: to itself
  *                             (used when FA_TUNE_UF_EDGE_HOOKS is 0 or 1)

@@ -16,8 +16,8 @@ from . import (FA_TUNE_OCC_LANE_TEXELS, FA_TUNE_OCC_SMALL_TEXELS, FA_TUNE_PACK_B
                FA_TUNE_UF_EDGE_HOOKS, FA_TUNE_UF_LINK_INIT, AtlasOutputs, Context)
 
 KNOBS = {
-    FA_TUNE_OCC_SMALL_TEXELS: [64, 128, 256, 512, 1024],
-    FA_TUNE_OCC_LANE_TEXELS: [8, 16, 32, 64, 128],
+    FA_TUNE_OCC_SMALL_TEXELS: [64, 16, 32, 128, 256],
+    FA_TUNE_OCC_LANE_TEXELS: [64, 0, 16, 256],
     FA_TUNE_UF_LINK_INIT: [1, 0],
     FA_TUNE_UF_EDGE_HOOKS: [2, 1, 0],
     FA_TUNE_PACK_BLOCK: [256, 512, 1024],

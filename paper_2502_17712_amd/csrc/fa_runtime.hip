@@ -55,7 +55,7 @@ struct fa_ctx {
   bool ev_recorded = false;
   int ev_marks = 0;
   int pack_block = 1024;
-  int small_texels = 256;
+  int small_texels = 64;
   int lane_texels = 64;
   int uf_link_init = 1;
   int uf_edge_hooks = 2;

@@ -17,11 +17,11 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // union-find over visible triangles. parent[x] <= x always holds; a root has
-// parent[x] == x. The eight XCDs have separate L2 caches and parent[] is
-// rewritten every frame, so a plain load can return another XCD's or an
-// earlier frame's value; a path-halving store built on such a value can undo
-// a hook. Every read of parent[] and of the vertex minima is therefore an
-// agent-scope atomic load and every write an agent-scope atomic store.
+// parent[x] == x. Walks inside a join use plain loads: a stale value (the
+// eight XCDs have separate L2 caches) is an older ancestor, and the hooking
+// compare-and-swap always sees the current value. Reads whose value is the
+// result (vertex minima, the flattened root, the root test) are agent-scope
+// atomic loads; every write of parent[] is an agent-scope atomic store.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int aload(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -31,11 +31,11 @@ __device__ __forceinline__ void astore(int32_t* p, int v) {
 }
 
 __device__ __forceinline__ int uf_root(int32_t* parent, int x) {
-  int cur = aload(&parent[x]);
+  int cur = parent[x];
   if (cur == x) return x;
   int prev = x;
   for (;;) {
-    int nxt = aload(&parent[cur]);
+    int nxt = parent[cur];
     if (nxt >= cur) return cur;  // parent[cur] == cur
     astore(&parent[prev], nxt);
     prev = cur;
@@ -208,8 +208,8 @@ __global__ void k_uf_cross(const uint8_t* __restrict__ vis, const int32_t* __res
       bool want = valid && n > last && vis[n];
       int a = 0, b = 0;
       if (want) {
-        a = aload(&parent[t]);
-        b = aload(&parent[n]);
+        a = parent[t];
+        b = parent[n];
         if (a > b) { const int s = a; a = b; b = s; }
         want = a != b;
       }

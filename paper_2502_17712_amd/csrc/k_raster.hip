@@ -260,35 +260,46 @@ __device__ __forceinline__ void raster_lane(const Footprint& fp, int32_t* __rest
 
 __device__ __forceinline__ int rl(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
-// All texels of lane src's footprint by the whole wave: lane k takes texels
-// k, k+64, ... of the range in row-major order.
-__device__ __forceinline__ void raster_wave(const Footprint& mine, int src,
-                                            int32_t* __restrict__ occ, int omega) {
-  Footprint fp;
-  fp.ax = rl(mine.ax, src); fp.ay = rl(mine.ay, src);
-  fp.bx = rl(mine.bx, src); fp.by = rl(mine.by, src);
-  fp.cx = rl(mine.cx, src); fp.cy = rl(mine.cy, src);
-  fp.tx0 = rl(mine.tx0, src); fp.tx1 = rl(mine.tx1, src);
-  fp.ty0 = rl(mine.ty0, src); fp.ty1 = rl(mine.ty1, src);
-  fp.chart = rl(mine.chart, src); fp.neg = rl(mine.neg, src);
-  const int nx = fp.tx1 - fp.tx0 + 1, n = nx * (fp.ty1 - fp.ty0 + 1);
+// The texels of every lane's footprint (n texels; 0 for none), concatenated in
+// lane order and row-major inside a footprint, by the whole wave 64 at a time:
+// the lane taking texel g finds the footprint holding it by a binary search
+// over the wave's inclusive prefix of n and fetches that footprint from its
+// lane. Neighbouring lanes then write neighbouring texels of one row, so the
+// stores coalesce (one lane per footprint scatters 4-byte stores over the
+// map, several times slower).
+__device__ __forceinline__ void raster_expand(const Footprint& f, int n, int32_t* __restrict__ occ,
+                                              int omega) {
   const int lane = lane_id();
-  int col = lane % nx, row = lane / nx;
-  const int dcol = kWave % nx, drow = kWave / nx;
-  const Edges dx = step_x(fp), dy = step_y(fp);
-  const Edges adv = madd(madd(Edges{0, 0, 0}, drow, dy), dcol, dx);  // one stride of 64
-  const Edges wrap = madd(dy, -(int64_t)nx, dx);                        // next row, first column
-  Edges e = edges_at(fp, fp.tx0 + col, fp.ty0 + row);
-  for (int k = lane; k < n; k += kWave) {
-    if (inside(e)) occ[(int64_t)(fp.ty0 + row) * omega + fp.tx0 + col] = fp.chart;
-    col += dcol;
-    row += drow;
-    add(e, adv);
-    if (col >= nx) {
-      col -= nx;
-      row += 1;
-      add(e, wrap);
+  const int incl = wave_incl_scan<int>(n);
+  const int total = __shfl(incl, kWave - 1, kWave);
+  const int start = incl - n;
+  for (int c = 0; c < total; c += kWave) {
+    const int g = c + lane;
+    int pos = 0;  // first lane whose inclusive prefix exceeds g
+#pragma unroll
+    for (int s = kWave / 2; s > 0; s >>= 1) {
+      const int v = __shfl(incl, pos + s - 1, kWave);
+      if (v <= g) pos += s;
     }
+    Footprint o;
+    o.ax = __shfl(f.ax, pos, kWave);
+    o.ay = __shfl(f.ay, pos, kWave);
+    o.bx = __shfl(f.bx, pos, kWave);
+    o.by = __shfl(f.by, pos, kWave);
+    o.cx = __shfl(f.cx, pos, kWave);
+    o.cy = __shfl(f.cy, pos, kWave);
+    o.tx0 = __shfl(f.tx0, pos, kWave);
+    o.tx1 = __shfl(f.tx1, pos, kWave);
+    o.ty0 = __shfl(f.ty0, pos, kWave);
+    o.chart = __shfl(f.chart, pos, kWave);
+    o.neg = __shfl(f.neg, pos, kWave);
+    const int li = g - __shfl(start, pos, kWave);
+    const int nx = max(o.tx1 - o.tx0 + 1, 1);  // lanes past the total read an unused lane
+    int row = (int)((float)li / (float)nx);
+    if (row * nx > li) --row;
+    else if ((row + 1) * nx <= li) ++row;
+    const int tx = o.tx0 + (li - row * nx), ty = o.ty0 + row;
+    if (g < total && inside(edges_at(o, tx, ty))) occ[(int64_t)ty * omega + tx] = o.chart;
   }
 }
 
@@ -297,7 +308,7 @@ constexpr unsigned long long kSlotShift = 40;  // queue counter: footprints << 4
 
 // Occupancy of the visible triangles. Per fan footprint (texel range of n
 // texels): n <= lane_texels by its own lane; lane_texels < n <= small_texels
-// by its whole wave; larger ones are queued for k_occ_big. Both fans of every
+// by the wave's coalesced expansion; larger ones are queued for k_occ_big. Both fans of every
 // triangle are set up first and the queue is reserved with one atomic per
 // workgroup and step (a single counter serializes at about 12 ns per atomic);
 // the rasterization after it runs without barriers.
@@ -385,10 +396,8 @@ __global__ __launch_bounds__(kOccSmallBlock) void k_occ_small(
     const bool ca = oka && !qa && na > lane_texels, cb = okb && !qb && nb > lane_texels;
     if (oka && !qa && !ca) raster_lane(fa, occ, p.omega);
     if (okb && !qb && !cb) raster_lane(fb, occ, p.omega);
-    for (unsigned long long cm = __ballot(ca); cm; cm &= cm - 1)
-      raster_wave(fa, __ffsll((long long)cm) - 1, occ, p.omega);
-    for (unsigned long long cm = __ballot(cb); cm; cm &= cm - 1)
-      raster_wave(fb, __ffsll((long long)cm) - 1, occ, p.omega);
+    raster_expand(fa, ca ? na : 0, occ, p.omega);
+    if (__ballot(cb)) raster_expand(fb, cb ? nb : 0, occ, p.omega);
   }
 }
 
