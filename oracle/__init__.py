@@ -59,13 +59,13 @@ def lib():
         L.oracle_select.restype = i32
         L.oracle_uv.argtypes = [P, i64, P, P, P, P, P, P, i32, i32, f32, i32, i32, i32, i64, i32, P]
         L.oracle_occupancy.argtypes = [P, P, P, P, i64, P, P, P, P, P, P, P, i32, i32, f32, i32,
-                                       i32, i32, i64, i32, P]
+                                       i32, i32, i64, i32, P, P]
         L.oracle_occupancy.restype = i64
         L.oracle_visibility.argtypes = [P, i64, P, i64, P, P, ctypes.c_double, i32, i32, i32, P]
         L.oracle_reuse_flags.argtypes = [P, i64, P, i64, P, P, P, P]
-        L.oracle_profiles.argtypes = [P, P, P, P, i64, P, P, P, P, i32, i32, f32, f32, i32, P, P,
-                                      P, i64, P, P]
-        L.oracle_candidate_fp.argtypes = [P, P, P, P, i64, i32, P, P, P]
+        L.oracle_fine_profiles.argtypes = [P, P, P, P, i64, P, P, P, P, i32, i32, f32, P, P, P]
+        L.oracle_pool_profile.argtypes = [P, P, i32, i32, i32, i32, i32, i32, i32, P, P]
+        L.oracle_candidate_fp.argtypes = [P, P, P, P, P, i64, i32, P, P, P]
         L.oracle_reuse_flags.restype = i64
         _lib = L
     return _lib
@@ -178,53 +178,73 @@ def candidate(sbw, sbh, j, J, omega, gutter=1, min_box=2):
                 x=x, y=y, a=a, b=b)
 
 
-def profiles(clip_c, indices, nonempty, chart_of_tri, frame, target, oriented, rotated, W, H,
-             rate, s, gutter, a, b, prof_off):
-    """Footprint profiles (top, bottom rows per box column) of every chart at
-    scale s; a, b, prof_off are chart-indexed; returns (top, bottom)."""
-    C = a.shape[0]
-    total = int((prof_off + a).max()) if C else 0
-    top = np.empty(total, np.int32)
-    bot = np.empty(total, np.int32)
+def fine_profiles(clip_c, indices, nonempty, chart_of_tri, frame, target, oriented, rotated,
+                  W, H, rate):
+    """Full-scale footprint profile of every chart (FP1). Returns (foff, ft, fb):
+    chart c owns columns foff[c] .. foff[c + 1] - 1 (Uc = floor(bw) + 1 of
+    them); empty columns hold ft = INT32_MAX, fb = -1."""
+    C = oriented.shape[0]
+    uc = np.floor(np.asarray(oriented, np.float32)[:, 0]).astype(np.int64) + 1
+    foff = np.zeros(C + 1, np.int64)
+    foff[1:] = np.cumsum(uc)
+    n = int(foff[-1])
+    ft = np.full(n, np.iinfo(np.int32).max, np.int32)
+    fb = np.full(n, -1, np.int32)
     idx = _c(indices, np.int32)
-    lib().oracle_profiles(_p(_c(clip_c, np.float32)), _p(idx), _p(_c(nonempty, np.uint8)),
-                          _p(_c(chart_of_tri, np.int32)), idx.shape[0], _p(_c(frame, np.float32)),
-                          _p(_c(target, np.float32)), _p(_c(oriented, np.float32)),
-                          _p(_c(rotated, np.int32)), int(W), int(H), float(rate), float(s),
-                          int(gutter), _p(_c(a, np.int32)), _p(_c(b, np.int32)),
-                          _p(_c(prof_off, np.int64)), C, _p(top), _p(bot))
+    lib().oracle_fine_profiles(_p(_c(clip_c, np.float32)), _p(idx), _p(_c(nonempty, np.uint8)),
+                               _p(_c(chart_of_tri, np.int32)), idx.shape[0],
+                               _p(_c(frame, np.float32)), _p(_c(target, np.float32)),
+                               _p(_c(oriented, np.float32)), _p(_c(rotated, np.int32)), int(W),
+                               int(H), float(rate), _p(foff), _p(ft), _p(fb))
+    return foff, ft, fb
+
+
+def pool_profile(ft_c, fb_c, Rc, a, b, j, J, gutter):
+    """Profile (top, bottom per column) of one chart's a x b box at candidate j
+    (FP2) from its full-scale columns ft_c, fb_c and row count Rc."""
+    ft_c, fb_c = _c(ft_c, np.int32), _c(fb_c, np.int32)
+    top = np.empty(int(a), np.int32)
+    bot = np.empty(int(a), np.int32)
+    lib().oracle_pool_profile(_p(ft_c), _p(fb_c), ft_c.shape[0], int(Rc), int(a), int(b), int(j),
+                              int(J), int(gutter), _p(top), _p(bot))
     return top, bot
 
 
-def candidate_fp(a_o, top, bot, poff_o, omega):
-    """Footprint-aware push of one candidate (inputs in packing order)."""
+def candidate_fp(a_o, b_o, top, bot, poff_o, omega):
+    """Footprint-aware push of one candidate (FP3; inputs in packing order)."""
     C = a_o.shape[0]
     x = np.empty(C, np.int32)
     y = np.empty(C, np.int32)
     out = np.zeros(5, np.int64)
-    lib().oracle_candidate_fp(_p(_c(a_o, np.int32)), _p(top), _p(bot), _p(_c(poff_o, np.int64)),
+    lib().oracle_candidate_fp(_p(_c(a_o, np.int32)), _p(_c(b_o, np.int32)), _p(_c(top, np.int32)),
+                              _p(_c(bot, np.int32)), _p(_c(poff_o, np.int64)),
                               C, int(omega), _p(x), _p(y), _p(out))
     return dict(fit=bool(out[0]), m=int(out[1]), L=int(out[2]), H=int(out[3]), rows=int(out[4]),
                 x=x, y=y)
 
 
-def footprint_candidate(clip_c, idx, ne, cot, frame, target, oriented, rot, W, H, rate, j, J,
-                        omega, gutter, order_, box_cd):
-    """Candidate j with the footprint-aware push; sizes from the box candidate."""
+def footprint_candidate(fine, oriented, j, J, omega, gutter, order_, box_cd):
+    """Candidate j with the footprint-aware push; sizes (a, b) and fold from
+    the box candidate, profiles pooled from the full-scale ones (FP2).
+    Boxes are in packing order; prof_off[i] = fold position X_i."""
+    foff, ft, fb = fine
     a_o, b_o = box_cd["a"], box_cd["b"]
     C = a_o.shape[0]
     poff_o = np.zeros(C, np.int64)
     if C:
         poff_o[1:] = np.cumsum(a_o[:-1].astype(np.int64))
-    a = np.empty(C, np.int32)
-    b = np.empty(C, np.int32)
-    poff = np.empty(C, np.int64)
-    a[order_], b[order_], poff[order_] = a_o, b_o, poff_o
-    s = np.float32(j) / np.float32(J)
-    top, bot = profiles(clip_c, idx, ne, cot, frame, target, oriented, rot, W, H, rate, s, gutter,
-                        a, b, poff)
-    fp = candidate_fp(a_o, top, bot, poff_o, omega)
-    fp.update(a=a_o, b=b_o, top=top, bot=bot, prof_off=poff, H_box=box_cd["H"])
+    n = int(poff_o[-1] + a_o[-1]) if C else 0
+    top = np.empty(n, np.int32)
+    bot = np.empty(n, np.int32)
+    rc = np.floor(np.asarray(oriented, np.float32)[:, 1]).astype(np.int64) + 1
+    for i in range(C):
+        c = int(order_[i])
+        t, b_ = pool_profile(ft[foff[c]:foff[c + 1]], fb[foff[c]:foff[c + 1]], rc[c], a_o[i],
+                             b_o[i], j, J, gutter)
+        top[poff_o[i]:poff_o[i] + a_o[i]] = t
+        bot[poff_o[i]:poff_o[i] + a_o[i]] = b_
+    fp = candidate_fp(a_o, b_o, top, bot, poff_o, omega)
+    fp.update(a=a_o, b=b_o, top=top, bot=bot, prof_off=poff_o, H_box=box_cd["H"])
     return fp
 
 
@@ -270,14 +290,20 @@ def build_atlas(positions, indices, visible, view_proj, width, height, atlas_siz
     sbh = np.ascontiguousarray(oriented[o, 1])
     table = np.zeros((J, 5), np.int64)
     cands = []
+    if footprint:
+        if gutter < 1:
+            raise ValueError("the footprint-aware push needs a gutter of at least 1")
+        fine = fine_profiles(r["clip"], idx, ne, cot, frame, target, oriented, rot, W, H, rate)
+        r["fine_profiles"] = fine
     for j in range(1, J + 1):
         cd = candidate(sbw, sbh, j, J, omega, gutter, min_box)
         if footprint:
-            cd = footprint_candidate(r["clip"], idx, ne, cot, frame, target, oriented, rot, W, H,
-                                     rate, j, J, omega, gutter, o, cd)
+            cd = footprint_candidate(fine, oriented, j, J, omega, gutter, o, cd)
         cands.append(cd)
         table[j - 1] = [cd["fit"], cd["m"], cd["L"], cd["H"], cd["rows"]]
     r["cand"] = table
+    if footprint:
+        r["fp_cands"] = cands
     js = select(table)
     r["jstar"] = js
     px = np.zeros(C, np.int32)
@@ -299,19 +325,21 @@ def build_atlas(positions, indices, visible, view_proj, width, height, atlas_siz
     lib().oracle_uv(_p(clip_c), V, _p(cov), _p(frame), _p(target), _p(rot), _p(px), _p(py), W, H,
                     float(rate), js, J, omega, L, gutter, _p(uv))
     r["uv"] = uv
+    conflicts = np.zeros(1, np.int64)
     if want_occupancy:
         occ = np.empty((omega, omega), np.int32)
         n = lib().oracle_occupancy(_p(clip_c), _p(idx), _p(ne), _p(cot), T, _p(frame), _p(target),
                                    _p(rot), _p(px), _p(py), _p(pa), _p(pb), W, H, float(rate), js,
-                                   J, omega, L, gutter, _p(occ))
-        r.update(occupancy=occ, occupied=int(n))
+                                   J, omega, L, gutter, _p(occ), _p(conflicts))
+        r.update(occupancy=occ, occupied=int(n), occupancy_conflicts=int(conflicts[0]))
     if low_shift:
         ol = omega >> int(low_shift)
         occ_l = np.empty((ol, ol), np.int32)
         n = lib().oracle_occupancy(_p(clip_c), _p(idx), _p(ne), _p(cot), T, _p(frame), _p(target),
                                    _p(rot), _p(px), _p(py), _p(pa), _p(pb), W, H, float(rate), js,
-                                   J, ol, L, gutter, _p(occ_l))
-        r.update(occupancy_low=occ_l, occupied_low=int(n))
+                                   J, ol, L, gutter, _p(occ_l), _p(conflicts))
+        r.update(occupancy_low=occ_l, occupied_low=int(n),
+                 occupancy_low_conflicts=int(conflicts[0]))
     return r
 
 

@@ -16,7 +16,8 @@
 //
 // Parity status per step:
 //   adjacency, clip, charts, per-triangle boxes, chart frames, order, fold,
-//   push, select, UV, occupancy, visibility, reuse flags: pinned by independent tests
+//   push, select, UV, occupancy, visibility, reuse flags, footprint profiles,
+//   pooled profiles and the footprint push: pinned by independent tests
 //   (brute force, closed forms, exact double clipping, invariants, an
 //   independent vectorized implementation); see tests/test_oracle_*.
 #include <algorithm>
@@ -456,15 +457,17 @@ void oracle_uv(const float* clip, int64_t V, const int32_t* chart_of_vert, const
 // triangle crosses the near plane, snapped to 1/256 texel (round to nearest
 // even, clamped to +-2^28), fan-triangulated from its first vertex, edges
 // inclusive. Triangles with an empty box in O4 claim nothing.
-// Returns the number of occupied texels.
+// Returns the number of occupied texels; `conflicts` (optional) counts texel
+// claims by a second chart (none when the packing keeps footprints apart).
 // ---------------------------------------------------------------------------
 int64_t oracle_occupancy(const float* clip, const int32_t* idx, const uint8_t* nonempty,
                          const int32_t* chart_of_tri, int64_t T, const float* frame,
                          const float* target, const int32_t* rotated, const int32_t* place_x,
                          const int32_t* place_y, const int32_t* box_a, const int32_t* box_b,
                          int32_t W, int32_t H, float rate, int32_t jstar, int32_t J, int32_t omega,
-                         int64_t L, int32_t gutter, int32_t* occ) {
+                         int64_t L, int32_t gutter, int32_t* occ, int64_t* conflicts) {
   const int64_t N = (int64_t)omega * omega;
+  if (conflicts) *conflicts = 0;
   for (int64_t i = 0; i < N; ++i) occ[i] = -1;
   float s = (float)jstar / (float)J;
   float q = (float)omega / (float)L;
@@ -516,7 +519,11 @@ int64_t oracle_occupancy(const float* clip, const int32_t* idx, const uint8_t* n
           int64_t e1 = (cx - bxv) * (pyc - byv) - (cy - byv) * (pxc - bxv);
           int64_t e2 = (ax - cx) * (pyc - cy) - (ay - cy) * (pxc - cx);
           bool in = area > 0 ? (e0 >= 0 && e1 >= 0 && e2 >= 0) : (e0 <= 0 && e1 <= 0 && e2 <= 0);
-          if (in) occ[ty * omega + tx] = c;
+          if (in) {
+            int32_t& o = occ[ty * omega + tx];
+            if (conflicts && o >= 0 && o != c) ++*conflicts;
+            o = c;
+          }
         }
       }
     }
@@ -666,46 +673,38 @@ int64_t oracle_reuse_flags(const float* pos, int64_t V, const int32_t* idx, int6
 // (top, bottom row) of its footprint instead of its full box, so a chart can
 // rise into the empty corners under its neighbours in the frontline.
 //
-// Profiles of chart c at scale s (box a x b): every triangle of c with a
-// non-empty box (the near-clipped polygon as in O10, all w > 0) is mapped to
-// box-local layout coordinates (g + lx*s, g + ly*s) (lx, ly as in O9) and
-// clipped to the chart frame [g, g + bw*s] x [g, g + bh*s]; for each column
-// strip [k, k+1) overlapping it, the polygon is cut to the strip (inside
-// endpoint first, t = (x_line - A.x) / (B.x - A.x)) and its y-range, clamped
-// to the frame, covers rows floor(ylo) .. ceil(yhi) - 1 (at least one row).
-// The union over triangles is dilated by g columns and rows (the gutter) and
-// clamped to the box. Empty columns: top = INT32_MAX, bottom = -1.
+// FP1 full-scale profile. Chart c's footprint is measured once per frame on
+// the unit grid of its chart-local layout coordinates (lx, ly) of O9 before
+// the scale s and the gutter: columns u in [0, Uc), Uc = floor(bw) + 1, rows
+// r in [0, Rc), Rc = floor(bh) + 1 ((bw, bh): the oriented size of O5). Every
+// triangle that claims texels in O10 (non-empty box, near-clipped polygon
+// with all w > 0) is mapped to (lx, ly), snapped to 1/256 (round to nearest
+// even, clamped to +-2^28) and, in every column u its x-range touches, covers
+// the rows floor(ymin) .. floor(ymax) of its exact extent inside the closed
+// strip [u, u + 1]; the first strip extends to -inf, the last to +inf, and
+// rows are clamped to [0, Rc - 1], so geometry outside the chart frame folds
+// onto the frame's border cells. Exact: the extent is taken over the vertices
+// inside the strip and the edges' crossings of its sides, each crossing's row
+// a floor of an exact rational.
 // ---------------------------------------------------------------------------
 namespace {
-struct P2 { float x, y; };
 
-int cut_vertical(const P2* in, int n, float xl, bool keep_right, P2* out) {
-  int m = 0;
-  for (int i = 0; i < n; ++i) {
-    const P2 S = in[i], E = in[(i + 1) % n];
-    const bool iS = keep_right ? S.x >= xl : S.x <= xl;
-    const bool iE = keep_right ? E.x >= xl : E.x <= xl;
-    if (iS != iE) {
-      const P2 A = iS ? S : E, B = iS ? E : S;
-      const float t = (xl - A.x) / (B.x - A.x);
-      out[m++] = P2{xl, A.y + t * (B.y - A.y)};
-    }
-    if (iE) out[m++] = E;
-  }
-  return m;
+// floor((Py + (X0 - Px) (Qy - Py) / (Qx - Px)) / 256) for Px != Qx
+int64_t crossing_row(int64_t Px, int64_t Py, int64_t Qx, int64_t Qy, int64_t X0) {
+  int64_t num = Py * (Qx - Px) + (X0 - Px) * (Qy - Py);
+  int64_t den = Qx - Px;
+  if (den < 0) { num = -num; den = -den; }
+  return floor_div(num, 256 * den);
 }
+
 }  // namespace
 
-void oracle_profiles(const float* clip, const int32_t* idx, const uint8_t* nonempty,
-                     const int32_t* chart_of_tri, int64_t T, const float* frame,
-                     const float* target, const float* oriented, const int32_t* rotated,
-                     int32_t W, int32_t H, float rate, float s, int32_t gutter,
-                     const int32_t* box_a, const int32_t* box_b, const int64_t* prof_off,
-                     int64_t C, int32_t* top, int32_t* bot) {
-  int64_t total = 0;
-  for (int64_t c = 0; c < C; ++c) total = std::max(total, prof_off[c] + box_a[c]);
-  std::vector<int32_t> rt(total, INT32_MAX), rb(total, -1);
-  const float g = (float)gutter;
+void oracle_fine_profiles(const float* clip, const int32_t* idx, const uint8_t* nonempty,
+                          const int32_t* chart_of_tri, int64_t T, const float* frame,
+                          const float* target, const float* oriented, const int32_t* rotated,
+                          int32_t W, int32_t H, float rate, const int64_t* foff,
+                          int32_t* ft, int32_t* fb) {
+  const float lim = 268435456.0f;  // 2^28
   for (int64_t t = 0; t < T; ++t) {
     if (!nonempty[t]) continue;
     const int32_t c = chart_of_tri[t];
@@ -717,73 +716,125 @@ void oracle_profiles(const float* clip, const int32_t* idx, const uint8_t* nonem
                             plane_dist(tri[2], PN) < 0.0f;
     if (cross_near) n = clip_one_plane(tri, 3, PN, poly);
     else for (int k = 0; k < 3; ++k) poly[k] = tri[k];
-    bool ok = n >= 3;
+    bool ok = true;
     for (int k = 0; k < n; ++k) ok = ok && poly[k].w > 0.0f;
-    if (!ok) continue;
+    if (!ok || n < 1) continue;
     const float x0 = frame[4 * c], y1 = frame[4 * c + 3], tw = target[2 * c];
     const float halfW = 0.5f * (float)W, halfH = 0.5f * (float)H;
-    P2 P[4];
+    int64_t X[4], Y[4];
     for (int k = 0; k < n; ++k) {
       const float nx = poly[k].x / poly[k].w, ny = poly[k].y / poly[k].w;
       const float px = ((nx - x0) * halfW) * rate;
       const float py = ((y1 - ny) * halfH) * rate;
       const float lx = rotated[c] ? py : px;
       const float ly = rotated[c] ? (tw - px) : py;
-      P[k] = P2{g + lx * s, g + ly * s};
+      X[k] = (int64_t)std::rint(std::fmin(std::fmax(lx * 256.0f, -lim), lim));
+      Y[k] = (int64_t)std::rint(std::fmin(std::fmax(ly * 256.0f, -lim), lim));
     }
-    const float fx1 = g + oriented[2 * c] * s, fy1 = g + oriented[2 * c + 1] * s;
-    float xmin = P[0].x, xmax = P[0].x;
-    for (int k = 1; k < n; ++k) { xmin = std::min(xmin, P[k].x); xmax = std::max(xmax, P[k].x); }
-    const float xl = std::max(xmin, g), xr = std::min(xmax, fx1);
-    if (!(xl <= xr)) continue;
-    const int k0 = (int)std::floor(xl);
-    int k1 = (int)std::ceil(xr) - 1;
-    if (k1 < k0) k1 = k0;
-    for (int k = k0; k <= k1; ++k) {
-      const float sl = std::max((float)k, g), sr = std::min((float)(k + 1), fx1);
-      P2 A[6], B[6];
-      const int na = cut_vertical(P, n, sl, true, A);
-      const int nb = na ? cut_vertical(A, na, sr, false, B) : 0;
-      if (nb == 0) continue;
-      float ymin = B[0].y, ymax = B[0].y;
-      for (int q = 1; q < nb; ++q) { ymin = std::min(ymin, B[q].y); ymax = std::max(ymax, B[q].y); }
-      const float ylo = std::max(ymin, g), yhi = std::min(ymax, fy1);
-      if (!(ylo <= yhi)) continue;
-      const int r0 = (int)std::floor(ylo);
-      int r1 = (int)std::ceil(yhi) - 1;
-      if (r1 < r0) r1 = r0;
-      const int64_t at = prof_off[c] + k;
-      rt[at] = std::min(rt[at], r0);
-      rb[at] = std::max(rb[at], r1);
-    }
-  }
-  for (int64_t c = 0; c < C; ++c) {
-    const int a = box_a[c], b = box_b[c];
-    for (int k = 0; k < a; ++k) {
-      int tmin = INT32_MAX, bmax = -1;
-      for (int d = std::max(0, k - gutter); d <= std::min(a - 1, k + gutter); ++d) {
-        tmin = std::min(tmin, rt[prof_off[c] + d]);
-        bmax = std::max(bmax, rb[prof_off[c] + d]);
+    const int64_t Uc = (int64_t)std::floor(oriented[2 * c]) + 1;
+    const int64_t Rc = (int64_t)std::floor(oriented[2 * c + 1]) + 1;
+    int64_t xmin = X[0], xmax = X[0];
+    for (int k = 1; k < n; ++k) { xmin = std::min(xmin, X[k]); xmax = std::max(xmax, X[k]); }
+    const int64_t u0 = std::min(Uc - 1, std::max<int64_t>(0, floor_div(xmin, 256)));
+    const int64_t u1 = std::min(Uc - 1, std::max<int64_t>(0, floor_div(xmax, 256)));
+    for (int64_t u = u0; u <= u1; ++u) {
+      const bool open_l = u == 0, open_r = u == Uc - 1;
+      const int64_t sl = 256 * u, sr = 256 * (u + 1);
+      int64_t rlo = INT64_MAX, rhi = INT64_MIN;
+      for (int k = 0; k < n; ++k) {
+        if ((open_l || X[k] >= sl) && (open_r || X[k] <= sr)) {
+          const int64_t r = floor_div(Y[k], 256);
+          rlo = std::min(rlo, r);
+          rhi = std::max(rhi, r);
+        }
       }
-      if (bmax < 0) {
-        top[prof_off[c] + k] = INT32_MAX;
-        bot[prof_off[c] + k] = -1;
-      } else {
-        top[prof_off[c] + k] = std::max(0, tmin - gutter);
-        bot[prof_off[c] + k] = std::min(b - 1, bmax + gutter);
+      for (int k = 0; k < n; ++k) {
+        const int64_t Px = X[k], Py = Y[k], Qx = X[(k + 1) % n], Qy = Y[(k + 1) % n];
+        if (Px == Qx) continue;
+        const int64_t lo = std::min(Px, Qx), hi = std::max(Px, Qx);
+        if (!open_l && lo < sl && sl < hi) {
+          const int64_t r = crossing_row(Px, Py, Qx, Qy, sl);
+          rlo = std::min(rlo, r);
+          rhi = std::max(rhi, r);
+        }
+        if (!open_r && lo < sr && sr < hi) {
+          const int64_t r = crossing_row(Px, Py, Qx, Qy, sr);
+          rlo = std::min(rlo, r);
+          rhi = std::max(rhi, r);
+        }
       }
+      if (rlo > rhi) continue;  // the polygon misses this strip
+      rlo = std::min(Rc - 1, std::max<int64_t>(0, rlo));
+      rhi = std::min(Rc - 1, std::max<int64_t>(0, rhi));
+      int32_t& top = ft[foff[c] + u];
+      int32_t& bot = fb[foff[c] + u];
+      top = std::min<int32_t>(top, (int32_t)rlo);
+      bot = std::max<int32_t>(bot, (int32_t)rhi);
     }
   }
 }
 
-// Candidate j with footprint profiles (inputs in packing order): sizes, fold,
-// overflow and mirrored rows exactly as O7; the push reads, per box, y =
-// max(0, max over its non-empty columns of F[x+k] - top[k]), then sets
-// F[x+k] = y + bottom[k] + 1 on those columns (all reads of a row before its
-// writes). H = max F; fit iff m <= omega and H <= L.
-void oracle_candidate_fp(const int32_t* a, const int32_t* top, const int32_t* bot,
-                         const int64_t* poff, int64_t C, int32_t omega, int32_t* x, int32_t* y,
-                         int64_t* out) {
+// FP2 profile of one chart's box (a x b texels, gutter g >= 1) at candidate j
+// of J (s = j/J), pooled from its full-scale profile (ft, fb over Uc columns,
+// Rc rows; empty column: ft = INT32_MAX, fb = -1). The scaled cell of fine
+// column u touches content columns floor(u s) .. floor((u + 1) s), so content
+// column k pools fine columns ceil(k/s) - 1 .. ceil((k + 1)/s) - 1, clamped to
+// the chart (columns past the last fine one pool the last one, which holds
+// everything folded onto the frame's right border). Pooled rows: top T =
+// floor(min ft * s); bottom B = floor((max fb + 1) * s), or the box bottom
+// when the pooled cells reach the frame's last row (geometry folded onto the
+// bottom border). Box column d = content column d - g; the gutter dilates the
+// profile by g columns and rows: top[d] = min T, bot[d] = min(b - 1, 2g + max
+// B) over content columns k in [d - 2g, d] with k + g < a; no non-empty k ->
+// empty column (top = INT32_MAX, bottom = -1).
+void oracle_pool_profile(const int32_t* ft, const int32_t* fb, int32_t Uc, int32_t Rc,
+                         int32_t a, int32_t b, int32_t j, int32_t J, int32_t g, int32_t* top,
+                         int32_t* bot) {
+  const int64_t inf = INT64_MAX / 4;
+  std::vector<int64_t> T(a), B(a);
+  std::vector<char> has(a, 0);
+  for (int64_t k = 0; k + g < a; ++k) {
+    // ceil(k J / j) - 1 and ceil((k + 1) J / j) - 1, clamped to [0, Uc - 1]
+    int64_t lo = (k * J + j - 1) / j - 1, hi = ((k + 1) * J + j - 1) / j - 1;
+    lo = std::min<int64_t>(Uc - 1, std::max<int64_t>(0, lo));
+    hi = std::min<int64_t>(Uc - 1, hi);
+    int64_t tmin = INT64_MAX, bmax = -1;
+    for (int64_t u = lo; u <= hi; ++u) {
+      if (fb[u] < 0) continue;
+      tmin = std::min<int64_t>(tmin, ft[u]);
+      bmax = std::max<int64_t>(bmax, fb[u]);
+    }
+    if (bmax < 0) continue;
+    has[k] = 1;
+    T[k] = tmin * j / J;
+    B[k] = bmax == Rc - 1 ? inf : (bmax + 1) * j / J;
+  }
+  for (int64_t d = 0; d < a; ++d) {
+    int64_t tmin = INT64_MAX, bmax = -1;
+    for (int64_t k = std::max<int64_t>(0, d - 2 * g); k <= d && k + g < a; ++k) {
+      if (!has[k]) continue;
+      tmin = std::min(tmin, T[k]);
+      bmax = std::max(bmax, B[k]);
+    }
+    if (bmax < 0) {
+      top[d] = INT32_MAX;
+      bot[d] = -1;
+    } else {
+      top[d] = (int32_t)tmin;
+      bot[d] = (int32_t)std::min<int64_t>(b - 1, 2 * g + bmax);
+    }
+  }
+}
+
+// FP3 candidate j with footprint profiles (inputs in packing order): sizes,
+// fold, overflow and mirrored rows exactly as O7; a candidate with m > omega
+// or a box taller than 2 omega (no layout of side L <= 2 omega holds it) is
+// rejected. The push reads, per box, y = max(0, max over its non-empty
+// columns of F[x+k] - top[k]), then sets F[x+k] = y + bottom[k] + 1 on those
+// columns (all reads of a row before its writes). H = max F; fit iff H <= L.
+void oracle_candidate_fp(const int32_t* a, const int32_t* b, const int32_t* top,
+                         const int32_t* bot, const int64_t* poff, int64_t C, int32_t omega,
+                         int32_t* x, int32_t* y, int64_t* out) {
   int log2w = 0;
   while ((1 << log2w) < omega) ++log2w;
   std::vector<int64_t> X(C), row(C), off(C);
@@ -799,7 +850,9 @@ void oracle_candidate_fp(const int32_t* a, const int32_t* top, const int32_t* bo
   out[1] = m;
   out[2] = L;
   out[4] = C ? row[C - 1] + 1 : 0;
-  if (m > omega) {
+  bool too_tall = false;
+  for (int64_t i = 0; i < C; ++i) too_tall = too_tall || b[i] > 2 * omega;
+  if (m > omega || too_tall) {
     out[0] = 0;
     out[3] = -1;
     for (int64_t i = 0; i < C; ++i) x[i] = y[i] = 0;
