@@ -56,7 +56,19 @@ enum {
   /* Clip straddling triangles against the near plane only (Blinn's estimate
      otherwise); the default also tries the side and far planes and keeps the
      smallest box (Sec. bounding boxes). */
-  FA_FLAG_NO_SIDE_CLIP = 1u << 0
+  FA_FLAG_NO_SIDE_CLIP = 1u << 0,
+  /* Footprint-aware push (Sec. "Box Packing" generalized to non-rectangular
+     footprints): each chart's footprint is measured once per frame as a
+     full-scale per-column profile (top and bottom row of every unit column of
+     its chart-local layout, geometry outside the chart frame folded onto the
+     border cells), pooled exactly to each candidate scale and dilated by the
+     gutter; the push raises a box until its profile, not its full box, meets
+     the frontline. Sizes, fold, overflow, mirrored rows and selection are the
+     box packer's; boxes may overlap where their footprints do not. Needs a
+     gutter >= 1 (fa_create returns FA_ERR_INVALID_ARG otherwise); not
+     available with fa_build_dual_atlas (FA_ERR_UNSUPPORTED). fa_pack_boxes
+     has no footprints and always uses the box push. */
+  FA_FLAG_FOOTPRINT_PUSH = 1u << 2
 };
 
 typedef struct fa_config {
@@ -70,6 +82,11 @@ typedef struct fa_config {
   int32_t min_box;       /* minimum box side in texels before the gutter (2)    */
   uint32_t flags;        /* FA_FLAG_*                                           */
   int32_t max_views;     /* views per fa_build_atlas_batch call (>= 1)          */
+  int64_t max_profile_columns; /* with FA_FLAG_FOOTPRINT_PUSH: capacity for the
+                              full-scale profile columns of one frame, the sum
+                              over charts of floor(oriented width) + 1 (0: 64 x
+                              max_atlas; at most 2^28); a frame above it ends
+                              with FA_ERR_CAPACITY in meta->status          */
 } fa_config;
 
 typedef struct fa_mesh {
@@ -218,7 +235,9 @@ int fa_build_atlas(fa_ctx* ctx, const fa_mesh* mesh, const uint8_t* visible,
  * of at least 2^low_shift texels (charts whose triangles leave the view can
  * still reach their box edge). low_shift: 1..6, atlas_size >> low_shift >= 16.
  * Errors as fa_build_atlas, plus FA_ERR_INVALID_ARG for a bad low_shift or a
- * null occupancy_low. */
+ * null occupancy_low, and FA_ERR_UNSUPPORTED on a context created with
+ * FA_FLAG_FOOTPRINT_PUSH (overlapping boxes can share texels at the lower
+ * resolution). */
 int fa_build_dual_atlas(fa_ctx* ctx, const fa_mesh* mesh, const uint8_t* visible,
                         const fa_camera* cam, int32_t atlas_size, float texel_per_pixel,
                         int32_t low_shift, fa_atlas_out* out, int32_t* occupancy_low,
@@ -274,13 +293,14 @@ int fa_set_tuning(fa_ctx* ctx, int knob, int value);
 int fa_get_tuning(fa_ctx* ctx, int knob);
 
 /* Per-kernel timing: when enabled, fa_build_atlas (with uv and occupancy
- * outputs) records an event after each of its 19 kernels; fa_stage_times
+ * outputs) records an event after each of its 21 kernels; fa_stage_times
  * (after the stream completed) fills up to n floats with milliseconds for, in
  * order: prologue (state, clip transform, union-find start), vis_scan,
  * vis_compact (list of the visible triangles), uf_hook, uf_vertex_min,
  * uf_vertex_hook, uf_flatten, chart_scan, assign_roots, gather_boxes,
- * sizes_order, pack, select_place, uv, occ_fill, occ_small, occ_big,
- * occ_count, meta; it returns the number filled (0 if none recorded).
+ * sizes_order, fp_clear, fp_raster (footprint profiles; empty without
+ * FA_FLAG_FOOTPRINT_PUSH), pack, select_place, uv, occ_fill, occ_small,
+ * occ_big, occ_count, meta; it returns the number filled (0 if none recorded).
  * Enabling costs a little host time and device idle time between kernels. */
 int fa_set_stage_timing(fa_ctx* ctx, int enable);
 int fa_stage_times(fa_ctx* ctx, float* ms_host, int n);

@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libfastatlas.so")
 FA_OK, FA_ERR_INVALID_ARG, FA_ERR_OUT_OF_MEMORY, FA_ERR_CAPACITY = 0, 1, 2, 3
 FA_ERR_NOFIT, FA_ERR_DEVICE, FA_ERR_UNSUPPORTED = 4, 5, 6
 FA_FLAG_NO_SIDE_CLIP = 1
+FA_FLAG_FOOTPRINT_PUSH = 4
 FA_TUNE_PACK_BLOCK, FA_TUNE_OCC_SMALL_TEXELS, FA_TUNE_UF_LINK_INIT, FA_TUNE_BATCH_GRAPH = 1, 2, 3, 4
 FA_TUNE_UF_EDGE_HOOKS, FA_TUNE_OCC_LANE_TEXELS = 5, 6
 
@@ -33,7 +34,7 @@ class fa_config(ctypes.Structure):
     _fields_ = [("device", c_int32), ("num_scales", c_int32), ("max_triangles", c_int64),
                 ("max_vertices", c_int64), ("max_charts", c_int32), ("max_atlas", c_int32),
                 ("gutter", c_int32), ("min_box", c_int32), ("flags", c_uint32),
-                ("max_views", c_int32)]
+                ("max_views", c_int32), ("max_profile_columns", c_int64)]
 
 
 class fa_mesh(ctypes.Structure):
@@ -129,8 +130,9 @@ fa_reuse_flags = _lib.fa_reuse_flags
 fa_build_dual_atlas = _lib.fa_build_dual_atlas
 
 STAGES = ["prologue", "vis_scan", "vis_compact", "uf_hook", "uf_vertex_min", "uf_vertex_hook",
-          "uf_flatten", "chart_scan", "assign_roots", "gather_boxes", "sizes_order", "pack",
-          "select_place", "uv", "occ_fill", "occ_small", "occ_big", "occ_count", "meta"]
+          "uf_flatten", "chart_scan", "assign_roots", "gather_boxes", "sizes_order", "fp_clear",
+          "fp_raster", "pack", "select_place", "uv", "occ_fill", "occ_small", "occ_big",
+          "occ_count", "meta"]
 
 
 class FastAtlasError(RuntimeError):
@@ -233,9 +235,10 @@ class Context:
     """Owns an fa_ctx (scratch + resident scene adjacency) on one device."""
 
     def __init__(self, max_triangles, max_vertices, max_charts=65536, max_atlas=8192,
-                 num_scales=64, gutter=1, min_box=2, flags=0, device=0, max_views=1):
+                 num_scales=64, gutter=1, min_box=2, flags=0, device=0, max_views=1,
+                 max_profile_columns=0):
         cfg = fa_config(device, num_scales, max_triangles, max_vertices, max_charts, max_atlas,
-                        gutter, min_box, flags, max_views)
+                        gutter, min_box, flags, max_views, max_profile_columns)
         h = c_void_p()
         _check(fa_create(ctypes.byref(cfg), ctypes.byref(h)), "fa_create")
         self.h = h

@@ -36,7 +36,7 @@ struct FrameState {
   float s_star;       // j*/J
   float q_star;       // omega/L*
   int32_t visible;    // visible triangles (length of the visible list)
-  int32_t pad;
+  int32_t fp_columns; // full-scale footprint profile columns of the frame (footprint push)
   unsigned long long occupied;
 };
 
@@ -64,6 +64,7 @@ struct FrameParams {
   uint32_t flags;
   int32_t max_charts;
   int32_t edge_hooks;  // edge hooks of the union-find: 0 none, 1 global, 2 per tile in LDS
+  int32_t fp_cap;      // footprint push: capacity of the profile columns (0: box push)
 };
 
 // Scratch buffers of one context (sized by the capacities).
@@ -95,6 +96,8 @@ struct Work {
   int32_t* cand_rs;      // [J][max_charts + 1] row starts of each candidate (frames above
                          // the LDS capacity of the packer)
   int4* chart_tex;       // [max_charts] texel range of each placed box (lo_x, hi_x, lo_y, hi_y)
+  int32_t* fp_off;       // [max_charts + 1] first profile column of each chart (footprint push)
+  int2* fp_prof;         // [max_profile_columns] full-scale (top, bottom) row of each column
   FrameState* state;     // [1]
 };
 
@@ -227,7 +230,13 @@ hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* 
                          fa_chart* charts, Marker& mk, hipStream_t st);
 hipError_t launch_order(const FrameParams& p, const Work& w, fa_chart* charts, int from_accum,
                         hipStream_t st);
-hipError_t launch_pack(const FrameParams& p, const Work& w, int block, hipStream_t st);
+// footprint push: the full-scale profile of every chart (clear, then raster)
+hipError_t launch_footprint(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
+                            const int32_t* cot, const fa_chart* charts, Marker& mk,
+                            hipStream_t st);
+// footprint: pack with the chart profiles (p.fp_cap > 0 and a frame's charts)
+hipError_t launch_pack(const FrameParams& p, const Work& w, int block, bool footprint,
+                       hipStream_t st);
 hipError_t launch_select_place(const FrameParams& p, const Work& w, fa_chart* charts,
                                int32_t* cand_out, hipStream_t st);
 hipError_t launch_uv(const int64_t V, const FrameParams& p, const Work& w, const int32_t* cov,

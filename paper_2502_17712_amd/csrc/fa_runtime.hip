@@ -22,7 +22,7 @@ struct Scene {
   int64_t T = 0, V = 0;
 };
 
-enum { kStages = 19 };
+enum { kStages = 21 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -112,6 +112,13 @@ int fa_create(const fa_config* cfg_in, fa_ctx** out_ctx) {
   if (cfg.gutter < 0 || cfg.gutter > 64 || cfg.min_box < 1 || cfg.min_box > 64)
     return FA_ERR_INVALID_ARG;
   if (cfg.max_views < 1) return FA_ERR_INVALID_ARG;
+  const bool footprint = (cfg.flags & FA_FLAG_FOOTPRINT_PUSH) != 0;
+  if (footprint && cfg.max_profile_columns == 0)
+    cfg.max_profile_columns = 64 * (int64_t)cfg.max_atlas;
+  if (footprint && (cfg.gutter < 1 || cfg.max_profile_columns < 1 ||
+                    cfg.max_profile_columns > (int64_t(1) << 28)))
+    return FA_ERR_INVALID_ARG;
+  if (!footprint) cfg.max_profile_columns = 0;
 
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || cfg.device < 0 || cfg.device >= ndev)
@@ -149,6 +156,8 @@ int fa_create(const fa_config* cfg_in, fa_ctx** out_ctx) {
         {(void**)&w.big_counter, 8},             {(void**)&w.partial, 8 * kCountGrid},
         {(void**)&w.pack_charts, sizeof(fa_chart) * C}, {(void**)&w.chart_tex, 16 * C},
         {(void**)&w.cand_rs, 4 * J * (C + 1)},
+        {(void**)&w.fp_off, footprint ? 4 * (C + 1) : 4},
+        {(void**)&w.fp_prof, footprint ? 8 * (size_t)cfg.max_profile_columns : 8},
         {(void**)&w.state, sizeof(FrameState)}};
     size_t total = 0;
     for (auto& p : parts) total += align_up(p.bytes);
@@ -401,6 +410,7 @@ static int frame_params(const fa_ctx* ctx, const fa_camera* cam, int32_t atlas, 
   p->flags = ctx->cfg.flags;
   p->max_charts = ctx->cfg.max_charts;
   p->edge_hooks = ctx->uf_edge_hooks;
+  p->fp_cap = (int32_t)ctx->cfg.max_profile_columns;
   return FA_OK;
 }
 
@@ -422,7 +432,8 @@ static int run_frame(fa_ctx* ctx, const Work& w, const fa_mesh* mesh, Scene* sc,
                    mk, st));
   ok(launch_order(p, w, out->charts, 1, st));
   mk(st);
-  ok(launch_pack(p, w, ctx->pack_block, st));
+  ok(launch_footprint(mesh->indices, T, p, w, out->chart_of_tri, out->charts, mk, st));
+  ok(launch_pack(p, w, ctx->pack_block, p.fp_cap > 0, st));
   mk(st);
   ok(launch_select_place(p, w, out->charts, out->candidates, st));
   mk(st);
@@ -463,6 +474,7 @@ int fa_build_dual_atlas(fa_ctx* ctx, const fa_mesh* mesh, const uint8_t* visible
   if (!ctx || !visible || !cam || !out || !occupancy_low) return FA_ERR_INVALID_ARG;
   if (!out->chart_of_tri || !out->charts || !out->meta) return FA_ERR_INVALID_ARG;
   if (low_shift < 1 || low_shift > 6 || (atlas_size >> low_shift) < 16) return FA_ERR_INVALID_ARG;
+  if (ctx->cfg.flags & FA_FLAG_FOOTPRINT_PUSH) return FA_ERR_UNSUPPORTED;
   int rc = check_mesh(ctx, mesh);
   if (rc) return rc;
   FrameParams p;
@@ -591,7 +603,7 @@ int fa_pack_boxes(fa_ctx* ctx, const float* sizes, int32_t n, int32_t atlas_size
   auto ok = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
   ok(launch_pack_prepare(sizes, n, p, w, charts, st));
   ok(launch_order(p, w, charts, 0, st));
-  ok(launch_pack(p, w, ctx->pack_block, st));
+  ok(launch_pack(p, w, ctx->pack_block, false, st));
   ok(launch_select_place(p, w, charts, candidates, st));
   ok(launch_pack_emit(n, charts, placements, w, st));
   ok(launch_meta(p, w, meta, 0, st));

@@ -9,11 +9,25 @@
 //   mirror  rows with row % 3 != 0 run right to left;
 //   push    row by row, a box rises to the top of the frontline under its span
 //           and raises that span by its height. The frontline (L <= 2 omega
-//           columns) lives in LDS; threads own contiguous column ranges, find
-//           the box entering their range with a tagged max-scan over start
-//           markers and reduce per-box maxima with LDS atomics.
+//           columns) lives in LDS; the boxes of a row have disjoint spans, so
+//           each wave takes whole boxes and one barrier per row orders rows.
 // A candidate fits iff m <= omega and the layout height H <= L. Selection takes
 // the largest effective scale (j/J) * omega / L, compared exactly.
+//
+// Footprint push (a generalization of the push to non-rectangular charts):
+// a box meets the frontline with its footprint profile instead of its full
+// height. The profile of content column k (box column k + g) at scale j/J is
+// pooled from the chart's full-scale profile: the fine columns whose scaled
+// cells touch k give top row T = floor(min top * j / J) and bottom row B =
+// floor((max bottom + 1) * j / J) (inclusive), or the box bottom when they
+// reach the chart's last row; the gutter then widens it by g columns and
+// rows. With top[d] / bottom[d] = min(b - 1, 2g + B) the widened profile of
+// box column d:
+//   y = max(0, max_d F[x+d] - top[d]),  F[x+d] = y + bottom[d] + 1,
+// computed per content column k (its widened window is d in [k, k + 2g]):
+// y = max over k of (max F over the window) - T_k, and, since the new
+// frontline value only grows, F[x+d] = max over the k covering d of
+// min(y + b, y + 2g + B_k + 1), applied with LDS atomic max.
 #include <climits>
 
 #include "fa_internal.h"
@@ -25,15 +39,38 @@ namespace {
 // and sizes in LDS next to the frontline, so the sequential row loop never
 // waits on global memory.
 constexpr int kPackLds = 4096;
+constexpr int kRowInf = 1 << 29;  // pooled bottom that reaches the box bottom
 
-template <int NT>
+// Pooled full-scale profile of content column k at scale j/J (false: empty).
+__device__ __forceinline__ bool pool_column(const int2* __restrict__ pr, int Uc, int Rc, int k,
+                                            int j, int J, int& T, int& B) {
+  const int lo = min(Uc - 1, max(0, (k * J + j - 1) / j - 1));
+  const int hi = min(Uc - 1, ((k + 1) * J + j - 1) / j - 1);
+  int tmin = INT_MAX, bmax = -1;
+  for (int u = lo; u <= hi; ++u) {
+    const int2 v = pr[u];
+    if (v.y >= 0) {
+      tmin = min(tmin, v.x);
+      bmax = max(bmax, v.y);
+    }
+  }
+  if (bmax < 0) return false;
+  T = tmin * j / J;
+  B = bmax == Rc - 1 ? kRowInf : (bmax + 1) * j / J;
+  return true;
+}
+
+template <int NT, bool FP>
 __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
                                              const FrameState* __restrict__ st, FrameParams p,
                                              long long* __restrict__ cand_x,
                                              uint32_t* __restrict__ cand_ab,
                                              int32_t* __restrict__ cand_y,
                                              int32_t* __restrict__ cand_rs,
-                                             int32_t* __restrict__ cand_tab, int64_t stride) {
+                                             int32_t* __restrict__ cand_tab, int64_t stride,
+                                             const int32_t* __restrict__ order,
+                                             const int32_t* __restrict__ fp_off,
+                                             const int2* __restrict__ fp_prof) {
   // [2 * omega] frontline, then the LDS copies of X, AB and the row starts
   extern __shared__ int32_t F[];
   __shared__ long long sh64[NT / kWave];
@@ -131,12 +168,42 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
       const int a = (int)(ab & 0xFFFFu), b = (int)(ab >> 16);
       const int o = (int)(Xk - (r << lg));
       const int x = right ? L - o - a : o;
-      int mx = 0;
-      for (int c = x + lane; c < x + a; c += kWave) mx = max(mx, F[c]);
-      const int y = wave_max<int>(mx);
-      for (int c = x + lane; c < x + a; c += kWave) F[c] = y + b;
-      if (lane == 0) Y[k] = y;
-      Hw = max(Hw, y + b);
+      if constexpr (!FP) {
+        int mx = 0;
+        for (int c = x + lane; c < x + a; c += kWave) mx = max(mx, F[c]);
+        const int y = wave_max<int>(mx);
+        for (int c = x + lane; c < x + a; c += kWave) F[c] = y + b;
+        if (lane == 0) Y[k] = y;
+        Hw = max(Hw, y + b);
+      } else {
+        const int g = p.gutter, ncol = a - g;
+        const float2 sz = wh[k];
+        const int Uc = (int)floorf(sz.x) + 1, Rc = (int)floorf(sz.y) + 1;
+        const int2* pr = fp_prof + fp_off[order[k]];
+        int mx = 0;
+        for (int kk = lane; kk < ncol; kk += kWave) {
+          int Tk, Bk;
+          if (pool_column(pr, Uc, Rc, kk, j, p.J, Tk, Bk)) {
+            const int dend = min(kk + 2 * g, a - 1);
+            int fm = 0;
+            for (int d = kk; d <= dend; ++d) fm = max(fm, F[x + d]);
+            mx = max(mx, fm - Tk);
+          }
+        }
+        const int y = wave_max<int>(mx);
+        int hv = 0;
+        for (int kk = lane; kk < ncol; kk += kWave) {
+          int Tk, Bk;
+          if (pool_column(pr, Uc, Rc, kk, j, p.J, Tk, Bk)) {
+            const int v = Bk >= kRowInf ? y + b : min(y + b, y + 2 * g + Bk + 1);
+            const int dend = min(kk + 2 * g, a - 1);
+            for (int d = kk; d <= dend; ++d) atomicMax(&F[x + d], v);
+            hv = max(hv, v);
+          }
+        }
+        Hw = max(Hw, wave_max<int>(hv));  // lane 0 publishes the wave's height
+        if (lane == 0) Y[k] = y;
+      }
     }
     if (lane == 0) atomicMax(&Hsh[rr & 1], Hw);
     __syncthreads();
@@ -286,30 +353,49 @@ __global__ void k_pack_emit(int32_t n, const fa_chart* __restrict__ charts,
 
 }  // namespace
 
-hipError_t pack_kernel_attributes(int max_frontline_bytes) {
-  const int max_dyn_bytes = max_frontline_bytes + kPackLds * 16 + 4;
-  hipError_t e = hipFuncSetAttribute((const void*)k_pack<256>,
+namespace {
+template <bool FP>
+hipError_t pack_attributes(int max_dyn_bytes) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_pack<256, FP>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn_bytes);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_pack<512>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          max_dyn_bytes);
+  e = hipFuncSetAttribute((const void*)k_pack<512, FP>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn_bytes);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_pack<1024>,
+  return hipFuncSetAttribute((const void*)k_pack<1024, FP>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn_bytes);
 }
 
-hipError_t launch_pack(const FrameParams& p, const Work& w, int block, hipStream_t st) {
-  const size_t dyn = (size_t)2 * p.omega * sizeof(int32_t) + (size_t)kPackLds * 16 + 4;
+template <bool FP>
+void pack_launch(const FrameParams& p, const Work& w, int block, size_t dyn, hipStream_t st) {
   const int64_t stride = p.max_charts;
   if (block == 1024)
-    k_pack<1024><<<p.J, 1024, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab, w.cand_y,
-                                         w.cand_rs, w.cand_tab, stride);
+    k_pack<1024, FP><<<p.J, 1024, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab,
+                                             w.cand_y, w.cand_rs, w.cand_tab, stride, w.vals_a,
+                                             w.fp_off, w.fp_prof);
   else if (block == 512)
-    k_pack<512><<<p.J, 512, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab, w.cand_y,
-                                       w.cand_rs, w.cand_tab, stride);
+    k_pack<512, FP><<<p.J, 512, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab,
+                                           w.cand_y, w.cand_rs, w.cand_tab, stride, w.vals_a,
+                                           w.fp_off, w.fp_prof);
   else
-    k_pack<256><<<p.J, 256, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab, w.cand_y,
-                                       w.cand_rs, w.cand_tab, stride);
+    k_pack<256, FP><<<p.J, 256, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab,
+                                           w.cand_y, w.cand_rs, w.cand_tab, stride, w.vals_a,
+                                           w.fp_off, w.fp_prof);
+}
+}  // namespace
+
+hipError_t pack_kernel_attributes(int max_frontline_bytes) {
+  const int max_dyn_bytes = max_frontline_bytes + kPackLds * 16 + 4;
+  const hipError_t e = pack_attributes<false>(max_dyn_bytes);
+  if (e != hipSuccess) return e;
+  return pack_attributes<true>(max_dyn_bytes);
+}
+
+hipError_t launch_pack(const FrameParams& p, const Work& w, int block, bool footprint,
+                       hipStream_t st) {
+  const size_t dyn = (size_t)2 * p.omega * sizeof(int32_t) + (size_t)kPackLds * 16 + 4;
+  if (footprint) pack_launch<true>(p, w, block, dyn, st);
+  else pack_launch<false>(p, w, block, dyn, st);
   return hipGetLastError();
 }
 

@@ -11,6 +11,7 @@
 // are rasterized by one lane, medium ones by their wave, large ones are queued
 // and cut into 16x16 tiles shared by all waves.
 #include <algorithm>
+#include <climits>
 
 #include "fa_internal.h"
 
@@ -604,6 +605,133 @@ hipError_t launch_occupancy_scaled(const int32_t* idx, int64_t T, const FramePar
       p, charts, w.chart_tex, w.big_counter, w.state);
   Marker none;
   return launch_occupancy(idx, T, p, w, cot, charts, occ, small_texels, lane_texels, none, st);
+}
+
+namespace {
+// ---------------------------------------------------------------------------
+// footprint push: full-scale profile of every chart
+// ---------------------------------------------------------------------------
+// Column u of chart c (prof[fp_off[c] + u], u < floor(oriented width) + 1)
+// holds the first and last row, on the unit grid of the chart-local layout
+// before scale and gutter, that the chart's snapped polygons reach inside the
+// closed strip [u, u + 1] (first and last strips open outwards, rows clamped
+// to the chart's floor(oriented height) + 1 rows). Exact integer arithmetic
+// on the 1/256 snapped vertices: a side crossing's row is the floor of an
+// exact rational. Empty column: (INT_MAX, -1).
+__global__ void k_fp_clear(int2* __restrict__ prof, const FrameState* __restrict__ st) {
+  if (st->status != FA_OK) return;
+  const int n = st->fp_columns;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    prof[i] = make_int2(INT_MAX, -1);
+}
+
+// floor((py + (x0 - px) (qy - py) / (qx - px)) / 256), px != qx
+__device__ __forceinline__ int32_t crossing_row(int64_t px, int64_t py, int64_t qx, int64_t qy,
+                                                int64_t x0) {
+  int64_t num = py * (qx - px) + (x0 - px) * (qy - py);
+  int64_t den = qx - px;
+  if (den < 0) {
+    num = -num;
+    den = -den;
+  }
+  return (int32_t)floor_div64(num, 256 * den);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fp_raster(
+    const int32_t* __restrict__ vlist, const int32_t* __restrict__ idx,
+    const float4* __restrict__ clip, const int32_t* __restrict__ cot,
+    const fa_chart* __restrict__ charts, const int32_t* __restrict__ fp_off,
+    int2* __restrict__ prof, FrameParams p, const FrameState* __restrict__ stp) {
+  if (stp->status != FA_OK) return;
+  const int nv = stp->visible;
+  const float halfW = 0.5f * (float)p.W, halfH = 0.5f * (float)p.H;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
+    const int t = vlist[i];
+    const int c = cot[t];
+    if (c < 0) continue;
+    const float4 a = clip[idx[3 * (int64_t)t]], b = clip[idx[3 * (int64_t)t + 1]],
+                 cc = clip[idx[3 * (int64_t)t + 2]];
+    if (outside<0>(a, b, cc) || outside<1>(a, b, cc) || outside<2>(a, b, cc) ||
+        outside<3>(a, b, cc) || outside<4>(a, b, cc) || outside<5>(a, b, cc))
+      continue;
+    float4 poly[4];
+    int n;
+    if (pd<4>(a) < 0.0f || pd<4>(b) < 0.0f || pd<4>(cc) < 0.0f) {
+      n = near_clip(a, b, cc, poly);
+    } else {
+      poly[0] = a; poly[1] = b; poly[2] = cc; poly[3] = cc; n = 3;
+    }
+    bool ok = n > 0;
+    for (int k = 0; k < n; ++k) ok = ok && poly[k].w > 0.0f;
+    if (!ok) continue;
+    const fa_chart& ch = charts[c];
+    const float x0 = ch.ndc_box[0], y1 = ch.ndc_box[3], tw = ch.target_w;
+    const int rot = ch.rotated;
+    int32_t X[4], Y[4];
+    int32_t xmin = INT_MAX, xmax = INT_MIN;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k < n) {
+        const float nx = poly[k].x / poly[k].w, ny = poly[k].y / poly[k].w;
+        const float px = ((nx - x0) * halfW) * p.rate;
+        const float py = ((y1 - ny) * halfH) * p.rate;
+        X[k] = snap(rot ? py : px);
+        Y[k] = snap(rot ? (tw - px) : py);
+        xmin = min(xmin, X[k]);
+        xmax = max(xmax, X[k]);
+      }
+    }
+    const int Uc = (int)floorf(ch.oriented_w) + 1, Rc = (int)floorf(ch.oriented_h) + 1;
+    int2* pr = prof + fp_off[c];
+    const int u0 = min(Uc - 1, max(0, xmin >> 8)), u1 = min(Uc - 1, max(0, xmax >> 8));
+    for (int u = u0; u <= u1; ++u) {
+      const bool open_l = u == 0, open_r = u == Uc - 1;
+      const int64_t sl = 256 * (int64_t)u, sr = sl + 256;
+      int32_t rlo = INT_MAX, rhi = INT_MIN;
+      for (int k = 0; k < n; ++k) {
+        if ((open_l || X[k] >= sl) && (open_r || X[k] <= sr)) {
+          rlo = min(rlo, Y[k] >> 8);
+          rhi = max(rhi, Y[k] >> 8);
+        }
+      }
+      for (int k = 0; k < n; ++k) {
+        const int k1 = k + 1 == n ? 0 : k + 1;
+        const int64_t Px = X[k], Py = Y[k], Qx = X[k1], Qy = Y[k1];
+        if (Px == Qx) continue;
+        const int64_t lo = min(Px, Qx), hi = max(Px, Qx);
+        if (!open_l && lo < sl && sl < hi) {
+          const int32_t r = crossing_row(Px, Py, Qx, Qy, sl);
+          rlo = min(rlo, r);
+          rhi = max(rhi, r);
+        }
+        if (!open_r && lo < sr && sr < hi) {
+          const int32_t r = crossing_row(Px, Py, Qx, Qy, sr);
+          rlo = min(rlo, r);
+          rhi = max(rhi, r);
+        }
+      }
+      if (rlo > rhi) continue;
+      rlo = min(Rc - 1, max(0, rlo));
+      rhi = min(Rc - 1, max(0, rhi));
+      atomicMin(&pr[u].x, rlo);
+      atomicMax(&pr[u].y, rhi);
+    }
+  }
+}
+}  // namespace
+
+hipError_t launch_footprint(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
+                            const int32_t* cot, const fa_chart* charts, Marker& mk,
+                            hipStream_t st) {
+  if (p.fp_cap > 0)
+    k_fp_clear<<<(unsigned)std::min<int64_t>(1024, (p.fp_cap + kBlock - 1) / kBlock), kBlock, 0,
+                 st>>>(w.fp_prof, w.state);
+  mk(st);
+  if (p.fp_cap > 0 && T > 0)
+    k_fp_raster<<<visible_grid(T), kBlock, 0, st>>>(w.vlist, idx, w.clip, cot, charts, w.fp_off,
+                                                    w.fp_prof, p, w.state);
+  mk(st);
+  return hipGetLastError();
 }
 
 hipError_t launch_meta(const FrameParams& p, const Work& w, fa_atlas_meta* meta,

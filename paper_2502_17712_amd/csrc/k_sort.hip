@@ -207,18 +207,22 @@ __device__ __forceinline__ void chart_size(const FrameParams& p, const uint4 e, 
 // Sizes (when from_accum) and the stable order by (height desc, chart asc):
 // two 8-bit LSD radix passes over the 13-bit keys in one workgroup, items
 // ranked 1024 at a time (ballot matching inside a wave, per-wave digit counts
-// across the 16 waves), then the sorted oriented sizes for the packer.
+// across the 16 waves), then the sorted oriented sizes for the packer. With
+// fp_off (footprint push): each chart's full-scale profile columns,
+// floor(oriented width) + 1, are laid out in chart order (exclusive scan);
+// a total above the capacity ends the frame with FA_ERR_CAPACITY.
 constexpr int kOrderThreads = 1024;
 
 __global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
     FrameParams p, const uint32_t* __restrict__ accum, fa_chart* __restrict__ charts,
     uint32_t* __restrict__ keys_a, int32_t* __restrict__ vals_a, uint32_t* __restrict__ keys_b,
     int32_t* __restrict__ vals_b, float2* __restrict__ sorted_wh, int from_accum,
-    const FrameState* __restrict__ st) {
+    int32_t* __restrict__ fp_off, FrameState* __restrict__ st) {
   constexpr int NW = kOrderThreads / kWave;
   __shared__ uint32_t base[kRadix];
   __shared__ uint32_t wcnt[NW][kRadix];
   __shared__ uint32_t sh[NW];
+  __shared__ long long sh64[NW];
   if (st->status != FA_OK) return;
   const int C = min(st->num_charts, p.max_charts);
   const int tid = threadIdx.x, w = tid / kWave;
@@ -299,6 +303,22 @@ __global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
     sorted_wh[i] = make_float2(ch.oriented_w, ch.oriented_h);
     ch.order_rank = i;
   }
+  if (fp_off) {
+    long long run = 0;
+    for (int base0 = 0; base0 < C; base0 += kOrderThreads) {
+      const int c = base0 + tid;
+      const long long n = c < C ? (long long)floorf(charts[c].oriented_w) + 1 : 0;
+      long long tot;
+      const long long incl = block_incl_scan<long long>(n, sh64, &tot);
+      if (c < C) fp_off[c] = (int32_t)min(run + incl - n, (long long)p.fp_cap);
+      run += tot;
+    }
+    if (tid == 0) {
+      fp_off[C] = (int32_t)min(run, (long long)p.fp_cap);
+      st->fp_columns = (int32_t)min(run, (long long)p.fp_cap);
+      if (run > p.fp_cap) st->status = FA_ERR_CAPACITY;
+    }
+  }
 }
 
 }  // namespace
@@ -327,8 +347,9 @@ hipError_t launch_adjacency(const int32_t* idx, int64_t T, int64_t V, const AdjT
 
 hipError_t launch_order(const FrameParams& p, const Work& w, fa_chart* charts, int from_accum,
                         hipStream_t st) {
+  int32_t* fp_off = (from_accum && p.fp_cap > 0) ? w.fp_off : nullptr;
   k_sizes_order<<<1, kOrderThreads, 0, st>>>(p, w.accum, charts, w.keys_a, w.vals_a, w.keys_b,
-                                             w.vals_b, w.sorted_wh, from_accum, w.state);
+                                             w.vals_b, w.sorted_wh, from_accum, fp_off, w.state);
   return hipGetLastError();
 }
 

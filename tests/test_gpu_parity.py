@@ -304,7 +304,7 @@ def test_stage_timing_one_event_per_kernel():
         st = ctx.stage_times()
     finally:
         ctx.set_stage_timing(False)
-    assert list(st) == fa.STAGES and len(st) == 19
+    assert list(st) == fa.STAGES and len(st) == 21
     assert all(v >= 0.0 for v in st.values())
     # timing changes nothing
     compare(g, oracle.build_frame(f))
@@ -455,3 +455,74 @@ def test_union_find_modes_all_combinations(link, hooks):
     finally:
         ctx.set_tuning(3, old[0])
         ctx.set_tuning(5, old[1])
+
+
+# ---------------------------------------------------------------------------
+# footprint-aware push
+# ---------------------------------------------------------------------------
+FP = 4  # FA_FLAG_FOOTPRINT_PUSH
+
+
+def _fp_frame(kind, k, omega, rate):
+    if kind == "grid":
+        return scenes.grid_frame(k, atlas_size=omega, rate=rate)
+    if kind == "orbit":
+        return scenes.orbit_frame(k, atlas_size=omega, rate=rate)
+    return scenes.city_frame(k, rate=rate, atlas_size=omega)
+
+
+@pytest.mark.parametrize("kind,k,omega,rate", [("grid", 3, 256, 1.0), ("grid", 11, 512, 2.0),
+                                               ("grid", 20, 1024, 1.0), ("orbit", 20, 512, 1.0),
+                                               ("orbit", 77, 2048, 1.0), ("city", 5, 4096, 1.0),
+                                               ("city", 9, 2048, 2.0)])
+def test_footprint_push(kind, k, omega, rate):
+    f = _fp_frame(kind, k, omega, rate)
+    g = run_gpu(f, ctx_for(flags=FP))
+    r = oracle.build_frame(f, footprint=True)
+    compare(g, r)
+    assert r["occupancy_conflicts"] == 0
+
+
+@pytest.mark.parametrize("J,gutter,omega,rate", [(16, 2, 256, 1.0), (32, 1, 1024, 2.0),
+                                                 (64, 3, 128, 0.5)])
+def test_footprint_variants(J, gutter, omega, rate):
+    f = scenes.grid_frame(9, atlas_size=omega, rate=rate)
+    g = run_gpu(f, ctx_for(J=J, gutter=gutter, flags=FP))
+    compare(g, oracle.build_frame(f, J=J, gutter=gutter, footprint=True))
+
+
+def test_footprint_empty_frame_and_batch():
+    fa = _fa()
+    ctx = ctx_for(flags=FP)
+    f = scenes.grid_frame(2, atlas_size=512)
+    mesh = mesh_for(f)
+    # nothing visible: no charts, the largest scale
+    none = torch.zeros(f.num_triangles, dtype=torch.uint8, device="cuda")
+    out = ctx.outputs(mesh, 512)
+    ctx.build_atlas(mesh, none, f.view_proj, f.width, f.height, 512, 1.0, out=out)
+    torch.cuda.synchronize()
+    m = fa.parse_meta(out.meta)
+    assert m["status"] == 0 and m["num_charts"] == 0 and m["chosen_j"] == 64
+    # views of a batch (one mesh) equal the single-frame results
+    frames = [scenes.orbit_frame(k, atlas_size=512) for k in (5, 40, 90)]
+    mesh = mesh_for(frames[0])
+    vis = [torch.as_tensor(x.visible).cuda() for x in frames]
+    outs = [ctx.outputs(mesh, 512) for _ in frames]
+    ctx.build_atlas_batch(mesh, [(v, x.view_proj, x.width, x.height, 512, 1.0)
+                                 for v, x in zip(vis, frames)], outs)
+    torch.cuda.synchronize()
+    for x, o in zip(frames, outs):
+        compare(o.to_numpy(), oracle.build_frame(x, footprint=True))
+
+
+def test_footprint_capacity_and_dual_rejected():
+    fa = _fa()
+    f = scenes.grid_frame(6, atlas_size=512)
+    small = fa.Context(10_000, 5_000, max_charts=4096, max_atlas=1024, flags=FP,
+                       max_profile_columns=8)
+    g = run_gpu(f, small)
+    assert g["meta"]["status"] == fa.FA_ERR_CAPACITY
+    mesh = mesh_for(f)
+    vis = torch.as_tensor(f.visible).cuda()
+    with pytest.raises(fa.FastAtlasError):
+        small.build_dual_atlas(mesh, vis, f.view_proj, f.width, f.height, 512, 1.0, 1)
