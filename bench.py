@@ -186,6 +186,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-dual", action="store_true")
+    ap.add_argument("--no-footprint", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the no-occupancy, copy, visibility and reuse measurements")
     ap.add_argument("--serve-rate", type=float, nargs="+", default=[60.0, 250.0, 1000.0, 2000.0])
@@ -385,6 +386,63 @@ def main():
         del dout, dlow
         dctx.close()
 
+    # footprint-aware push against the box push on the same frames
+    footprint = None
+    if not args.no_footprint:
+        fctx = fa.Context(T, V, max_charts=65536, max_atlas=args.atlas,
+                          flags=fa.FA_FLAG_FOOTPRINT_PUSH)
+        for knob_ in TUNED:
+            fctx.set_tuning(knob_, ctx.get_tuning(knob_))
+        footprint = {}
+        for r_ in (1.0, 2.0):
+            ffr = [scenes.city_frame(k, rate=r_, atlas_size=args.atlas) for k in range(0, 32, 8)]
+            fvis = [torch.as_tensor(f.visible).to(dev) for f in ffr]
+            res_f = {}
+            for name_, c_ in (("box", ctx), ("footprint", fctx)):
+                o_ = c_.outputs(mesh, args.atlas)
+
+                def fstep(k):
+                    f = ffr[k % len(ffr)]
+                    c_.build_atlas(mesh, fvis[k % len(ffr)], f.view_proj, f.width, f.height,
+                                   args.atlas, r_, out=o_, stream=stream)
+                metas = []
+                for k in range(len(ffr)):
+                    fstep(k)
+                    torch.cuda.synchronize()
+                    metas.append(fa.parse_meta(o_.meta))
+                assert all(m_["status"] == fa.FA_OK for m_ in metas), metas
+                evf = []
+                for k in range(32):
+                    a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a_.record(stream)
+                    fstep(k)
+                    b_.record(stream)
+                    evf.append((a_, b_))
+                torch.cuda.synchronize()
+                res_f[name_] = dict(
+                    ms_per_frame=float(np.mean([a_.elapsed_time(b_) for a_, b_ in evf])),
+                    chosen_j=[m_["chosen_j"] for m_ in metas],
+                    s_eff_mean=float(np.mean([m_["s_eff"] for m_ in metas])),
+                    fill_fraction_mean=float(np.mean([m_["occupied_texels"] for m_ in metas]))
+                    / float(args.atlas) ** 2,
+                    layout_height_over_width=float(np.mean(
+                        [m_["layout_height"] / m_["layout_width"] for m_ in metas])))
+                if name_ == "footprint":
+                    c_.set_stage_timing(True)
+                    acc_ = {}
+                    for k in range(8):
+                        fstep(k)
+                        torch.cuda.synchronize()
+                        for sn, ms_ in c_.stage_times().items():
+                            acc_.setdefault(sn, []).append(ms_)
+                    c_.set_stage_timing(False)
+                    res_f[name_]["stages_ms"] = {
+                        sn: float(np.mean(acc_[sn])) for sn in ("fp_clear", "fp_raster", "pack")}
+                del o_
+            footprint[f"rate{r_:g}"] = dict(frames=len(ffr), **res_f)
+        fctx.close()
+        log("footprint:", json.dumps(footprint))
+
     # batched views vs the plain per-view path
     batch = None
     if not args.no_batch:
@@ -516,12 +574,13 @@ def main():
             "ms_per_frame": ms_nocc, "algorithmic_bytes": B - 4.0 * args.atlas * args.atlas,
             "hbm_roofline_frac": (B - 4.0 * args.atlas * args.atlas) / (ms_nocc * 1e-3)
             / (HBM_PEAK_GBS * 1e9)},
-        "dependent_phases": len(stages),
+        "dependent_phases": len([k_ for k_ in stages if not k_.startswith("fp_")]),
         "pack_rows_at_chosen_scale": meta["rows"],
         "copy_gbs": copy_gbs,
         "device_visibility": visibility,
         "temporal_reuse": reuse,
         "dual_atlas": dual,
+        "footprint_push": footprint,
         "batch": batch,
         "served": served,
         "secondary": secondary,

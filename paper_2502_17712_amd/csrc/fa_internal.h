@@ -65,6 +65,7 @@ struct FrameParams {
   int32_t max_charts;
   int32_t edge_hooks;  // edge hooks of the union-find: 0 none, 1 global, 2 per tile in LDS
   int32_t fp_cap;      // footprint push: capacity of the profile columns (0: box push)
+  int64_t pool_stride; // footprint push: pooled profile entries per candidate
 };
 
 // Scratch buffers of one context (sized by the capacities).
@@ -98,6 +99,7 @@ struct Work {
   int4* chart_tex;       // [max_charts] texel range of each placed box (lo_x, hi_x, lo_y, hi_y)
   int32_t* fp_off;       // [max_charts + 1] first profile column of each chart (footprint push)
   int2* fp_prof;         // [max_profile_columns] full-scale (top, bottom) row of each column
+  uint32_t* fp_pool;     // [J][pool_stride] pooled profile of every box at every candidate
   FrameState* state;     // [1]
 };
 

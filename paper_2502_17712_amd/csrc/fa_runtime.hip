@@ -34,6 +34,15 @@ int log2i(int64_t x) {
   return l;
 }
 
+// Footprint push: pooled profile entries per candidate. A box of chart c is
+// a = max(min_box, ceil(w s)) + 2 gutter <= floor(w) + 1 + min_box + 2 gutter
+// columns wide, so one candidate's fold is at most the profile columns plus
+// (min_box + 2 gutter) per chart.
+size_t pool_stride(const fa_config& cfg) {
+  return (size_t)cfg.max_profile_columns +
+         (size_t)cfg.max_charts * (size_t)(cfg.min_box + 2 * cfg.gutter);
+}
+
 }  // namespace
 
 struct fa_ctx {
@@ -158,6 +167,7 @@ int fa_create(const fa_config* cfg_in, fa_ctx** out_ctx) {
         {(void**)&w.cand_rs, 4 * J * (C + 1)},
         {(void**)&w.fp_off, footprint ? 4 * (C + 1) : 4},
         {(void**)&w.fp_prof, footprint ? 8 * (size_t)cfg.max_profile_columns : 8},
+        {(void**)&w.fp_pool, footprint ? 4 * J * pool_stride(cfg) : 4},
         {(void**)&w.state, sizeof(FrameState)}};
     size_t total = 0;
     for (auto& p : parts) total += align_up(p.bytes);
@@ -411,6 +421,7 @@ static int frame_params(const fa_ctx* ctx, const fa_camera* cam, int32_t atlas, 
   p->max_charts = ctx->cfg.max_charts;
   p->edge_hooks = ctx->uf_edge_hooks;
   p->fp_cap = (int32_t)ctx->cfg.max_profile_columns;
+  p->pool_stride = (int64_t)pool_stride(ctx->cfg);
   return FA_OK;
 }
 

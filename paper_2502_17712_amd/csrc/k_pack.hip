@@ -39,28 +39,12 @@ namespace {
 // and sizes in LDS next to the frontline, so the sequential row loop never
 // waits on global memory.
 constexpr int kPackLds = 4096;
-constexpr int kRowInf = 1 << 29;  // pooled bottom that reaches the box bottom
 
-// Pooled full-scale profile of content column k at scale j/J (false: empty).
-__device__ __forceinline__ bool pool_column(const int2* __restrict__ pr, int Uc, int Rc, int k,
-                                            int j, int J, int& T, int& B) {
-  const int lo = min(Uc - 1, max(0, (k * J + j - 1) / j - 1));
-  const int hi = min(Uc - 1, ((k + 1) * J + j - 1) / j - 1);
-  int tmin = INT_MAX, bmax = -1;
-  for (int u = lo; u <= hi; ++u) {
-    const int2 v = pr[u];
-    if (v.y >= 0) {
-      tmin = min(tmin, v.x);
-      bmax = max(bmax, v.y);
-    }
-  }
-  if (bmax < 0) return false;
-  T = tmin * j / J;
-  B = bmax == Rc - 1 ? kRowInf : (bmax + 1) * j / J;
-  return true;
-}
-
-template <int NT, bool FP>
+// MODE 0: the whole box packing of one candidate. Footprint push in three
+// launches: MODE 1 sizes, fold, overflow and row starts (to global memory;
+// tab[3] = -1 marks a rejected candidate, tab[5] the number of rows with
+// boxes), then k_fp_pool, then MODE 2 the push.
+template <int NT, int MODE>
 __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
                                              const FrameState* __restrict__ st, FrameParams p,
                                              long long* __restrict__ cand_x,
@@ -68,9 +52,8 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
                                              int32_t* __restrict__ cand_y,
                                              int32_t* __restrict__ cand_rs,
                                              int32_t* __restrict__ cand_tab, int64_t stride,
-                                             const int32_t* __restrict__ order,
-                                             const int32_t* __restrict__ fp_off,
-                                             const int2* __restrict__ fp_prof) {
+                                             const uint32_t* __restrict__ fp_pool,
+                                             int64_t pool_stride) {
   // [2 * omega] frontline, then the LDS copies of X, AB and the row starts
   extern __shared__ int32_t F[];
   __shared__ long long sh64[NT / kWave];
@@ -85,72 +68,100 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
   const int omega = p.omega, lg = p.log2omega;
   long long* Xg = cand_x + (int64_t)(j - 1) * stride;
   uint32_t* ABg = cand_ab + (int64_t)(j - 1) * stride;
+  int32_t* RSg = cand_rs + (int64_t)(j - 1) * (stride + 1);
   const bool in_lds = C <= kPackLds;
   long long* X = in_lds ? reinterpret_cast<long long*>(F + 2 * omega) : Xg;
   uint32_t* AB = in_lds ? reinterpret_cast<uint32_t*>(F + 2 * omega + 2 * kPackLds) : ABg;
-  int32_t* RS = in_lds ? F + 2 * omega + 3 * kPackLds : cand_rs + (int64_t)(j - 1) * (stride + 1);
+  int32_t* RS = (in_lds && MODE != 1) ? F + 2 * omega + 3 * kPackLds : RSg;
   int32_t* Y = cand_y + (int64_t)(j - 1) * stride;
   int32_t* tab = cand_tab + (j - 1) * kCandStride;
-  const float s = (float)j / (float)p.J;
-  const int pad = 2 * p.gutter;
+  long long m, rows;
+  int nr;
 
-  // ---- sizes, fold and overflow -------------------------------------------
-  long long run = 0, mloc = 0;
-  int bad = 0;
-  for (int base = 0; base < C; base += NT) {
-    const int i = base + tid;
-    int a = 0, b = 0;
-    if (i < C) {
-      const float2 v = wh[i];
-      const int wi = (int)ceilf(v.x * s);
-      const int hi = (int)ceilf(v.y * s);
-      a = max(p.min_box, wi) + pad;
-      b = max(p.min_box, hi) + pad;
-    }
-    long long tot;
-    const long long incl = block_incl_scan<long long>((long long)a, sh64, &tot);
-    const long long Xi = run + incl - a;
-    run += tot;
-    if (i < C) {
-      Xg[i] = Xi;
-      if (a > 2 * omega || b > 2 * omega) bad = 1;  // cannot fit: m > omega or H > L
-      const uint32_t ca = (uint32_t)min(a, 2 * omega + 1), cb = (uint32_t)min(b, 2 * omega + 1);
-      ABg[i] = ca | (cb << 16);
-      if (in_lds) {
-        X[i] = Xi;
-        AB[i] = ca | (cb << 16);
+  if constexpr (MODE != 2) {
+    const float s = (float)j / (float)p.J;
+    const int pad = 2 * p.gutter;
+    // ---- sizes, fold and overflow -----------------------------------------
+    long long run = 0, mloc = 0;
+    int bad = 0;
+    for (int base = 0; base < C; base += NT) {
+      const int i = base + tid;
+      int a = 0, b = 0;
+      if (i < C) {
+        const float2 v = wh[i];
+        const int wi = (int)ceilf(v.x * s);
+        const int hi = (int)ceilf(v.y * s);
+        a = max(p.min_box, wi) + pad;
+        b = max(p.min_box, hi) + pad;
       }
-      mloc = max(mloc, (Xi & (long long)(omega - 1)) + a - omega);
+      long long tot;
+      const long long incl = block_incl_scan<long long>((long long)a, sh64, &tot);
+      const long long Xi = run + incl - a;
+      run += tot;
+      if (i < C) {
+        Xg[i] = Xi;
+        if (a > 2 * omega || b > 2 * omega) bad = 1;  // cannot fit: m > omega or H > L
+        const uint32_t ca = (uint32_t)min(a, 2 * omega + 1), cb = (uint32_t)min(b, 2 * omega + 1);
+        ABg[i] = ca | (cb << 16);
+        if (in_lds) {
+          X[i] = Xi;
+          AB[i] = ca | (cb << 16);
+        }
+        mloc = max(mloc, (Xi & (long long)(omega - 1)) + a - omega);
+      }
     }
-  }
-  const long long m = block_max<long long>(mloc, sh64);
-  bad = block_max<int>(bad, sh32);
-  const long long rows = C > 0 ? (X[C - 1] >> lg) + 1 : 0;
-  if (m > omega || bad) {
-    if (tid == 0) {
-      tab[0] = 0;
-      tab[1] = (int32_t)min(m, (long long)INT_MAX);
-      tab[2] = (int32_t)min(m + omega, (long long)INT_MAX);
-      tab[3] = -1;
-      tab[4] = (int32_t)min(rows, (long long)INT_MAX);
+    m = block_max<long long>(mloc, sh64);
+    bad = block_max<int>(bad, sh32);
+    rows = C > 0 ? (X[C - 1] >> lg) + 1 : 0;
+    if (m > omega || bad) {
+      if (tid == 0) {
+        tab[0] = 0;
+        tab[1] = (int32_t)min(m, (long long)INT_MAX);
+        tab[2] = (int32_t)min(m + omega, (long long)INT_MAX);
+        tab[3] = -1;
+        tab[4] = (int32_t)min(rows, (long long)INT_MAX);
+      }
+      return;
     }
-    return;
+    // ---- row starts: first box of every non-empty row, in order ------------
+    nr = 0;
+    for (int base = 0; base < C; base += NT) {
+      const int i = base + tid;
+      const int first = (i < C && (i == 0 || (X[i] >> lg) != (X[i - 1] >> lg))) ? 1 : 0;
+      int tot;
+      const int incl = block_incl_scan<int>(first, sh32, &tot);
+      if (first) RS[nr + incl - 1] = i;
+      nr += tot;
+    }
+    if (tid == 0) RS[nr] = C;
+    if constexpr (MODE == 1) {
+      if (tid == 0) {
+        tab[0] = 0;
+        tab[1] = (int32_t)m;
+        tab[2] = omega + (int)m;
+        tab[3] = 0;
+        tab[4] = (int32_t)min(rows, (long long)INT_MAX);
+        tab[5] = nr;
+      }
+      return;
+    }
+  } else {
+    if (tab[3] < 0) return;  // rejected by its fold
+    m = tab[1];
+    rows = tab[4];
+    nr = tab[5];
+    if (in_lds) {
+      for (int i = tid; i < C; i += NT) {
+        X[i] = Xg[i];
+        AB[i] = ABg[i];
+      }
+      for (int i = tid; i <= nr; i += NT) RS[i] = RSg[i];
+    }
   }
   const int L = omega + (int)m;
-
-  // ---- row starts: first box of every non-empty row, in order --------------
-  int nr = 0;
-  for (int base = 0; base < C; base += NT) {
-    const int i = base + tid;
-    const int first = (i < C && (i == 0 || (X[i] >> lg) != (X[i - 1] >> lg))) ? 1 : 0;
-    int tot;
-    const int incl = block_incl_scan<int>(first, sh32, &tot);
-    if (first) RS[nr + incl - 1] = i;
-    nr += tot;
-  }
-  if (tid == 0) RS[nr] = C;
   for (int c = tid; c < L; c += NT) F[c] = 0;
   if (tid < 2) Hsh[tid] = 0;
+  const uint32_t* pool = fp_pool + (int64_t)(j - 1) * pool_stride;
   __syncthreads();
 
   // ---- push: row by row; the boxes of a row have disjoint spans, so each
@@ -158,6 +169,34 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
   // one barrier per row orders the rows. The height test reads a slot that
   // no wave can touch again before every wave has read it.
   int Hw = 0;
+  // footprint push: the pooled values do not depend on the frontline, so each
+  // wave loads its next box's first R x 64 columns while it pushes the current
+  constexpr int R = 4;
+  constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+  uint32_t nxt[R];
+  int prr = 0, pk = 0;
+  auto advance = [&](bool first) {
+    if (!first) pk += NW;
+    else pk = nr > 0 ? RS[0] + w : 0;
+    while (prr < nr && pk >= RS[prr + 1]) {
+      ++prr;
+      if (prr < nr) pk = RS[prr] + w;
+    }
+  };
+  auto prefetch = [&]() {
+    if (prr >= nr) return;
+    const uint32_t* src = pool + X[pk];
+    const int ncol = (int)(AB[pk] & 0xFFFFu) - p.gutter;
+#pragma unroll
+    for (int rk = 0; rk < R; ++rk) {
+      const int kk = lane + rk * kWave;
+      nxt[rk] = kk < ncol ? src[kk] : kEmpty;
+    }
+  };
+  if constexpr (MODE == 2) {
+    advance(true);
+    prefetch();
+  }
   for (int rr = 0; rr < nr; ++rr) {
     const int s0 = RS[rr], s1 = RS[rr + 1];
     const long long r = X[s0] >> lg;
@@ -168,7 +207,7 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
       const int a = (int)(ab & 0xFFFFu), b = (int)(ab >> 16);
       const int o = (int)(Xk - (r << lg));
       const int x = right ? L - o - a : o;
-      if constexpr (!FP) {
+      if constexpr (MODE == 0) {
         int mx = 0;
         for (int c = x + lane; c < x + a; c += kWave) mx = max(mx, F[c]);
         const int y = wave_max<int>(mx);
@@ -176,31 +215,38 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
         if (lane == 0) Y[k] = y;
         Hw = max(Hw, y + b);
       } else {
+        // one lane per content column; the pooled values come from k_fp_pool
         const int g = p.gutter, ncol = a - g;
-        const float2 sz = wh[k];
-        const int Uc = (int)floorf(sz.x) + 1, Rc = (int)floorf(sz.y) + 1;
-        const int2* pr = fp_prof + fp_off[order[k]];
+        const uint32_t* src = pool + Xk;
+        uint32_t keep[R];
+#pragma unroll
+        for (int rk = 0; rk < R; ++rk) keep[rk] = nxt[rk];
+        advance(false);
+        prefetch();
         int mx = 0;
-        for (int kk = lane; kk < ncol; kk += kWave) {
-          int Tk, Bk;
-          if (pool_column(pr, Uc, Rc, kk, j, p.J, Tk, Bk)) {
-            const int dend = min(kk + 2 * g, a - 1);
-            int fm = 0;
-            for (int d = kk; d <= dend; ++d) fm = max(fm, F[x + d]);
-            mx = max(mx, fm - Tk);
-          }
-        }
+        auto rise = [&](int kk, uint32_t q) {
+          if (q == kEmpty) return;
+          const int dend = min(kk + 2 * g, a - 1);
+          int fm = 0;
+          for (int d = kk; d <= dend; ++d) fm = max(fm, F[x + d]);
+          mx = max(mx, fm - (int)(q & 0xFFFFu));
+        };
+#pragma unroll
+        for (int rk = 0; rk < R; ++rk) rise(lane + rk * kWave, keep[rk]);
+        for (int kk = lane + R * kWave; kk < ncol; kk += kWave) rise(kk, src[kk]);
         const int y = wave_max<int>(mx);
         int hv = 0;
-        for (int kk = lane; kk < ncol; kk += kWave) {
-          int Tk, Bk;
-          if (pool_column(pr, Uc, Rc, kk, j, p.J, Tk, Bk)) {
-            const int v = Bk >= kRowInf ? y + b : min(y + b, y + 2 * g + Bk + 1);
-            const int dend = min(kk + 2 * g, a - 1);
-            for (int d = kk; d <= dend; ++d) atomicMax(&F[x + d], v);
-            hv = max(hv, v);
-          }
-        }
+        auto raise = [&](int kk, uint32_t q) {
+          if (q == kEmpty) return;
+          const int Bk = (int)(q >> 16);
+          const int v = Bk == 0x7FFF ? y + b : min(y + b, y + 2 * g + Bk + 1);
+          const int dend = min(kk + 2 * g, a - 1);
+          for (int d = kk; d <= dend; ++d) atomicMax(&F[x + d], v);
+          hv = max(hv, v);
+        };
+#pragma unroll
+        for (int rk = 0; rk < R; ++rk) raise(lane + rk * kWave, keep[rk]);
+        for (int kk = lane + R * kWave; kk < ncol; kk += kWave) raise(kk, src[kk]);
         Hw = max(Hw, wave_max<int>(hv));  // lane 0 publishes the wave's height
         if (lane == 0) Y[k] = y;
       }
@@ -216,6 +262,63 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
     tab[2] = L;
     tab[3] = H;
     tab[4] = (int32_t)min(rows, (long long)INT_MAX);
+  }
+}
+
+// Footprint push: pooled profile of every box of every candidate that its
+// fold did not reject, content column k of box i at pool[X_i + k] as
+// T | B << 16 (B = 0x7FFF: the box bottom; 0xFFFFFFFF: empty). One lane per
+// fold position of candidate blockIdx.y + 1: the box is the last one starting
+// at or before it (binary search over the fold), positions in the box's
+// right gutter are skipped.
+__global__ __launch_bounds__(kBlock) void k_fp_pool(
+    const float2* __restrict__ wh, const FrameState* __restrict__ st, FrameParams p,
+    const long long* __restrict__ cand_x, const uint32_t* __restrict__ cand_ab,
+    const int32_t* __restrict__ cand_tab, int64_t stride, const int32_t* __restrict__ order,
+    const int32_t* __restrict__ fp_off, const int2* __restrict__ fp_prof,
+    uint32_t* __restrict__ fp_pool, int64_t pool_stride) {
+  if (st->status != FA_OK) return;
+  const int j = blockIdx.y + 1;
+  if (cand_tab[(j - 1) * kCandStride + 3] < 0) return;
+  const int C = st->num_charts;
+  if (C == 0) return;
+  const int J = p.J;
+  const long long* X = cand_x + (int64_t)(j - 1) * stride;
+  const uint32_t* AB = cand_ab + (int64_t)(j - 1) * stride;
+  uint32_t* pool = fp_pool + (int64_t)(j - 1) * pool_stride;
+  const long long end = X[C - 1] + (long long)(AB[C - 1] & 0xFFFFu);
+  for (long long pos = (long long)blockIdx.x * kBlock + threadIdx.x; pos < end;
+       pos += (long long)gridDim.x * kBlock) {
+    int lo = 0, hi = C - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (X[mid] <= pos) lo = mid;
+      else hi = mid - 1;
+    }
+    const int i = lo;
+    const int kk = (int)(pos - X[i]);
+    if (kk >= (int)(AB[i] & 0xFFFFu) - p.gutter) continue;
+    const float2 sz = wh[i];
+    const int Uc = (int)floorf(sz.x) + 1, Rc = (int)floorf(sz.y) + 1;
+    const int2* pr = fp_prof + fp_off[order[i]];
+    const int u0 = min(Uc - 1, max(0, (kk * J + j - 1) / j - 1));
+    const int u1 = min(Uc - 1, ((kk + 1) * J + j - 1) / j - 1);
+    int tmin = INT_MAX, bmax = -1;
+#pragma unroll 4
+    for (int u = u0; u <= u1; ++u) {
+      const int2 v = pr[u];
+      if (v.y >= 0) {
+        tmin = min(tmin, v.x);
+        bmax = max(bmax, v.y);
+      }
+    }
+    uint32_t q = 0xFFFFFFFFu;
+    if (bmax >= 0) {
+      const int T = tmin * j / J;
+      const int B = bmax == Rc - 1 ? 0x7FFF : min((bmax + 1) * j / J, 0x7FFF);
+      q = (uint32_t)T | ((uint32_t)B << 16);
+    }
+    pool[pos] = q;
   }
 }
 
@@ -354,48 +457,56 @@ __global__ void k_pack_emit(int32_t n, const fa_chart* __restrict__ charts,
 }  // namespace
 
 namespace {
-template <bool FP>
+template <int MODE>
 hipError_t pack_attributes(int max_dyn_bytes) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_pack<256, FP>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_pack<256, MODE>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn_bytes);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_pack<512, FP>,
+  e = hipFuncSetAttribute((const void*)k_pack<512, MODE>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn_bytes);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_pack<1024, FP>,
+  return hipFuncSetAttribute((const void*)k_pack<1024, MODE>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn_bytes);
 }
 
-template <bool FP>
+template <int MODE>
 void pack_launch(const FrameParams& p, const Work& w, int block, size_t dyn, hipStream_t st) {
   const int64_t stride = p.max_charts;
   if (block == 1024)
-    k_pack<1024, FP><<<p.J, 1024, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab,
-                                             w.cand_y, w.cand_rs, w.cand_tab, stride, w.vals_a,
-                                             w.fp_off, w.fp_prof);
+    k_pack<1024, MODE><<<p.J, 1024, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab,
+                                               w.cand_y, w.cand_rs, w.cand_tab, stride,
+                                               w.fp_pool, p.pool_stride);
   else if (block == 512)
-    k_pack<512, FP><<<p.J, 512, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab,
-                                           w.cand_y, w.cand_rs, w.cand_tab, stride, w.vals_a,
-                                           w.fp_off, w.fp_prof);
+    k_pack<512, MODE><<<p.J, 512, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab,
+                                             w.cand_y, w.cand_rs, w.cand_tab, stride, w.fp_pool,
+                                             p.pool_stride);
   else
-    k_pack<256, FP><<<p.J, 256, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab,
-                                           w.cand_y, w.cand_rs, w.cand_tab, stride, w.vals_a,
-                                           w.fp_off, w.fp_prof);
+    k_pack<256, MODE><<<p.J, 256, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab,
+                                             w.cand_y, w.cand_rs, w.cand_tab, stride, w.fp_pool,
+                                             p.pool_stride);
 }
 }  // namespace
 
 hipError_t pack_kernel_attributes(int max_frontline_bytes) {
   const int max_dyn_bytes = max_frontline_bytes + kPackLds * 16 + 4;
-  const hipError_t e = pack_attributes<false>(max_dyn_bytes);
-  if (e != hipSuccess) return e;
-  return pack_attributes<true>(max_dyn_bytes);
+  hipError_t e = pack_attributes<0>(max_dyn_bytes);
+  if (e == hipSuccess) e = pack_attributes<1>(max_dyn_bytes);
+  if (e == hipSuccess) e = pack_attributes<2>(max_dyn_bytes);
+  return e;
 }
 
 hipError_t launch_pack(const FrameParams& p, const Work& w, int block, bool footprint,
                        hipStream_t st) {
   const size_t dyn = (size_t)2 * p.omega * sizeof(int32_t) + (size_t)kPackLds * 16 + 4;
-  if (footprint) pack_launch<true>(p, w, block, dyn, st);
-  else pack_launch<false>(p, w, block, dyn, st);
+  if (!footprint) {
+    pack_launch<0>(p, w, block, dyn, st);
+    return hipGetLastError();
+  }
+  pack_launch<1>(p, w, block, dyn, st);
+  k_fp_pool<<<dim3(32, p.J), kBlock, 0, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab,
+                                              w.cand_tab, p.max_charts, w.vals_a, w.fp_off,
+                                              w.fp_prof, w.fp_pool, p.pool_stride);
+  pack_launch<2>(p, w, block, dyn, st);
   return hipGetLastError();
 }
 

@@ -625,7 +625,9 @@ __global__ void k_fp_clear(int2* __restrict__ prof, const FrameState* __restrict
     prof[i] = make_int2(INT_MAX, -1);
 }
 
-// floor((py + (x0 - px) (qy - py) / (qx - px)) / 256), px != qx
+// floor((py + (x0 - px) (qy - py) / (qx - px)) / 256), px != qx. Below 2^52
+// the numerator and divisor are exact doubles: the rounded quotient is within
+// one of the floor, and the exact integer remainder settles it.
 __device__ __forceinline__ int32_t crossing_row(int64_t px, int64_t py, int64_t qx, int64_t qy,
                                                 int64_t x0) {
   int64_t num = py * (qx - px) + (x0 - px) * (qy - py);
@@ -634,69 +636,126 @@ __device__ __forceinline__ int32_t crossing_row(int64_t px, int64_t py, int64_t 
     num = -num;
     den = -den;
   }
-  return (int32_t)floor_div64(num, 256 * den);
+  const int64_t d = 256 * den;
+  const int64_t lim = int64_t(1) << 52;
+  if (num > -lim && num < lim) {
+    int64_t q = (int64_t)floor((double)num / (double)d);
+    const int64_t r = num - q * d;
+    if (r < 0) --q;
+    else if (r >= d) ++q;
+    return (int32_t)q;
+  }
+  return (int32_t)floor_div64(num, d);
 }
+
+// One wave takes 64 visible triangles at a time: every lane sets up its
+// triangle's snapped polygon and column range, then the wave walks the
+// (triangle, column) pairs 64 at a time (owner found by a binary search over
+// the inclusive column counts), so one triangle's columns spread over lanes.
+// Neighbouring triangles share columns: when the wave's columns span fewer
+// than kFpWin profile entries they are reduced in a per-wave LDS window and
+// flushed with one pair of global atomics per touched entry.
+constexpr int kFpWin = 1024;
 
 __global__ __launch_bounds__(kBlock) void k_fp_raster(
     const int32_t* __restrict__ vlist, const int32_t* __restrict__ idx,
     const float4* __restrict__ clip, const int32_t* __restrict__ cot,
     const fa_chart* __restrict__ charts, const int32_t* __restrict__ fp_off,
     int2* __restrict__ prof, FrameParams p, const FrameState* __restrict__ stp) {
+  __shared__ int2 win_all[kBlock / kWave][kFpWin];
   if (stp->status != FA_OK) return;
   const int nv = stp->visible;
   const float halfW = 0.5f * (float)p.W, halfH = 0.5f * (float)p.H;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
-    const int t = vlist[i];
-    const int c = cot[t];
-    if (c < 0) continue;
-    const float4 a = clip[idx[3 * (int64_t)t]], b = clip[idx[3 * (int64_t)t + 1]],
-                 cc = clip[idx[3 * (int64_t)t + 2]];
-    if (outside<0>(a, b, cc) || outside<1>(a, b, cc) || outside<2>(a, b, cc) ||
-        outside<3>(a, b, cc) || outside<4>(a, b, cc) || outside<5>(a, b, cc))
-      continue;
-    float4 poly[4];
-    int n;
-    if (pd<4>(a) < 0.0f || pd<4>(b) < 0.0f || pd<4>(cc) < 0.0f) {
-      n = near_clip(a, b, cc, poly);
-    } else {
-      poly[0] = a; poly[1] = b; poly[2] = cc; poly[3] = cc; n = 3;
-    }
-    bool ok = n > 0;
-    for (int k = 0; k < n; ++k) ok = ok && poly[k].w > 0.0f;
-    if (!ok) continue;
-    const fa_chart& ch = charts[c];
-    const float x0 = ch.ndc_box[0], y1 = ch.ndc_box[3], tw = ch.target_w;
-    const int rot = ch.rotated;
-    int32_t X[4], Y[4];
-    int32_t xmin = INT_MAX, xmax = INT_MIN;
+  const int lane = lane_id();
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  const int nwaves = (int)(gridDim.x * blockDim.x / kWave);
+  int2* win = win_all[threadIdx.x / kWave];
+  for (int e = lane; e < kFpWin; e += kWave) win[e] = make_int2(INT_MAX, -1);
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  for (int base = wave * kWave; base < nv; base += nwaves * kWave) {
+    const int i = base + lane;
+    int32_t X[4] = {0, 0, 0, 0}, Y[4] = {0, 0, 0, 0};
+    int n = 0, Uc = 1, Rc = 1, off = 0, u0 = 0, cnt = 0;
+    if (i < nv) {
+      const int t = vlist[i];
+      const int c = cot[t];
+      const float4 a = clip[idx[3 * (int64_t)t]], b = clip[idx[3 * (int64_t)t + 1]],
+                   cc = clip[idx[3 * (int64_t)t + 2]];
+      const bool out = c < 0 || outside<0>(a, b, cc) || outside<1>(a, b, cc) ||
+                       outside<2>(a, b, cc) || outside<3>(a, b, cc) || outside<4>(a, b, cc) ||
+                       outside<5>(a, b, cc);
+      float4 poly[4];
+      if (!out) {
+        if (pd<4>(a) < 0.0f || pd<4>(b) < 0.0f || pd<4>(cc) < 0.0f) {
+          n = near_clip(a, b, cc, poly);
+        } else {
+          poly[0] = a; poly[1] = b; poly[2] = cc; poly[3] = cc; n = 3;
+        }
+        bool ok = n > 0;
+        for (int k = 0; k < n; ++k) ok = ok && poly[k].w > 0.0f;
+        if (!ok) n = 0;
+      }
+      if (n > 0) {
+        const fa_chart& ch = charts[c];
+        const float x0 = ch.ndc_box[0], y1 = ch.ndc_box[3], tw = ch.target_w;
+        const int rot = ch.rotated;
+        int32_t xmin = INT_MAX, xmax = INT_MIN;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (k < n) {
-        const float nx = poly[k].x / poly[k].w, ny = poly[k].y / poly[k].w;
-        const float px = ((nx - x0) * halfW) * p.rate;
-        const float py = ((y1 - ny) * halfH) * p.rate;
-        X[k] = snap(rot ? py : px);
-        Y[k] = snap(rot ? (tw - px) : py);
-        xmin = min(xmin, X[k]);
-        xmax = max(xmax, X[k]);
+        for (int k = 0; k < 4; ++k) {
+          if (k < n) {
+            const float nx = poly[k].x / poly[k].w, ny = poly[k].y / poly[k].w;
+            const float px = ((nx - x0) * halfW) * p.rate;
+            const float py = ((y1 - ny) * halfH) * p.rate;
+            X[k] = snap(rot ? py : px);
+            Y[k] = snap(rot ? (tw - px) : py);
+            xmin = min(xmin, X[k]);
+            xmax = max(xmax, X[k]);
+          }
+        }
+        Uc = (int)floorf(ch.oriented_w) + 1;
+        Rc = (int)floorf(ch.oriented_h) + 1;
+        off = fp_off[c];
+        u0 = min(Uc - 1, max(0, xmin >> 8));
+        cnt = min(Uc - 1, max(0, xmax >> 8)) - u0 + 1;
       }
     }
-    const int Uc = (int)floorf(ch.oriented_w) + 1, Rc = (int)floorf(ch.oriented_h) + 1;
-    int2* pr = prof + fp_off[c];
-    const int u0 = min(Uc - 1, max(0, xmin >> 8)), u1 = min(Uc - 1, max(0, xmax >> 8));
-    for (int u = u0; u <= u1; ++u) {
-      const bool open_l = u == 0, open_r = u == Uc - 1;
+    const int incl = wave_incl_scan<int>(cnt);
+    const int total = __shfl(incl, kWave - 1, kWave);
+    // profile entries this wave touches: [elo, ehi]
+    const int elo = wave_min<int>(cnt > 0 ? off + u0 : INT_MAX);
+    const int ehi = wave_max<int>(cnt > 0 ? off + u0 + cnt - 1 : INT_MIN);
+    const bool use_win = total > 0 && ehi - elo < kFpWin;
+    for (int w0 = 0; w0 < total; w0 += kWave) {
+      const int item = w0 + lane;
+      int o = 0;  // owner: the first lane whose inclusive count exceeds item
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1)
+        if (__shfl(incl, o + step - 1, kWave) <= item) o += step;
+      o = min(o, kWave - 1);
+      const int on = __shfl(n, o, kWave);
+      int32_t PX[4], PY[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        PX[k] = __shfl(X[k], o, kWave);
+        PY[k] = __shfl(Y[k], o, kWave);
+      }
+      const int oUc = __shfl(Uc, o, kWave), oRc = __shfl(Rc, o, kWave);
+      const int ooff = __shfl(off, o, kWave);
+      const int u = __shfl(u0, o, kWave) + item - (__shfl(incl, o, kWave) - __shfl(cnt, o, kWave));
+      if (item >= total) continue;
+      const bool open_l = u == 0, open_r = u == oUc - 1;
       const int64_t sl = 256 * (int64_t)u, sr = sl + 256;
       int32_t rlo = INT_MAX, rhi = INT_MIN;
-      for (int k = 0; k < n; ++k) {
-        if ((open_l || X[k] >= sl) && (open_r || X[k] <= sr)) {
-          rlo = min(rlo, Y[k] >> 8);
-          rhi = max(rhi, Y[k] >> 8);
+      for (int k = 0; k < on; ++k) {
+        if ((open_l || PX[k] >= sl) && (open_r || PX[k] <= sr)) {
+          rlo = min(rlo, PY[k] >> 8);
+          rhi = max(rhi, PY[k] >> 8);
         }
       }
-      for (int k = 0; k < n; ++k) {
-        const int k1 = k + 1 == n ? 0 : k + 1;
-        const int64_t Px = X[k], Py = Y[k], Qx = X[k1], Qy = Y[k1];
+      for (int k = 0; k < on; ++k) {
+        const int k1 = k + 1 == on ? 0 : k + 1;
+        const int64_t Px = PX[k], Py = PY[k], Qx = PX[k1], Qy = PY[k1];
         if (Px == Qx) continue;
         const int64_t lo = min(Px, Qx), hi = max(Px, Qx);
         if (!open_l && lo < sl && sl < hi) {
@@ -711,10 +770,29 @@ __global__ __launch_bounds__(kBlock) void k_fp_raster(
         }
       }
       if (rlo > rhi) continue;
-      rlo = min(Rc - 1, max(0, rlo));
-      rhi = min(Rc - 1, max(0, rhi));
-      atomicMin(&pr[u].x, rlo);
-      atomicMax(&pr[u].y, rhi);
+      rlo = min(oRc - 1, max(0, rlo));
+      rhi = min(oRc - 1, max(0, rhi));
+      if (use_win) {
+        atomicMin(&win[ooff + u - elo].x, rlo);
+        atomicMax(&win[ooff + u - elo].y, rhi);
+      } else {
+        atomicMin(&prof[ooff + u].x, rlo);
+        atomicMax(&prof[ooff + u].y, rhi);
+      }
+    }
+    if (use_win) {
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      for (int e = lane; e <= ehi - elo; e += kWave) {
+        const int2 v = win[e];
+        if (v.y >= 0) {
+          atomicMin(&prof[elo + e].x, v.x);
+          atomicMax(&prof[elo + e].y, v.y);
+          win[e] = make_int2(INT_MAX, -1);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
   }
 }
