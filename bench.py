@@ -394,17 +394,23 @@ def main():
         for knob_ in TUNED:
             fctx.set_tuning(knob_, ctx.get_tuning(knob_))
         footprint = {}
-        for r_ in (1.0, 2.0):
-            ffr = [scenes.city_frame(k, rate=r_, atlas_size=args.atlas) for k in range(0, 32, 8)]
+        o0 = scenes.orbit_frame(0)
+        omesh = fa.Mesh(o0.positions, o0.indices, o0.scene_key)
+        cases = [(f"city2m_3840x2160_atlas{args.atlas}_rate{r_:g}", mesh, args.atlas, r_,
+                  [scenes.city_frame(k, rate=r_, atlas_size=args.atlas) for k in range(0, 32, 8)])
+                 for r_ in (1.0, 2.0)]
+        cases.append(("orbit86k_1920x1080_atlas512_rate1", omesh, 512, 1.0,
+                      [scenes.orbit_frame(k, atlas_size=512) for k in range(0, 120, 15)]))
+        for case_name, mesh_, atlas_, r_, ffr in cases:
             fvis = [torch.as_tensor(f.visible).to(dev) for f in ffr]
             res_f = {}
             for name_, c_ in (("box", ctx), ("footprint", fctx)):
-                o_ = c_.outputs(mesh, args.atlas)
+                o_ = c_.outputs(mesh_, atlas_)
 
                 def fstep(k):
                     f = ffr[k % len(ffr)]
-                    c_.build_atlas(mesh, fvis[k % len(ffr)], f.view_proj, f.width, f.height,
-                                   args.atlas, r_, out=o_, stream=stream)
+                    c_.build_atlas(mesh_, fvis[k % len(ffr)], f.view_proj, f.width, f.height,
+                                   atlas_, r_, out=o_, stream=stream)
                 metas = []
                 for k in range(len(ffr)):
                     fstep(k)
@@ -424,7 +430,7 @@ def main():
                     chosen_j=[m_["chosen_j"] for m_ in metas],
                     s_eff_mean=float(np.mean([m_["s_eff"] for m_ in metas])),
                     fill_fraction_mean=float(np.mean([m_["occupied_texels"] for m_ in metas]))
-                    / float(args.atlas) ** 2,
+                    / float(atlas_) ** 2,
                     layout_height_over_width=float(np.mean(
                         [m_["layout_height"] / m_["layout_width"] for m_ in metas])))
                 if name_ == "footprint":
@@ -439,7 +445,7 @@ def main():
                     res_f[name_]["stages_ms"] = {
                         sn: float(np.mean(acc_[sn])) for sn in ("fp_clear", "fp_raster", "pack")}
                 del o_
-            footprint[f"rate{r_:g}"] = dict(frames=len(ffr), **res_f)
+            footprint[case_name] = dict(frames=len(ffr), **res_f)
         fctx.close()
         log("footprint:", json.dumps(footprint))
 
