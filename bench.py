@@ -212,7 +212,7 @@ def main():
     import torch
     import paper_2502_17712_amd as fa
     TUNED = (fa.FA_TUNE_OCC_SMALL_TEXELS, fa.FA_TUNE_OCC_LANE_TEXELS, fa.FA_TUNE_UF_LINK_INIT,
-             fa.FA_TUNE_UF_EDGE_HOOKS, fa.FA_TUNE_PACK_BLOCK)
+             fa.FA_TUNE_UF_EDGE_HOOKS, fa.FA_TUNE_PACK_BLOCK, fa.FA_TUNE_UF_TILE)
     from synth import scenes
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -247,7 +247,12 @@ def main():
     tuning = None
     if args.autotune:
         from paper_2502_17712_amd import autotune
-        tuning = autotune.tune(ctx, lambda: step(0), out)
+        cyc = [0]
+
+        def tune_step():  # every trial sees the same spread of frames
+            step(cyc[0])
+            cyc[0] += 1
+        tuning = autotune.tune(ctx, tune_step, out, reps=len(frames), ref_run=lambda: step(0))
         log("autotune:", json.dumps(tuning))
     for k in range(args.warmup):
         step(k)

@@ -279,16 +279,21 @@ int fa_pack_boxes(fa_ctx* ctx, const float* sizes, int32_t n, int32_t atlas_size
  *                             vertices (Alg. 1); 2 (default): shared edges
  *                             inside tiles of 2048 visible triangles joined in
  *                             LDS first, then the edges between tiles, then
- *                             vertices; 0: vertices only
+ *                             vertices; 3: the tiles in LDS, then vertices
+ *                             (edges between tiles are shared vertices);
+ *                             0: vertices only
  *                             (every shared edge is a shared vertex: the
- *                             charts are the same for all three)
+ *                             charts are the same for all four)
+ *   FA_TUNE_UF_TILE           visible-list entries per LDS union-find tile
+ *                             (modes 2 and 3): 2048 (default), 4096, 8192
  *   FA_TUNE_BATCH_GRAPH       1: fa_build_atlas_batch captures its views into
  *                             a hipGraph once per distinct set of view
  *                             descriptors and replays it (one launch); 0: off
  * fa_set_tuning returns FA_ERR_INVALID_ARG for unknown knobs or values;
  * fa_get_tuning returns the current value or -1. */
 enum { FA_TUNE_PACK_BLOCK = 1, FA_TUNE_OCC_SMALL_TEXELS = 2, FA_TUNE_UF_LINK_INIT = 3,
-       FA_TUNE_BATCH_GRAPH = 4, FA_TUNE_UF_EDGE_HOOKS = 5, FA_TUNE_OCC_LANE_TEXELS = 6 };
+       FA_TUNE_BATCH_GRAPH = 4, FA_TUNE_UF_EDGE_HOOKS = 5, FA_TUNE_OCC_LANE_TEXELS = 6,
+       FA_TUNE_UF_TILE = 7 };
 int fa_set_tuning(fa_ctx* ctx, int knob, int value);
 int fa_get_tuning(fa_ctx* ctx, int knob);
 

@@ -27,7 +27,7 @@ FA_ERR_NOFIT, FA_ERR_DEVICE, FA_ERR_UNSUPPORTED = 4, 5, 6
 FA_FLAG_NO_SIDE_CLIP = 1
 FA_FLAG_FOOTPRINT_PUSH = 4
 FA_TUNE_PACK_BLOCK, FA_TUNE_OCC_SMALL_TEXELS, FA_TUNE_UF_LINK_INIT, FA_TUNE_BATCH_GRAPH = 1, 2, 3, 4
-FA_TUNE_UF_EDGE_HOOKS, FA_TUNE_OCC_LANE_TEXELS = 5, 6
+FA_TUNE_UF_EDGE_HOOKS, FA_TUNE_OCC_LANE_TEXELS, FA_TUNE_UF_TILE = 5, 6, 7
 
 
 class fa_config(ctypes.Structure):

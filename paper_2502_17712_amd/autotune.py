@@ -1,8 +1,9 @@
 """Autotuner for the library's performance knobs (fa_set_tuning).
 
 Greedy coordinate descent over the knobs on a representative workload: for
-each knob in turn, every allowed value is timed with HIP events (median of
-`reps` runs) and the fastest is kept. Every knob value must give identical
+each knob in turn, every allowed value is timed with HIP events (mean of
+`reps` runs, so that a setting with a slow tail is not preferred) and the
+fastest is kept. Every knob value must give identical
 results; the tuner checks that by comparing all outputs of each trial with
 the reference run, and refuses (raises) on any difference.
 """
@@ -13,18 +14,20 @@ import json
 import torch
 
 from . import (FA_TUNE_OCC_LANE_TEXELS, FA_TUNE_OCC_SMALL_TEXELS, FA_TUNE_PACK_BLOCK,
-               FA_TUNE_UF_EDGE_HOOKS, FA_TUNE_UF_LINK_INIT, AtlasOutputs, Context)
+               FA_TUNE_UF_EDGE_HOOKS, FA_TUNE_UF_LINK_INIT, FA_TUNE_UF_TILE, AtlasOutputs,
+               Context)
 
 KNOBS = {
     FA_TUNE_OCC_SMALL_TEXELS: [64, 16, 32, 128, 256],
     FA_TUNE_OCC_LANE_TEXELS: [64, 0, 16, 256],
     FA_TUNE_UF_LINK_INIT: [1, 0],
-    FA_TUNE_UF_EDGE_HOOKS: [2, 1, 0],
+    FA_TUNE_UF_EDGE_HOOKS: [2, 3, 1, 0],
+    FA_TUNE_UF_TILE: [2048, 4096, 8192],
     FA_TUNE_PACK_BLOCK: [256, 512, 1024],
 }
 NAMES = {FA_TUNE_PACK_BLOCK: "pack_block", FA_TUNE_OCC_SMALL_TEXELS: "occ_small_texels",
          FA_TUNE_UF_LINK_INIT: "uf_link_init", FA_TUNE_UF_EDGE_HOOKS: "uf_edge_hooks",
-         FA_TUNE_OCC_LANE_TEXELS: "occ_lane_texels"}
+         FA_TUNE_OCC_LANE_TEXELS: "occ_lane_texels", FA_TUNE_UF_TILE: "uf_tile"}
 
 
 def _snapshot(out: AtlasOutputs):
@@ -50,16 +53,19 @@ def _time(run, reps, stream):
         run()
         b.record(stream)
     torch.cuda.synchronize()
-    ts = sorted(a.elapsed_time(b) for a, b in evs)
-    return ts[len(ts) // 2]
+    return sum(a.elapsed_time(b) for a, b in evs) / len(evs)
 
 
-def tune(ctx: Context, run, out: AtlasOutputs, reps: int = 15, knobs=None, stream=None):
-    """run(): enqueue one representative call writing into `out`.
+def tune(ctx: Context, run, out: AtlasOutputs, reps: int = 30, knobs=None, stream=None,
+         ref_run=None):
+    """run(): enqueue one representative call writing into `out` (it may cycle
+    through several inputs); ref_run() (default: run) enqueues the one call
+    whose outputs every knob value must reproduce.
     Returns {"choice": {name: value}, "trials": {name: {value: ms}}}."""
     knobs = knobs or KNOBS
     stream = stream or torch.cuda.current_stream()
-    run()
+    ref_run = ref_run or run
+    ref_run()
     torch.cuda.synchronize()
     ref = _snapshot(out)
     report = {"choice": {}, "trials": {}}
@@ -68,6 +74,8 @@ def tune(ctx: Context, run, out: AtlasOutputs, reps: int = 15, knobs=None, strea
         for v in values:
             ctx.set_tuning(knob, v)
             ms = _time(run, reps, stream)
+            ref_run()
+            torch.cuda.synchronize()
             if not _same(_snapshot(out), ref):
                 raise RuntimeError(f"knob {NAMES[knob]}={v} changed the results")
             trials[v] = ms

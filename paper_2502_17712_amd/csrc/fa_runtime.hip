@@ -68,6 +68,7 @@ struct fa_ctx {
   int lane_texels = 64;
   int uf_link_init = 1;
   int uf_edge_hooks = 2;
+  int uf_tile = 2048;
   int32_t* check_flag = nullptr;  // device int for index validation
   // visibility pass scratch: occluder list [max_triangles] + its counter, and
   // a depth buffer that grows to the largest grid asked for
@@ -420,6 +421,7 @@ static int frame_params(const fa_ctx* ctx, const fa_camera* cam, int32_t atlas, 
   p->flags = ctx->cfg.flags;
   p->max_charts = ctx->cfg.max_charts;
   p->edge_hooks = ctx->uf_edge_hooks;
+  p->uf_tile = ctx->uf_tile;
   p->fp_cap = (int32_t)ctx->cfg.max_profile_columns;
   p->pool_stride = (int64_t)pool_stride(ctx->cfg);
   return FA_OK;
@@ -438,7 +440,7 @@ static int run_frame(fa_ctx* ctx, const Work& w, const fa_mesh* mesh, Scene* sc,
   if (ctx->timing) { mk.ev = ctx->ev; mk.cap = kStages + 1; }
   mk(st);
   ok(launch_prologue(mesh->positions, V, visible, sc->nbr, T, p, w, cov, out->chart_of_tri,
-                     p.edge_hooks == 2 ? 0 : (ctx->uf_link_init ? 2 : 1), mk, st));
+                     p.edge_hooks >= 2 ? 0 : (ctx->uf_link_init ? 2 : 1), mk, st));
   ok(launch_charts(visible, mesh->indices, sc->nbr, T, p, w, out->chart_of_tri, cov, out->charts,
                    mk, st));
   ok(launch_order(p, w, out->charts, 1, st));
@@ -562,7 +564,7 @@ int fa_build_atlas_batch(fa_ctx* ctx, const fa_mesh* mesh, int32_t n, const fa_v
   }
   std::string sig(reinterpret_cast<const char*>(mesh), sizeof(fa_mesh));
   sig.append(reinterpret_cast<const char*>(views), sizeof(fa_view) * (size_t)n);
-  sig.append(reinterpret_cast<const char*>(&ctx->pack_block), sizeof(int) * 3);
+  sig.append(reinterpret_cast<const char*>(&ctx->pack_block), sizeof(int) * 6);  // every knob
   if (!ctx->graph_exec || sig != ctx->graph_sig) {
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
@@ -641,8 +643,12 @@ int fa_set_tuning(fa_ctx* ctx, int knob, int value) {
       ctx->batch_graph = value;
       return FA_OK;
     case FA_TUNE_UF_EDGE_HOOKS:
-      if (value < 0 || value > 2) return FA_ERR_INVALID_ARG;
+      if (value < 0 || value > 3) return FA_ERR_INVALID_ARG;
       ctx->uf_edge_hooks = value;
+      return FA_OK;
+    case FA_TUNE_UF_TILE:
+      if (value != 2048 && value != 4096 && value != 8192) return FA_ERR_INVALID_ARG;
+      ctx->uf_tile = value;
       return FA_OK;
     case FA_TUNE_OCC_LANE_TEXELS:
       if (value < 0 || value > 4096) return FA_ERR_INVALID_ARG;
@@ -661,6 +667,7 @@ int fa_get_tuning(fa_ctx* ctx, int knob) {
     case FA_TUNE_UF_LINK_INIT: return ctx->uf_link_init;
     case FA_TUNE_BATCH_GRAPH: return ctx->batch_graph;
     case FA_TUNE_UF_EDGE_HOOKS: return ctx->uf_edge_hooks;
+    case FA_TUNE_UF_TILE: return ctx->uf_tile;
     case FA_TUNE_OCC_LANE_TEXELS: return ctx->lane_texels;
     default: return -1;
   }

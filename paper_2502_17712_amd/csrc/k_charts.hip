@@ -228,15 +228,13 @@ __global__ void k_uf_cross(const uint8_t* __restrict__ vis, const int32_t* __res
   }
 }
 
-// Edge hooks inside one tile of kUfTile consecutive entries of the visible
+// Edge hooks inside one tile of TILE consecutive entries of the visible
 // list, in LDS: entries are local indices (ascending with the triangle index),
 // a shared edge whose other triangle lies in the tile joins the two local sets
 // (larger local root hooked below the smaller by compare-and-swap). Then every
 // entry's parent becomes the smallest triangle of its local set, which is a
 // valid union-find start for the vertex passes; edges leaving the tile are
 // shared vertices too, so those passes complete the charts.
-constexpr int kUfTile = 2048;
-constexpr int kUfThreads = 512;
 
 __device__ __forceinline__ int lds_get(int* a, int i) {
   return __hip_atomic_load(&a[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -264,17 +262,18 @@ __device__ __forceinline__ void lds_join(int* lp, int a, int b) {
   }
 }
 
-__global__ __launch_bounds__(kUfThreads) void k_uf_local(const uint8_t* __restrict__ vis,
-                                                         const int32_t* __restrict__ nbr,
-                                                         const int32_t* __restrict__ vlist,
-                                                         int32_t* __restrict__ parent,
-                                                         const FrameState* __restrict__ st) {
-  __shared__ int lv[kUfTile];
-  __shared__ int lp[kUfTile];
+template <int TILE, int NT>
+__global__ __launch_bounds__(NT) void k_uf_local(const uint8_t* __restrict__ vis,
+                                                 const int32_t* __restrict__ nbr,
+                                                 const int32_t* __restrict__ vlist,
+                                                 int32_t* __restrict__ parent,
+                                                 const FrameState* __restrict__ st) {
+  __shared__ int lv[TILE];
+  __shared__ int lp[TILE];
   const int nv = st->visible;
-  const int64_t s0 = (int64_t)blockIdx.x * kUfTile;
+  const int64_t s0 = (int64_t)blockIdx.x * TILE;
   if (s0 >= nv) return;
-  const int cnt = (int)min<int64_t>(kUfTile, nv - s0);
+  const int cnt = (int)min<int64_t>(TILE, nv - s0);
   for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
     lv[i] = vlist[s0 + i];
     lp[i] = i;
@@ -424,12 +423,19 @@ struct Quad {
   int n;
 };
 
+// Append a vertex. Value selects on every slot (not a branch per slot, which
+// the optimizer turns into a runtime-indexed store that moves the polygon to
+// scratch memory).
+__device__ __forceinline__ float4 pick(bool c, const float4& a, const float4& b) {
+  return make_float4(c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z, c ? a.w : b.w);
+}
 __device__ __forceinline__ void quad_put(Quad& q, const float4& p) {
-  if (q.n == 0) q.v0 = p;
-  else if (q.n == 1) q.v1 = p;
-  else if (q.n == 2) q.v2 = p;
-  else q.v3 = p;
-  q.n++;
+  const int n = q.n;
+  q.v0 = pick(n == 0, p, q.v0);
+  q.v1 = pick(n == 1, p, q.v1);
+  q.v2 = pick(n == 2, p, q.v2);
+  q.v3 = pick(n >= 3, p, q.v3);
+  q.n = n + 1;
 }
 
 // One edge S->E of a Sutherland-Hodgman pass against plane P.
@@ -579,18 +585,30 @@ __global__ __launch_bounds__(kBlock) void k_gather_boxes(
   for (int k = 0; k < kGatherItems; ++k)
 #pragma unroll
     for (int e = 0; e < 3; ++e) q[k][e] = clip[vi[k][e]];
-#pragma unroll
+  // items are taken from slot 0 and shifted down after each one: constant
+  // indices keep the arrays in registers (the clipping body is too large to
+  // unroll, and a runtime index would move them to scratch memory)
   for (int k = 0; k < kGatherItems; ++k) {
-    const bool valid = tv[k] >= 0;
-    const int c = cv[k];
+    const bool valid = tv[0] >= 0;
+    const int c = cv[0];
     bool has = false;
     float4 box = make_float4(0.f, 0.f, 0.f, 0.f);
     if (valid) {
-      cot[tv[k]] = c;
-      cov[vi[k][0]] = c;
-      cov[vi[k][1]] = c;
-      cov[vi[k][2]] = c;
-      has = triangle_ndc_box(q[k][0], q[k][1], q[k][2], !(flags & FA_FLAG_NO_SIDE_CLIP), box);
+      cot[tv[0]] = c;
+      cov[vi[0][0]] = c;
+      cov[vi[0][1]] = c;
+      cov[vi[0][2]] = c;
+      has = triangle_ndc_box(q[0][0], q[0][1], q[0][2], !(flags & FA_FLAG_NO_SIDE_CLIP), box);
+    }
+#pragma unroll
+    for (int m = 0; m + 1 < kGatherItems; ++m) {
+      tv[m] = tv[m + 1];
+      cv[m] = cv[m + 1];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        vi[m][e] = vi[m + 1][e];
+        q[m][e] = q[m + 1][e];
+      }
     }
     const uint32_t e0 = ord_of(box.x), e1 = ord_of(box.y), e2 = ord_of(box.z), e3 = ord_of(box.w);
     unsigned long long todo = __ballot(has);
@@ -669,10 +687,19 @@ hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* 
   if (T > 0) {
     if (p.edge_hooks == 1) {
       k_uf_hook<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, 0, w.state);
-    } else if (p.edge_hooks == 2) {
-      k_uf_local<<<std::max(1u, grid_for(T, kUfTile)), kUfThreads, 0, st>>>(vis, nbr, w.vlist,
-                                                                            w.parent, w.state);
-      k_uf_cross<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, kUfTile, w.state);
+    } else if (p.edge_hooks >= 2) {
+      const int tile = p.uf_tile;
+      if (tile == 8192)
+        k_uf_local<8192, 1024><<<std::max(1u, grid_for(T, 8192)), 1024, 0, st>>>(
+            vis, nbr, w.vlist, w.parent, w.state);
+      else if (tile == 4096)
+        k_uf_local<4096, 1024><<<std::max(1u, grid_for(T, 4096)), 1024, 0, st>>>(
+            vis, nbr, w.vlist, w.parent, w.state);
+      else
+        k_uf_local<2048, 512><<<std::max(1u, grid_for(T, 2048)), 512, 0, st>>>(
+            vis, nbr, w.vlist, w.parent, w.state);
+      if (p.edge_hooks == 2)
+        k_uf_cross<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, tile, w.state);
     }
     mk(st);
     k_uf_vertex_min<<<g, kBlock, 0, st>>>(idx, w.vlist, w.parent, w.vmin, w.state);

@@ -88,10 +88,24 @@ __device__ __forceinline__ bool outside(const float4& a, const float4& b, const 
   return pd<P>(a) < 0.0f && pd<P>(b) < 0.0f && pd<P>(c) < 0.0f;
 }
 
-// near-plane Sutherland-Hodgman of one triangle into up to 4 vertices
+__device__ __forceinline__ float4 pick4(bool c, const float4& a, const float4& b) {
+  return make_float4(c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z, c ? a.w : b.w);
+}
+
+// near-plane Sutherland-Hodgman of one triangle into up to 4 vertices; each
+// output slot is written with value selects (a runtime index into `o` would
+// move the polygon to scratch memory)
 __device__ __forceinline__ int near_clip(const float4& a, const float4& b, const float4& c,
                                          float4* o) {
   int n = 0;
+  float4 o0 = a, o1 = a, o2 = a, o3 = a;
+  auto put = [&](const float4& v) {
+    o0 = pick4(n == 0, v, o0);
+    o1 = pick4(n == 1, v, o1);
+    o2 = pick4(n == 2, v, o2);
+    o3 = pick4(n >= 3, v, o3);
+    ++n;
+  };
   const float4 in[3] = {a, b, c};
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -107,10 +121,14 @@ __device__ __forceinline__ int near_clip(const float4& a, const float4& b, const
       I.y = A.y + t * (B.y - A.y);
       I.z = A.z + t * (B.z - A.z);
       I.w = A.w + t * (B.w - A.w);
-      o[n++] = I;
+      put(I);
     }
-    if (iE) o[n++] = E;
+    if (iE) put(E);
   }
+  o[0] = o0;
+  o[1] = o1;
+  o[2] = o2;
+  o[3] = o3;
   return n;
 }
 
@@ -170,7 +188,10 @@ __device__ __forceinline__ bool fan_footprint(const SnapPoly& sp, int f, const i
                                               Footprint& fp) {
   if (f + 2 >= sp.n) return false;
   const int32_t ax = sp.u[0], ay = sp.v[0];
-  const int32_t ub = sp.u[f + 1], vb = sp.v[f + 1], uc = sp.u[f + 2], vc = sp.v[f + 2];
+  // constant indices only (a runtime index would put the polygon in scratch)
+  const bool f1 = f != 0;
+  const int32_t ub = f1 ? sp.u[2] : sp.u[1], vb = f1 ? sp.v[2] : sp.v[1];
+  const int32_t uc = f1 ? sp.u[3] : sp.u[2], vc = f1 ? sp.v[3] : sp.v[2];
   fp.ax = ax; fp.ay = ay;
   fp.bx = ub - ax; fp.by = vb - ay;
   fp.cx = uc - ax; fp.cy = vc - ay;
@@ -693,7 +714,8 @@ __global__ __launch_bounds__(kBlock) void k_fp_raster(
           poly[0] = a; poly[1] = b; poly[2] = cc; poly[3] = cc; n = 3;
         }
         bool ok = n > 0;
-        for (int k = 0; k < n; ++k) ok = ok && poly[k].w > 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ok = ok && (k >= n || poly[k].w > 0.0f);
         if (!ok) n = 0;
       }
       if (n > 0) {
@@ -747,15 +769,21 @@ __global__ __launch_bounds__(kBlock) void k_fp_raster(
       const bool open_l = u == 0, open_r = u == oUc - 1;
       const int64_t sl = 256 * (int64_t)u, sr = sl + 256;
       int32_t rlo = INT_MAX, rhi = INT_MIN;
-      for (int k = 0; k < on; ++k) {
-        if ((open_l || PX[k] >= sl) && (open_r || PX[k] <= sr)) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (k < on && (open_l || PX[k] >= sl) && (open_r || PX[k] <= sr)) {
           rlo = min(rlo, PY[k] >> 8);
           rhi = max(rhi, PY[k] >> 8);
         }
       }
-      for (int k = 0; k < on; ++k) {
-        const int k1 = k + 1 == on ? 0 : k + 1;
-        const int64_t Px = PX[k], Py = PY[k], Qx = PX[k1], Qy = PY[k1];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (k >= on) continue;
+        // next vertex with constant indices: k + 1, or vertex 0 after the last
+        const bool wrap = k + 1 >= on;
+        const int64_t Px = PX[k], Py = PY[k];
+        const int64_t Qx = wrap ? PX[0] : PX[k < 3 ? k + 1 : 0];
+        const int64_t Qy = wrap ? PY[0] : PY[k < 3 ? k + 1 : 0];
         if (Px == Qx) continue;
         const int64_t lo = min(Px, Qx), hi = max(Px, Qx);
         if (!open_l && lo < sl && sl < hi) {
