@@ -22,6 +22,7 @@ constexpr int kCandStride = 8;       // int32 per candidate in the table
 constexpr int kMaxAtlas = 8192;
 constexpr int kCountGrid = 1024;     // blocks of the occupancy count
 constexpr int kOccBigGrid = 2048;    // blocks of the large-footprint raster
+constexpr int64_t kBigCap = 1 << 20; // queue capacity (more: rasterized where found)
 
 
 // Device-resident results of one frame that later stages read (kept on the
@@ -91,7 +92,8 @@ struct Work {
   int32_t* cand_tab;     // [J][kCandStride] fit, m, L, H, rows
   int32_t* vlist;        // [T] visible triangles in ascending order
   uint32_t* tile_voff;   // [T/kTriTile + 1] visible-list offset of each triangle tile
-  ulonglong2* big;       // [min(2T, 2^24)] large occupancy footprints
+  ulonglong2* big;       // [kBigCap] queued large occupancy footprints: code, tiles
+  int4* big_fp;          // [kBigCap][3] their footprints (edge data, texel range, chart)
   unsigned long long* big_counter; // [1] queued footprints << 40 | queued tiles
   unsigned long long* partial;     // [kCountGrid] per-block partial counts
   fa_chart* pack_charts; // [max_charts] chart records of the packer-only entry

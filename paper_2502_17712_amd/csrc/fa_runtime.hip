@@ -162,7 +162,8 @@ int fa_create(const fa_config* cfg_in, fa_ctx** out_ctx) {
         {(void**)&w.cand_ab, 4 * J * C},         {(void**)&w.cand_y, 4 * J * C},
         {(void**)&w.cand_tab, 4 * kCandStride * J},
         {(void**)&w.vlist, 4 * T},               {(void**)&w.tile_voff, 4 * tiles},
-        {(void**)&w.big, 16 * std::min<size_t>(2 * T, size_t(1) << 24)},
+        {(void**)&w.big, 16 * std::min<size_t>(2 * T, (size_t)kBigCap)},
+        {(void**)&w.big_fp, 48 * std::min<size_t>(2 * T, (size_t)kBigCap)},
         {(void**)&w.big_counter, 8},             {(void**)&w.partial, 8 * kCountGrid},
         {(void**)&w.pack_charts, sizeof(fa_chart) * C}, {(void**)&w.chart_tex, 16 * C},
         {(void**)&w.cand_rs, 4 * J * (C + 1)},

@@ -211,17 +211,20 @@ __device__ __forceinline__ bool fan_footprint(const SnapPoly& sp, int f, const i
   return true;
 }
 
-__device__ __forceinline__ bool footprint(int64_t t, int f, const int32_t* __restrict__ idx,
-                                          const float4* __restrict__ clip,
-                                          const int32_t* __restrict__ cot,
-                                          const fa_chart* __restrict__ charts,
-                                          const int4* __restrict__ chart_tex,
-                                          const FrameParams& p, const FrameState& st,
-                                          Footprint& fp) {
-  SnapPoly sp;
-  snap_polygon(t, idx, clip, cot, charts, p, st, sp);
-  if (sp.n == 0) return false;
-  return fan_footprint(sp, f, chart_tex[sp.chart], p.omega, fp);
+// A queued footprint travels whole (three 16-byte words), so the tile kernel
+// needs no dependent loads to rebuild it.
+__device__ __forceinline__ void put_footprint(int4* d, const Footprint& f) {
+  d[0] = make_int4(f.ax, f.ay, f.bx, f.by);
+  d[1] = make_int4(f.cx, f.cy, f.tx0, f.tx1);
+  d[2] = make_int4(f.ty0, f.ty1, f.chart, f.neg);
+}
+__device__ __forceinline__ Footprint get_footprint(const int4* d) {
+  const int4 a = d[0], b = d[1], c = d[2];
+  Footprint f;
+  f.ax = a.x; f.ay = a.y; f.bx = a.z; f.by = a.w;
+  f.cx = b.x; f.cy = b.y; f.tx0 = b.z; f.tx1 = b.w;
+  f.ty0 = c.x; f.ty1 = c.y; f.chart = c.z; f.neg = c.w;
+  return f;
 }
 
 // The three edge functions at the centre of texel (tx, ty), exact in 64-bit
@@ -345,7 +348,8 @@ __global__ __launch_bounds__(kOccSmallBlock) void k_occ_small(
     const int32_t* __restrict__ idx, const int32_t* __restrict__ vlist, FrameParams p,
     const float4* __restrict__ clip, const int32_t* __restrict__ cot,
     const fa_chart* __restrict__ charts, const int4* __restrict__ chart_tex,
-    int32_t* __restrict__ occ, ulonglong2* __restrict__ big, uint32_t big_cap, int small_texels,
+    int32_t* __restrict__ occ, ulonglong2* __restrict__ big, int4* __restrict__ big_fp,
+    uint32_t big_cap, int small_texels,
     int lane_texels, unsigned long long* __restrict__ big_counter,
     const FrameState* __restrict__ stp) {
   __shared__ uint32_t wcnt[kOccSmallBlock / kWave], wtil[kOccSmallBlock / kWave];
@@ -404,6 +408,7 @@ __global__ __launch_bounds__(kOccSmallBlock) void k_occ_small(
         big[slot] = make_ulonglong2((unsigned long long)(2 * (int64_t)t) |
                                         ((unsigned long long)txa << 32),
                                     tile | ((unsigned long long)nta << kSlotShift));
+        put_footprint(big_fp + 3 * slot, fa);
         qa = true;
       }
       slot += wa;
@@ -412,6 +417,7 @@ __global__ __launch_bounds__(kOccSmallBlock) void k_occ_small(
         big[slot] = make_ulonglong2((unsigned long long)(2 * (int64_t)t + 1) |
                                         ((unsigned long long)txb << 32),
                                     tile | ((unsigned long long)ntb << kSlotShift));
+        put_footprint(big_fp + 3 * slot, fb);
         qb = true;
       }
     }
@@ -431,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void k_occ_big(
     const int32_t* __restrict__ idx, FrameParams p, const float4* __restrict__ clip,
     const int32_t* __restrict__ cot, const fa_chart* __restrict__ charts,
     const int4* __restrict__ chart_tex, int32_t* __restrict__ occ,
-    const ulonglong2* __restrict__ big, uint32_t big_cap,
+    const ulonglong2* __restrict__ big, const int4* __restrict__ big_fp, uint32_t big_cap,
     const unsigned long long* __restrict__ big_counter, const FrameState* __restrict__ stp) {
   const FrameState st = *stp;
   if (st.status != FA_OK) return;
@@ -478,9 +484,8 @@ __global__ __launch_bounds__(kBlock) void k_occ_big(
       tiles_x = (uint32_t)(ent.x >> 32);
       mine = base < k1;
       if (mine) {
-        const uint32_t code = (uint32_t)ent.x;
-        ok = footprint((int64_t)(code >> 1), (int)(code & 1u), idx, clip, cot, charts, chart_tex,
-                       p, st, f);
+        f = get_footprint(big_fp + 3 * (int64_t)my);
+        ok = true;
       }
     }
     const int cnt = __popcll(__ballot(mine));  // entries start in order: a prefix of lanes
@@ -581,14 +586,14 @@ hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p,
   const unsigned fill_grid = (unsigned)std::min<int64_t>((n4 + kBlock - 1) / kBlock, 4096);
   k_occ_fill<<<fill_grid, kBlock, 0, st>>>(reinterpret_cast<int4*>(occ), n4, w.state);
   mk(st);
-  const uint32_t cap = (uint32_t)std::min<int64_t>(2 * std::max<int64_t>(T, 1), 1 << 24);
+  const uint32_t cap = (uint32_t)std::min<int64_t>(2 * std::max<int64_t>(T, 1), kBigCap);
   if (T > 0) {
     k_occ_small<<<visible_grid(T), kOccSmallBlock, 0, st>>>(
-        idx, w.vlist, p, w.clip, cot, charts, w.chart_tex, occ, w.big, cap, small_texels,
+        idx, w.vlist, p, w.clip, cot, charts, w.chart_tex, occ, w.big, w.big_fp, cap, small_texels,
         lane_texels, w.big_counter, w.state);
     mk(st);
     k_occ_big<<<kOccBigGrid, kBlock, 0, st>>>(idx, p, w.clip, cot, charts, w.chart_tex, occ,
-                                              w.big, cap, w.big_counter, w.state);
+                                              w.big, w.big_fp, cap, w.big_counter, w.state);
   } else {
     mk(st);
   }
