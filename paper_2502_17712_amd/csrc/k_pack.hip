@@ -201,56 +201,89 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
     const int s0 = RS[rr], s1 = RS[rr + 1];
     const long long r = X[s0] >> lg;
     const bool right = (r % 3) != 0;
-    for (int k = s0 + w; k < s1; k += NW) {
-      const long long Xk = X[k];
-      const uint32_t ab = AB[k];
-      const int a = (int)(ab & 0xFFFFu), b = (int)(ab >> 16);
-      const int o = (int)(Xk - (r << lg));
-      const int x = right ? L - o - a : o;
-      if constexpr (MODE == 0) {
-        int mx = 0;
-        for (int c = x + lane; c < x + a; c += kWave) mx = max(mx, F[c]);
-        const int y = wave_max<int>(mx);
-        for (int c = x + lane; c < x + a; c += kWave) F[c] = y + b;
-        if (lane == 0) Y[k] = y;
-        Hw = max(Hw, y + b);
-      } else {
-        // one lane per content column; the pooled values come from k_fp_pool
-        const int g = p.gutter, ncol = a - g;
-        const uint32_t* src = pool + Xk;
-        uint32_t keep[R];
+    if constexpr (MODE == 0) {
+      // four consecutive boxes per wave step, 16 lanes each (a box's reads,
+      // a 16-lane max, then its writes); a group with a box wider than 64
+      // columns takes its boxes one at a time with the whole wave
+      const int sub = lane >> 4, sl = lane & 15;
+      for (int kb = s0 + 4 * w; kb < s1; kb += 4 * NW) {
+        const int k = kb + sub;
+        const bool act = k < s1;
+        int a = 0, b = 0, x = 0;
+        if (act) {
+          const uint32_t ab = AB[k];
+          a = (int)(ab & 0xFFFFu);
+          b = (int)(ab >> 16);
+          const int o = (int)(X[k] - (r << lg));
+          x = right ? L - o - a : o;
+        }
+        if (__ballot(act && a > kWave)) {
+          for (int q = 0; q < 4 && kb + q < s1; ++q) {
+            const int aq = __shfl(a, 16 * q, kWave), bq = __shfl(b, 16 * q, kWave);
+            const int xq = __shfl(x, 16 * q, kWave);
+            int mx = 0;
+            for (int c = xq + lane; c < xq + aq; c += kWave) mx = max(mx, F[c]);
+            const int y = wave_max<int>(mx);
+            for (int c = xq + lane; c < xq + aq; c += kWave) F[c] = y + bq;
+            if (lane == 0) Y[kb + q] = y;
+            Hw = max(Hw, y + bq);
+          }
+        } else {
+          int mx = 0;
+          for (int c = x + sl; c < x + a; c += 16) mx = max(mx, F[c]);
 #pragma unroll
-        for (int rk = 0; rk < R; ++rk) keep[rk] = nxt[rk];
-        advance(false);
-        prefetch();
-        int mx = 0;
-        auto rise = [&](int kk, uint32_t q) {
-          if (q == kEmpty) return;
-          const int dend = min(kk + 2 * g, a - 1);
-          int fm = 0;
-          for (int d = kk; d <= dend; ++d) fm = max(fm, F[x + d]);
-          mx = max(mx, fm - (int)(q & 0xFFFFu));
-        };
-#pragma unroll
-        for (int rk = 0; rk < R; ++rk) rise(lane + rk * kWave, keep[rk]);
-        for (int kk = lane + R * kWave; kk < ncol; kk += kWave) rise(kk, src[kk]);
-        const int y = wave_max<int>(mx);
-        int hv = 0;
-        auto raise = [&](int kk, uint32_t q) {
-          if (q == kEmpty) return;
-          const int Bk = (int)(q >> 16);
-          const int v = Bk == 0x7FFF ? y + b : min(y + b, y + 2 * g + Bk + 1);
-          const int dend = min(kk + 2 * g, a - 1);
-          for (int d = kk; d <= dend; ++d) atomicMax(&F[x + d], v);
-          hv = max(hv, v);
-        };
-#pragma unroll
-        for (int rk = 0; rk < R; ++rk) raise(lane + rk * kWave, keep[rk]);
-        for (int kk = lane + R * kWave; kk < ncol; kk += kWave) raise(kk, src[kk]);
-        Hw = max(Hw, wave_max<int>(hv));  // lane 0 publishes the wave's height
-        if (lane == 0) Y[k] = y;
+          for (int o2 = 1; o2 < 16; o2 <<= 1) mx = max(mx, __shfl_xor(mx, o2, kWave));
+          for (int c = x + sl; c < x + a; c += 16) F[c] = mx + b;
+          if (act && sl == 0) Y[k] = mx;
+          if (act) Hw = max(Hw, mx + b);
+        }
+      }
+    } else {
+      for (int k = s0 + w; k < s1; k += NW) {
+        const long long Xk = X[k];
+        const uint32_t ab = AB[k];
+        const int a = (int)(ab & 0xFFFFu), b = (int)(ab >> 16);
+        const int o = (int)(Xk - (r << lg));
+        const int x = right ? L - o - a : o;
+        {
+          // one lane per content column; the pooled values come from k_fp_pool
+          const int g = p.gutter, ncol = a - g;
+          const uint32_t* src = pool + Xk;
+          uint32_t keep[R];
+  #pragma unroll
+          for (int rk = 0; rk < R; ++rk) keep[rk] = nxt[rk];
+          advance(false);
+          prefetch();
+          int mx = 0;
+          auto rise = [&](int kk, uint32_t q) {
+            if (q == kEmpty) return;
+            const int dend = min(kk + 2 * g, a - 1);
+            int fm = 0;
+            for (int d = kk; d <= dend; ++d) fm = max(fm, F[x + d]);
+            mx = max(mx, fm - (int)(q & 0xFFFFu));
+          };
+  #pragma unroll
+          for (int rk = 0; rk < R; ++rk) rise(lane + rk * kWave, keep[rk]);
+          for (int kk = lane + R * kWave; kk < ncol; kk += kWave) rise(kk, src[kk]);
+          const int y = wave_max<int>(mx);
+          int hv = 0;
+          auto raise = [&](int kk, uint32_t q) {
+            if (q == kEmpty) return;
+            const int Bk = (int)(q >> 16);
+            const int v = Bk == 0x7FFF ? y + b : min(y + b, y + 2 * g + Bk + 1);
+            const int dend = min(kk + 2 * g, a - 1);
+            for (int d = kk; d <= dend; ++d) atomicMax(&F[x + d], v);
+            hv = max(hv, v);
+          };
+  #pragma unroll
+          for (int rk = 0; rk < R; ++rk) raise(lane + rk * kWave, keep[rk]);
+          for (int kk = lane + R * kWave; kk < ncol; kk += kWave) raise(kk, src[kk]);
+          Hw = max(Hw, wave_max<int>(hv));
+          if (lane == 0) Y[k] = y;
+        }
       }
     }
+    Hw = wave_max<int>(Hw);  // lane 0 publishes the wave's height
     if (lane == 0) atomicMax(&Hsh[rr & 1], Hw);
     __syncthreads();
     if (Hsh[rr & 1] > L) break;
