@@ -280,9 +280,11 @@ struct AdjTmp {
   int32_t* vals_a;
   int32_t* vals_b;
   uint32_t* hist;
+  uint32_t* part;  // per-chunk sums of the histogram scan
   uint32_t* n_dev;
 };
 size_t adjacency_hist_words(int64_t T);
+size_t adjacency_part_words(int64_t T);
 hipError_t launch_adjacency(const int32_t* idx, int64_t T, int64_t V, const AdjTmp& tmp,
                             int32_t* nbr, hipStream_t st);
 

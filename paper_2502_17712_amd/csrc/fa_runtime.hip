@@ -265,8 +265,10 @@ static int get_scene(fa_ctx* ctx, const fa_mesh* mesh, hipStream_t st, Scene** o
     AdjTmp tmp{};
     const int64_t n = 3 * T;
     size_t hist_words = adjacency_hist_words(T);
+    size_t part_words = adjacency_part_words(T);
     void* blk = nullptr;
-    size_t bytes = align_up(8 * n) * 2 + align_up(4 * n) * 2 + align_up(4 * hist_words) + 256;
+    size_t bytes = align_up(8 * n) * 2 + align_up(4 * n) * 2 + align_up(4 * hist_words) +
+                   align_up(4 * part_words) + 256;
     if (hipMalloc(&blk, bytes) != hipSuccess) {
       (void)hipFree(sc.nbr);
       return FA_ERR_OUT_OF_MEMORY;
@@ -276,7 +278,8 @@ static int get_scene(fa_ctx* ctx, const fa_mesh* mesh, hipStream_t st, Scene** o
     tmp.keys_b = (unsigned long long*)b; b += align_up(8 * n);
     tmp.vals_a = (int32_t*)b; b += align_up(4 * n);
     tmp.vals_b = (int32_t*)b; b += align_up(4 * n);
-    tmp.hist = (uint32_t*)b;
+    tmp.hist = (uint32_t*)b; b += align_up(4 * hist_words);
+    tmp.part = (uint32_t*)b;
     hipError_t e = launch_adjacency(mesh->indices, T, V, tmp, sc.nbr, st);
     hipError_t e2 = hipStreamSynchronize(st);
     (void)hipFree(blk);

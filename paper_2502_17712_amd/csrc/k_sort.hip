@@ -34,30 +34,67 @@ __global__ void k_radix_hist(const K* __restrict__ keys, const int32_t* __restri
   for (int d = threadIdx.x; d < kRadix; d += blockDim.x) hist[(int64_t)d * ntiles + b] = h[d];
 }
 
-// Exclusive scan of the digit-major histogram (one workgroup of 1024): chunks
-// of 4 consecutive words per thread, a block scan per chunk, running total.
-__global__ __launch_bounds__(1024) void k_radix_scan(uint32_t* __restrict__ hist,
-                                                     const int32_t* __restrict__ n_dev,
-                                                     int64_t n_host) {
-  __shared__ uint32_t sh[1024 / kWave];
+// Exclusive scan of the digit-major histogram in three launches: every
+// workgroup of 1024 threads sums its chunk of kScanChunk words (4 per
+// thread), one workgroup scans those sums, and every workgroup scans its
+// chunk again from its offset.
+constexpr int kScanThreads = 1024;
+constexpr int kScanChunk = 4 * kScanThreads;
+
+__device__ __forceinline__ int64_t hist_words(const int32_t* n_dev, int64_t n_host) {
   const int64_t n = n_dev ? min((int64_t)*n_dev, n_host) : n_host;
-  const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
-  const int64_t total = ntiles * kRadix;
+  return (n + kSortTile - 1) / kSortTile * kRadix;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ hist,
+                                                              const int32_t* __restrict__ n_dev,
+                                                              int64_t n_host,
+                                                              uint32_t* __restrict__ part) {
+  __shared__ uint32_t sh[kScanThreads / kWave];
+  const int64_t total = hist_words(n_dev, n_host);
+  const int64_t i0 = (int64_t)blockIdx.x * kScanChunk + 4 * (int64_t)threadIdx.x;
+  if ((int64_t)blockIdx.x * kScanChunk >= total) return;
+  uint32_t v = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v += i0 + k < total ? hist[i0 + k] : 0u;
+  v = block_sum<uint32_t>(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_parts(uint32_t* __restrict__ part,
+                                                             const int32_t* __restrict__ n_dev,
+                                                             int64_t n_host) {
+  __shared__ uint32_t sh[kScanThreads / kWave];
+  const int64_t nb = (hist_words(n_dev, n_host) + kScanChunk - 1) / kScanChunk;
   uint32_t run = 0;
-  for (int64_t c0 = 0; c0 < total; c0 += 4 * (int64_t)blockDim.x) {
-    const int64_t i0 = c0 + 4 * (int64_t)threadIdx.x;
-    uint32_t v[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) v[k] = i0 + k < total ? hist[i0 + k] : 0u;
-    const uint32_t mine = v[0] + v[1] + v[2] + v[3];
+  for (int64_t c0 = 0; c0 < nb; c0 += kScanThreads) {
+    const int64_t i = c0 + threadIdx.x;
+    const uint32_t v = i < nb ? part[i] : 0u;
     uint32_t tot;
-    uint32_t pre = run + block_incl_scan<uint32_t>(mine, sh, &tot) - mine;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (i0 + k < total) hist[i0 + k] = pre;
-      pre += v[k];
-    }
+    const uint32_t ex = run + block_incl_scan<uint32_t>(v, sh, &tot) - v;
+    if (i < nb) part[i] = ex;
     run += tot;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(uint32_t* __restrict__ hist,
+                                                             const int32_t* __restrict__ n_dev,
+                                                             int64_t n_host,
+                                                             const uint32_t* __restrict__ part) {
+  __shared__ uint32_t sh[kScanThreads / kWave];
+  const int64_t total = hist_words(n_dev, n_host);
+  if ((int64_t)blockIdx.x * kScanChunk >= total) return;
+  const int64_t i0 = (int64_t)blockIdx.x * kScanChunk + 4 * (int64_t)threadIdx.x;
+  uint32_t v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = i0 + k < total ? hist[i0 + k] : 0u;
+  const uint32_t mine = v[0] + v[1] + v[2] + v[3];
+  uint32_t tot;
+  uint32_t pre = part[blockIdx.x] + block_incl_scan<uint32_t>(mine, sh, &tot) - mine;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (i0 + k < total) hist[i0 + k] = pre;
+    pre += v[k];
   }
 }
 
@@ -117,8 +154,11 @@ __global__ __launch_bounds__(kRadix) void k_radix_scatter(
 
 template <typename K>
 hipError_t radix_sort(K* keys_a, int32_t* vals_a, K* keys_b, int32_t* vals_b, uint32_t* hist,
-                      const int32_t* n_dev, int64_t n_cap, int bits, hipStream_t st, bool* in_b) {
+                      uint32_t* part, const int32_t* n_dev, int64_t n_cap, int bits,
+                      hipStream_t st, bool* in_b) {
   const unsigned tiles = (unsigned)((n_cap + kSortTile - 1) / kSortTile);
+  const unsigned chunks =
+      std::max(1u, (unsigned)(((int64_t)tiles * kRadix + kScanChunk - 1) / kScanChunk));
   bool flip = false;
   for (int shift = 0; shift < bits; shift += kRadixBits) {
     const K* ki = flip ? keys_b : keys_a;
@@ -126,7 +166,9 @@ hipError_t radix_sort(K* keys_a, int32_t* vals_a, K* keys_b, int32_t* vals_b, ui
     K* ko = flip ? keys_a : keys_b;
     int32_t* vo = flip ? vals_a : vals_b;
     if (tiles) k_radix_hist<K><<<tiles, kRadix, 0, st>>>(ki, n_dev, n_cap, shift, hist);
-    k_radix_scan<<<1, 1024, 0, st>>>(hist, n_dev, n_cap);
+    k_scan_reduce<<<chunks, kScanThreads, 0, st>>>(hist, n_dev, n_cap, part);
+    k_scan_parts<<<1, kScanThreads, 0, st>>>(part, n_dev, n_cap);
+    k_scan_apply<<<chunks, kScanThreads, 0, st>>>(hist, n_dev, n_cap, part);
     if (tiles)
       k_radix_scatter<K><<<tiles, kRadix, 0, st>>>(ki, vi, ko, vo, n_dev, n_cap, shift, hist);
     flip = !flip;
@@ -327,6 +369,10 @@ size_t adjacency_hist_words(int64_t T) {
   return (size_t)((3 * T + kSortTile - 1) / kSortTile + 1) * kRadix;
 }
 
+size_t adjacency_part_words(int64_t T) {
+  return adjacency_hist_words(T) / kScanChunk + 2;
+}
+
 hipError_t launch_adjacency(const int32_t* idx, int64_t T, int64_t V, const AdjTmp& tmp,
                             int32_t* nbr, hipStream_t st) {
   const int64_t n = 3 * T;
@@ -338,7 +384,7 @@ hipError_t launch_adjacency(const int32_t* idx, int64_t T, int64_t V, const AdjT
                                                                        tmp.keys_a, tmp.vals_a);
   bool in_b = false;
   hipError_t e = radix_sort<unsigned long long>(tmp.keys_a, tmp.vals_a, tmp.keys_b, tmp.vals_b,
-                                                tmp.hist, nullptr, n, bits, st, &in_b);
+                                                tmp.hist, tmp.part, nullptr, n, bits, st, &in_b);
   if (e != hipSuccess) return e;
   k_edge_runs<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(
       in_b ? tmp.keys_b : tmp.keys_a, in_b ? tmp.vals_b : tmp.vals_a, n, deg, nbr);
