@@ -77,7 +77,6 @@ struct Work {
   int32_t* vmin;         // [V]
   int32_t* cov;          // [V] when the caller passes no chart_of_vert
   uint32_t* tile_count;  // [T/kTriTile + 1]
-  uint32_t* tile_off;    // [T/kTriTile + 1]
   uint32_t* tile_vis;    // [T/kTriTile + 1] visible triangles per tile
   uint32_t* accum;       // [max_charts][4] order-preserving encoded min/max
   uint32_t* keys_a;      // [max_charts]
@@ -91,11 +90,10 @@ struct Work {
   int32_t* cand_y;       // [J][max_charts]
   int32_t* cand_tab;     // [J][kCandStride] fit, m, L, H, rows
   int32_t* vlist;        // [T] visible triangles in ascending order
-  uint32_t* tile_voff;   // [T/kTriTile + 1] visible-list offset of each triangle tile
+  unsigned long long* partial;  // [kCountGrid] per-block occupied texel counts
   ulonglong2* big;       // [kBigCap] queued large occupancy footprints: code, tiles
   int4* big_fp;          // [kBigCap][3] their footprints (edge data, texel range, chart)
   unsigned long long* big_counter; // [1] queued footprints << 40 | queued tiles
-  unsigned long long* partial;     // [kCountGrid] per-block partial counts
   fa_chart* pack_charts; // [max_charts] chart records of the packer-only entry
   int32_t* cand_rs;      // [J][max_charts + 1] row starts of each candidate (frames above
                          // the LDS capacity of the packer)
@@ -246,9 +244,12 @@ hipError_t launch_select_place(const FrameParams& p, const Work& w, fa_chart* ch
                                int32_t* cand_out, hipStream_t st);
 hipError_t launch_uv(const int64_t V, const FrameParams& p, const Work& w, const int32_t* cov,
                      const fa_chart* charts, float* uv, hipStream_t st);
+// count: also count the occupied texels for the frame record (the frame's
+// own atlas; a scaled copy is drawn without).
 hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
                             const int32_t* cot, const fa_chart* charts, int32_t* occ,
-                            int small_texels, int lane_texels, Marker& mk, hipStream_t st);
+                            int small_texels, int lane_texels, bool count, Marker& mk,
+                            hipStream_t st);
 // Occupancy of the frame's packing drawn into an atlas of side p.omega (a
 // scaled copy of the frame's atlas): box ranges for that side, then the
 // occupancy kernels.

@@ -153,7 +153,7 @@ int fa_create(const fa_config* cfg_in, fa_ctx** out_ctx) {
     std::vector<Part> parts = {
         {(void**)&w.clip, sizeof(float4) * V},   {(void**)&w.parent, 4 * T},
         {(void**)&w.vmin, 4 * V},                {(void**)&w.cov, 4 * V},
-        {(void**)&w.tile_count, 4 * tiles},      {(void**)&w.tile_off, 4 * tiles},
+        {(void**)&w.tile_count, 4 * tiles},
         {(void**)&w.tile_vis, 4 * tiles},
         {(void**)&w.accum, 16 * C},              {(void**)&w.keys_a, 4 * C},
         {(void**)&w.vals_a, 4 * C},              {(void**)&w.keys_b, 4 * C},
@@ -161,7 +161,7 @@ int fa_create(const fa_config* cfg_in, fa_ctx** out_ctx) {
         {(void**)&w.sorted_wh, 8 * C},           {(void**)&w.cand_x, 8 * J * C},
         {(void**)&w.cand_ab, 4 * J * C},         {(void**)&w.cand_y, 4 * J * C},
         {(void**)&w.cand_tab, 4 * kCandStride * J},
-        {(void**)&w.vlist, 4 * T},               {(void**)&w.tile_voff, 4 * tiles},
+        {(void**)&w.vlist, 4 * T},
         {(void**)&w.big, 16 * std::min<size_t>(2 * T, (size_t)kBigCap)},
         {(void**)&w.big_fp, 48 * std::min<size_t>(2 * T, (size_t)kBigCap)},
         {(void**)&w.big_counter, 8},             {(void**)&w.partial, 8 * kCountGrid},
@@ -458,7 +458,7 @@ static int run_frame(fa_ctx* ctx, const Work& w, const fa_mesh* mesh, Scene* sc,
   mk(st);
   if (out->occupancy)
     ok(launch_occupancy(mesh->indices, T, p, w, out->chart_of_tri, out->charts, out->occupancy,
-                        ctx->small_texels, ctx->lane_texels, mk, st));
+                        ctx->small_texels, ctx->lane_texels, true, mk, st));
   ok(launch_meta(p, w, out->meta, out->occupancy != nullptr, st));
   mk(st);
   ctx->ev_marks = mk.n;

@@ -124,36 +124,23 @@ __global__ void k_prologue(const float* __restrict__ pos, int64_t V, FrameParams
   if (threadIdx.x == 0) tile_vis[tile] = nv;
 }
 
-// Exclusive scan of per-tile counts (one workgroup of 1024). Used for the
-// visible compaction (counts per triangle tile) and for the roots (counts per
-// tile of the visible list). *total receives the sum.
-__global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict__ cnt,
-                                                      uint32_t* __restrict__ off,
-                                                      const int32_t* __restrict__ n_dev,
-                                                      int64_t n_host, int32_t* total,
-                                                      int32_t max_total, FrameState* st) {
-  __shared__ uint32_t sh[1024 / kWave];
-  const int64_t items = n_dev ? (int64_t)*n_dev : n_host;
-  const int64_t ntiles = (items + kTriTile - 1) / kTriTile;
-  uint32_t run = 0;
-  for (int64_t b0 = 0; b0 < ntiles; b0 += blockDim.x) {
-    const int64_t b = b0 + threadIdx.x;
-    const uint32_t v = b < ntiles ? cnt[b] : 0;
-    uint32_t tot;
-    const uint32_t inc = block_incl_scan<uint32_t>(v, sh, &tot);
-    if (b < ntiles) off[b] = run + inc - v;
-    run += tot;
-  }
-  if (threadIdx.x == 0) {
-    *total = (int32_t)run;
-    if (max_total >= 0 && (int64_t)run > (int64_t)max_total) st->status = FA_ERR_CAPACITY;
-  }
+// Sum of cnt[0 .. n) by one workgroup (the exclusive prefix of tile n).
+__device__ __forceinline__ uint32_t tiles_before(const uint32_t* __restrict__ cnt, int64_t n,
+                                                 uint32_t* sh) {
+  uint32_t v = 0;
+  for (int64_t u = threadIdx.x; u < n; u += blockDim.x) v += cnt[u];
+  return block_sum<uint32_t>(v, sh);
 }
 
 // Stable compaction of the visible triangles into vlist (ascending index).
+// Each workgroup sums the visible counts of the tiles before its own (a few
+// thousand words at most) instead of waiting for a separate scan; the last
+// one records the total.
 __global__ void k_vis_compact(const uint8_t* __restrict__ vis, int64_t T,
-                              const uint32_t* __restrict__ off, int32_t* __restrict__ vlist) {
+                              const uint32_t* __restrict__ tile_vis, int32_t* __restrict__ vlist,
+                              FrameState* __restrict__ st) {
   __shared__ uint32_t sh[kBlock / kWave];
+  const uint32_t off = tiles_before(tile_vis, blockIdx.x, sh);
   const int64_t base = (int64_t)blockIdx.x * kTriTile + (int64_t)threadIdx.x * 4;
   bool f[4];
   uint32_t mine = 0;
@@ -163,10 +150,11 @@ __global__ void k_vis_compact(const uint8_t* __restrict__ vis, int64_t T,
     mine += f[k];
   }
   uint32_t tot;
-  uint32_t at = off[blockIdx.x] + block_incl_scan<uint32_t>(mine, sh, &tot) - mine;
+  uint32_t at = off + block_incl_scan<uint32_t>(mine, sh, &tot) - mine;
 #pragma unroll
   for (int k = 0; k < 4; ++k)
     if (f[k]) vlist[at++] = (int32_t)(base + k);
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) st->visible = (int32_t)(off + tot);
 }
 
 // Hook across every shared edge once (u < v) (Alg. 1, second loop).
@@ -370,16 +358,20 @@ __global__ void k_uf_flatten_count(const int32_t* __restrict__ vlist, int32_t* p
 
 // Chart index of each root = its rank among roots; the visible list ascends
 // with the triangle index, so chart indices ascend with the chart's lowest
-// triangle.
+// triangle. Each workgroup sums the root counts of the tiles before its own;
+// the last one records the chart count (above max_charts: FA_ERR_CAPACITY;
+// no chart index at or past max_charts is written, and every later stage
+// stops on the status).
 __global__ void k_assign_roots(const int32_t* __restrict__ vlist,
                                const int32_t* __restrict__ parent,
-                               const uint32_t* __restrict__ off, int32_t* __restrict__ cot,
+                               const uint32_t* __restrict__ tile_count, int32_t* __restrict__ cot,
                                fa_chart* __restrict__ charts, uint32_t* __restrict__ accum,
-                               const FrameState* __restrict__ st) {
+                               int32_t max_charts, FrameState* __restrict__ st) {
   __shared__ uint32_t sh[kBlock / kWave];
   if (st->status != FA_OK) return;
   const int nv = st->visible;
   if ((int64_t)blockIdx.x * kTriTile >= nv) return;
+  const uint32_t off = tiles_before(tile_count, blockIdx.x, sh);
   const int64_t base = (int64_t)blockIdx.x * kTriTile + (int64_t)threadIdx.x * 4;
   bool root[4];
   int tv[4];
@@ -392,14 +384,21 @@ __global__ void k_assign_roots(const int32_t* __restrict__ vlist,
     mine += root[k];
   }
   uint32_t tot;
-  uint32_t c = off[blockIdx.x] + block_incl_scan<uint32_t>(mine, sh, &tot) - mine;
+  uint32_t c = off + block_incl_scan<uint32_t>(mine, sh, &tot) - mine;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (!root[k]) continue;
-    cot[tv[k]] = (int32_t)c;
-    charts[c].root_tri = tv[k];
-    reinterpret_cast<uint4*>(accum)[c] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u);
+    if (c < (uint32_t)max_charts) {
+      cot[tv[k]] = (int32_t)c;
+      charts[c].root_tri = tv[k];
+      reinterpret_cast<uint4*>(accum)[c] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u);
+    }
     ++c;
+  }
+  if ((int64_t)(blockIdx.x + 1) * kTriTile >= nv && threadIdx.x == 0) {
+    const uint32_t total = off + tot;
+    st->num_charts = (int32_t)total;  // reported even when above the capacity
+    if (total > (uint32_t)max_charts) st->status = FA_ERR_CAPACITY;
   }
 }
 
@@ -671,10 +670,8 @@ hipError_t launch_prologue(const float* pos, int64_t V, const uint8_t* vis, cons
                                          cot, w.tile_vis, uf_init, vb, w.state,
                                          w.big_counter);
   mk(st);
-  k_scan_counts<<<1, 1024, 0, st>>>(w.tile_vis, w.tile_voff, nullptr, T, &w.state->visible, -1,
-                                    w.state);
-  mk(st);
-  if (T > 0) k_vis_compact<<<tt, kBlock, 0, st>>>(vis, T, w.tile_voff, w.vlist);
+  mk(st);  // (the visible-count scan is part of the compaction)
+  if (T > 0) k_vis_compact<<<tt, kBlock, 0, st>>>(vis, T, w.tile_vis, w.vlist, w.state);
   mk(st);
   return hipGetLastError();
 }
@@ -713,12 +710,10 @@ hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* 
     mk(st);
   }
   mk(st);
-  k_scan_counts<<<1, 1024, 0, st>>>(w.tile_count, w.tile_off, &w.state->visible, T,
-                                    &w.state->num_charts, p.max_charts, w.state);
-  mk(st);
+  mk(st);  // (the root-count scan is part of the root assignment)
   if (T > 0) {
-    k_assign_roots<<<vt, kBlock, 0, st>>>(w.vlist, w.parent, w.tile_off, cot, charts, w.accum,
-                                          w.state);
+    k_assign_roots<<<vt, kBlock, 0, st>>>(w.vlist, w.parent, w.tile_count, cot, charts, w.accum,
+                                          p.max_charts, w.state);
     mk(st);
     k_gather_boxes<<<grid_for(T, kBlock * kGatherItems), kBlock, 0, st>>>(
         w.vlist, idx, w.parent, w.clip, cot, cov, w.accum, p.flags, w.state);

@@ -523,7 +523,8 @@ __global__ __launch_bounds__(kBlock) void k_occ_big(
   }
 }
 
-// Occupied texels: per-block partial counts (no global atomics).
+// Occupied texels: per-workgroup partial counts (no global atomics; the
+// frame record kernel sums them).
 __global__ void k_occ_count(const int4* __restrict__ occ, int64_t n4,
                             unsigned long long* __restrict__ partial) {
   __shared__ unsigned long long sh[kBlock / kWave];
@@ -581,7 +582,8 @@ hipError_t launch_uv(const int64_t V, const FrameParams& p, const Work& w, const
 
 hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
                             const int32_t* cot, const fa_chart* charts, int32_t* occ,
-                            int small_texels, int lane_texels, Marker& mk, hipStream_t st) {
+                            int small_texels, int lane_texels, bool count, Marker& mk,
+                            hipStream_t st) {
   const int64_t n4 = (int64_t)p.omega * p.omega / 4;
   const unsigned fill_grid = (unsigned)std::min<int64_t>((n4 + kBlock - 1) / kBlock, 4096);
   k_occ_fill<<<fill_grid, kBlock, 0, st>>>(reinterpret_cast<int4*>(occ), n4, w.state);
@@ -598,7 +600,9 @@ hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p,
     mk(st);
   }
   mk(st);
-  k_occ_count<<<kCountGrid, kBlock, 0, st>>>(reinterpret_cast<const int4*>(occ), n4, w.partial);
+  if (count)  // a scaled copy (no frame record) needs no count
+    k_occ_count<<<kCountGrid, kBlock, 0, st>>>(reinterpret_cast<const int4*>(occ), n4,
+                                               w.partial);
   mk(st);
   return hipGetLastError();
 }
@@ -630,7 +634,8 @@ hipError_t launch_occupancy_scaled(const int32_t* idx, int64_t T, const FramePar
   k_chart_tex<<<(unsigned)((p.max_charts + kBlock - 1) / kBlock), kBlock, 0, st>>>(
       p, charts, w.chart_tex, w.big_counter, w.state);
   Marker none;
-  return launch_occupancy(idx, T, p, w, cot, charts, occ, small_texels, lane_texels, none, st);
+  return launch_occupancy(idx, T, p, w, cot, charts, occ, small_texels, lane_texels, false,
+                          none, st);
 }
 
 namespace {
