@@ -223,7 +223,7 @@ __global__ void k_edge_runs(const unsigned long long* __restrict__ keys,
 // zero box, -0 -> +0), viewport transform times the rate, rotation so the box
 // is at least as tall as wide (Sec. "Box Ordering…"), 13-bit height key.
 __device__ __forceinline__ void chart_size(const FrameParams& p, const uint4 e, fa_chart& ch,
-                                           uint32_t& key_out) {
+                                           uint32_t& key_out, float2& oriented) {
   float x0 = 0.0f, y0 = 0.0f, x1 = 0.0f, y1 = 0.0f;
   if (e.z != 0u) {
     x0 = float_of(e.x);
@@ -244,16 +244,20 @@ __device__ __forceinline__ void chart_size(const FrameParams& p, const uint4 e, 
   ch.rotated = rot;
   ch.key = key;
   key_out = (uint32_t)(kKeyCap - key);
+  oriented = make_float2(bw, bh);
 }
 
 // Sizes (when from_accum) and the stable order by (height desc, chart asc):
 // two 8-bit LSD radix passes over the 13-bit keys in one workgroup, items
 // ranked 1024 at a time (ballot matching inside a wave, per-wave digit counts
-// across the 16 waves), then the sorted oriented sizes for the packer. With
+// across the 16 waves), then the sorted oriented sizes for the packer. Frames
+// of up to kOrderLds charts keep keys, values and sizes in LDS throughout
+// (only the final order goes to global memory). With
 // fp_off (footprint push): each chart's full-scale profile columns,
 // floor(oriented width) + 1, are laid out in chart order (exclusive scan);
 // a total above the capacity ends the frame with FA_ERR_CAPACITY.
 constexpr int kOrderThreads = 1024;
+constexpr int kOrderLds = 1024;
 
 __global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
     FrameParams p, const uint32_t* __restrict__ accum, fa_chart* __restrict__ charts,
@@ -265,9 +269,17 @@ __global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
   __shared__ uint32_t wcnt[NW][kRadix];
   __shared__ uint32_t sh[NW];
   __shared__ long long sh64[NW];
+  __shared__ uint32_t lk[2][kOrderLds];
+  __shared__ int32_t lv[2][kOrderLds];
+  __shared__ float2 lwh[kOrderLds];
   if (st->status != FA_OK) return;
   const int C = min(st->num_charts, p.max_charts);
   const int tid = threadIdx.x, w = tid / kWave;
+  const bool lds = from_accum && C <= kOrderLds;
+  uint32_t* KA = lds ? lk[0] : keys_a;
+  int32_t* VA = lds ? lv[0] : vals_a;
+  uint32_t* KB = lds ? lk[1] : keys_b;
+  int32_t* VB = lds ? lv[1] : vals_b;
   if (from_accum) {
     for (int c = tid; c < C; c += kOrderThreads) {
       uint32_t key;
@@ -278,18 +290,20 @@ __global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
       box.y = __hip_atomic_load(&accum[4 * c + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       box.z = __hip_atomic_load(&accum[4 * c + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       box.w = __hip_atomic_load(&accum[4 * c + 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      chart_size(p, box, charts[c], key);
-      keys_a[c] = key;
-      vals_a[c] = c;
+      float2 wh;
+      chart_size(p, box, charts[c], key, wh);
+      KA[c] = key;
+      VA[c] = c;
+      if (lds) lwh[c] = wh;
     }
     __syncthreads();
   }
   for (int pass = 0; pass < 2; ++pass) {
     const int shift = kRadixBits * pass;
-    const uint32_t* kin = pass ? keys_b : keys_a;
-    const int32_t* vin = pass ? vals_b : vals_a;
-    uint32_t* kout = pass ? keys_a : keys_b;
-    int32_t* vout = pass ? vals_a : vals_b;
+    const uint32_t* kin = pass ? KB : KA;
+    const int32_t* vin = pass ? VB : VA;
+    uint32_t* kout = pass ? KA : KB;
+    int32_t* vout = pass ? VA : VB;
     if (tid < kRadix) base[tid] = 0;
     __syncthreads();
     for (int c = tid; c < C; c += kOrderThreads) atomicAdd(&base[(kin[c] >> shift) & (kRadix - 1)], 1u);
@@ -340,16 +354,22 @@ __global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
     }
   }
   for (int i = tid; i < C; i += kOrderThreads) {
-    const int c = vals_a[i];
+    const int c = VA[i];
     fa_chart& ch = charts[c];
-    sorted_wh[i] = make_float2(ch.oriented_w, ch.oriented_h);
+    if (lds) {
+      sorted_wh[i] = lwh[c];
+      vals_a[i] = c;
+    } else {
+      sorted_wh[i] = make_float2(ch.oriented_w, ch.oriented_h);
+    }
     ch.order_rank = i;
   }
   if (fp_off) {
     long long run = 0;
     for (int base0 = 0; base0 < C; base0 += kOrderThreads) {
       const int c = base0 + tid;
-      const long long n = c < C ? (long long)floorf(charts[c].oriented_w) + 1 : 0;
+      const long long n =
+          c < C ? (long long)floorf(lds ? lwh[c].x : charts[c].oriented_w) + 1 : 0;
       long long tot;
       const long long incl = block_incl_scan<long long>(n, sh64, &tot);
       if (c < C) fp_off[c] = (int32_t)min(run + incl - n, (long long)p.fp_cap);
