@@ -276,16 +276,18 @@ int fa_pack_boxes(fa_ctx* ctx, const float* sizes, int32_t n, int32_t atlas_size
  *                             visible edge neighbour (Alg. 1); 0: to itself
  *                             (used when FA_TUNE_UF_EDGE_HOOKS is 0 or 1)
  *   FA_TUNE_UF_EDGE_HOOKS     1: join across shared edges, then across shared
- *                             vertices (Alg. 1); 2 (default): shared edges
+ *                             vertices (Alg. 1); 2: shared edges
  *                             inside tiles of 2048 visible triangles joined in
  *                             LDS first, then the edges between tiles, then
  *                             vertices; 3: the tiles in LDS, then vertices
  *                             (edges between tiles are shared vertices);
+ *                             4 (default): as 3, with the vertex minima taken
+ *                             from the tiles' local roots in the same pass;
  *                             0: vertices only
  *                             (every shared edge is a shared vertex: the
- *                             charts are the same for all four)
+ *                             charts are the same for all five)
  *   FA_TUNE_UF_TILE           visible-list entries per LDS union-find tile
- *                             (modes 2 and 3): 2048 (default), 4096, 8192
+ *                             (modes 2, 3, 4): 2048, 4096 (default), 8192
  *   FA_TUNE_BATCH_GRAPH       1: fa_build_atlas_batch captures its views into
  *                             a hipGraph once per distinct set of view
  *                             descriptors and replays it (one launch); 0: off

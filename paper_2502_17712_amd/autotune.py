@@ -21,8 +21,8 @@ KNOBS = {
     FA_TUNE_OCC_SMALL_TEXELS: [64, 16, 32, 128, 256],
     FA_TUNE_OCC_LANE_TEXELS: [64, 0, 16, 256],
     FA_TUNE_UF_LINK_INIT: [1, 0],
-    FA_TUNE_UF_EDGE_HOOKS: [2, 3, 1, 0],
-    FA_TUNE_UF_TILE: [2048, 4096, 8192],
+    FA_TUNE_UF_EDGE_HOOKS: [4, 2, 3, 1, 0],
+    FA_TUNE_UF_TILE: [4096, 2048, 8192],
     FA_TUNE_PACK_BLOCK: [256, 512, 1024],
 }
 NAMES = {FA_TUNE_PACK_BLOCK: "pack_block", FA_TUNE_OCC_SMALL_TEXELS: "occ_small_texels",
@@ -31,7 +31,9 @@ NAMES = {FA_TUNE_PACK_BLOCK: "pack_block", FA_TUNE_OCC_SMALL_TEXELS: "occ_small_
 
 
 def _snapshot(out: AtlasOutputs):
-    ts = [out.chart_of_tri, out.chart_of_vert, out.charts, out.meta[:12]]
+    # chart records past the frame's chart count are not outputs of the frame
+    n = int(out.meta[1].item())
+    ts = [out.chart_of_tri, out.chart_of_vert, out.charts[:n], out.meta[:12]]
     for t in (out.uv, out.occupancy, out.candidates):
         if t is not None:
             ts.append(t)

@@ -64,7 +64,8 @@ struct FrameParams {
   int32_t J, gutter, min_box;
   uint32_t flags;
   int32_t max_charts;
-  int32_t edge_hooks;  // union-find edge hooks: 0 none, 1 global, 2 LDS tiles + between tiles, 3 LDS tiles
+  int32_t edge_hooks;  // union-find edge hooks: 0 none, 1 global, 2 LDS tiles + between tiles, 3 LDS
+                       // tiles, 4 LDS tiles that also lower the vertex minima
   int32_t uf_tile;     // visible-list entries per LDS union-find tile (2048, 4096, 8192)
   int32_t fp_cap;      // footprint push: capacity of the profile columns (0: box push)
   int64_t pool_stride; // footprint push: pooled profile entries per candidate

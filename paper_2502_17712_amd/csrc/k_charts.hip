@@ -250,11 +250,18 @@ __device__ __forceinline__ void lds_join(int* lp, int a, int b) {
   }
 }
 
+// With idx (hook mode 4), every entry also lowers the minimum of its three
+// vertices to its local root: a vertex minimum only has to name some
+// triangle of a set that touches the vertex, so the local root serves, and
+// the vertex hook then joins every set that touches a common vertex (which
+// covers the edges between tiles too).
 template <int TILE, int NT>
 __global__ __launch_bounds__(NT) void k_uf_local(const uint8_t* __restrict__ vis,
                                                  const int32_t* __restrict__ nbr,
                                                  const int32_t* __restrict__ vlist,
                                                  int32_t* __restrict__ parent,
+                                                 const int32_t* __restrict__ idx,
+                                                 int32_t* __restrict__ vmin,
                                                  const FrameState* __restrict__ st) {
   __shared__ int lv[TILE];
   __shared__ int lp[TILE];
@@ -284,8 +291,14 @@ __global__ __launch_bounds__(NT) void k_uf_local(const uint8_t* __restrict__ vis
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < cnt; i += blockDim.x)
-    astore(&parent[lv[i]], lv[lds_root(lp, i)]);
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const int t = lv[i], r = lv[lds_root(lp, i)];
+    astore(&parent[t], r);
+    if (idx) {
+#pragma unroll
+      for (int e = 0; e < 3; ++e) atomicMin(&vmin[idx[3 * (int64_t)t + e]], r);
+    }
+  }
 }
 
 // Vertex minimum (Alg. 1, third loop): every visible triangle is compressed
@@ -305,22 +318,40 @@ __global__ void k_uf_vertex_min(const int32_t* __restrict__ idx,
 }
 
 // Vertex hook: join every visible triangle with the recorded root of each of
-// its vertices, merging charts that share only a vertex.
+// its vertices, merging charts that share only a vertex. parent[t] is an
+// ancestor of t: a vertex whose minimum equals it needs no join, which skips
+// most of them; along a tile border many lanes of a wave name the same
+// (parent, minimum) pair, and only the lowest lane of each pair joins.
 __global__ void k_uf_vertex_hook(const int32_t* __restrict__ idx,
                                  const int32_t* __restrict__ vlist, int32_t* parent,
                                  const int32_t* __restrict__ vmin,
                                  const FrameState* __restrict__ st) {
   const int nv = st->visible;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
-    const int t = vlist[i];
-    const int m0 = aload(&vmin[idx[3 * (int64_t)t]]), m1 = aload(&vmin[idx[3 * (int64_t)t + 1]]);
-    const int m2 = aload(&vmin[idx[3 * (int64_t)t + 2]]);
-    // parent[t] is an ancestor of t (its root at the vertex minimum): a vertex
-    // whose minimum equals it needs no join, which skips almost every one
-    const int pt = aload(&parent[t]);
-    if (m0 != pt) uf_join(parent, pt, m0);
-    if (m1 != pt && m1 != m0) uf_join(parent, pt, m1);
-    if (m2 != pt && m2 != m0 && m2 != m1) uf_join(parent, pt, m2);
+  const int lane = lane_id();
+  for (int i0 = blockIdx.x * blockDim.x; i0 < nv; i0 += gridDim.x * blockDim.x) {
+    const int i = i0 + threadIdx.x;
+    const bool valid = i < nv;
+    int pt = 0, m[3] = {0, 0, 0};
+    if (valid) {
+      const int t = vlist[i];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) m[e] = aload(&vmin[idx[3 * (int64_t)t + e]]);
+      pt = aload(&parent[t]);
+    }
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      bool want = valid && m[e] != pt && (e < 1 || m[e] != m[0]) && (e < 2 || m[e] != m[1]);
+      const int a = min(pt, m[e]), b = max(pt, m[e]);
+      unsigned long long todo = __ballot(want);
+      bool keep = false;
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int la = __shfl(a, leader, kWave), lb = __shfl(b, leader, kWave);
+        if (lane == leader) keep = true;
+        todo &= ~__ballot(want && a == la && b == lb);
+      }
+      if (keep) uf_join(parent, a, b);
+    }
   }
 }
 
@@ -686,20 +717,22 @@ hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* 
       k_uf_hook<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, 0, w.state);
     } else if (p.edge_hooks >= 2) {
       const int tile = p.uf_tile;
+      const int32_t* vidx = p.edge_hooks == 4 ? idx : nullptr;
       if (tile == 8192)
         k_uf_local<8192, 1024><<<std::max(1u, grid_for(T, 8192)), 1024, 0, st>>>(
-            vis, nbr, w.vlist, w.parent, w.state);
+            vis, nbr, w.vlist, w.parent, vidx, w.vmin, w.state);
       else if (tile == 4096)
         k_uf_local<4096, 1024><<<std::max(1u, grid_for(T, 4096)), 1024, 0, st>>>(
-            vis, nbr, w.vlist, w.parent, w.state);
+            vis, nbr, w.vlist, w.parent, vidx, w.vmin, w.state);
       else
         k_uf_local<2048, 512><<<std::max(1u, grid_for(T, 2048)), 512, 0, st>>>(
-            vis, nbr, w.vlist, w.parent, w.state);
+            vis, nbr, w.vlist, w.parent, vidx, w.vmin, w.state);
       if (p.edge_hooks == 2)
         k_uf_cross<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, tile, w.state);
     }
     mk(st);
-    k_uf_vertex_min<<<g, kBlock, 0, st>>>(idx, w.vlist, w.parent, w.vmin, w.state);
+    if (p.edge_hooks != 4)  // mode 4: the tile kernel lowered the vertex minima
+      k_uf_vertex_min<<<g, kBlock, 0, st>>>(idx, w.vlist, w.parent, w.vmin, w.state);
     mk(st);
     k_uf_vertex_hook<<<g, kBlock, 0, st>>>(idx, w.vlist, w.parent, w.vmin, w.state);
     mk(st);
