@@ -87,6 +87,17 @@ def measured_traffic(kernel):
     return float(fields["hbm_bytes_per_launch"])
 
 
+def dependent_phases(ctx, fa):
+    """Kernel launches of one frame (box push, with occupancy): the 21 timing
+    stages minus the ones this configuration leaves empty."""
+    hooks = ctx.get_tuning(fa.FA_TUNE_UF_EDGE_HOOKS)
+    n = 21 - 4  # visible-count and root-count scans folded in; no footprint stages
+    n -= 1 if hooks == 4 else 0  # vertex minima lowered by the tile kernel
+    n += 1 if hooks == 2 else 0  # tile kernel and cross-tile hooks share a stage
+    n -= 1 if hooks == 0 else 0  # no edge-hook kernel
+    return n
+
+
 def extras(args, ctx, mesh, frames, vis, out, stream, dev, T):
     """No-occupancy frame time, device copy bandwidth, the device visibility
     pass and temporal reuse on the benchmark frames."""
@@ -588,7 +599,7 @@ def main():
             "ms_per_frame": ms_nocc, "algorithmic_bytes": B - 4.0 * args.atlas * args.atlas,
             "hbm_roofline_frac": (B - 4.0 * args.atlas * args.atlas) / (ms_nocc * 1e-3)
             / (HBM_PEAK_GBS * 1e9)},
-        "dependent_phases": len([k_ for k_ in stages if not k_.startswith("fp_")]),
+        "dependent_phases": dependent_phases(ctx, fa),
         "pack_rows_at_chosen_scale": meta["rows"],
         "copy_gbs": copy_gbs,
         "device_visibility": visibility,

@@ -300,7 +300,8 @@ int fa_set_tuning(fa_ctx* ctx, int knob, int value);
 int fa_get_tuning(fa_ctx* ctx, int knob);
 
 /* Per-kernel timing: when enabled, fa_build_atlas (with uv and occupancy
- * outputs) records an event after each of its 21 kernels; fa_stage_times
+ * outputs) records an event after each of its 21 stages (a stage is one
+ * kernel, or none when the configuration folds it into another); fa_stage_times
  * (after the stream completed) fills up to n floats with milliseconds for, in
  * order: prologue (state, clip transform, union-find start), vis_scan,
  * vis_compact (list of the visible triangles), uf_hook, uf_vertex_min,
