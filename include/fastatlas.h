@@ -281,11 +281,14 @@ int fa_pack_boxes(fa_ctx* ctx, const float* sizes, int32_t n, int32_t atlas_size
  *                             LDS first, then the edges between tiles, then
  *                             vertices; 3: the tiles in LDS, then vertices
  *                             (edges between tiles are shared vertices);
- *                             4 (default): as 3, with the vertex minima taken
- *                             from the tiles' local roots in the same pass;
+ *                             4: as 3, with the vertex minima taken from the
+ *                             tiles' local roots in the same pass;
+ *                             5 (default): as 4, tiles of 2048 entries joined
+ *                             in LDS through shared vertices (an LDS hash
+ *                             table of vertex ids) instead of shared edges;
  *                             0: vertices only
  *                             (every shared edge is a shared vertex: the
- *                             charts are the same for all five)
+ *                             charts are the same for all six)
  *   FA_TUNE_UF_TILE           visible-list entries per LDS union-find tile
  *                             (modes 2, 3, 4): 2048, 4096 (default), 8192
  *   FA_TUNE_BATCH_GRAPH       1: fa_build_atlas_batch captures its views into

@@ -21,7 +21,7 @@ KNOBS = {
     FA_TUNE_OCC_SMALL_TEXELS: [64, 16, 32, 128, 256],
     FA_TUNE_OCC_LANE_TEXELS: [64, 0, 16, 256],
     FA_TUNE_UF_LINK_INIT: [1, 0],
-    FA_TUNE_UF_EDGE_HOOKS: [4, 2, 3, 1, 0],
+    FA_TUNE_UF_EDGE_HOOKS: [5, 4, 2, 3, 1, 0],
     FA_TUNE_UF_TILE: [4096, 2048, 8192],
     FA_TUNE_PACK_BLOCK: [256, 512, 1024],
 }

@@ -67,7 +67,7 @@ struct fa_ctx {
   int small_texels = 64;
   int lane_texels = 64;
   int uf_link_init = 1;
-  int uf_edge_hooks = 4;
+  int uf_edge_hooks = 5;
   int uf_tile = 4096;
   int32_t* check_flag = nullptr;  // device int for index validation
   // visibility pass scratch: occluder list [max_triangles] + its counter, and
@@ -647,7 +647,7 @@ int fa_set_tuning(fa_ctx* ctx, int knob, int value) {
       ctx->batch_graph = value;
       return FA_OK;
     case FA_TUNE_UF_EDGE_HOOKS:
-      if (value < 0 || value > 4) return FA_ERR_INVALID_ARG;
+      if (value < 0 || value > 5) return FA_ERR_INVALID_ARG;
       ctx->uf_edge_hooks = value;
       return FA_OK;
     case FA_TUNE_UF_TILE:

@@ -301,6 +301,65 @@ __global__ __launch_bounds__(NT) void k_uf_local(const uint8_t* __restrict__ vis
   }
 }
 
+// Hook mode 5: the tile of TILE list entries is joined in LDS through shared
+// vertices instead of shared edges (a shared edge is a shared vertex): every
+// vertex reference is entered into an LDS hash table of (vertex << 32 | first
+// entry) words, and an entry that finds its vertex already there joins that
+// entry's set. This also merges the pieces of a chart that touch only at a
+// vertex inside the tile. A vertex that finds no free slot is skipped (the
+// global vertex pass merges through every vertex anyway). Then, as in mode 4,
+// each entry's parent becomes its local root and its vertices' minima are
+// lowered to it.
+template <int TILE, int NT, int HS>
+__global__ __launch_bounds__(NT) void k_uf_local_vertex(const int32_t* __restrict__ idx,
+                                                        const int32_t* __restrict__ vlist,
+                                                        int32_t* __restrict__ parent,
+                                                        int32_t* __restrict__ vmin,
+                                                        const FrameState* __restrict__ st) {
+  static_assert((HS & (HS - 1)) == 0, "hash slots: a power of two");
+  constexpr unsigned long long kFree = ~0ull;
+  __shared__ int lv[TILE];
+  __shared__ int lp[TILE];
+  __shared__ unsigned long long tab[HS];
+  const int nv = st->visible;
+  const int64_t s0 = (int64_t)blockIdx.x * TILE;
+  if (s0 >= nv) return;
+  const int cnt = (int)min<int64_t>(TILE, nv - s0);
+  for (int i = threadIdx.x; i < cnt; i += NT) {
+    lv[i] = vlist[s0 + i];
+    lp[i] = i;
+  }
+  for (int h = threadIdx.x; h < HS; h += NT) tab[h] = kFree;
+  __syncthreads();
+  for (int i = threadIdx.x; i < cnt; i += NT) {
+    const int t = lv[i];
+    int v[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) v[e] = idx[3 * (int64_t)t + e];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const unsigned long long mine = ((unsigned long long)(uint32_t)v[e] << 32) | (uint32_t)i;
+      uint32_t h = ((uint32_t)v[e] * 2654435761u) & (HS - 1);
+      for (int probe = 0; probe < 32; ++probe) {
+        const unsigned long long old = atomicCAS(&tab[h], kFree, mine);
+        if (old == kFree) break;                       // first entry with this vertex
+        if ((uint32_t)(old >> 32) == (uint32_t)v[e]) {  // joined through the vertex
+          lds_join(lp, i, (int)(uint32_t)old);
+          break;
+        }
+        h = (h + 1) & (HS - 1);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < cnt; i += NT) {
+    const int t = lv[i], r = lv[lds_root(lp, i)];
+    astore(&parent[t], r);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) atomicMin(&vmin[idx[3 * (int64_t)t + e]], r);
+  }
+}
+
 // Vertex minimum (Alg. 1, third loop): every visible triangle is compressed
 // to its current root and every vertex records the smallest root among its
 // visible triangles. The compression keeps the vertex hook's walks short.
@@ -715,6 +774,10 @@ hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* 
   if (T > 0) {
     if (p.edge_hooks == 1) {
       k_uf_hook<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, 0, w.state);
+    } else if (p.edge_hooks == 5) {
+      // tiles of 2048 entries and a 4096-slot table (at most ~3/4 full)
+      k_uf_local_vertex<2048, 512, 4096><<<std::max(1u, grid_for(T, 2048)), 512, 0, st>>>(
+          idx, w.vlist, w.parent, w.vmin, w.state);
     } else if (p.edge_hooks >= 2) {
       const int tile = p.uf_tile;
       const int32_t* vidx = p.edge_hooks == 4 ? idx : nullptr;
@@ -731,7 +794,7 @@ hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* 
         k_uf_cross<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, tile, w.state);
     }
     mk(st);
-    if (p.edge_hooks != 4)  // mode 4: the tile kernel lowered the vertex minima
+    if (p.edge_hooks < 4)  // modes 4, 5: the tile kernel lowered the vertex minima
       k_uf_vertex_min<<<g, kBlock, 0, st>>>(idx, w.vlist, w.parent, w.vmin, w.state);
     mk(st);
     k_uf_vertex_hook<<<g, kBlock, 0, st>>>(idx, w.vlist, w.parent, w.vmin, w.state);

@@ -149,8 +149,9 @@ def test_city_frames_more():
 
 
 @pytest.mark.parametrize("knob,value", [(1, 256), (1, 512), (2, 0), (2, 16), (2, 1024),
-                                        (2, 4096), (3, 0), (5, 0), (5, 1), (5, 3), (5, 4), (6, 0), (6, 1),
-                                        (6, 4096), (7, 2048), (7, 8192)])
+                                        (2, 4096), (3, 0), (5, 0), (5, 1), (5, 2), (5, 3),
+                                        (5, 4), (6, 0), (6, 1), (6, 4096), (7, 2048),
+                                        (7, 8192)])
 def test_tuning_knobs_do_not_change_results(knob, value):
     fa = _fa()
     ctx = ctx_for()
@@ -163,7 +164,7 @@ def test_tuning_knobs_do_not_change_results(knob, value):
     finally:
         ctx.set_tuning(knob, old)
     with pytest.raises(fa.FastAtlasError):
-        ctx.set_tuning(knob, {1: 3, 2: -1, 3: 3, 5: 5, 6: 4097, 7: 1024}[knob])
+        ctx.set_tuning(knob, {1: 3, 2: -1, 3: 3, 5: 6, 6: 4097, 7: 1024}[knob])
 
 
 # ---------------------------------------------------------------------------
@@ -437,8 +438,8 @@ def test_serve_mix_equals_alone():
         assert r.meta["status"] == 0
 
 
-@pytest.mark.parametrize("link,hooks", [(0, 0), (0, 1), (0, 2), (0, 3), (0, 4), (1, 0), (1, 1),
-                                        (1, 2), (1, 3), (1, 4)])
+@pytest.mark.parametrize("link,hooks", [(0, 0), (0, 1), (0, 2), (0, 3), (0, 4), (0, 5), (1, 0),
+                                        (1, 1), (1, 2), (1, 3), (1, 4), (1, 5)])
 def test_union_find_modes_all_combinations(link, hooks):
     """Every (start link, edge-hook mode) pair gives the oracle's charts, frame
     after frame (the charts do not depend on how the union-find gets there)."""
