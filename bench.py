@@ -92,7 +92,7 @@ def dependent_phases(ctx, fa):
     stages minus the ones this configuration leaves empty."""
     hooks = ctx.get_tuning(fa.FA_TUNE_UF_EDGE_HOOKS)
     n = 21 - 4  # visible-count and root-count scans folded in; no footprint stages
-    n -= 1 if hooks == 4 else 0  # vertex minima lowered by the tile kernel
+    n -= 1 if hooks >= 4 else 0  # vertex minima lowered by the tile kernel
     n += 1 if hooks == 2 else 0  # tile kernel and cross-tile hooks share a stage
     n -= 1 if hooks == 0 else 0  # no edge-hook kernel
     return n

@@ -65,7 +65,8 @@ struct FrameParams {
   uint32_t flags;
   int32_t max_charts;
   int32_t edge_hooks;  // union-find edge hooks: 0 none, 1 global, 2 LDS tiles + between tiles, 3 LDS
-                       // tiles, 4 LDS tiles that also lower the vertex minima
+                       // tiles, 4 LDS tiles that also lower the vertex minima, 5 LDS tiles joined
+                       // through shared vertices
   int32_t uf_tile;     // visible-list entries per LDS union-find tile (2048, 4096, 8192)
   int32_t fp_cap;      // footprint push: capacity of the profile columns (0: box push)
   int64_t pool_stride; // footprint push: pooled profile entries per candidate

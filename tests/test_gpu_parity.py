@@ -460,6 +460,46 @@ def test_union_find_modes_all_combinations(link, hooks):
         ctx.set_tuning(5, old[1])
 
 
+def _bowtie_frame():
+    """The 8k grid with every corner a vertex of its own, except that the two
+    triangles of each grid quad keep one common vertex: charts are bowtie
+    pairs joined only through a vertex, and a tile of 2048 visible triangles
+    names about 5120 distinct vertices, more than the 4096 slots of the
+    vertex-hashed tile pass, so some references overflow its table."""
+    f = scenes.grid_frame(4, atlas_size=2048)
+    tris = f.indices
+    T = tris.shape[0]
+    ind = np.arange(3 * T, dtype=np.int32).reshape(T, 3)
+    for k in range(0, T - 1, 2):
+        common = [c for c in tris[k] if c in tris[k + 1]]
+        if common:
+            ca = int(np.flatnonzero(tris[k] == common[0])[0])
+            cb = int(np.flatnonzero(tris[k + 1] == common[0])[0])
+            ind[k + 1, cb] = ind[k, ca]
+    f.positions = np.ascontiguousarray(f.positions[tris.reshape(-1)])
+    f.indices = ind
+    f.scene_key = 4242
+    f.name = "grid8k-bowties"
+    return f
+
+
+@pytest.mark.parametrize("hooks", [0, 1, 2, 3, 4, 5])
+def test_union_find_vertex_only_charts(hooks):
+    """Charts joined only through a vertex, with more distinct vertices per
+    tile than the vertex-hashed tile table holds, in every hook mode."""
+    f = _bowtie_frame()
+    r = oracle.build_frame(f)
+    assert r["num_charts"] < int(np.count_nonzero(f.visible))  # pairs did merge
+    ctx = ctx_for()
+    old = ctx.get_tuning(5)
+    ctx.set_tuning(5, hooks)
+    try:
+        g = run_gpu(f, ctx)
+        compare(g, r)
+    finally:
+        ctx.set_tuning(5, old)
+
+
 # ---------------------------------------------------------------------------
 # footprint-aware push
 # ---------------------------------------------------------------------------
