@@ -317,6 +317,8 @@ __global__ __launch_bounds__(NT) void k_uf_local_vertex(const int32_t* __restric
                                                         int32_t* __restrict__ vmin,
                                                         const FrameState* __restrict__ st) {
   static_assert((HS & (HS - 1)) == 0, "hash slots: a power of two");
+  static_assert(TILE % NT == 0, "whole entries per thread");
+  constexpr int kPer = TILE / NT;  // entries per thread: i = threadIdx.x + k NT
   constexpr unsigned long long kFree = ~0ull;
   __shared__ int lv[TILE];
   __shared__ int lp[TILE];
@@ -325,25 +327,39 @@ __global__ __launch_bounds__(NT) void k_uf_local_vertex(const int32_t* __restric
   const int64_t s0 = (int64_t)blockIdx.x * TILE;
   if (s0 >= nv) return;
   const int cnt = (int)min<int64_t>(TILE, nv - s0);
-  for (int i = threadIdx.x; i < cnt; i += NT) {
-    lv[i] = vlist[s0 + i];
-    lp[i] = i;
+  // every entry's triangle and vertices are loaded up front (the loads of
+  // a thread's entries overlap) and kept in registers until the end
+  int tk[kPer], vk[kPer][3];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = threadIdx.x + k * NT;
+    tk[k] = i < cnt ? vlist[s0 + i] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = threadIdx.x + k * NT;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) vk[k][e] = i < cnt ? idx[3 * (int64_t)tk[k] + e] : 0;
+    if (i < cnt) {
+      lv[i] = tk[k];
+      lp[i] = i;
+    }
   }
   for (int h = threadIdx.x; h < HS; h += NT) tab[h] = kFree;
   __syncthreads();
-  for (int i = threadIdx.x; i < cnt; i += NT) {
-    const int t = lv[i];
-    int v[3];
 #pragma unroll
-    for (int e = 0; e < 3; ++e) v[e] = idx[3 * (int64_t)t + e];
+  for (int k = 0; k < kPer; ++k) {
+    const int i = threadIdx.x + k * NT;
+    if (i >= cnt) continue;
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
-      const unsigned long long mine = ((unsigned long long)(uint32_t)v[e] << 32) | (uint32_t)i;
-      uint32_t h = ((uint32_t)v[e] * 2654435761u) & (HS - 1);
+      const int v = vk[k][e];
+      const unsigned long long mine = ((unsigned long long)(uint32_t)v << 32) | (uint32_t)i;
+      uint32_t h = ((uint32_t)v * 2654435761u) & (HS - 1);
       for (int probe = 0; probe < 32; ++probe) {
         const unsigned long long old = atomicCAS(&tab[h], kFree, mine);
-        if (old == kFree) break;                       // first entry with this vertex
-        if ((uint32_t)(old >> 32) == (uint32_t)v[e]) {  // joined through the vertex
+        if (old == kFree) break;                    // first entry with this vertex
+        if ((uint32_t)(old >> 32) == (uint32_t)v) {  // joined through the vertex
           lds_join(lp, i, (int)(uint32_t)old);
           break;
         }
@@ -352,11 +368,14 @@ __global__ __launch_bounds__(NT) void k_uf_local_vertex(const int32_t* __restric
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < cnt; i += NT) {
-    const int t = lv[i], r = lv[lds_root(lp, i)];
-    astore(&parent[t], r);
 #pragma unroll
-    for (int e = 0; e < 3; ++e) atomicMin(&vmin[idx[3 * (int64_t)t + e]], r);
+  for (int k = 0; k < kPer; ++k) {
+    const int i = threadIdx.x + k * NT;
+    if (i >= cnt) continue;
+    const int r = lv[lds_root(lp, i)];
+    astore(&parent[tk[k]], r);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) atomicMin(&vmin[vk[k][e]], r);
   }
 }
 
@@ -776,7 +795,7 @@ hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* 
       k_uf_hook<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, 0, w.state);
     } else if (p.edge_hooks == 5) {
       // tiles of 2048 entries and a 4096-slot table (at most ~3/4 full)
-      k_uf_local_vertex<2048, 512, 4096><<<std::max(1u, grid_for(T, 2048)), 512, 0, st>>>(
+      k_uf_local_vertex<2048, 1024, 4096><<<std::max(1u, grid_for(T, 2048)), 1024, 0, st>>>(
           idx, w.vlist, w.parent, w.vmin, w.state);
     } else if (p.edge_hooks >= 2) {
       const int tile = p.uf_tile;
