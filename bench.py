@@ -462,7 +462,7 @@ def main():
                             acc_.setdefault(sn, []).append(ms_)
                     c_.set_stage_timing(False)
                     res_f[name_]["stages_ms"] = {
-                        sn: float(np.mean(acc_[sn])) for sn in ("fp_clear", "fp_raster", "pack")}
+                        sn: float(np.mean(acc_[sn])) for sn in ("fp_count", "fp_raster", "pack")}
                 del o_
             footprint[case_name] = dict(frames=len(ffr), **res_f)
         fctx.close()

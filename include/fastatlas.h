@@ -309,7 +309,8 @@ int fa_get_tuning(fa_ctx* ctx, int knob);
  * order: prologue (state, clip transform, union-find start), vis_scan,
  * vis_compact (list of the visible triangles), uf_hook, uf_vertex_min,
  * uf_vertex_hook, uf_flatten, chart_scan, assign_roots, gather_boxes,
- * sizes_order, fp_clear, fp_raster (footprint profiles; empty without
+ * sizes_order, fp_count, fp_raster (footprint profiles: item counts and
+ * profile clear, then the item scan and the balanced raster; empty without
  * FA_FLAG_FOOTPRINT_PUSH), pack, select_place, uv, occ_fill, occ_small,
  * occ_big, occ_count, meta; it returns the number filled (0 if none recorded).
  * Enabling costs a little host time and device idle time between kernels. */

@@ -130,7 +130,7 @@ fa_reuse_flags = _lib.fa_reuse_flags
 fa_build_dual_atlas = _lib.fa_build_dual_atlas
 
 STAGES = ["prologue", "vis_scan", "vis_compact", "uf_hook", "uf_vertex_min", "uf_vertex_hook",
-          "uf_flatten", "chart_scan", "assign_roots", "gather_boxes", "sizes_order", "fp_clear",
+          "uf_flatten", "chart_scan", "assign_roots", "gather_boxes", "sizes_order", "fp_count",
           "fp_raster", "pack", "select_place", "uv", "occ_fill", "occ_small", "occ_big",
           "occ_count", "meta"]
 

@@ -102,6 +102,8 @@ struct Work {
   int4* chart_tex;       // [max_charts] texel range of each placed box (lo_x, hi_x, lo_y, hi_y)
   int32_t* fp_off;       // [max_charts + 1] first profile column of each chart (footprint push)
   int2* fp_prof;         // [max_profile_columns] full-scale (top, bottom) row of each column
+  unsigned long long* fp_group;  // [T/64 + 2] profile-raster items of each group of 64 list entries,
+                         // then their exclusive prefix and the total
   uint32_t* fp_pool;     // [J][pool_stride] pooled profile of every box at every candidate
   FrameState* state;     // [1]
 };

@@ -169,6 +169,7 @@ int fa_create(const fa_config* cfg_in, fa_ctx** out_ctx) {
         {(void**)&w.cand_rs, 4 * J * (C + 1)},
         {(void**)&w.fp_off, footprint ? 4 * (C + 1) : 4},
         {(void**)&w.fp_prof, footprint ? 8 * (size_t)cfg.max_profile_columns : 8},
+        {(void**)&w.fp_group, footprint ? 8 * (T / kWave + 2) : 8},
         {(void**)&w.fp_pool, footprint ? 4 * J * pool_stride(cfg) : 4},
         {(void**)&w.state, sizeof(FrameState)}};
     size_t total = 0;

@@ -649,12 +649,6 @@ namespace {
 // to the chart's floor(oriented height) + 1 rows). Exact integer arithmetic
 // on the 1/256 snapped vertices: a side crossing's row is the floor of an
 // exact rational. Empty column: (INT_MAX, -1).
-__global__ void k_fp_clear(int2* __restrict__ prof, const FrameState* __restrict__ st) {
-  if (st->status != FA_OK) return;
-  const int n = st->fp_columns;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    prof[i] = make_int2(INT_MAX, -1);
-}
 
 // floor((py + (x0 - px) (qy - py) / (qx - px)) / 256), px != qx. Below 2^52
 // the numerator and divisor are exact doubles: the rounded quotient is within
@@ -679,11 +673,128 @@ __device__ __forceinline__ int32_t crossing_row(int64_t px, int64_t py, int64_t 
   return (int32_t)floor_div64(num, d);
 }
 
-// One wave takes 64 visible triangles at a time: every lane sets up its
-// triangle's snapped polygon and column range, then the wave walks the
-// (triangle, column) pairs 64 at a time (owner found by a binary search over
-// the inclusive column counts), so one triangle's columns spread over lanes.
-// Neighbouring triangles share columns: when the wave's columns span fewer
+// Setup of one visible-list entry for the profile raster: its near-clipped
+// polygon snapped to the chart-local unit grid (1/256), the chart's column
+// and row counts and first profile entry, and the columns [u0, u0 + cnt) it
+// reaches (cnt = 0: nothing).
+struct FpSetup {
+  int32_t X[4], Y[4];
+  int n, Uc, Rc, off, u0, cnt;
+};
+__device__ __forceinline__ void fp_setup(int i, int nv, const int32_t* __restrict__ vlist,
+                                         const int32_t* __restrict__ idx,
+                                         const float4* __restrict__ clip,
+                                         const int32_t* __restrict__ cot,
+                                         const fa_chart* __restrict__ charts,
+                                         const int32_t* __restrict__ fp_off, const FrameParams& p,
+                                         FpSetup& s) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s.X[k] = s.Y[k] = 0;
+  s.n = 0; s.Uc = 1; s.Rc = 1; s.off = 0; s.u0 = 0; s.cnt = 0;
+  if (i >= nv) return;
+  const float halfW = 0.5f * (float)p.W, halfH = 0.5f * (float)p.H;
+  const int t = vlist[i];
+  const int c = cot[t];
+  const float4 a = clip[idx[3 * (int64_t)t]], b = clip[idx[3 * (int64_t)t + 1]],
+               cc = clip[idx[3 * (int64_t)t + 2]];
+  const bool out = c < 0 || outside<0>(a, b, cc) || outside<1>(a, b, cc) ||
+                   outside<2>(a, b, cc) || outside<3>(a, b, cc) || outside<4>(a, b, cc) ||
+                   outside<5>(a, b, cc);
+  if (out) return;
+  float4 poly[4];
+  int n;
+  if (pd<4>(a) < 0.0f || pd<4>(b) < 0.0f || pd<4>(cc) < 0.0f) {
+    n = near_clip(a, b, cc, poly);
+  } else {
+    poly[0] = a; poly[1] = b; poly[2] = cc; poly[3] = cc; n = 3;
+  }
+  bool ok = n > 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) ok = ok && (k >= n || poly[k].w > 0.0f);
+  if (!ok) return;
+  const fa_chart& ch = charts[c];
+  const float x0 = ch.ndc_box[0], y1 = ch.ndc_box[3], tw = ch.target_w;
+  const int rot = ch.rotated;
+  int32_t xmin = INT_MAX, xmax = INT_MIN;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k < n) {
+      const float nx = poly[k].x / poly[k].w, ny = poly[k].y / poly[k].w;
+      const float px = ((nx - x0) * halfW) * p.rate;
+      const float py = ((y1 - ny) * halfH) * p.rate;
+      s.X[k] = snap(rot ? py : px);
+      s.Y[k] = snap(rot ? (tw - px) : py);
+      xmin = min(xmin, s.X[k]);
+      xmax = max(xmax, s.X[k]);
+    }
+  }
+  s.n = n;
+  s.Uc = (int)floorf(ch.oriented_w) + 1;
+  s.Rc = (int)floorf(ch.oriented_h) + 1;
+  s.off = fp_off[c];
+  s.u0 = min(s.Uc - 1, max(0, xmin >> 8));
+  s.cnt = min(s.Uc - 1, max(0, xmax >> 8)) - s.u0 + 1;
+}
+
+// Count: the (triangle, column) items of every group of 64 consecutive
+// visible-list entries (group g = entries 64 g .. 64 g + 63), one wave per
+// group; the blocks past the groups clear the profile.
+__global__ __launch_bounds__(kBlock) void k_fp_count(
+    const int32_t* __restrict__ vlist, const int32_t* __restrict__ idx,
+    const float4* __restrict__ clip, const int32_t* __restrict__ cot,
+    const fa_chart* __restrict__ charts, const int32_t* __restrict__ fp_off,
+    unsigned long long* __restrict__ group_items, int2* __restrict__ prof, unsigned count_blocks,
+    FrameParams p, const FrameState* __restrict__ stp) {
+  if (stp->status != FA_OK) return;
+  if (blockIdx.x >= count_blocks) {
+    const int ncol = stp->fp_columns;
+    const int64_t stride = (int64_t)(gridDim.x - count_blocks) * blockDim.x;
+    for (int64_t e = (int64_t)(blockIdx.x - count_blocks) * blockDim.x + threadIdx.x; e < ncol;
+         e += stride)
+      prof[e] = make_int2(INT_MAX, -1);
+    return;
+  }
+  const int nv = stp->visible;
+  const int groups = (nv + kWave - 1) / kWave;
+  const int nw = (int)(count_blocks * (blockDim.x / kWave));
+  for (int g = (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave); g < groups;
+       g += nw) {
+    FpSetup s;
+    fp_setup(g * kWave + lane_id(), nv, vlist, idx, clip, cot, charts, fp_off, p, s);
+    const int tot = wave_sum<int>(s.cnt);
+    if (lane_id() == 0) group_items[g] = (unsigned long long)tot;
+  }
+}
+
+// Scan: exclusive prefix of the groups' item counts in place, the total after
+// the last group (one workgroup).
+__global__ __launch_bounds__(1024) void k_fp_scan(unsigned long long* __restrict__ group_items,
+                                                 const FrameState* __restrict__ stp) {
+  __shared__ unsigned long long sh[1024 / kWave];
+  if (stp->status != FA_OK) return;
+  const int groups = (stp->visible + kWave - 1) / kWave;
+  const int per = (groups + 1023) / 1024;
+  const int b = min(groups, (int)threadIdx.x * per), e = min(groups, b + per);
+  unsigned long long sum = 0;
+  for (int g = b; g < e; ++g) sum += group_items[g];
+  unsigned long long total = 0;
+  unsigned long long run = block_incl_scan<unsigned long long>(sum, sh, &total) - sum;
+  for (int g = b; g < e; ++g) {
+    const unsigned long long v = group_items[g];
+    group_items[g] = run;
+    run += v;
+  }
+  if (threadIdx.x == 0) group_items[groups] = total;
+}
+
+// Raster: the frame's (triangle, column) items are split evenly over all
+// waves (a wave's share is a contiguous range of the groups' items), so the
+// columns of a few large triangles no longer load one wave. A wave finds the
+// group holding its first item by a 64-way search over the group prefix and
+// walks forward; for each group it touches, its lanes set up the group's 64
+// entries again and the wave takes that group's items in its range 64 at a
+// time (owner found by a binary search over the inclusive column counts).
+// Neighbouring triangles share columns: when a group's columns span fewer
 // than kFpWin profile entries they are reduced in a per-wave LDS window and
 // flushed with one pair of global atomics per touched entry.
 constexpr int kFpWin = 1024;
@@ -692,90 +803,68 @@ __global__ __launch_bounds__(kBlock) void k_fp_raster(
     const int32_t* __restrict__ vlist, const int32_t* __restrict__ idx,
     const float4* __restrict__ clip, const int32_t* __restrict__ cot,
     const fa_chart* __restrict__ charts, const int32_t* __restrict__ fp_off,
-    int2* __restrict__ prof, FrameParams p, const FrameState* __restrict__ stp) {
+    const unsigned long long* __restrict__ group_first, int2* __restrict__ prof, FrameParams p,
+    const FrameState* __restrict__ stp) {
   __shared__ int2 win_all[kBlock / kWave][kFpWin];
   if (stp->status != FA_OK) return;
   const int nv = stp->visible;
-  const float halfW = 0.5f * (float)p.W, halfH = 0.5f * (float)p.H;
+  const int groups = (nv + kWave - 1) / kWave;
+  if (groups == 0) return;
+  const unsigned long long total = group_first[groups];
   const int lane = lane_id();
-  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
-  const int nwaves = (int)(gridDim.x * blockDim.x / kWave);
+  const unsigned long long nwaves = gridDim.x * (blockDim.x / kWave);
+  const unsigned long long wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const unsigned long long per = (total + nwaves - 1) / nwaves;
+  const unsigned long long k0 = min(total, wave * per), k1 = min(total, k0 + per);
+  if (k0 >= k1) return;
   int2* win = win_all[threadIdx.x / kWave];
   for (int e = lane; e < kFpWin; e += kWave) win[e] = make_int2(INT_MAX, -1);
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  for (int base = wave * kWave; base < nv; base += nwaves * kWave) {
-    const int i = base + lane;
-    int32_t X[4] = {0, 0, 0, 0}, Y[4] = {0, 0, 0, 0};
-    int n = 0, Uc = 1, Rc = 1, off = 0, u0 = 0, cnt = 0;
-    if (i < nv) {
-      const int t = vlist[i];
-      const int c = cot[t];
-      const float4 a = clip[idx[3 * (int64_t)t]], b = clip[idx[3 * (int64_t)t + 1]],
-                   cc = clip[idx[3 * (int64_t)t + 2]];
-      const bool out = c < 0 || outside<0>(a, b, cc) || outside<1>(a, b, cc) ||
-                       outside<2>(a, b, cc) || outside<3>(a, b, cc) || outside<4>(a, b, cc) ||
-                       outside<5>(a, b, cc);
-      float4 poly[4];
-      if (!out) {
-        if (pd<4>(a) < 0.0f || pd<4>(b) < 0.0f || pd<4>(cc) < 0.0f) {
-          n = near_clip(a, b, cc, poly);
-        } else {
-          poly[0] = a; poly[1] = b; poly[2] = cc; poly[3] = cc; n = 3;
-        }
-        bool ok = n > 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) ok = ok && (k >= n || poly[k].w > 0.0f);
-        if (!ok) n = 0;
-      }
-      if (n > 0) {
-        const fa_chart& ch = charts[c];
-        const float x0 = ch.ndc_box[0], y1 = ch.ndc_box[3], tw = ch.target_w;
-        const int rot = ch.rotated;
-        int32_t xmin = INT_MAX, xmax = INT_MIN;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (k < n) {
-            const float nx = poly[k].x / poly[k].w, ny = poly[k].y / poly[k].w;
-            const float px = ((nx - x0) * halfW) * p.rate;
-            const float py = ((y1 - ny) * halfH) * p.rate;
-            X[k] = snap(rot ? py : px);
-            Y[k] = snap(rot ? (tw - px) : py);
-            xmin = min(xmin, X[k]);
-            xmax = max(xmax, X[k]);
-          }
-        }
-        Uc = (int)floorf(ch.oriented_w) + 1;
-        Rc = (int)floorf(ch.oriented_h) + 1;
-        off = fp_off[c];
-        u0 = min(Uc - 1, max(0, xmin >> 8));
-        cnt = min(Uc - 1, max(0, xmax >> 8)) - u0 + 1;
-      }
-    }
-    const int incl = wave_incl_scan<int>(cnt);
-    const int total = __shfl(incl, kWave - 1, kWave);
-    // profile entries this wave touches: [elo, ehi]
-    const int elo = wave_min<int>(cnt > 0 ? off + u0 : INT_MAX);
-    const int ehi = wave_max<int>(cnt > 0 ? off + u0 + cnt - 1 : INT_MIN);
-    const bool use_win = total > 0 && ehi - elo < kFpWin;
-    for (int w0 = 0; w0 < total; w0 += kWave) {
+  // last group whose first item <= k0 (group 0 starts at item 0)
+  int lo = 0, hi = groups;
+  while (hi - lo > 1) {
+    const int step = (hi - lo + kWave - 1) / kWave;
+    const int probe = lo + lane * step;
+    const bool le = probe < hi && group_first[probe] <= k0;
+    const int c = __popcll(__ballot(le));
+    lo += (c - 1) * step;
+    hi = min(hi, lo + step);
+  }
+  for (int g = lo; g < groups; ++g) {
+    const unsigned long long gfirst = group_first[g];
+    if (gfirst >= k1) break;
+    FpSetup s;
+    fp_setup(g * kWave + lane, nv, vlist, idx, clip, cot, charts, fp_off, p, s);
+    const int incl = wave_incl_scan<int>(s.cnt);
+    const int gtot = __shfl(incl, kWave - 1, kWave);
+    // this wave's items of the group: [ia, ib) in group-local numbering
+    const int ia = (int)(k0 > gfirst ? k0 - gfirst : 0ull);
+    const int ib = (int)min<unsigned long long>((unsigned long long)gtot, k1 - gfirst);
+    if (ia >= ib) continue;
+    // profile entries the group touches: [elo, ehi]
+    const int elo = wave_min<int>(s.cnt > 0 ? s.off + s.u0 : INT_MAX);
+    const int ehi = wave_max<int>(s.cnt > 0 ? s.off + s.u0 + s.cnt - 1 : INT_MIN);
+    const bool use_win = ehi - elo < kFpWin;
+    for (int w0 = ia; w0 < ib; w0 += kWave) {
       const int item = w0 + lane;
       int o = 0;  // owner: the first lane whose inclusive count exceeds item
 #pragma unroll
       for (int step = 32; step > 0; step >>= 1)
         if (__shfl(incl, o + step - 1, kWave) <= item) o += step;
       o = min(o, kWave - 1);
-      const int on = __shfl(n, o, kWave);
+      const int on = __shfl(s.n, o, kWave);
       int32_t PX[4], PY[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        PX[k] = __shfl(X[k], o, kWave);
-        PY[k] = __shfl(Y[k], o, kWave);
+        PX[k] = __shfl(s.X[k], o, kWave);
+        PY[k] = __shfl(s.Y[k], o, kWave);
       }
-      const int oUc = __shfl(Uc, o, kWave), oRc = __shfl(Rc, o, kWave);
-      const int ooff = __shfl(off, o, kWave);
-      const int u = __shfl(u0, o, kWave) + item - (__shfl(incl, o, kWave) - __shfl(cnt, o, kWave));
-      if (item >= total) continue;
+      const int oUc = __shfl(s.Uc, o, kWave), oRc = __shfl(s.Rc, o, kWave);
+      const int ooff = __shfl(s.off, o, kWave);
+      const int u =
+          __shfl(s.u0, o, kWave) + item - (__shfl(incl, o, kWave) - __shfl(s.cnt, o, kWave));
+      if (item >= ib) continue;
       const bool open_l = u == 0, open_r = u == oUc - 1;
       const int64_t sl = 256 * (int64_t)u, sr = sl + 256;
       int32_t rlo = INT_MAX, rhi = INT_MIN;
@@ -795,13 +884,13 @@ __global__ __launch_bounds__(kBlock) void k_fp_raster(
         const int64_t Qx = wrap ? PX[0] : PX[k < 3 ? k + 1 : 0];
         const int64_t Qy = wrap ? PY[0] : PY[k < 3 ? k + 1 : 0];
         if (Px == Qx) continue;
-        const int64_t lo = min(Px, Qx), hi = max(Px, Qx);
-        if (!open_l && lo < sl && sl < hi) {
+        const int64_t lo2 = min(Px, Qx), hi2 = max(Px, Qx);
+        if (!open_l && lo2 < sl && sl < hi2) {
           const int32_t r = crossing_row(Px, Py, Qx, Qy, sl);
           rlo = min(rlo, r);
           rhi = max(rhi, r);
         }
-        if (!open_r && lo < sr && sr < hi) {
+        if (!open_r && lo2 < sr && sr < hi2) {
           const int32_t r = crossing_row(Px, Py, Qx, Qy, sr);
           rlo = min(rlo, r);
           rhi = max(rhi, r);
@@ -839,13 +928,20 @@ __global__ __launch_bounds__(kBlock) void k_fp_raster(
 hipError_t launch_footprint(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
                             const int32_t* cot, const fa_chart* charts, Marker& mk,
                             hipStream_t st) {
-  if (p.fp_cap > 0)
-    k_fp_clear<<<(unsigned)std::min<int64_t>(1024, (p.fp_cap + kBlock - 1) / kBlock), kBlock, 0,
-                 st>>>(w.fp_prof, w.state);
+  if (p.fp_cap > 0) {
+    // one wave per group of 64 entries, then the blocks that clear the profile
+    const unsigned cb = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>((T + kBlock - 1) / kBlock, 2048));
+    const unsigned clear = (unsigned)std::min<int64_t>(1024, (p.fp_cap + kBlock - 1) / kBlock);
+    k_fp_count<<<cb + clear, kBlock, 0, st>>>(w.vlist, idx, w.clip, cot, charts, w.fp_off,
+                                              w.fp_group, w.fp_prof, cb, p, w.state);
+  }
   mk(st);
-  if (p.fp_cap > 0 && T > 0)
+  if (p.fp_cap > 0 && T > 0) {
+    k_fp_scan<<<1, 1024, 0, st>>>(w.fp_group, w.state);
     k_fp_raster<<<visible_grid(T), kBlock, 0, st>>>(w.vlist, idx, w.clip, cot, charts, w.fp_off,
-                                                    w.fp_prof, p, w.state);
+                                                    w.fp_group, w.fp_prof, p, w.state);
+  }
   mk(st);
   return hipGetLastError();
 }
