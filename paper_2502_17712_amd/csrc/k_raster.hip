@@ -794,9 +794,10 @@ __global__ __launch_bounds__(1024) void k_fp_scan(unsigned long long* __restrict
 // walks forward; for each group it touches, its lanes set up the group's 64
 // entries again and the wave takes that group's items in its range 64 at a
 // time (owner found by a binary search over the inclusive column counts).
-// Neighbouring triangles share columns: when a group's columns span fewer
-// than kFpWin profile entries they are reduced in a per-wave LDS window and
-// flushed with one pair of global atomics per touched entry.
+// Neighbouring triangles share columns: when the columns of a wave's items
+// of a group span fewer than kFpWin profile entries they are reduced in a
+// per-wave LDS window and flushed with one pair of global atomics per
+// touched entry.
 constexpr int kFpWin = 1024;
 
 __global__ __launch_bounds__(kBlock) void k_fp_raster(
@@ -842,9 +843,13 @@ __global__ __launch_bounds__(kBlock) void k_fp_raster(
     const int ia = (int)(k0 > gfirst ? k0 - gfirst : 0ull);
     const int ib = (int)min<unsigned long long>((unsigned long long)gtot, k1 - gfirst);
     if (ia >= ib) continue;
-    // profile entries the group touches: [elo, ehi]
-    const int elo = wave_min<int>(s.cnt > 0 ? s.off + s.u0 : INT_MAX);
-    const int ehi = wave_max<int>(s.cnt > 0 ? s.off + s.u0 + s.cnt - 1 : INT_MIN);
+    // profile entries this wave's items of the group touch: [elo, ehi] (a
+    // lane's items are [incl - cnt, incl), its columns from u0 on)
+    const int st0 = incl - s.cnt;
+    const int ja = max(st0, ia), jb = min(incl, ib) - 1;
+    const bool mine = s.cnt > 0 && ja <= jb;
+    const int elo = wave_min<int>(mine ? s.off + s.u0 + (ja - st0) : INT_MAX);
+    const int ehi = wave_max<int>(mine ? s.off + s.u0 + (jb - st0) : INT_MIN);
     const bool use_win = ehi - elo < kFpWin;
     for (int w0 = ia; w0 < ib; w0 += kWave) {
       const int item = w0 + lane;
