@@ -67,6 +67,8 @@ def lib():
         L.oracle_pool_profile.argtypes = [P, P, i32, i32, i32, i32, i32, i32, i32, P, P]
         L.oracle_candidate_fp.argtypes = [P, P, P, P, P, i64, i32, P, P, P]
         L.oracle_reuse_flags.restype = i64
+        L.oracle_near_polygon.argtypes = [P, P]
+        L.oracle_near_polygon.restype = i32
         _lib = L
     return _lib
 
@@ -144,6 +146,15 @@ def triangle_boxes(clip_xyzw, indices, visible, side_clip=True):
     ne = np.empty(T, np.uint8)
     lib().oracle_triangle_boxes(_p(c), _p(idx), _p(vis), T, int(side_clip), _p(box), _p(ne))
     return box, ne
+
+
+def near_polygon(tri_clip):
+    """The triangle (3 x xyzw clip coordinates) clipped against the near plane
+    w + z >= 0 as O4 (ii), O10 and FP1 clip it: float32 [n, 4], n in 0, 3, 4."""
+    t = _c(tri_clip, np.float32).reshape(3, 4)
+    out = np.zeros((4, 4), np.float32)
+    n = lib().oracle_near_polygon(_p(t), _p(out))
+    return out[:n].copy()
 
 
 def chart_frames(box, nonempty, chart_of_tri, C, W, H, rate):

@@ -260,6 +260,20 @@ void oracle_triangle_boxes(const float* clip, const int32_t* idx, const uint8_t*
   }
 }
 
+// The polygon O4 (ii), O10 and FP1 use for a triangle that crosses the near
+// plane: the triangle (clip coordinates, 3 x xyzw) clipped against w + z >= 0
+// by clip_one_plane. Returns the vertex count (0, 3 or 4) and writes the
+// vertices to poly (4 x xyzw).
+int32_t oracle_near_polygon(const float* tri, float* poly) {
+  V4 c[3] = {load_clip(tri, 0), load_clip(tri, 1), load_clip(tri, 2)};
+  V4 p[4];
+  int n = clip_one_plane(c, 3, PN, p);
+  for (int k = 0; k < n; ++k) {
+    poly[4 * k] = p[k].x; poly[4 * k + 1] = p[k].y; poly[4 * k + 2] = p[k].z; poly[4 * k + 3] = p[k].w;
+  }
+  return n;
+}
+
 // ---------------------------------------------------------------------------
 // O5  chart frame and target size. The chart box is the union of its
 // triangles' boxes (all empty -> zero box); the viewport transform maps NDC

@@ -514,6 +514,75 @@ def city_frame(frame: int = 0, rate: float = 1.0, atlas_size: int = 4096,
                  atlas_size, rate, 3002, cam.eye, cam.near, 8)
 
 
+# --------------------------------------------------------------------------
+# near-plane frames: cameras close enough to the geometry that visible
+# triangles cross the near plane (the special case of the box step), some of
+# them with vertices behind the eye (w <= 0)
+# --------------------------------------------------------------------------
+def _grazing_dir(yaw, pitch):
+    return np.array([math.cos(pitch) * math.cos(yaw), math.cos(pitch) * math.sin(yaw),
+                     math.sin(pitch)])
+
+
+def grid_near_frame(seed: int, atlas_size: int = 1024, rate: float = 1.0) -> Frame:
+    """The 8192-triangle heightfield of grid_frame(seed) seen from a grazing
+    camera 0.05-0.15 above the surface with near = 0.4, so that tens of
+    visible triangles cross the near plane (with one or two vertices in front
+    of it)."""
+    pos, tris, yaw = scene_grid(seed)
+    rng = np.random.default_rng(10_000 + seed)
+    xy = rng.uniform(-0.6, 0.6, 2)
+    k = int(np.argmin(((pos[:, :2].astype(np.float64) - xy) ** 2).sum(1)))
+    eye = np.array([xy[0], xy[1], float(pos[k, 2]) + rng.uniform(0.05, 0.15)])
+    d = _grazing_dir(yaw, math.radians(rng.uniform(-25.0, 0.0)))
+    cam = make_camera(eye, eye + d, 1280, 720, 0.4, 100.0)
+    vis = visible_set(pos, tris, cam)
+    return Frame(f"gridnear/seed{seed}", pos, tris, vis, cam.view_proj, 1280, 720,
+                 atlas_size, rate, 1000 + seed, cam.eye, cam.near, 0)
+
+
+def scene_floor(seed: int):
+    """16x16-quad floor over [-4, 4]^2 (512 triangles of side 0.5) with
+    N(0, 0.05) height noise."""
+    rng = np.random.default_rng(seed)
+    pos, tris = grid_mesh(16, -4.0, 4.0)
+    pos[:, 2] = rng.normal(0, 0.05, pos.shape[0])
+    return pos.astype(np.float32), tris.astype(np.int32)
+
+
+def floor_near_frame(seed: int, atlas_size: int = 512, rate: float = 1.0) -> Frame:
+    """A coarse floor seen from 0.15 above it with near = 0.3: the large
+    triangles under the camera reach behind the eye (w <= 0) and cross the
+    near plane."""
+    pos, tris = scene_floor(6000)
+    rng = np.random.default_rng(6000 + seed)
+    eye = np.array([*rng.uniform(-1.0, 1.0, 2), 0.15])
+    d = _grazing_dir(rng.uniform(0, 2 * np.pi), math.radians(rng.uniform(-30.0, -5.0)))
+    cam = make_camera(eye, eye + d, 1280, 720, 0.3, 100.0)
+    vis = visible_set(pos, tris, cam)
+    return Frame(f"floornear/seed{seed}", pos, tris, vis, cam.view_proj, 1280, 720,
+                 atlas_size, rate, 6000, cam.eye, cam.near, 0)
+
+
+def city_near_frame(frame: int = 0, rate: float = 1.0, atlas_size: int = 4096,
+                    width: int = 3840, height: int = 2160, seed: int = 2) -> Frame:
+    """The ~2.24M-triangle scene from the orbit of city_frame, with the eye
+    lowered to 0.05 above the terrain: the terrain triangles around the eye
+    cross the near plane (0.1) and some reach behind it."""
+    pos, tris = city_scene()
+    c0 = city_camera(seed, frame, width, height)
+    rng = np.random.default_rng(seed)
+    xy = rng.uniform(-60, 60, 2)
+    yaw0 = rng.uniform(0, 2 * np.pi)
+    eye = np.array([xy[0], xy[1], float(terrain_height(xy[0:1], xy[1:2], 2)[0]) + 0.05])
+    assert np.allclose(eye[:2], c0.eye[:2])
+    d = _grazing_dir(yaw0 + 2 * np.pi * frame / 32, math.radians(-10.0))
+    cam = make_camera(eye, eye + d, width, height, 0.1, 1000.0)
+    vis = visible_set(pos, tris, cam, coarse_occlusion=True)
+    return Frame(f"citynear/s{seed}f{frame}", pos, tris, vis, cam.view_proj, width, height,
+                 atlas_size, rate, 3002, cam.eye, cam.near, 8)
+
+
 _RES = [(1280, 720), (1920, 1080), (2560, 1440), (3840, 2160)]
 
 

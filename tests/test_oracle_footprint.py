@@ -150,16 +150,23 @@ def _clip_half(poly, x0, keep_right):
     return out
 
 
-def _snapped_local(f, r, t):
+def _snapped_local(f, r, t, near=False):
     """Snapped chart-local polygon of triangle t (1/256 units), float32 chain
-    of the UV map before scale and gutter; None if it claims nothing."""
+    of the UV map before scale and gutter; None if it claims nothing. A
+    triangle crossing the near plane gives "near", or with near=True its
+    near-clipped polygon (the oracle's clip, pinned against exact clipping in
+    test_oracle_geometry)."""
     c = int(r["chart_of_tri"][t])
     if c < 0 or not r["nonempty"][t]:
         return None, c
     clip = r["clip"]
     P = [clip[int(v)] for v in f.indices[t]]
-    if any(p[3] + p[2] < 0 for p in P):
-        return "near", c
+    if any(np.float32(p[3] + p[2]) < 0 for p in P):
+        if not near:
+            return "near", c
+        P = list(oracle.near_polygon(np.array(P)))
+        if not all(p[3] > 0 for p in P):
+            return None, c
     x0 = np.float32(r["frame"][c, 0])
     y1 = np.float32(r["frame"][c, 3])
     tw = np.float32(r["target"][c, 0])
@@ -176,9 +183,15 @@ def _snapped_local(f, r, t):
     return out, c
 
 
-@pytest.mark.parametrize("seed", [2, 7])
-def test_fine_profile_exact(seed):
-    f = scenes.grid_frame(seed)
+def _near_case(k):
+    return [scenes.grid_near_frame(1), scenes.grid_near_frame(4, rate=0.5),
+            scenes.floor_near_frame(2)][k]
+
+
+@pytest.mark.parametrize("case", ["grid2", "grid7", "near0", "near1", "near2"])
+def test_fine_profile_exact(case):
+    near = case.startswith("near")
+    f = _near_case(int(case[4:])) if near else scenes.grid_frame(int(case[4:]))
     r = oracle.build_frame(f, want_occupancy=False)
     foff, ft, fb = oracle.fine_profiles(r["clip"], f.indices, r["nonempty"], r["chart_of_tri"],
                                         r["frame"], r["target"], r["oriented"], r["rotated"],
@@ -189,11 +202,14 @@ def test_fine_profile_exact(seed):
     assert np.array_equal(np.diff(foff), uc)
     ref_t = np.full(ft.shape, INT_MAX, np.int64)
     ref_b = np.full(fb.shape, -1, np.int64)
+    shapes = {3: 0, 4: 0}
     for t in np.nonzero(f.visible)[0]:
-        poly, c = _snapped_local(f, r, t)
+        poly, c = _snapped_local(f, r, t, near=near)
         assert poly != "near"      # the small scene never crosses the near plane
         if poly is None:
             continue
+        if near and any(r["clip"][int(v), 3] + r["clip"][int(v), 2] < 0 for v in f.indices[t]):
+            shapes[len(poly)] += 1
         poly = [(Fraction(x), Fraction(y)) for x, y in poly]
         xs = [p[0] for p in poly]
         u0 = min(uc[c] - 1, max(0, math.floor(min(xs) / 256)))
@@ -214,6 +230,8 @@ def test_fine_profile_exact(seed):
             ref_b[k] = max(ref_b[k], hi)
     assert np.array_equal(ft.astype(np.int64), ref_t)
     assert np.array_equal(fb.astype(np.int64), ref_b)
+    if near:   # near-clipped triangles and quads both took part
+        assert shapes[3] > 0 and shapes[4] > 0, shapes
     # every chart has some footprint
     for c in range(C):
         assert (fb[foff[c]:foff[c + 1]] >= 0).any()

@@ -226,3 +226,103 @@ def test_order_lexicographic():
         got = oracle.order(key)
         want = sorted(range(C), key=lambda c: (-int(key[c]), c))
         assert got.tolist() == want
+
+
+# ---------------------------------------------------------------------------
+# the near-plane special case (O4 ii; App. "Bounding Box Computation
+# Alternatives": a triangle that crosses the near plane is clipped there
+# before Blinn's divide)
+# ---------------------------------------------------------------------------
+def _exact_near_clip(T):
+    """Sutherland-Hodgman against w + z >= 0 in exact rationals on the float32
+    inputs (edges c0->c1, c1->c2, c2->c0; the intersection before the end
+    vertex)."""
+    from fractions import Fraction
+    P = [[Fraction(float(v)) for v in T[k]] for k in range(3)]
+    out = []
+    for i in range(3):
+        S, E = P[i], P[(i + 1) % 3]
+        dS, dE = S[3] + S[2], E[3] + E[2]
+        if (dS >= 0) != (dE >= 0):
+            t = dS / (dS - dE)
+            out.append([S[k] + t * (E[k] - S[k]) for k in range(4)])
+        if dE >= 0:
+            out.append(E)
+    return out
+
+
+def _near_crossers(rng, n):
+    tris = _random_clip_triangles(rng, n, 1.2)
+    dn = tris[:, :, 3] + tris[:, :, 2]
+    return tris[(dn.min(1) < 0) & (dn.max(1) >= 0)]
+
+
+def _frame_near_crossers(f):
+    clip = oracle.clip(f.positions, f.view_proj)
+    T = clip[f.indices]
+    dn = T[:, :, 3] + T[:, :, 2]
+    sel = f.visible.astype(bool) & (dn.min(1) < 0) & (dn.max(1) >= 0)
+    return T[sel]
+
+
+def test_near_polygon_exact():
+    # the near-clipped polygon equals exact clipping of the same float32
+    # vertices within the rounding of t and of one lerp per component, with
+    # the vertices in the same order; both shapes (quad: one vertex behind
+    # near, triangle: two behind) occur
+    rng = np.random.default_rng(11)
+    tris = np.concatenate([_near_crossers(rng, 3000)] +
+                          [_frame_near_crossers(f) for f in
+                           (scenes.grid_near_frame(1), scenes.floor_near_frame(2))])
+    eps = float(np.finfo(np.float32).eps)
+    counts = {3: 0, 4: 0}
+    for T in tris:
+        got = oracle.near_polygon(T)
+        want = _exact_near_clip(T)
+        assert got.shape[0] == len(want) and len(want) in (3, 4)
+        counts[len(want)] += 1
+        mag = float(np.abs(T).max())
+        for k in range(len(want)):
+            w = np.array([float(v) for v in want[k]])
+            assert np.abs(got[k].astype(np.float64) - w).max() <= 8 * eps * mag, (T, got, want)
+        # the clipped polygon lies on or in front of the near plane, up to rounding
+        assert ((got[:, 3].astype(np.float64) + got[:, 2]) >= -8 * eps * mag).all()
+    assert counts[3] > 40 and counts[4] > 100, counts
+
+
+def test_box_near_only_is_tight():
+    # a triangle that crosses the near plane and no other plane is clipped at
+    # near, so its box is the exact visible extent up to rounding (a wrong
+    # plane, a dropped intersection or a swapped end point would show here)
+    rng = np.random.default_rng(12)
+    tris = np.concatenate([_near_crossers(rng, 6000)] +
+                          [_frame_near_crossers(f) for f in
+                           (scenes.grid_near_frame(s) for s in range(4))])
+    box, ne = _boxes(tris)
+    checked = 0
+    for t in range(tris.shape[0]):
+        T64 = tris[t].astype(np.float64)
+        crossing = [i for i, d in enumerate(_PLANES) if min(d(T64[k]) for k in range(3)) < 0]
+        if crossing != [4]:
+            continue
+        E, minw = _exact_box(T64, with_minw=True)
+        assert ne[t] == 1 and E is not None
+        tol = 1e-6 + 64 * float(np.finfo(np.float32).eps) * float(np.abs(tris[t]).max()) / minw
+        assert np.allclose(box[t], E, atol=tol, rtol=0), (box[t], E)
+        checked += 1
+    assert checked > 100, checked
+
+
+def test_near_frames_have_near_crossers():
+    # the seeded near-plane frames hold visible triangles of both clipped
+    # shapes, and the coarse floor and the low city camera also hold visible
+    # triangles with a vertex behind the eye (w <= 0)
+    for f in (scenes.grid_near_frame(0), scenes.floor_near_frame(0)):
+        clip = oracle.clip(f.positions, f.view_proj)
+        dn = (clip[:, 3] + clip[:, 2])[f.indices]
+        vis = f.visible.astype(bool)
+        assert (vis & ((dn < 0).sum(1) == 1)).sum() >= 3
+        assert (vis & ((dn < 0).sum(1) == 2)).sum() >= 2
+    f = scenes.floor_near_frame(2)
+    clip = oracle.clip(f.positions, f.view_proj)
+    assert (f.visible.astype(bool) & (clip[f.indices, 3] <= 0).any(1)).sum() >= 1

@@ -145,3 +145,104 @@ def test_occupancy_owner_inside_box_and_count():
     assert (2 * r["y"][c].astype(np.int64) * omega <= (2 * ty + 1) * L).all()
     assert ((2 * ty + 1) * L < 2 * (r["y"][c] + r["b"][c]).astype(np.int64) * omega).all()
     assert r["occupied"] == int((occ >= 0).sum())
+
+
+# ---------------------------------------------------------------------------
+# the near-plane case of the occupancy (O10): a triangle that crosses the
+# near plane claims the texels of its near-clipped polygon (a triangle or a
+# quad), fanned from its first vertex
+# ---------------------------------------------------------------------------
+def _exact_poly(T):
+    """Float64 polygon of a triangle's visible part in front of the near
+    plane, clipped in exact rationals (None when nothing is in front)."""
+    from fractions import Fraction
+    dn = T[:, 3].astype(np.float64) + T[:, 2]
+    if not (dn < 0).any():
+        return T.astype(np.float64), False
+    P = [[Fraction(float(v)) for v in T[k]] for k in range(3)]
+    out = []
+    for i in range(3):
+        S, E = P[i], P[(i + 1) % 3]
+        dS, dE = S[3] + S[2], E[3] + E[2]
+        if (dS >= 0) != (dE >= 0):
+            t = dS / (dS - dE)
+            out.append([S[k] + t * (E[k] - S[k]) for k in range(4)])
+        if dE >= 0:
+            out.append(E)
+    return np.array([[float(v) for v in p] for p in out]), True
+
+
+def _map64(P, r, c, f, s, q, g=1):
+    # the chart's map (O9) evaluated in float64 on the float32 chart records
+    x0, y1 = float(r["frame"][c, 0]), float(r["frame"][c, 3])
+    tw = float(r["target"][c, 0])
+    nx, ny = P[:, 0] / P[:, 3], P[:, 1] / P[:, 3]
+    px = (nx - x0) * (0.5 * f.width) * f.rate
+    py = (y1 - ny) * (0.5 * f.height) * f.rate
+    lx, ly = (py, tw - px) if r["rotated"][c] else (px, py)
+    return np.stack([(r["x"][c] + g + lx * s) * q, (r["y"][c] + g + ly * s) * q], 1)
+
+
+@pytest.mark.parametrize("maker", [lambda: scenes.grid_near_frame(1, atlas_size=512),
+                                   lambda: scenes.grid_near_frame(4, atlas_size=512, rate=0.5),
+                                   lambda: scenes.floor_near_frame(2, atlas_size=512)])
+def test_occupancy_near_exact(maker):
+    f = maker()
+    r = oracle.build_frame(f)
+    assert r["status"] == 0
+    occ, omega, L = r["occupancy"], f.atlas_size, r["L"]
+    s = float(np.float32(r["jstar"]) / np.float32(64))
+    q = float(np.float32(omega) / np.float32(L))
+    clip = r["clip"]
+    want = np.full((omega, omega), -1, np.int64)
+    ambiguous = np.zeros((omega, omega), bool)
+    near_claims = {3: 0, 4: 0}
+    tx = np.arange(omega)
+    for t in np.nonzero(r["nonempty"])[0]:
+        c = int(r["chart_of_tri"][t])
+        P, crossed = _exact_poly(clip[f.indices[t]])
+        if P.shape[0] < 3 or (P[:, 3] <= 0).any():
+            continue
+        Q = _map64(P, r, c, f, s, q)
+        n = Q.shape[0]
+        x0, x1 = int(np.floor(Q[:, 0].min() - 1)), int(np.ceil(Q[:, 0].max() + 1))
+        y0, y1 = int(np.floor(Q[:, 1].min() - 1)), int(np.ceil(Q[:, 1].max() + 1))
+        xs = tx[max(0, x0):max(0, min(omega, x1))]
+        ys = tx[max(0, y0):max(0, min(omega, y1))]
+        if xs.size == 0 or ys.size == 0:
+            continue
+        X, Y = np.meshgrid(xs + 0.5, ys + 0.5)
+        e = [(Q[(k + 1) % n, 0] - Q[k, 0]) * (Y - Q[k, 1]) - (Q[(k + 1) % n, 1] - Q[k, 1]) * (X - Q[k, 0])
+             for k in range(n)]
+        inside = np.logical_and.reduce([ek >= 0 for ek in e]) | np.logical_and.reduce([ek <= 0 for ek in e])
+        d = np.minimum.reduce([_edge_dist(X, Y, Q[k, 0], Q[k, 1], Q[(k + 1) % n, 0], Q[(k + 1) % n, 1])
+                               for k in range(n)])
+        bx, by, ba, bb = r["x"][c], r["y"][c], r["a"][c], r["b"][c]
+        inbox = ((2 * bx * omega <= (2 * X) * L) & ((2 * X) * L < 2 * (bx + ba) * omega) &
+                 (2 * by * omega <= (2 * Y) * L) & ((2 * Y) * L < 2 * (by + bb) * omega))
+        sl = (slice(ys[0], ys[-1] + 1), slice(xs[0], xs[-1] + 1))
+        claim = inside & inbox & (d >= 4.0 / 256)
+        want[sl][inside & inbox] = c
+        ambiguous[sl] |= d < 4.0 / 256
+        if crossed:
+            near_claims[n] += int(claim.sum())
+    agree = (occ == want) | ambiguous
+    assert agree.all(), int((~agree).sum())
+    # the near branch was taken: clipped triangles and clipped quads claim texels
+    assert near_claims[3] > 0 and near_claims[4] > 0, near_claims
+
+
+def test_uv_nan_behind_eye():
+    # a vertex of a visible triangle with w <= 0 has no image: its UV is NaN,
+    # while the triangle's near-clipped part still claims texels
+    f = scenes.floor_near_frame(2, atlas_size=512)
+    r = oracle.build_frame(f)
+    clip = r["clip"]
+    behind = (r["chart_of_vert"] >= 0) & (clip[:, 3] <= 0)
+    assert behind.sum() >= 1
+    assert np.isnan(r["uv"][behind]).all()
+    front = (r["chart_of_vert"] >= 0) & (clip[:, 3] > 0)
+    assert not np.isnan(r["uv"][front]).any()
+    tris_behind = np.nonzero(f.visible.astype(bool) & (clip[f.indices, 3] <= 0).any(1))[0]
+    claimed = set(np.unique(r["occupancy"][r["occupancy"] >= 0]).tolist())
+    assert any(int(r["chart_of_tri"][t]) in claimed for t in tris_behind)
