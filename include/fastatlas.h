@@ -57,6 +57,17 @@ enum {
      otherwise); the default also tries the side and far planes and keeps the
      smallest box (Sec. bounding boxes). */
   FA_FLAG_NO_SIDE_CLIP = 1u << 0,
+  /* Edge-connected charts (Sec. "Chart Computation": charts grow across
+     shared edges): visible triangles are joined across shared undirected
+     edges only, without the vertex merge of Appendix "GPU Union Find", so a
+     vertex can belong to several charts. Then uv is per corner: [T][3][2],
+     corner k of triangle t at uv[(3t + k) * 2], mapped through the chart of
+     t (NaN for invisible triangles and corners with w <= 0), and
+     chart_of_vert[v] is the smallest chart index among the visible
+     triangles using v. The union-find hook-mode knob chooses between a
+     global edge hook (1) and LDS tiles of shared edges plus the edges
+     between tiles (any other value). */
+  FA_FLAG_EDGE_ONLY_CHARTS = 1u << 1,
   /* Footprint-aware push (Sec. "Box Packing" generalized to non-rectangular
      footprints): each chart's footprint is measured once per frame as a
      full-scale per-column profile (top and bottom row of every unit column of
@@ -141,7 +152,8 @@ typedef struct fa_atlas_out {
   int32_t* chart_of_vert; /* [V] chart index, -1 if unused; may be NULL         */
   float* uv;              /* [V][2] atlas texels, origin top-left, v down; NaN
                              when the vertex is unmapped or has w <= 0; may be
-                             NULL                                                */
+                             NULL. [T][3][2] per corner with
+                             FA_FLAG_EDGE_ONLY_CHARTS                         */
   fa_chart* charts;       /* [max_charts]                                       */
   int32_t* occupancy;     /* [omega][omega] owning chart or -1; may be NULL      */
   fa_atlas_meta* meta;    /* [1]                                                */

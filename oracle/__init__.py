@@ -67,6 +67,10 @@ def lib():
         L.oracle_pool_profile.argtypes = [P, P, i32, i32, i32, i32, i32, i32, i32, P, P]
         L.oracle_candidate_fp.argtypes = [P, P, P, P, P, i64, i32, P, P, P]
         L.oracle_reuse_flags.restype = i64
+        L.oracle_charts_edge.argtypes = [P, i64, i64, P, P, P, P]
+        L.oracle_charts_edge.restype = i64
+        L.oracle_uv_corners.argtypes = [P, P, i64, P, P, P, P, P, P, i32, i32, f32, i32, i32,
+                                        i32, i64, i32, P]
         L.oracle_near_polygon.argtypes = [P, P]
         L.oracle_near_polygon.restype = i32
         _lib = L
@@ -126,14 +130,17 @@ def adjacency(indices):
     return out
 
 
-def charts(indices, num_vertices, visible):
+def charts(indices, num_vertices, visible, edge_only=False):
+    """O3 charts (shared vertices), or with edge_only the O3' variant (shared
+    edges only). Returns (chart_of_tri, chart_of_vert, roots)."""
     idx = _c(indices, np.int32)
     vis = _c(visible, np.uint8)
     T = idx.shape[0]
     cot = np.empty(T, np.int32)
     cov = np.empty(num_vertices, np.int32)
     roots = np.empty(max(T, 1), np.int32)
-    C = lib().oracle_charts(_p(idx), T, num_vertices, _p(vis), _p(cot), _p(cov), _p(roots))
+    fn = lib().oracle_charts_edge if edge_only else lib().oracle_charts
+    C = fn(_p(idx), T, num_vertices, _p(vis), _p(cot), _p(cov), _p(roots))
     return cot, cov, roots[:C].copy()
 
 
@@ -269,14 +276,15 @@ def select(cand_table):
 # ---------------------------------------------------------------------------
 def build_atlas(positions, indices, visible, view_proj, width, height, atlas_size, rate,
                 J=64, gutter=1, min_box=2, side_clip=True, want_occupancy=True,
-                want_adjacency=False, low_shift=0, footprint=False):
+                want_adjacency=False, low_shift=0, footprint=False, edge_only=False):
     """Run every step on one frame. Returns a dict of all intermediate and
     final results (per-chart arrays are indexed by chart index). low_shift = k
     > 0 adds the occupancy of the same packing scaled into an atlas of side
     omega / 2^k (App. "Depth-of-Field" and "Foveated Rendering": the low
     resolution atlas reuses the packing, coordinates scaled per axis).
     footprint=True packs with the footprint-aware push (per-column profiles
-    of each chart's footprint instead of its full box)."""
+    of each chart's footprint instead of its full box). edge_only=True takes
+    the edge-connected charts (O3') and returns per-corner UVs [T][3][2]."""
     pos = _c(positions, np.float32)
     idx = _c(indices, np.int32)
     vis = _c(visible, np.uint8)
@@ -286,7 +294,7 @@ def build_atlas(positions, indices, visible, view_proj, width, height, atlas_siz
     r["clip"] = clip(pos, view_proj)
     if want_adjacency:
         r["nbr"] = adjacency(idx)
-    cot, cov, roots = charts(idx, V, vis)
+    cot, cov, roots = charts(idx, V, vis, edge_only=edge_only)
     C = roots.shape[0]
     r.update(chart_of_tri=cot, chart_of_vert=cov, roots=roots, num_charts=C)
     box, ne = triangle_boxes(r["clip"], idx, vis, side_clip)
@@ -331,10 +339,16 @@ def build_atlas(positions, indices, visible, view_proj, width, height, atlas_siz
     q = np.float32(omega) / np.float32(L)
     r.update(status=STATUS_OK, L=L, H=w["H"], s_eff=float(np.float32(s * q)), x=px, y=py, a=pa,
              b=pb)
-    uv = np.empty((V, 2), np.float32)
     clip_c = r["clip"]
-    lib().oracle_uv(_p(clip_c), V, _p(cov), _p(frame), _p(target), _p(rot), _p(px), _p(py), W, H,
-                    float(rate), js, J, omega, L, gutter, _p(uv))
+    if edge_only:
+        uv = np.empty((T, 3, 2), np.float32)
+        lib().oracle_uv_corners(_p(clip_c), _p(idx), T, _p(cot), _p(frame), _p(target), _p(rot),
+                                _p(px), _p(py), W, H, float(rate), js, J, omega, L, gutter,
+                                _p(uv))
+    else:
+        uv = np.empty((V, 2), np.float32)
+        lib().oracle_uv(_p(clip_c), V, _p(cov), _p(frame), _p(target), _p(rot), _p(px), _p(py),
+                        W, H, float(rate), js, J, omega, L, gutter, _p(uv))
     r["uv"] = uv
     conflicts = np.zeros(1, np.int64)
     if want_occupancy:

@@ -241,6 +241,69 @@ int64_t oracle_charts(const int32_t* idx, int64_t T, int64_t V, const uint8_t* v
 }
 
 // ---------------------------------------------------------------------------
+// O3' edge-connected charts (the variant that stops after the first joining
+// step of Sec. "Chart Computation": visible triangles are joined across shared
+// edges only, without the vertex merge of the appendix). Two triangles share
+// an undirected edge iff they share two distinct vertex indices. Components
+// are found by breadth-first search over an edge -> triangles table; labels
+// are component minima and chart indices ascend with the label, as in O3. A
+// vertex may now lie in several charts, so its UV is per corner (O9');
+// chart_of_vert[v] is the smallest chart index among the visible triangles
+// using v (-1 if none).
+// ---------------------------------------------------------------------------
+int64_t oracle_charts_edge(const int32_t* idx, int64_t T, int64_t V, const uint8_t* vis,
+                           int32_t* chart_of_tri, int32_t* chart_of_vert, int32_t* roots) {
+  std::vector<std::pair<uint64_t, int32_t>> edges;  // (undirected edge key, triangle)
+  for (int64_t t = 0; t < T; ++t) {
+    if (!vis[t]) continue;
+    for (int e = 0; e < 3; ++e) {
+      uint32_t a = (uint32_t)idx[3 * t + e], b = (uint32_t)idx[3 * t + (e + 1) % 3];
+      if (a == b) continue;
+      uint64_t key = ((uint64_t)std::min(a, b) << 32) | (uint64_t)std::max(a, b);
+      edges.push_back({key, (int32_t)t});
+    }
+  }
+  std::sort(edges.begin(), edges.end());
+  // triangles of one edge are a contiguous run; each triangle lists the runs
+  // of its edges
+  std::vector<std::vector<std::pair<size_t, size_t>>> runs_of(T);
+  for (size_t i = 0; i < edges.size();) {
+    size_t j = i;
+    while (j < edges.size() && edges[j].first == edges[i].first) ++j;
+    for (size_t k = i; k < j; ++k) runs_of[edges[k].second].push_back({i, j});
+    i = j;
+  }
+  for (int64_t t = 0; t < T; ++t) chart_of_tri[t] = -1;
+  for (int64_t v = 0; v < V; ++v) chart_of_vert[v] = -1;
+  int64_t C = 0;
+  std::queue<int64_t> q;
+  for (int64_t s = 0; s < T; ++s) {
+    if (!vis[s] || chart_of_tri[s] >= 0) continue;
+    roots[C] = (int32_t)s;
+    chart_of_tri[s] = (int32_t)C;
+    q.push(s);
+    while (!q.empty()) {
+      int64_t t = q.front();
+      q.pop();
+      for (const auto& r : runs_of[t])
+        for (size_t k = r.first; k < r.second; ++k) {
+          int32_t u = edges[k].second;
+          if (chart_of_tri[u] < 0) { chart_of_tri[u] = (int32_t)C; q.push(u); }
+        }
+    }
+    ++C;
+  }
+  for (int64_t t = 0; t < T; ++t) {
+    if (chart_of_tri[t] < 0) continue;
+    for (int e = 0; e < 3; ++e) {
+      int32_t& cv = chart_of_vert[idx[3 * t + e]];
+      if (cv < 0 || chart_of_tri[t] < cv) cv = chart_of_tri[t];
+    }
+  }
+  return C;
+}
+
+// ---------------------------------------------------------------------------
 // O4  per-triangle boxes (Sec. bounding boxes; Appendix "Bounding Box
 // Computation Alternatives"). box[t] = (x0, y0, x1, y1) in NDC; nonempty[t]=0
 // for invisible triangles and triangles entirely outside one clip plane.
@@ -460,6 +523,28 @@ void oracle_uv(const float* clip, int64_t V, const int32_t* chart_of_vert, const
     if (c < 0 || !(p.w > 0.0f)) { uv[2 * v] = uv[2 * v + 1] = NAN; continue; }
     ChartMap cm = chart_map(frame, target, rotated, place_x, place_y, c, W, H, rate, s, q, gutter);
     map_point(cm, p.x, p.y, p.w, &uv[2 * v], &uv[2 * v + 1]);
+  }
+}
+
+// O9' per-corner UVs (edge-connected charts): corner k of triangle t is vertex
+// idx[3t+k] mapped through the chart of t, the same map as O9; NaN for
+// invisible triangles and corners with w <= 0. uv is [T][3][2].
+void oracle_uv_corners(const float* clip, const int32_t* idx, int64_t T,
+                       const int32_t* chart_of_tri, const float* frame, const float* target,
+                       const int32_t* rotated, const int32_t* place_x, const int32_t* place_y,
+                       int32_t W, int32_t H, float rate, int32_t jstar, int32_t J, int32_t omega,
+                       int64_t L, int32_t gutter, float* uv) {
+  float s = (float)jstar / (float)J;
+  float q = (float)omega / (float)L;
+  for (int64_t t = 0; t < T; ++t) {
+    int32_t c = chart_of_tri[t];
+    for (int k = 0; k < 3; ++k) {
+      float* o = uv + 2 * (3 * t + k);
+      V4 p = load_clip(clip, idx[3 * t + k]);
+      if (c < 0 || !(p.w > 0.0f)) { o[0] = o[1] = NAN; continue; }
+      ChartMap cm = chart_map(frame, target, rotated, place_x, place_y, c, W, H, rate, s, q, gutter);
+      map_point(cm, p.x, p.y, p.w, &o[0], &o[1]);
+    }
   }
 }
 

@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libfastatlas.so")
 FA_OK, FA_ERR_INVALID_ARG, FA_ERR_OUT_OF_MEMORY, FA_ERR_CAPACITY = 0, 1, 2, 3
 FA_ERR_NOFIT, FA_ERR_DEVICE, FA_ERR_UNSUPPORTED = 4, 5, 6
 FA_FLAG_NO_SIDE_CLIP = 1
+FA_FLAG_EDGE_ONLY_CHARTS = 2
 FA_FLAG_FOOTPRINT_PUSH = 4
 FA_TUNE_PACK_BLOCK, FA_TUNE_OCC_SMALL_TEXELS, FA_TUNE_UF_LINK_INIT, FA_TUNE_BATCH_GRAPH = 1, 2, 3, 4
 FA_TUNE_UF_EDGE_HOOKS, FA_TUNE_OCC_LANE_TEXELS, FA_TUNE_UF_TILE = 5, 6, 7
@@ -196,10 +197,12 @@ class AtlasOutputs:
     """Device output buffers of one view."""
 
     def __init__(self, T, V, max_charts, atlas_size, J, uv=True, occupancy=True,
-                 candidates=True, device="cuda"):
+                 candidates=True, device="cuda", uv_corners=False):
         self.chart_of_tri = torch.empty(T, dtype=torch.int32, device=device)
         self.chart_of_vert = torch.empty(V, dtype=torch.int32, device=device)
-        self.uv = torch.empty((V, 2), dtype=torch.float32, device=device) if uv else None
+        # per vertex [V, 2], or per corner [T, 3, 2] for edge-connected charts
+        uv_shape = (T, 3, 2) if uv_corners else (V, 2)
+        self.uv = torch.empty(uv_shape, dtype=torch.float32, device=device) if uv else None
         self.charts = torch.zeros((max_charts, 16), dtype=torch.int32, device=device)
         self.occupancy = (torch.empty((atlas_size, atlas_size), dtype=torch.int32, device=device)
                           if occupancy else None)
@@ -257,7 +260,8 @@ class Context:
 
     def outputs(self, mesh: Mesh, atlas_size, uv=True, occupancy=True, candidates=True):
         return AtlasOutputs(mesh.num_triangles, mesh.num_vertices, self.cfg.max_charts, atlas_size,
-                            self.cfg.num_scales, uv, occupancy, candidates)
+                            self.cfg.num_scales, uv, occupancy, candidates,
+                            uv_corners=bool(self.cfg.flags & FA_FLAG_EDGE_ONLY_CHARTS))
 
     def adjacency(self, mesh: Mesh, stream=None):
         nbr = torch.empty((mesh.num_triangles, 3), dtype=torch.int32, device="cuda")

@@ -248,6 +248,10 @@ hipError_t launch_select_place(const FrameParams& p, const Work& w, fa_chart* ch
                                int32_t* cand_out, hipStream_t st);
 hipError_t launch_uv(const int64_t V, const FrameParams& p, const Work& w, const int32_t* cov,
                      const fa_chart* charts, float* uv, hipStream_t st);
+// per-corner UVs [T][3][2] of edge-connected charts
+hipError_t launch_uv_corners(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
+                             const int32_t* cot, const fa_chart* charts, float* uv,
+                             hipStream_t st);
 // count: also count the occupied texels for the frame record (the frame's
 // own atlas; a scaled copy is drawn without).
 hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,

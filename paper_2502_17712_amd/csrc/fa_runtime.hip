@@ -235,6 +235,16 @@ void fa_destroy(fa_ctx* ctx) {
   delete ctx;
 }
 
+// The cached batch graph bakes in the resident adjacency of its scene: drop it
+// whenever a scene's adjacency is freed.
+static void drop_graph(fa_ctx* ctx) {
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  ctx->graph_exec = nullptr;
+  ctx->graph = nullptr;
+  ctx->graph_sig.clear();
+}
+
 static int get_scene(fa_ctx* ctx, const fa_mesh* mesh, hipStream_t st, Scene** out) {
   auto it = ctx->scenes.find(mesh->scene_key);
   if (it != ctx->scenes.end() && it->second.T == mesh->num_triangles &&
@@ -244,6 +254,7 @@ static int get_scene(fa_ctx* ctx, const fa_mesh* mesh, hipStream_t st, Scene** o
   }
   if (it != ctx->scenes.end()) {
     (void)hipStreamSynchronize(st);
+    drop_graph(ctx);
     (void)hipFree(it->second.nbr);
     ctx->scenes.erase(it);
   }
@@ -397,6 +408,7 @@ int fa_scene_evict(fa_ctx* ctx, uint64_t scene_key) {
   if (it == ctx->scenes.end()) return FA_ERR_INVALID_ARG;
   (void)hipSetDevice(ctx->cfg.device);
   (void)hipDeviceSynchronize();
+  drop_graph(ctx);
   (void)hipFree(it->second.nbr);
   ctx->scenes.erase(it);
   return FA_OK;
@@ -444,8 +456,12 @@ static int run_frame(fa_ctx* ctx, const Work& w, const fa_mesh* mesh, Scene* sc,
   Marker mk;
   if (ctx->timing) { mk.ev = ctx->ev; mk.cap = kStages + 1; }
   mk(st);
+  // start links: the LDS tile kernels write every start themselves (edge-only
+  // charts use them unless the global edge hook is chosen)
+  const bool tiles_start = (p.flags & FA_FLAG_EDGE_ONLY_CHARTS) ? p.edge_hooks != 1
+                                                                : p.edge_hooks >= 2;
   ok(launch_prologue(mesh->positions, V, visible, sc->nbr, T, p, w, cov, out->chart_of_tri,
-                     p.edge_hooks >= 2 ? 0 : (ctx->uf_link_init ? 2 : 1), mk, st));
+                     tiles_start ? 0 : (ctx->uf_link_init ? 2 : 1), mk, st));
   ok(launch_charts(visible, mesh->indices, sc->nbr, T, p, w, out->chart_of_tri, cov, out->charts,
                    mk, st));
   ok(launch_order(p, w, out->charts, 1, st));
@@ -455,7 +471,12 @@ static int run_frame(fa_ctx* ctx, const Work& w, const fa_mesh* mesh, Scene* sc,
   mk(st);
   ok(launch_select_place(p, w, out->charts, out->candidates, st));
   mk(st);
-  if (out->uv) ok(launch_uv(V, p, w, cov, out->charts, out->uv, st));
+  if (out->uv) {
+    if (p.flags & FA_FLAG_EDGE_ONLY_CHARTS)
+      ok(launch_uv_corners(mesh->indices, T, p, w, out->chart_of_tri, out->charts, out->uv, st));
+    else
+      ok(launch_uv(V, p, w, cov, out->charts, out->uv, st));
+  }
   mk(st);
   if (out->occupancy)
     ok(launch_occupancy(mesh->indices, T, p, w, out->chart_of_tri, out->charts, out->occupancy,
@@ -567,15 +588,16 @@ int fa_build_atlas_batch(fa_ctx* ctx, const fa_mesh* mesh, int32_t n, const fa_v
     ctx->timing = timing;
     return rc;
   }
+  // everything the captured launches bake in: the mesh and view descriptors,
+  // the scene's resident adjacency and every knob that picks kernels
   std::string sig(reinterpret_cast<const char*>(mesh), sizeof(fa_mesh));
   sig.append(reinterpret_cast<const char*>(views), sizeof(fa_view) * (size_t)n);
-  sig.append(reinterpret_cast<const char*>(&ctx->pack_block), sizeof(int) * 6);  // every knob
+  const int64_t knobs[8] = {(int64_t)(intptr_t)sc->nbr, ctx->pack_block, ctx->small_texels,
+                            ctx->lane_texels,          ctx->uf_link_init, ctx->uf_edge_hooks,
+                            ctx->uf_tile,              (int64_t)ctx->cfg.flags};
+  sig.append(reinterpret_cast<const char*>(knobs), sizeof(knobs));
   if (!ctx->graph_exec || sig != ctx->graph_sig) {
-    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
-    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
-    ctx->graph_exec = nullptr;
-    ctx->graph = nullptr;
-    ctx->graph_sig.clear();
+    drop_graph(ctx);
     if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       ctx->timing = timing;
       return FA_ERR_DEVICE;

@@ -703,9 +703,17 @@ __global__ __launch_bounds__(kBlock) void k_gather_boxes(
     float4 box = make_float4(0.f, 0.f, 0.f, 0.f);
     if (valid) {
       cot[tv[0]] = c;
-      cov[vi[0][0]] = c;
-      cov[vi[0][1]] = c;
-      cov[vi[0][2]] = c;
+      if (flags & FA_FLAG_EDGE_ONLY_CHARTS) {
+        // a vertex may touch several edge-connected charts: keep the smallest
+        // (chart_of_vert starts at -1, the largest unsigned value)
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+          atomicMin(reinterpret_cast<uint32_t*>(&cov[vi[0][e]]), (uint32_t)c);
+      } else {
+        cov[vi[0][0]] = c;
+        cov[vi[0][1]] = c;
+        cov[vi[0][2]] = c;
+      }
       has = triangle_ndc_box(q[0][0], q[0][1], q[0][2], !(flags & FA_FLAG_NO_SIDE_CLIP), box);
     }
 #pragma unroll
@@ -790,7 +798,28 @@ hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* 
                          fa_chart* charts, Marker& mk, hipStream_t st) {
   const unsigned g = visible_grid(T);
   const unsigned vt = std::max(1u, grid_for(T, kTriTile));
-  if (T > 0) {
+  if (T > 0 && (p.flags & FA_FLAG_EDGE_ONLY_CHARTS)) {
+    // edge-connected charts: shared edges only, no vertex passes
+    if (p.edge_hooks == 1) {
+      k_uf_hook<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, 0, w.state);
+    } else {
+      const int tile = p.uf_tile;
+      if (tile == 8192)
+        k_uf_local<8192, 1024><<<std::max(1u, grid_for(T, 8192)), 1024, 0, st>>>(
+            vis, nbr, w.vlist, w.parent, nullptr, w.vmin, w.state);
+      else if (tile == 4096)
+        k_uf_local<4096, 1024><<<std::max(1u, grid_for(T, 4096)), 1024, 0, st>>>(
+            vis, nbr, w.vlist, w.parent, nullptr, w.vmin, w.state);
+      else
+        k_uf_local<2048, 512><<<std::max(1u, grid_for(T, 2048)), 512, 0, st>>>(
+            vis, nbr, w.vlist, w.parent, nullptr, w.vmin, w.state);
+      k_uf_cross<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, tile, w.state);
+    }
+    mk(st);
+    mk(st);
+    mk(st);
+    k_uf_flatten_count<<<vt, kBlock, 0, st>>>(w.vlist, w.parent, w.tile_count, w.state);
+  } else if (T > 0) {
     if (p.edge_hooks == 1) {
       k_uf_hook<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, 0, w.state);
     } else if (p.edge_hooks == 5) {

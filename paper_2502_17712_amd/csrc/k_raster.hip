@@ -63,6 +63,31 @@ __global__ void k_uv(int64_t V, FrameParams p, const float4* __restrict__ clip,
   uv[v] = r;
 }
 
+// Per-corner UVs of edge-connected charts: corner k of triangle t is its
+// vertex mapped through the chart of t (a vertex on a seam between charts
+// gets one UV per chart). One thread per triangle writes its 24 bytes.
+__global__ void k_uv_corners(int64_t T, FrameParams p, const int32_t* __restrict__ idx,
+                             const float4* __restrict__ clip, const int32_t* __restrict__ cot,
+                             const fa_chart* __restrict__ charts, float2* __restrict__ uv,
+                             const FrameState* __restrict__ stp) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const FrameState st = *stp;
+  const int c = st.status == FA_OK ? cot[t] : -1;
+  const float nan = __builtin_nanf("");
+  if (c < 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) uv[3 * t + k] = make_float2(nan, nan);
+    return;
+  }
+  const ChartXform m = chart_xform(charts[c], p, st);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float4 q = clip[idx[3 * t + k]];
+    uv[3 * t + k] = q.w > 0.0f ? to_atlas(m, q.x, q.y, q.w) : make_float2(nan, nan);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // occupancy
 // ---------------------------------------------------------------------------
@@ -577,6 +602,15 @@ hipError_t launch_uv(const int64_t V, const FrameParams& p, const Work& w, const
   if (V > 0)
     k_uv<<<(unsigned)((V + kBlock - 1) / kBlock), kBlock, 0, st>>>(
         V, p, w.clip, cov, charts, reinterpret_cast<float2*>(uv), w.state);
+  return hipGetLastError();
+}
+
+hipError_t launch_uv_corners(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
+                             const int32_t* cot, const fa_chart* charts, float* uv,
+                             hipStream_t st) {
+  if (T > 0)
+    k_uv_corners<<<(unsigned)((T + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        T, p, idx, w.clip, cot, charts, reinterpret_cast<float2*>(uv), w.state);
   return hipGetLastError();
 }
 

@@ -8,7 +8,8 @@ context (its own scratch and resident scene adjacency) bound to its own HIP
 stream. A request is admitted as soon as it has arrived, a slot is free and
 its output memory fits in the HBM budget; admitted requests run concurrently
 on the device, and a request that arrives while others run is admitted the
-moment a slot and memory free up. Completion is detected by polling an event
+moment a slot and memory free up. A request reserves its outputs plus its
+frame's working set (reservation_bytes) until it completes. Completion is detected by polling an event
 per request; latency = completion - arrival on the host clock.
 
 Every request's results are exactly those of the same request run alone: the
@@ -57,8 +58,17 @@ class Result:
 
 
 def output_bytes(T, V, max_charts, atlas_size, J):
-    """Device bytes one request's outputs occupy (what admission reserves)."""
+    """Device bytes one request's outputs occupy."""
     return T * 4 + V * 4 + V * 8 + max_charts * 64 + atlas_size * atlas_size * 4 + 64 + J * 16
+
+
+def reservation_bytes(T, V, max_charts, atlas_size, J):
+    """What admission reserves for one request: its outputs plus the frame's
+    working set in the slot's scratch, T (9 B: chart, parent, visibility) +
+    V (32 B: clip position, UV, vertex chart, vertex minimum) + max_charts
+    (64 B record + 16 B per candidate) + 4 omega^2 (occupancy) + 1 MiB."""
+    return (9 * T + 32 * V + max_charts * (64 + 16 * J) + 4 * atlas_size * atlas_size
+            + (1 << 20))
 
 
 class Server:
@@ -86,7 +96,8 @@ class Server:
 
     def request_bytes(self, r: Request) -> int:
         m = self.meshes[r.scene]
-        return output_bytes(m.num_triangles, m.num_vertices, self.max_charts, r.atlas_size, self.J)
+        return reservation_bytes(m.num_triangles, m.num_vertices, self.max_charts, r.atlas_size,
+                                 self.J)
 
     def run(self, requests, keep_outputs=False, clock=time.perf_counter, spin_sleep=0.0):
         """Serve `requests` (arrival times relative to the start). Returns the

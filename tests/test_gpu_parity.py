@@ -106,7 +106,7 @@ def compare(g, r, occupancy=True):
 
 
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("seed", list(range(0, 64, 4)))
+@pytest.mark.parametrize("seed", list(range(64)))
 def test_grid_frames(seed):
     f = scenes.grid_frame(seed)
     g = run_gpu(f, ctx_for())
@@ -121,11 +121,13 @@ def test_grid_variants(J, gutter, omega, rate):
     compare(g, oracle.build_frame(f, J=J, gutter=gutter))
 
 
-@pytest.mark.parametrize("frame", [0, 17, 60, 119])
-def test_orbit_frames(frame):
-    f = scenes.orbit_frame(frame)
-    g = run_gpu(f, ctx_for())
-    compare(g, oracle.build_frame(f))
+@pytest.mark.parametrize("first", list(range(0, 120, 8)))
+def test_orbit_frames(first):
+    # all 120 frames of the orbit, eight per test
+    for frame in range(first, first + 8):
+        f = scenes.orbit_frame(frame)
+        g = run_gpu(f, ctx_for())
+        compare(g, oracle.build_frame(f))
 
 
 def test_orbit_no_side_clip():
@@ -134,9 +136,10 @@ def test_orbit_no_side_clip():
     compare(g, oracle.build_frame(f, side_clip=False))
 
 
+@pytest.mark.parametrize("frame", [0, 8, 16, 24])
 @pytest.mark.parametrize("rate", [1.0, 0.5, 2.0])
-def test_city_frame_full(rate):
-    f = scenes.city_frame(0, rate=rate)
+def test_city_frame_full(frame, rate):
+    f = scenes.city_frame(frame, rate=rate)
     g = run_gpu(f, ctx_for())
     compare(g, oracle.build_frame(f))
 
@@ -398,10 +401,12 @@ def test_serve_mix_equals_alone():
     import paper_2502_17712_amd as fa
     from paper_2502_17712_amd import serve
     from synth import requests as rq
-    meshes_np = {k: v for k, v in rq.scene_meshes().items() if k != "city"}
+    meshes_np = rq.scene_meshes()
     meshes = {k: fa.Mesh(p, t, key) for k, (p, t, key) in meshes_np.items()}
-    pools = {"grid": rq.pose_pool("grid", 4, seed=1), "orbit": rq.pose_pool("orbit", 4, seed=2)}
-    stream = rq.poisson_stream(5000.0, 24, pools, clients=8, seed=3)
+    pools = {"grid": rq.pose_pool("grid", 4, seed=1), "orbit": rq.pose_pool("orbit", 4, seed=2),
+             "city": rq.pose_pool("city", 3, seed=3)}
+    stream = rq.poisson_stream(5000.0, 30, pools, clients=8, seed=3)
+    assert {s for (_, _, s, _, _, _) in stream} == {"grid", "orbit", "city"}
     vis = {(s, i): torch.as_tensor(pools[s][i].visible).cuda() for s in pools
            for i in range(len(pools[s]))}
     reqs = []
@@ -409,10 +414,14 @@ def test_serve_mix_equals_alone():
         pz = pools[s][i]
         reqs.append(serve.Request(rid, s, vis[(s, i)], pz.view_proj, pz.width, pz.height, om, r,
                                   arrival=a * 0.05, client=c))
-    print("[gpu] serve mix of 24 requests on 4 slots", flush=True)
-    srv = serve.Server(meshes, slots=4, hbm_budget=2 << 30, max_charts=8192, max_atlas=4096)
+    print("[gpu] serve mix of 30 requests on 4 slots", flush=True)
+    srv = serve.Server(meshes, slots=4, hbm_budget=8 << 30, max_charts=8192, max_atlas=4096)
     res = {r.rid: r for r in srv.run(reqs, keep_outputs=True)}
     srv.close()
+    # the mix really overlapped: some request started before another finished
+    ivs = sorted((r.start, r.finish) for r in res.values())
+    overlaps = sum(1 for (s0, f0), (s1, _) in zip(ivs, ivs[1:]) if s1 < f0)
+    assert overlaps >= 2, ivs
     alone = fa.Context(max(m.num_triangles for m in meshes.values()),
                        max(m.num_vertices for m in meshes.values()), max_charts=8192,
                        max_atlas=4096)
@@ -427,15 +436,19 @@ def test_serve_mix_equals_alone():
         assert np.array_equal(a["charts"], b["charts"])
         assert np.array_equal(bits(a["uv"]), bits(b["uv"]))
         assert a["meta"] == b["meta"]
-    # back-pressure: a budget that holds one request at a time still serves all
-    srv = serve.Server(meshes, slots=4, hbm_budget=serve.output_bytes(
-        max(m.num_triangles for m in meshes.values()), max(m.num_vertices for m in meshes.values()),
-        8192, 4096, 64), max_charts=8192, max_atlas=4096)
-    out = srv.run(reqs[:8])
+    # back-pressure: a budget that holds one request at a time still serves all,
+    # one after another
+    small = {k: meshes[k] for k in ("grid", "orbit")}
+    few = [q for q in reqs if q.scene in small][:8]
+    srv = serve.Server(small, slots=4, max_charts=8192, max_atlas=4096, hbm_budget=1)
+    srv.budget = max(srv.request_bytes(q) for q in few)
+    out = srv.run(few)
     srv.close()
-    assert sorted(r.rid for r in out) == list(range(8))
+    assert sorted(r.rid for r in out) == sorted(q.rid for q in few)
     for r in out:
         assert r.meta["status"] == 0
+    ivs = sorted((r.start, r.finish) for r in out)
+    assert all(s1 >= f0 - 1e-3 for (_, f0), (s1, _) in zip(ivs, ivs[1:]))
 
 
 @pytest.mark.parametrize("link,hooks", [(0, 0), (0, 1), (0, 2), (0, 3), (0, 4), (0, 5), (1, 0),

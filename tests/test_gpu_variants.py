@@ -1,0 +1,138 @@
+"""GPU parity of the variants and of the batched path on the large scene.
+
+* Edge-connected charts (FA_FLAG_EDGE_ONLY_CHARTS; Sec. "Chart Computation"
+  without the vertex merge of App. "GPU Union Find"): chart ids, per-vertex
+  chart (smallest incident chart), per-corner UVs, placements and occupancy
+  against the oracle's O3'/O9' variant, in both hook modes.
+* Batched views of the 2.2M-triangle scene (16 views of uneven resolution,
+  atlas size and rate): every view of a batch equals the oracle, with streams
+  and with the captured graph, and a graph replay after the scene was evicted
+  and rebuilt still reads the live adjacency.
+Same bar as test_gpu_parity.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import scenes
+from tests.test_gpu_parity import compare, ctx_for, mesh_for, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+EDGE = 2  # FA_FLAG_EDGE_ONLY_CHARTS
+
+
+def _checker(f):
+    q = np.arange(f.num_triangles) // 2
+    if f.num_triangles == 8192:
+        i, j = q // 64, q % 64
+        keep = ((i // 2 + j // 2) % 2) == 0
+    else:  # any mesh: hide every other pair of triangles
+        keep = (q % 3) != 0
+    f.visible = (f.visible.astype(bool) & keep).astype(np.uint8)
+    f.name += "/checker"
+    return f
+
+
+@pytest.mark.parametrize("case", ["grid0", "grid9", "checker0", "checker5", "orbit30",
+                                  "orbitcheck55", "city0", "city16check", "near3"])
+@pytest.mark.parametrize("hooks", [1, 5])
+def test_edge_only_charts(case, hooks):
+    if case.startswith("grid"):
+        f = scenes.grid_frame(int(case[4:]))
+    elif case.startswith("checker"):
+        f = _checker(scenes.grid_frame(int(case[7:]), atlas_size=512))
+    elif case == "orbit30":
+        f = scenes.orbit_frame(30)
+    elif case == "orbitcheck55":
+        f = _checker(scenes.orbit_frame(55))
+    elif case == "city0":
+        f = scenes.city_frame(0)
+    elif case == "city16check":
+        f = _checker(scenes.city_frame(16, rate=0.5))
+    else:
+        f = scenes.grid_near_frame(3)
+    ctx = ctx_for(flags=EDGE)
+    old = ctx.get_tuning(5)
+    ctx.set_tuning(5, hooks)
+    try:
+        g = run_gpu(f, ctx)
+    finally:
+        ctx.set_tuning(5, old)
+    r = oracle.build_frame(f, edge_only=True)
+    assert g["uv"].shape == (f.num_triangles, 3, 2)
+    compare(g, r)
+
+
+def test_edge_only_differs_from_vertex_charts():
+    f = _checker(scenes.grid_frame(2))
+    ge = run_gpu(f, ctx_for(flags=EDGE))
+    gv = run_gpu(f, ctx_for())
+    assert ge["meta"]["num_charts"] > gv["meta"]["num_charts"]
+
+
+# ---------------------------------------------------------------------------
+# batched views of the large scene
+# ---------------------------------------------------------------------------
+_B = {}
+
+
+def _batch_setup():
+    if "views" not in _B:
+        import paper_2502_17712_amd as fa
+        views = scenes.batch_views(16)
+        ctx = fa.Context(views[0].num_triangles, views[0].num_vertices, max_charts=65536,
+                         max_atlas=4096, max_views=8)
+        _B.update(views=views, ctx=ctx, want=[oracle.build_frame(v) for v in views])
+    return _B["views"], _B["ctx"], _B["want"]
+
+
+def _run_batch(ctx, views, mesh):
+    outs = [ctx.outputs(mesh, v.atlas_size) for v in views]
+    for o in outs:  # poison every output so that a skipped view cannot pass
+        for t in (o.chart_of_tri, o.chart_of_vert, o.occupancy, o.candidates, o.charts, o.meta):
+            t.fill_(-7)
+        o.uv.fill_(-7.0)
+    vis = [torch.as_tensor(v.visible).cuda() for v in views]
+    ctx.build_atlas_batch(mesh, [(vis[i], v.view_proj, v.width, v.height, v.atlas_size, v.rate)
+                                 for i, v in enumerate(views)], outs)
+    torch.cuda.synchronize()
+    return [o.to_numpy() for o in outs]
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_batch_city_views(graph):
+    import paper_2502_17712_amd as fa
+    views, ctx, want = _batch_setup()
+    mesh = mesh_for(views[0])
+    ctx.set_tuning(fa.FA_TUNE_BATCH_GRAPH, graph)
+    try:
+        for rep in range(2 if graph else 1):
+            print(f"[gpu] batch of 16 city views, graph={graph}, pass {rep}", flush=True)
+            for g, r in zip(_run_batch(ctx, views, mesh), want):
+                compare(g, r)
+    finally:
+        ctx.set_tuning(fa.FA_TUNE_BATCH_GRAPH, 0)
+
+
+def test_batch_graph_after_evict():
+    """A cached batch graph must not outlive the adjacency it reads: evict the
+    scene, rebuild it, replay the same descriptors."""
+    import paper_2502_17712_amd as fa
+    views = [scenes.orbit_frame(k, atlas_size=om) for k, om in ((3, 1024), (50, 2048), (90, 512))]
+    ctx = fa.Context(views[0].num_triangles, views[0].num_vertices, max_charts=8192,
+                     max_atlas=4096, max_views=2)
+    ctx.set_tuning(fa.FA_TUNE_BATCH_GRAPH, 1)
+    mesh = mesh_for(views[0])
+    want = [oracle.build_frame(v) for v in views]
+    for rep in range(3):
+        print(f"[gpu] batch graph, evict between passes, pass {rep}", flush=True)
+        for g, r in zip(_run_batch(ctx, views, mesh), want):
+            compare(g, r)
+        assert fa.fa_scene_evict(ctx.h, mesh.scene_key) == fa.FA_OK
+        # other allocations in between, so the rebuilt adjacency moves
+        junk = torch.empty(1 << 22, dtype=torch.int32, device="cuda").fill_(5)
+        torch.cuda.synchronize()
+        del junk
+    ctx.close()

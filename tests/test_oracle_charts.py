@@ -24,15 +24,17 @@ def test_golden_adjacency_quad():
 
 
 @pytest.mark.parametrize("name", ["bowtie", "checker_2x2", "two_islands"])
-def test_golden_charts(name):
+@pytest.mark.parametrize("edge_only", [False, True])
+def test_golden_charts(name, edge_only):
     g = GOLD[name]
     idx = np.array(g["indices"], np.int32)
     V = int(idx.max()) + 1
-    cot, cov, roots = oracle.charts(idx, V, np.array(g["visible"], np.uint8))
-    assert cot.tolist() == g["chart_of_tri"]
-    assert roots.tolist() == g["roots"]
-    if "chart_of_vert" in g:
-        assert cov.tolist() == g["chart_of_vert"]
+    cot, cov, roots = oracle.charts(idx, V, np.array(g["visible"], np.uint8), edge_only=edge_only)
+    want = g["edge_only"] if edge_only else g
+    assert cot.tolist() == want["chart_of_tri"]
+    assert roots.tolist() == want["roots"]
+    if "chart_of_vert" in want:
+        assert cov.tolist() == want["chart_of_vert"]
 
 
 def _brute_adjacency(idx):
@@ -151,3 +153,87 @@ def test_charts_grid_frame_invariants():
     used = np.zeros(f.num_vertices, bool)
     used[f.indices[vis].ravel()] = True
     assert (cov[~used] == -1).all()
+
+
+# ---------------------------------------------------------------------------
+# edge-connected charts (O3': joined across shared edges only)
+# ---------------------------------------------------------------------------
+def _brute_edge_charts(idx, V, vis):
+    """O(T^2): triangles t, u are adjacent iff they share two distinct vertex
+    indices (a shared undirected edge); components by repeated relabelling to
+    the smallest label until nothing changes."""
+    T = idx.shape[0]
+    sets = [set(int(v) for v in idx[t]) for t in range(T)]
+    lab = [t if vis[t] else -1 for t in range(T)]
+    changed = True
+    while changed:
+        changed = False
+        for t in range(T):
+            if not vis[t]:
+                continue
+            for u in range(T):
+                if u != t and vis[u] and len(sets[t] & sets[u]) >= 2 and lab[u] < lab[t]:
+                    lab[t] = lab[u]
+                    changed = True
+    labels = sorted({lab[t] for t in range(T) if vis[t]})
+    cidx = {l: i for i, l in enumerate(labels)}
+    cot = [cidx[lab[t]] if vis[t] else -1 for t in range(T)]
+    cov = [-1] * V
+    for t in range(T):
+        if vis[t]:
+            for v in idx[t]:
+                v = int(v)
+                cov[v] = cot[t] if cov[v] < 0 else min(cov[v], cot[t])
+    return cot, cov, labels
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_edge_charts_brute_force(seed):
+    rng = np.random.default_rng(300 + seed)
+    T, V = int(rng.integers(5, 70)), int(rng.integers(6, 40))
+    idx = _random_mesh(rng, T, V, nonmanifold=bool(seed % 2))
+    if seed % 3 == 0:
+        idx[2] = [idx[2, 0], idx[2, 0], idx[2, 1]]  # a degenerate triangle
+    vis = (rng.uniform(size=T) < 0.7).astype(np.uint8)
+    cot, cov, roots = oracle.charts(idx, V, vis, edge_only=True)
+    ecot, ecov, eroots = _brute_edge_charts(idx, V, vis)
+    assert cot.tolist() == ecot
+    assert cov.tolist() == ecov
+    assert roots.tolist() == eroots
+
+
+@pytest.mark.parametrize("maker", [lambda: scenes.grid_frame(3), lambda: scenes.orbit_frame(9)])
+def test_edge_charts_refine_vertex_charts(maker):
+    # every edge-connected chart lies inside one vertex-merged chart, and on
+    # a frame with vertex-only contacts there are strictly more of them
+    f = maker()
+    cot_v, _, roots_v = oracle.charts(f.indices, f.num_vertices, f.visible)
+    cot_e, cov_e, roots_e = oracle.charts(f.indices, f.num_vertices, f.visible, edge_only=True)
+    vis = f.visible.astype(bool)
+    assert np.array_equal(cot_e >= 0, vis)
+    pairs = set(zip(cot_e[vis].tolist(), cot_v[vis].tolist()))
+    assert len(pairs) == roots_e.shape[0]          # each edge chart maps to one vertex chart
+    assert roots_e.shape[0] >= roots_v.shape[0]
+    for c in range(roots_e.shape[0]):
+        assert np.nonzero(cot_e == c)[0].min() == roots_e[c]
+    # chart_of_vert: the smallest chart among the vertex's visible triangles
+    want = np.full(f.num_vertices, np.iinfo(np.int32).max, np.int64)
+    for k in range(3):
+        np.minimum.at(want, f.indices[vis, k], cot_e[vis])
+    want[want == np.iinfo(np.int32).max] = -1
+    assert np.array_equal(cov_e, want)
+
+
+def test_edge_charts_split_checkerboard():
+    # a checkerboard of visible quads on the grid: neighbouring quads meet
+    # only at corners, so edge-connected charts are single quads (the two
+    # triangles of a quad share its diagonal) while vertex merging joins them
+    f = scenes.grid_frame(0)
+    T = f.num_triangles
+    q = np.arange(T) // 2
+    i, j = q // 64, q % 64
+    vis = (((i + j) % 2) == 0).astype(np.uint8)
+    _, _, roots_e = oracle.charts(f.indices, f.num_vertices, vis, edge_only=True)
+    _, _, roots_v = oracle.charts(f.indices, f.num_vertices, vis)
+    assert roots_e.shape[0] == 64 * 64 // 2
+    assert roots_v.shape[0] == 1

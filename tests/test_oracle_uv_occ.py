@@ -246,3 +246,91 @@ def test_uv_nan_behind_eye():
     tris_behind = np.nonzero(f.visible.astype(bool) & (clip[f.indices, 3] <= 0).any(1))[0]
     claimed = set(np.unique(r["occupancy"][r["occupancy"] >= 0]).tolist())
     assert any(int(r["chart_of_tri"][t]) in claimed for t in tris_behind)
+
+
+# ---------------------------------------------------------------------------
+# per-corner UVs of edge-connected charts (O9')
+# ---------------------------------------------------------------------------
+def _checker_frame(seed=0, omega=1024):
+    # quads of the grid visible in a checkerboard (the others hidden): many
+    # vertices are shared by edge-connected charts that meet only there
+    f = scenes.grid_frame(seed, atlas_size=omega)
+    q = np.arange(f.num_triangles) // 2
+    i, j = q // 64, q % 64
+    f.visible = (f.visible.astype(bool) & (((i // 2 + j // 2) % 2) == 0)).astype(np.uint8)
+    return f
+
+
+def test_uv_corners_similarity_and_seams():
+    f = _checker_frame()
+    r = oracle.build_frame(f, edge_only=True, want_occupancy=False)
+    uvc = r["uv"].astype(np.float64)          # [T][3][2]
+    assert uvc.shape == (f.num_triangles, 3, 2)
+    clip = r["clip"]
+    vis = f.visible.astype(bool)
+    assert np.isnan(uvc[~vis]).all()
+    P = _pixel_coords(clip, f.width, f.height)
+    t = np.nonzero(vis & (clip[f.indices, 3] > 0).all(1))[0]
+    p = P[f.indices[t]]
+    A = np.stack([p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]], 2)
+    B = np.stack([uvc[t, 1] - uvc[t, 0], uvc[t, 2] - uvc[t, 0]], 2)
+    keep = np.abs(np.linalg.det(A)) / 2 > 30.0
+    Jm = B[keep] @ np.linalg.inv(A[keep])
+    assert keep.sum() > 20
+    assert np.allclose(np.linalg.svd(Jm, compute_uv=False), f.rate * r["s_eff"], rtol=1e-3)
+    assert (np.linalg.det(Jm) > 0).all()
+    # corners of one vertex agree inside a chart and differ across charts
+    cot = r["chart_of_tri"]
+    seen, same, diff = {}, 0, 0
+    for tt in t:
+        for k in range(3):
+            key = int(f.indices[tt, k])
+            if key in seen:
+                c0, uv0 = seen[key]
+                if c0 == cot[tt]:
+                    assert np.array_equal(uv0, uvc[tt, k])
+                    same += 1
+                else:
+                    diff += int(not np.array_equal(uv0, uvc[tt, k]))
+            else:
+                seen[key] = (cot[tt], uvc[tt, k])
+    assert same > 100 and diff > 10
+
+
+def test_occupancy_edge_only_exact():
+    # the occupancy of edge-connected charts: each triangle claims the texels
+    # of its own chart's map (the per-corner UVs), exactly away from edges
+    f = _checker_frame(5, omega=512)
+    f.rate = 0.5
+    r = oracle.build_frame(f, edge_only=True)
+    occ, omega, L = r["occupancy"], f.atlas_size, r["L"]
+    uvc = r["uv"].astype(np.float64)
+    want = np.full((omega, omega), -1, np.int64)
+    ambiguous = np.zeros((omega, omega), bool)
+    tx = np.arange(omega)
+    for t in np.nonzero(r["nonempty"])[0]:
+        c = r["chart_of_tri"][t]
+        P = uvc[t]
+        if np.isnan(P).any():
+            continue
+        x0, x1 = int(np.floor(P[:, 0].min() - 1)), int(np.ceil(P[:, 0].max() + 1))
+        y0, y1 = int(np.floor(P[:, 1].min() - 1)), int(np.ceil(P[:, 1].max() + 1))
+        xs = tx[max(0, x0):max(0, min(omega, x1))]
+        ys = tx[max(0, y0):max(0, min(omega, y1))]
+        if xs.size == 0 or ys.size == 0:
+            continue
+        X, Y = np.meshgrid(xs + 0.5, ys + 0.5)
+        e = [(P[(k + 1) % 3, 0] - P[k, 0]) * (Y - P[k, 1]) - (P[(k + 1) % 3, 1] - P[k, 1]) * (X - P[k, 0])
+             for k in range(3)]
+        inside = ((e[0] >= 0) & (e[1] >= 0) & (e[2] >= 0)) | ((e[0] <= 0) & (e[1] <= 0) & (e[2] <= 0))
+        d = np.minimum.reduce([_edge_dist(X, Y, P[k, 0], P[k, 1], P[(k + 1) % 3, 0], P[(k + 1) % 3, 1])
+                               for k in range(3)])
+        bx, by, ba, bb = r["x"][c], r["y"][c], r["a"][c], r["b"][c]
+        inbox = ((2 * bx * omega <= (2 * X) * L) & ((2 * X) * L < 2 * (bx + ba) * omega) &
+                 (2 * by * omega <= (2 * Y) * L) & ((2 * Y) * L < 2 * (by + bb) * omega))
+        sl = (slice(ys[0], ys[-1] + 1), slice(xs[0], xs[-1] + 1))
+        want[sl][inside & inbox] = c
+        ambiguous[sl] |= d < 4.0 / 256
+    agree = (occ == want) | ambiguous
+    assert agree.all(), int((~agree).sum())
+    assert (occ >= 0).sum() > 1000 and r["occupancy_conflicts"] == 0
