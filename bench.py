@@ -87,6 +87,41 @@ def measured_traffic(kernel):
     return float(fields["hbm_bytes_per_launch"])
 
 
+def rocprof_kernel_ms(kernel):
+    """Average duration (ms) of `kernel` from the committed rocprofv3 kernel
+    trace of the bench workload, if it was taken on the current sources; the
+    two occupancy raster kernels are summed. None otherwise."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", "kernels_city2m_4k_atlas4096.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    for line in txt.splitlines():
+        if line.startswith("- sha256 "):
+            name, digest = line[len("- sha256 "):].split(":", 1)
+            src = os.path.join(HERE, "paper_2502_17712_amd", "csrc", name.strip())
+            if (not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()
+                    != digest.strip().strip("`")):
+                return None
+    names = {"occ_small+occ_big": ("k_occ_small", "k_occ_big")}.get(kernel, ("k_" + kernel,))
+    total = 0.0
+    for n in names:
+        hit = None
+        for line in txt.splitlines():
+            cells = [c.strip().strip("`") for c in line.split("|")]
+            if len(cells) > 3 and cells[1].startswith(n) and (cells[1] == n or
+                                                             cells[1].startswith(n + "<")):
+                try:
+                    hit = float(cells[3]) * 1e-3  # average, microseconds
+                except ValueError:
+                    pass
+                break
+        if hit is None:
+            return None
+        total += hit
+    return total
+
+
 def dependent_phases(ctx, fa):
     """Kernel launches of one frame (box push, with occupancy): the 21 timing
     stages minus the ones this configuration leaves empty."""
@@ -181,6 +216,58 @@ def extras(args, ctx, mesh, frames, vis, out, stream, dev, T):
     return ms_nocc, copy_gbs, visibility, reuse
 
 
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(args, frames):
+    """Time the oracle (test infrastructure, single-threaded C++) on this
+    host, pinned to one core: the 64 grid seeds, the 120 orbit frames and
+    four city frames at rates 0.5, 1 and 2 (frames 0, 8, 16, 24 of the
+    orbit; the city frames of the timed workload, re-rated)."""
+    import dataclasses
+
+    import oracle
+    from synth import scenes
+    oracle.lib()  # built and loaded before the clock starts
+    allowed = os.sched_getaffinity(0)
+    core = min(allowed)
+    os.sched_setaffinity(0, {core})  # this thread only: the oracle runs in it
+
+    def run(frs):
+        ts = []
+        for f in frs:
+            c0 = time.perf_counter()
+            oracle.build_frame(f)
+            ts.append((time.perf_counter() - c0) * 1e3)
+        return dict(mean_ms=float(np.mean(ts)), p50_ms=float(np.median(ts)), frames=len(ts))
+    try:
+        per = {}
+        per["grid8k_1280x720_atlas1024"] = run([scenes.grid_frame(k) for k in range(64)])
+        per["orbit86k_1920x1080_atlas2048"] = run([scenes.orbit_frame(k) for k in range(120)])
+        base = {f.name: f for f in frames}
+        city = [base.get(f"city2m/s2f{k}") or scenes.city_frame(k, atlas_size=args.atlas)
+                for k in (0, 8, 16, 24)]
+        for r_ in (0.5, 1.0, 2.0):
+            per[f"city2m_3840x2160_atlas{args.atlas}_rate{r_:g}"] = run(
+                [dataclasses.replace(f, rate=r_) for f in city])
+    finally:
+        os.sched_setaffinity(0, allowed)
+    main_key = f"city2m_3840x2160_atlas{args.atlas}_rate{args.rate:g}"
+    value = per[main_key]["mean_ms"] if main_key in per else None
+    return dict(value=value, unit="ms/frame", cores=1, kind="oracle",
+                sample=("oracle pinned to one core: 64 grid seeds, 120 orbit frames, city frames "
+                        "0/8/16/24 at rates 0.5/1/2; value = the city frames at the bench rate"),
+                per_workload=per, pinned_core=core, host_cpu=host_cpu_model(),
+                nproc=os.cpu_count())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,7 +278,6 @@ def main():
     ap.add_argument("--atlas", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--cpu-frames", type=int, default=4)
     ap.add_argument("--autotune", action="store_true",
                     help="tune the knobs on the first frame first (default: library defaults)")
     ap.add_argument("--no-serve", action="store_true")
@@ -319,10 +405,16 @@ def main():
     if dom is not None:
         kb = kernel_bytes(dom, T, V, Tv, Vv, C, 64, args.atlas, occupied)
         ach = kb / (timed[dom] * 1e-3) / 1e9 if kb else None
+        rp = rocprof_kernel_ms(dom)
         roofline = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": (ach / HBM_PEAK_GBS) if ach else None,
                     "traffic": measured_traffic(dom), "kernel_ms": timed[dom],
-                    "algorithmic_bytes": kb}
+                    "time_basis": ("HIP events on the launch stream before and after each "
+                                   "kernel, stage-timing pass over the timed frames"),
+                    "algorithmic_bytes": kb,
+                    "rocprof_kernel_ms": rp,
+                    "frac_rocprof": (kb / (rp * 1e-3) / 1e9 / HBM_PEAK_GBS) if (kb and rp)
+                    else None}
 
     # secondary workloads: the small and medium scenes, other rates on the large one
     def time_frames(ctx_, mesh_, frs, reps=3):
@@ -495,13 +587,32 @@ def main():
             for i, v in enumerate(views):
                 bctx.build_atlas(mesh, bvis[i], v.view_proj, v.width, v.height, v.atlas_size,
                                  v.rate, out=bouts[i], stream=stream)
+        def snapshot():
+            torch.cuda.synchronize()
+            out_ = []
+            for o in bouts:
+                d = o.to_numpy()
+                out_.append((d["meta"], d["chart_of_tri"], d["chart_of_vert"], d["charts"],
+                             d["occupancy"], d["candidates"], d["uv"].view(np.uint32)))
+                for t_ in (o.chart_of_tri, o.occupancy, o.charts, o.meta):
+                    t_.fill_(-7)  # the next mode must write everything again
+            return out_
+
+        def same(a_, b_):
+            return all(x == y if isinstance(x, dict) else np.array_equal(x, y)
+                       for va, vb in zip(a_, b_) for x, y in zip(va, vb))
         tp = timed(plain)
+        want_b = snapshot()
         bctx.set_tuning(fa.FA_TUNE_BATCH_GRAPH, 0)
         tb = timed(lambda: bctx.build_atlas_batch(mesh, desc, bouts, stream=stream))
+        ok_streams = same(snapshot(), want_b)
         bctx.set_tuning(fa.FA_TUNE_BATCH_GRAPH, 1)
         tg = timed(lambda: bctx.build_atlas_batch(mesh, desc, bouts, stream=stream))
+        ok_graph = same(snapshot(), want_b)
         bctx.close()
-        batch = dict(views=16, slots=8, plain_views_per_s=16 / tp,
+        assert ok_streams and ok_graph, "batched outputs differ from the per-view path"
+        batch = dict(views=16, slots=8, outputs_equal_plain=bool(ok_streams and ok_graph),
+                     plain_views_per_s=16 / tp,
                      batched_views_per_s=16 / min(tb, tg),
                      batched_streams_views_per_s=16 / tb, batched_graph_views_per_s=16 / tg,
                      speedup=tp / min(tb, tg))
@@ -555,18 +666,13 @@ def main():
             srv.close()
         log("served:", json.dumps(served))
 
-    # CPU oracle on a bounded sample of the same workload
+    # CPU oracle beside the GPU: the single-threaded oracle pinned to one core
+    # of this host, on every frame of the two smaller workloads and on four
+    # frames of the large one at each rate (the value: the large one at the
+    # bench rate, the workload of the line)
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        n = max(1, args.cpu_frames)
-        c0 = time.perf_counter()
-        for f in frames[:n]:
-            oracle.build_frame(f)
-        cms = (time.perf_counter() - c0) / n * 1e3
-        cpu = dict(value=cms, unit="ms/frame", cores=1, kind="oracle",
-                   sample=f"{n} frames of the same workload, single-threaded C++ oracle",
-                   host_cpu=platform.processor() or platform.machine(), nproc=os.cpu_count())
+        cpu = cpu_baseline(args, frames)
 
     ms = float(per.mean())
     res = {
@@ -582,8 +688,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+i32",
         "data": "synthetic (seeded scene generator)",
-        "config": {"workload": "city2m_3840x2160_atlas4096_rate1", "triangles": T,
-                   "vertices": V, "frames": len(frames), "atlas": args.atlas, "rate": args.rate,
+        "config": {"workload": f"city2m_3840x2160_atlas{args.atlas}_rate{args.rate:g}",
+                   "triangles": T, "vertices": V, "frames": min(len(frames), args.steps),
+                   "orbit_frames": len(frames), "atlas": args.atlas, "rate": args.rate,
                    "num_scales": 64, "visible_tris_mean": Tv, "charts_mean": C},
         "p50_ms": float(np.percentile(per, 50)),
         "p99_ms": float(np.percentile(per, 99)),

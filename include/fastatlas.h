@@ -98,6 +98,17 @@ typedef struct fa_config {
                               over charts of floor(oriented width) + 1 (0: 64 x
                               max_atlas; at most 2^28); a frame above it ends
                               with FA_ERR_CAPACITY in meta->status          */
+  int64_t hbm_budget_bytes; /* cap on the device memory the context holds
+                              (scratch, resident scene adjacency, visibility
+                              buffers); 0: no cap. fa_create fails with
+                              FA_ERR_OUT_OF_MEMORY when the scratch alone
+                              exceeds it. Before a new scene's adjacency
+                              (12 B per triangle, plus its sort buffers while
+                              it is built) or a larger visibility buffer
+                              would exceed it, the least recently used
+                              resident scenes are evicted (after waiting for
+                              the device); if it still does not fit, the call
+                              returns FA_ERR_OUT_OF_MEMORY                   */
 } fa_config;
 
 typedef struct fa_mesh {
@@ -157,7 +168,13 @@ typedef struct fa_atlas_out {
   fa_chart* charts;       /* [max_charts]                                       */
   int32_t* occupancy;     /* [omega][omega] owning chart or -1; may be NULL      */
   fa_atlas_meta* meta;    /* [1]                                                */
-  int32_t* candidates;    /* [J][4] fit, m, L, H per candidate; may be NULL      */
+  int32_t* candidates;    /* [J][4] per candidate j (row j - 1): fit (1: the
+                             packing fits the atlas), m, L, H; may be NULL.
+                             m and L are exact for every candidate; H is the
+                             packing height when fit = 1, and when fit = 0
+                             either -1 (rejected before the push: overflow
+                             m > omega, or a box side above 2 omega) or a
+                             height above L at which the push stopped      */
 } fa_atlas_out;
 
 typedef struct fa_view {
@@ -172,14 +189,18 @@ typedef struct fa_ctx fa_ctx;
 
 /* Create a context on cfg->device: checks the device is gfx950 and allocates
  * scratch sized from the capacities. Unset fields (0) take defaults: J=64,
- * min_box=2, max_atlas=8192, max_charts=65536, max_views=1 (gutter 0 means
- * no gutter; the usual value is 1).
+ * min_box=2, max_atlas=8192, max_charts=65536, max_views=1, no memory cap
+ * (gutter 0 means no gutter; the usual value is 1).
  * Returns FA_OK and *out_ctx, or an error and *out_ctx = NULL. */
 int fa_create(const fa_config* cfg, fa_ctx** out_ctx);
 
 /* Free the context, its scratch and every resident scene. No work may be in
  * flight on the context. */
 void fa_destroy(fa_ctx* ctx);
+
+/* Device bytes the context holds now (scratch, resident scenes, visibility
+ * buffers; see fa_config.hbm_budget_bytes), or -1 for a NULL context. */
+int64_t fa_device_bytes(const fa_ctx* ctx);
 
 const char* fa_status_string(int status);
 
@@ -272,6 +293,34 @@ int fa_build_atlas_batch(fa_ctx* ctx, const fa_mesh* mesh, int32_t n, const fa_v
  * meta: as for fa_build_atlas (num_charts = n, no occupancy). */
 int fa_pack_boxes(fa_ctx* ctx, const float* sizes, int32_t n, int32_t atlas_size,
                   int32_t* placements, fa_atlas_meta* meta, int32_t* candidates, void* stream);
+
+/* Allocation-free atlasing, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). The same frame as fa_build_atlas with a fixed configuration
+ * (J = 64, gutter 1, min_box 2, no flags, default knobs) and no context:
+ * every scratch buffer, including the triangle adjacency (rebuilt on every
+ * call, nothing stays resident), lives in one static device array of
+ * FA_STATIC_SCRATCH_MIB MiB that each device holds for the life of the
+ * process. The call allocates nothing and never synchronizes; it runs on the
+ * current device and enqueues on `stream`. Limits: T <= FA_STATIC_MAX_TRIANGLES,
+ * V <= FA_STATIC_MAX_VERTICES (FA_ERR_CAPACITY above them), at most
+ * FA_STATIC_MAX_CHARTS charts (FA_ERR_CAPACITY in meta->status),
+ * atlas_size a power of two 16..8192. Out-of-range indices are found on the
+ * device: meta->status = FA_ERR_INVALID_ARG and no other output is valid.
+ * Arguments, outputs and the other errors are as for fa_build_atlas
+ * (candidates, when given, has 64 rows). Every call on a device shares that
+ * device's array, which keeps the last call's contents: calls that overlap
+ * on one device (different streams, or different host threads) race, so
+ * order them on one stream. The first call on a device sets it up (device
+ * check, address of its copy of the array) and returns FA_ERR_DEVICE if the
+ * device is not gfx950. */
+#define FA_STATIC_MAX_TRIANGLES 65536
+#define FA_STATIC_MAX_VERTICES 65536
+#define FA_STATIC_MAX_CHARTS 4096
+#define FA_STATIC_SCRATCH_MIB 24
+int fa_build_atlas_static(const fa_mesh* mesh, const uint8_t* visible, const fa_camera* cam,
+                          int32_t atlas_size, float texel_per_pixel, fa_atlas_out* out,
+                          void* stream);
 
 /* Performance knobs of one context. Every accepted value produces identical
  * results; only the speed changes (an autotuner may pick any of them).

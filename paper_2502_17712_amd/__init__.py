@@ -35,7 +35,8 @@ class fa_config(ctypes.Structure):
     _fields_ = [("device", c_int32), ("num_scales", c_int32), ("max_triangles", c_int64),
                 ("max_vertices", c_int64), ("max_charts", c_int32), ("max_atlas", c_int32),
                 ("gutter", c_int32), ("min_box", c_int32), ("flags", c_uint32),
-                ("max_views", c_int32), ("max_profile_columns", c_int64)]
+                ("max_views", c_int32), ("max_profile_columns", c_int64),
+                ("hbm_budget_bytes", c_int64)]
 
 
 class fa_mesh(ctypes.Structure):
@@ -72,7 +73,7 @@ assert CHART_DTYPE.itemsize == 64 and META_DTYPE.itemsize == 64
 EXPORTS = ["fa_create", "fa_destroy", "fa_status_string", "fa_scene_adjacency", "fa_scene_evict",
            "fa_build_atlas", "fa_build_atlas_batch", "fa_pack_boxes", "fa_set_tuning",
            "fa_get_tuning", "fa_set_stage_timing", "fa_stage_times", "fa_visibility",
-           "fa_reuse_flags", "fa_build_dual_atlas"]
+           "fa_reuse_flags", "fa_build_dual_atlas", "fa_build_atlas_static", "fa_device_bytes"]
 
 
 def _load():
@@ -104,9 +105,14 @@ def _load():
     lib.fa_build_dual_atlas.argtypes = [c_void_p, POINTER(fa_mesh), c_void_p, POINTER(fa_camera),
                                         c_int32, c_float, c_int32, POINTER(fa_atlas_out),
                                         c_void_p, c_void_p]
+    lib.fa_device_bytes.argtypes = [c_void_p]
+    lib.fa_device_bytes.restype = c_int64
+    lib.fa_build_atlas_static.argtypes = [POINTER(fa_mesh), c_void_p, POINTER(fa_camera), c_int32,
+                                          c_float, POINTER(fa_atlas_out), c_void_p]
     for n in ("fa_scene_adjacency", "fa_scene_evict", "fa_build_atlas", "fa_build_atlas_batch",
               "fa_pack_boxes", "fa_set_tuning", "fa_get_tuning", "fa_set_stage_timing",
-              "fa_stage_times", "fa_visibility", "fa_reuse_flags", "fa_build_dual_atlas"):
+              "fa_stage_times", "fa_visibility", "fa_reuse_flags", "fa_build_dual_atlas",
+              "fa_build_atlas_static"):
         getattr(lib, n).restype = c_int
     return lib
 
@@ -129,6 +135,9 @@ fa_stage_times = _lib.fa_stage_times
 fa_visibility = _lib.fa_visibility
 fa_reuse_flags = _lib.fa_reuse_flags
 fa_build_dual_atlas = _lib.fa_build_dual_atlas
+fa_build_atlas_static = _lib.fa_build_atlas_static
+fa_device_bytes = _lib.fa_device_bytes
+STATIC_MAX_TRIANGLES, STATIC_MAX_VERTICES, STATIC_MAX_CHARTS = 65536, 65536, 4096
 
 STAGES = ["prologue", "vis_scan", "vis_compact", "uf_hook", "uf_vertex_min", "uf_vertex_hook",
           "uf_flatten", "chart_scan", "assign_roots", "gather_boxes", "sizes_order", "fp_count",
@@ -234,14 +243,29 @@ class AtlasOutputs:
         return r
 
 
+def build_atlas_static(mesh: Mesh, visible, view_proj, width, height, atlas_size, rate,
+                       out: AtlasOutputs = None, stream=None):
+    """fa_build_atlas_static: one frame with no device allocation inside the
+    library (fixed J = 64, gutter 1, min_box 2). `out` (allocated here when
+    None) must have at least STATIC_MAX_CHARTS chart records."""
+    if out is None:
+        out = AtlasOutputs(mesh.num_triangles, mesh.num_vertices, STATIC_MAX_CHARTS, atlas_size, 64)
+    cam = make_camera(view_proj, width, height)
+    oc = out.c()
+    _check(fa_build_atlas_static(ctypes.byref(mesh.c), _ptr(visible), ctypes.byref(cam),
+                                 int(atlas_size), float(rate), ctypes.byref(oc),
+                                 _stream_handle(stream)), "fa_build_atlas_static")
+    return out
+
+
 class Context:
     """Owns an fa_ctx (scratch + resident scene adjacency) on one device."""
 
     def __init__(self, max_triangles, max_vertices, max_charts=65536, max_atlas=8192,
                  num_scales=64, gutter=1, min_box=2, flags=0, device=0, max_views=1,
-                 max_profile_columns=0):
+                 max_profile_columns=0, hbm_budget_bytes=0):
         cfg = fa_config(device, num_scales, max_triangles, max_vertices, max_charts, max_atlas,
-                        gutter, min_box, flags, max_views, max_profile_columns)
+                        gutter, min_box, flags, max_views, max_profile_columns, hbm_budget_bytes)
         h = c_void_p()
         _check(fa_create(ctypes.byref(cfg), ctypes.byref(h)), "fa_create")
         self.h = h
@@ -257,6 +281,10 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def device_bytes(self):
+        """Device bytes the context holds now (fa_device_bytes)."""
+        return int(fa_device_bytes(self.h))
 
     def outputs(self, mesh: Mesh, atlas_size, uv=True, occupancy=True, candidates=True):
         return AtlasOutputs(mesh.num_triangles, mesh.num_vertices, self.cfg.max_charts, atlas_size,

@@ -22,7 +22,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfastatlas.so")
 
 SOURCES = ["k_charts.hip", "k_sort.hip", "k_pack.hip", "k_raster.hip", "k_visibility.hip",
-           "fa_runtime.hip"]
+           "fa_runtime.hip", "fa_static.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

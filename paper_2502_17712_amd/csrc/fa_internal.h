@@ -229,6 +229,15 @@ struct Marker {
   }
 };
 
+// Device-side index check of the allocation-free entry point: clear the flag,
+// then set it if any of the n indices is outside [0, V). The guard, launched
+// after the visible list is built, turns a set flag into FA_ERR_INVALID_ARG
+// in the frame state and an empty visible list, so no later kernel reads
+// an index.
+hipError_t launch_index_check(const int32_t* idx, int64_t n, int64_t V, int32_t* flag,
+                              hipStream_t st);
+hipError_t launch_index_guard(const int32_t* flag, const Work& w, hipStream_t st);
+
 hipError_t launch_prologue(const float* pos, int64_t V, const uint8_t* vis, const int32_t* nbr,
                            int64_t T, const FrameParams& p, const Work& w, int32_t* cov,
                            int32_t* cot, int uf_init, Marker& mk, hipStream_t st);
@@ -274,6 +283,22 @@ hipError_t launch_visibility(const float* pos, const int32_t* idx, int64_t T, co
                              uint8_t* vis, hipStream_t st);
 hipError_t launch_meta(const FrameParams& p, const Work& w, fa_atlas_meta* meta,
                        int with_occupancy, hipStream_t st);
+
+// Tuning knobs a frame reads (every accepted value gives the same results).
+struct Knobs {
+  int pack_block;    // threads per candidate packing
+  int small_texels;  // occupancy: queue footprints above this many texels
+  int lane_texels;   // occupancy: one lane per footprint up to this many texels
+  int uf_link_init;  // union-find start linked to the smallest edge neighbour
+};
+// Every stage of one frame (clip transform to frame record) on stream st with
+// the scratch buffers of w and the scene adjacency nbr. index_flag: NULL, or
+// the device flag of launch_index_check (the frame then stops with
+// FA_ERR_INVALID_ARG in meta->status when it is set). Returns FA_OK or
+// FA_ERR_DEVICE (a launch failed).
+int run_frame_core(const Knobs& kn, const Work& w, const fa_mesh* mesh, const int32_t* nbr,
+                   const uint8_t* visible, const FrameParams& p, const fa_atlas_out* out,
+                   const int32_t* index_flag, Marker& mk, hipStream_t st);
 
 // packer-only path: sizes [n][2] -> charts' oriented sizes and keys
 hipError_t launch_pack_prepare(const float* sizes, int32_t n, const FrameParams& p,

@@ -20,7 +20,10 @@ namespace {
 struct Scene {
   int32_t* nbr = nullptr;
   int64_t T = 0, V = 0;
+  uint64_t last_use = 0;  // use counter of the context when last used (LRU eviction)
 };
+
+size_t scene_bytes(int64_t T) { return (size_t)std::max<int64_t>(1, 3 * T) * 4; }
 
 enum { kStages = 21 };
 
@@ -54,6 +57,8 @@ struct fa_ctx {
   hipEvent_t ev_fork = nullptr, ev_done = nullptr;
   hipStream_t cap_stream = nullptr;  // batch graphs are captured and launched here
   size_t arena_bytes = 0;
+  size_t held_bytes = 0;             // every device allocation the context holds now
+  uint64_t use_clock = 0;
   std::unordered_map<uint64_t, Scene> scenes;
   int batch_graph = 0;
   std::string graph_sig;
@@ -122,6 +127,7 @@ int fa_create(const fa_config* cfg_in, fa_ctx** out_ctx) {
   if (cfg.gutter < 0 || cfg.gutter > 64 || cfg.min_box < 1 || cfg.min_box > 64)
     return FA_ERR_INVALID_ARG;
   if (cfg.max_views < 1) return FA_ERR_INVALID_ARG;
+  if (cfg.hbm_budget_bytes < 0) return FA_ERR_INVALID_ARG;
   const bool footprint = (cfg.flags & FA_FLAG_FOOTPRINT_PUSH) != 0;
   if (footprint && cfg.max_profile_columns == 0)
     cfg.max_profile_columns = 64 * (int64_t)cfg.max_atlas;
@@ -181,6 +187,7 @@ int fa_create(const fa_config* cfg_in, fa_ctx** out_ctx) {
     }
     ctx->arenas.push_back(arena);
     ctx->arena_bytes += total;
+    ctx->held_bytes += total;
     char* base = static_cast<char*>(arena);
     for (auto& p : parts) {
       *p.p = base;
@@ -195,6 +202,11 @@ int fa_create(const fa_config* cfg_in, fa_ctx** out_ctx) {
     }
     ctx->slot_streams.push_back(s);
     ctx->slot_join.push_back(e);
+  }
+  ctx->held_bytes += 4;
+  if (cfg.hbm_budget_bytes > 0 && (int64_t)ctx->held_bytes > cfg.hbm_budget_bytes) {
+    fa_destroy(ctx);
+    return FA_ERR_OUT_OF_MEMORY;
   }
   if (hipMalloc(&ctx->check_flag, 4) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -245,18 +257,47 @@ static void drop_graph(fa_ctx* ctx) {
   ctx->graph_sig.clear();
 }
 
+static void free_scene(fa_ctx* ctx, std::unordered_map<uint64_t, Scene>::iterator it) {
+  drop_graph(ctx);
+  (void)hipFree(it->second.nbr);
+  ctx->held_bytes -= scene_bytes(it->second.T);
+  ctx->scenes.erase(it);
+}
+
+// Make room for `need` more bytes under the context's budget by evicting the
+// least recently used resident scenes (not `keep`). Work on `st` is waited
+// for first. false: the budget cannot hold it even with no scene resident.
+static bool make_room(fa_ctx* ctx, size_t need, uint64_t keep, hipStream_t st) {
+  const int64_t budget = ctx->cfg.hbm_budget_bytes;
+  if (budget <= 0) return true;
+  bool synced = false;
+  while ((int64_t)(ctx->held_bytes + need) > budget) {
+    auto victim = ctx->scenes.end();
+    for (auto it = ctx->scenes.begin(); it != ctx->scenes.end(); ++it)
+      if (it->first != keep &&
+          (victim == ctx->scenes.end() || it->second.last_use < victim->second.last_use))
+        victim = it;
+    if (victim == ctx->scenes.end()) return false;
+    if (!synced) {
+      (void)hipDeviceSynchronize();  // nothing may still read the victim
+      synced = true;
+    }
+    free_scene(ctx, victim);
+  }
+  return true;
+}
+
 static int get_scene(fa_ctx* ctx, const fa_mesh* mesh, hipStream_t st, Scene** out) {
   auto it = ctx->scenes.find(mesh->scene_key);
   if (it != ctx->scenes.end() && it->second.T == mesh->num_triangles &&
       it->second.V == mesh->num_vertices) {
+    it->second.last_use = ++ctx->use_clock;
     *out = &it->second;
     return FA_OK;
   }
   if (it != ctx->scenes.end()) {
     (void)hipStreamSynchronize(st);
-    drop_graph(ctx);
-    (void)hipFree(it->second.nbr);
-    ctx->scenes.erase(it);
+    free_scene(ctx, it);
   }
   const int64_t T = mesh->num_triangles, V = mesh->num_vertices;
   // the indices are read by every later kernel: reject out-of-range ones once
@@ -272,15 +313,21 @@ static int get_scene(fa_ctx* ctx, const fa_mesh* mesh, hipStream_t st, Scene** o
   Scene sc;
   sc.T = T;
   sc.V = V;
-  if (hipMalloc(&sc.nbr, std::max<int64_t>(1, 3 * T) * 4) != hipSuccess) return FA_ERR_OUT_OF_MEMORY;
+  sc.last_use = ++ctx->use_clock;
+  const int64_t n = 3 * T;
+  const size_t tmp_bytes = T > 0 ? align_up(8 * n) * 2 + align_up(4 * n) * 2 +
+                                       align_up(4 * adjacency_hist_words(T)) +
+                                       align_up(4 * adjacency_part_words(T)) + 256
+                                 : 0;
+  // the adjacency and, while it is built, its sort buffers must fit the budget
+  if (!make_room(ctx, scene_bytes(T) + tmp_bytes, mesh->scene_key, st))
+    return FA_ERR_OUT_OF_MEMORY;
+  if (hipMalloc(&sc.nbr, scene_bytes(T)) != hipSuccess) return FA_ERR_OUT_OF_MEMORY;
   if (T > 0) {
     AdjTmp tmp{};
-    const int64_t n = 3 * T;
     size_t hist_words = adjacency_hist_words(T);
-    size_t part_words = adjacency_part_words(T);
     void* blk = nullptr;
-    size_t bytes = align_up(8 * n) * 2 + align_up(4 * n) * 2 + align_up(4 * hist_words) +
-                   align_up(4 * part_words) + 256;
+    const size_t bytes = tmp_bytes;
     if (hipMalloc(&blk, bytes) != hipSuccess) {
       (void)hipFree(sc.nbr);
       return FA_ERR_OUT_OF_MEMORY;
@@ -300,6 +347,7 @@ static int get_scene(fa_ctx* ctx, const fa_mesh* mesh, hipStream_t st, Scene** o
       return FA_ERR_DEVICE;
     }
   }
+  ctx->held_bytes += scene_bytes(T);
   auto res = ctx->scenes.emplace(mesh->scene_key, sc);
   *out = &res.first->second;
   return FA_OK;
@@ -359,18 +407,23 @@ int fa_visibility(fa_ctx* ctx, const fa_mesh* mesh, const fa_camera* cam, const 
   if (rc) return rc;
   if (!ctx->vis_list) {
     const size_t T = (size_t)std::max<int64_t>(ctx->cfg.max_triangles, 1);
+    if (!make_room(ctx, 4 * T + 4, mesh->scene_key, st)) return FA_ERR_OUT_OF_MEMORY;
     if (hipMalloc(&ctx->vis_list, 4 * T) != hipSuccess ||
         hipMalloc(&ctx->vis_count, 4) != hipSuccess)
       return FA_ERR_OUT_OF_MEMORY;
+    ctx->held_bytes += 4 * T + 4;
   }
   const int64_t nd = (int64_t)q.Wc * q.Hc;
   if (nd > ctx->vis_depth_cap) {
     (void)hipStreamSynchronize(st);
     if (ctx->vis_depth) (void)hipFree(ctx->vis_depth);
+    ctx->held_bytes -= 8 * (size_t)ctx->vis_depth_cap;
     ctx->vis_depth = nullptr;
     ctx->vis_depth_cap = 0;
+    if (!make_room(ctx, 8 * (size_t)nd, mesh->scene_key, st)) return FA_ERR_OUT_OF_MEMORY;
     if (hipMalloc(&ctx->vis_depth, 8 * (size_t)nd) != hipSuccess) return FA_ERR_OUT_OF_MEMORY;
     ctx->vis_depth_cap = nd;
+    ctx->held_bytes += 8 * (size_t)nd;
   }
   if (launch_visibility(mesh->positions, mesh->indices, mesh->num_triangles, q, ctx->vis_list,
                         ctx->vis_count, ctx->vis_depth, visible, st) != hipSuccess)
@@ -408,9 +461,7 @@ int fa_scene_evict(fa_ctx* ctx, uint64_t scene_key) {
   if (it == ctx->scenes.end()) return FA_ERR_INVALID_ARG;
   (void)hipSetDevice(ctx->cfg.device);
   (void)hipDeviceSynchronize();
-  drop_graph(ctx);
-  (void)hipFree(it->second.nbr);
-  ctx->scenes.erase(it);
+  free_scene(ctx, it);
   return FA_OK;
 }
 
@@ -445,29 +496,31 @@ static int frame_params(const fa_ctx* ctx, const fa_camera* cam, int32_t atlas, 
 }
 
 
-static int run_frame(fa_ctx* ctx, const Work& w, const fa_mesh* mesh, Scene* sc,
-                     const uint8_t* visible, const FrameParams& p, const fa_atlas_out* out,
-                     hipStream_t st) {
+}  // extern "C"
+
+namespace fa {
+// Every stage of one frame on stream st with scratch w (see fa_internal.h).
+int run_frame_core(const Knobs& kn, const Work& w, const fa_mesh* mesh, const int32_t* nbr,
+                   const uint8_t* visible, const FrameParams& p, const fa_atlas_out* out,
+                   const int32_t* index_flag, Marker& mk, hipStream_t st) {
   const int64_t T = mesh->num_triangles, V = mesh->num_vertices;
   int32_t* cov = out->chart_of_vert ? out->chart_of_vert : w.cov;
   hipError_t e = hipSuccess;
   auto ok = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
-  // one event after every kernel (names in order: fa_stage_times)
-  Marker mk;
-  if (ctx->timing) { mk.ev = ctx->ev; mk.cap = kStages + 1; }
   mk(st);
   // start links: the LDS tile kernels write every start themselves (edge-only
   // charts use them unless the global edge hook is chosen)
   const bool tiles_start = (p.flags & FA_FLAG_EDGE_ONLY_CHARTS) ? p.edge_hooks != 1
                                                                 : p.edge_hooks >= 2;
-  ok(launch_prologue(mesh->positions, V, visible, sc->nbr, T, p, w, cov, out->chart_of_tri,
-                     tiles_start ? 0 : (ctx->uf_link_init ? 2 : 1), mk, st));
-  ok(launch_charts(visible, mesh->indices, sc->nbr, T, p, w, out->chart_of_tri, cov, out->charts,
+  ok(launch_prologue(mesh->positions, V, visible, nbr, T, p, w, cov, out->chart_of_tri,
+                     tiles_start ? 0 : (kn.uf_link_init ? 2 : 1), mk, st));
+  if (index_flag) ok(launch_index_guard(index_flag, w, st));
+  ok(launch_charts(visible, mesh->indices, nbr, T, p, w, out->chart_of_tri, cov, out->charts,
                    mk, st));
   ok(launch_order(p, w, out->charts, 1, st));
   mk(st);
   ok(launch_footprint(mesh->indices, T, p, w, out->chart_of_tri, out->charts, mk, st));
-  ok(launch_pack(p, w, ctx->pack_block, p.fp_cap > 0, st));
+  ok(launch_pack(p, w, kn.pack_block, p.fp_cap > 0, st));
   mk(st);
   ok(launch_select_place(p, w, out->charts, out->candidates, st));
   mk(st);
@@ -480,12 +533,26 @@ static int run_frame(fa_ctx* ctx, const Work& w, const fa_mesh* mesh, Scene* sc,
   mk(st);
   if (out->occupancy)
     ok(launch_occupancy(mesh->indices, T, p, w, out->chart_of_tri, out->charts, out->occupancy,
-                        ctx->small_texels, ctx->lane_texels, true, mk, st));
+                        kn.small_texels, kn.lane_texels, true, mk, st));
   ok(launch_meta(p, w, out->meta, out->occupancy != nullptr, st));
   mk(st);
+  return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+}  // namespace fa
+
+extern "C" {
+
+static int run_frame(fa_ctx* ctx, const Work& w, const fa_mesh* mesh, Scene* sc,
+                     const uint8_t* visible, const FrameParams& p, const fa_atlas_out* out,
+                     hipStream_t st) {
+  // one event after every kernel (names in order: fa_stage_times)
+  Marker mk;
+  if (ctx->timing) { mk.ev = ctx->ev; mk.cap = kStages + 1; }
+  const Knobs kn{ctx->pack_block, ctx->small_texels, ctx->lane_texels, ctx->uf_link_init};
+  const int rc = run_frame_core(kn, w, mesh, sc->nbr, visible, p, out, nullptr, mk, st);
   ctx->ev_marks = mk.n;
   ctx->ev_recorded = ctx->timing && mk.n == kStages + 1;
-  return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+  return rc;
 }
 
 int fa_build_atlas(fa_ctx* ctx, const fa_mesh* mesh, const uint8_t* visible,
@@ -698,6 +765,10 @@ int fa_get_tuning(fa_ctx* ctx, int knob) {
     case FA_TUNE_OCC_LANE_TEXELS: return ctx->lane_texels;
     default: return -1;
   }
+}
+
+int64_t fa_device_bytes(const fa_ctx* ctx) {
+  return ctx ? (int64_t)ctx->held_bytes : -1;
 }
 
 int fa_set_stage_timing(fa_ctx* ctx, int enable) {

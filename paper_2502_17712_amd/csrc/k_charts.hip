@@ -772,7 +772,41 @@ __global__ __launch_bounds__(kBlock) void k_gather_boxes(
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
+__global__ void k_flag_clear(int32_t* flag) { *flag = 0; }
+
+__global__ void k_index_check(const int32_t* __restrict__ idx, int64_t n, int64_t V,
+                              int32_t* flag) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = idx[i];
+    bad = bad || v < 0 || (int64_t)v >= V;
+  }
+  if (__ballot(bad) && lane_id() == 0) atomicExch(flag, 1);
+}
+
+__global__ void k_index_guard(const int32_t* __restrict__ flag, FrameState* st) {
+  if (*flag) {
+    st->status = FA_ERR_INVALID_ARG;
+    st->visible = 0;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_index_check(const int32_t* idx, int64_t n, int64_t V, int32_t* flag,
+                              hipStream_t st) {
+  k_flag_clear<<<1, 1, 0, st>>>(flag);
+  if (n > 0)
+    k_index_check<<<(unsigned)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        idx, n, V, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_index_guard(const int32_t* flag, const Work& w, hipStream_t st) {
+  k_index_guard<<<1, 1, 0, st>>>(flag, w.state);
+  return hipGetLastError();
+}
 
 unsigned visible_grid(int64_t T) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((T + kBlock - 1) / kBlock, 2048));

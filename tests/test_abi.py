@@ -12,7 +12,8 @@ HEADER = os.path.join(ROOT, "include", "fastatlas.h")
 
 def _declared():
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(fa_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|void|const char\*)\s+(fa_\w+)\s*\(", txt,
+                                 re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -27,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts():
     import paper_2502_17712_amd as fa
-    assert ctypes.sizeof(fa.fa_config) == 56
+    assert ctypes.sizeof(fa.fa_config) == 64
     assert ctypes.sizeof(fa.fa_mesh) == 40
     assert ctypes.sizeof(fa.fa_camera) == 72
     assert ctypes.sizeof(fa.fa_atlas_out) == 56
@@ -42,7 +43,7 @@ def test_create_rejects_bad_config_on_host():
     for bad in (dict(num_scales=65), dict(max_atlas=1000), dict(max_charts=-1),
                 dict(max_atlas=16384), dict(gutter=-1), dict(flags=fp, gutter=0),
                 dict(flags=fp, max_profile_columns=(1 << 28) + 1),
-                dict(flags=fp, max_profile_columns=-5)):
+                dict(flags=fp, max_profile_columns=-5), dict(hbm_budget_bytes=-1)):
         kw = dict(device=0, num_scales=64, max_triangles=10, max_vertices=10, max_charts=16,
                   max_atlas=1024, gutter=1, min_box=2, flags=0, max_views=1)
         kw.update(bad)

@@ -136,3 +136,46 @@ def test_batch_graph_after_evict():
         torch.cuda.synchronize()
         del junk
     ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# the context's device-memory cap (fa_config.hbm_budget_bytes)
+# ---------------------------------------------------------------------------
+def test_hbm_budget_evicts_least_recently_used_scene():
+    import paper_2502_17712_amd as fa
+    frames = [scenes.grid_frame(s) for s in (0, 1, 2)]   # three scenes of 8192 triangles
+    T, V = frames[0].num_triangles, frames[0].num_vertices
+    probe = fa.Context(T, V, max_charts=4096, max_atlas=1024)
+    base = probe.device_bytes()
+    probe.close()
+    adj = 12 * T
+    # room for one resident scene plus a second one being built, not for two
+    # resident scenes plus a third being built
+    budget = base + 850_000
+    ctx = fa.Context(T, V, max_charts=4096, max_atlas=1024, hbm_budget_bytes=budget)
+    assert ctx.device_bytes() == base
+    order = [0, 1, 2, 0, 1]
+    for k in order:
+        f = frames[k]
+        print(f"[gpu] budgeted context: scene {f.scene_key}", flush=True)
+        g = run_gpu(f, ctx)
+        compare(g, oracle.build_frame(f))
+        held = ctx.device_bytes()
+        assert held <= budget
+        assert (held - base) % adj == 0 and 1 <= (held - base) // adj <= 2
+    # after 2 the scenes resident are the two most recent ones
+    assert (ctx.device_bytes() - base) // adj == 2
+    ctx.close()
+    # a cap below one scene and its build buffers: the call fails, nothing leaks
+    tiny = fa.Context(T, V, max_charts=4096, max_atlas=1024, hbm_budget_bytes=base + adj)
+    mesh = mesh_for(frames[0])
+    vis = torch.as_tensor(frames[0].visible).cuda()
+    with pytest.raises(fa.FastAtlasError) as e:
+        tiny.build_atlas(mesh, vis, frames[0].view_proj, 1280, 720, 1024, 1.0)
+    assert e.value.code == fa.FA_ERR_OUT_OF_MEMORY
+    assert tiny.device_bytes() == base
+    tiny.close()
+    # a cap below the scratch: fa_create fails
+    with pytest.raises(fa.FastAtlasError) as e:
+        fa.Context(T, V, max_charts=4096, max_atlas=1024, hbm_budget_bytes=base // 2)
+    assert e.value.code == fa.FA_ERR_OUT_OF_MEMORY
