@@ -601,3 +601,42 @@ def batch_views(n: int = 16, base_seed: int = 3000):
         views.append(Frame(f"city2m/view{i}", pos, tris, vis, cam.view_proj, W, H, om, r, 3002,
                            cam.eye, cam.near, 8))
     return views
+
+
+# --------------------------------------------------------------------------
+# many-chart frames: thousands of small separate objects in view, so that the
+# ordering and packing stages see the chart counts of the paper's archive
+# scenes (thousands to tens of thousands of charts per frame)
+# --------------------------------------------------------------------------
+def scene_scatter(seed: int = 4, count: int = 24000):
+    """``count`` small boxes (12 triangles each, side 0.05-0.2, random
+    orientation) scattered through the view volume of a camera at the
+    origin looking along +x: distance 4-40, lateral positions inside 95% of
+    a 60-degree vertical, 16:9 field of view."""
+    rng = np.random.default_rng(seed)
+    bp, bt = box_mesh(1)
+    b = _Builder()
+    ty = math.tan(math.radians(30.0)) * 0.95
+    tx = ty * 16.0 / 9.0
+    for _ in range(count):
+        d = rng.uniform(4.0, 40.0)
+        c = np.array([d, rng.uniform(-tx, tx) * d, rng.uniform(-ty, ty) * d])
+        R = _rot_uniform(rng)
+        s = rng.uniform(0.05, 0.2)
+        b.add((bp * s) @ R.T + c, bt)
+    return b.done()
+
+
+def scatter_frame(frame: int = 0, rate: float = 1.0, atlas_size: int = 4096,
+                  width: int = 3840, height: int = 2160, seed: int = 4) -> Frame:
+    """~24k small boxes (288k triangles), 3840x2160 view, 4096^2 atlas: about
+    20k charts per frame (every visible box is its own chart). Frame f turns
+    the camera by f degrees of yaw about the origin."""
+    pos, tris = _cached(("scatter", seed), lambda: scene_scatter(seed))
+    yaw = math.radians(float(frame))
+    eye = np.zeros(3)
+    d = np.array([math.cos(yaw), math.sin(yaw), 0.0])
+    cam = make_camera(eye, eye + d, width, height, 0.1, 1000.0)
+    vis = visible_set(pos, tris, cam)
+    return Frame(f"scatter24k/s{seed}f{frame}", pos, tris, vis, cam.view_proj, width, height,
+                 atlas_size, rate, 4000 + seed, cam.eye, cam.near, 0)

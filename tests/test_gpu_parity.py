@@ -144,6 +144,17 @@ def test_city_frame_full(frame, rate):
     compare(g, oracle.build_frame(f))
 
 
+@pytest.mark.parametrize("frame", [0, 5, 10])
+@pytest.mark.parametrize("rate", [1.0, 2.0])
+def test_scatter_many_charts(frame, rate):
+    # ~20k charts per frame: ordering and packing at the chart counts where
+    # the paper's packing cost grows, past the packer's in-LDS capacity
+    f = scenes.scatter_frame(frame, rate=rate)
+    r = oracle.build_frame(f)
+    assert r["num_charts"] >= 10000
+    compare(run_gpu(f, ctx_for()), r)
+
+
 def test_city_frames_more():
     for fr in (9, 23):
         f = scenes.city_frame(fr)

@@ -41,3 +41,13 @@ def test_meshes_are_welded_and_closed():
         p = pos[tris]
         vol = np.einsum("ij,ij->i", p[:, 0], np.cross(p[:, 1], p[:, 2])).sum() / 6
         assert vol > 0
+
+
+def test_scatter_frame_is_many_charts():
+    f = scenes.scatter_frame(0)
+    assert f.num_triangles == 24000 * 12 and f.num_vertices == 24000 * 8
+    assert scenes.scatter_frame(0).digest() == f.digest()
+    # every box is a closed 12-triangle object: the visible faces of one box
+    # share vertices, so the visible boxes are the charts
+    vis = f.visible.reshape(-1, 12).any(1)
+    assert int(vis.sum()) >= 20000
