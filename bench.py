@@ -286,7 +286,8 @@ def main():
     ap.add_argument("--no-footprint", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the no-occupancy, copy, visibility and reuse measurements")
-    ap.add_argument("--serve-rate", type=float, nargs="+", default=[60.0, 250.0, 1000.0, 2000.0])
+    ap.add_argument("--serve-rate", type=float, nargs="+",
+                    default=[60.0, 250.0, 1000.0, 2000.0, 5000.0, 10000.0, 20000.0])
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 4 plain device copies of 256 MiB (counter calibration)")
@@ -456,6 +457,26 @@ def main():
         for r_ in (0.5, 2.0):
             secondary[f"city2m_3840x2160_atlas4096_rate{r_}"] = time_frames(
                 ctx, mesh, [scenes.city_frame(k, rate=r_) for k in range(0, 32, 8)])
+        # many charts: ordering and packing at ~20k charts per frame
+        sfr = [scenes.scatter_frame(k) for k in range(8)]
+        smesh = fa.Mesh(sfr[0].positions, sfr[0].indices, sfr[0].scene_key)
+        res_sc = time_frames(sctx, smesh, sfr)
+        sv = [torch.as_tensor(f.visible).to(dev) for f in sfr]
+        sout = sctx.outputs(smesh, 4096)
+        sctx.set_stage_timing(True)
+        st_acc, charts_ = {}, []
+        for f, v in zip(sfr, sv):
+            sctx.build_atlas(smesh, v, f.view_proj, f.width, f.height, f.atlas_size, f.rate,
+                             out=sout, stream=stream)
+            torch.cuda.synchronize()
+            charts_.append(fa.parse_meta(sout.meta)["num_charts"])
+            for sn, ms_ in sctx.stage_times().items():
+                st_acc.setdefault(sn, []).append(ms_)
+        sctx.set_stage_timing(False)
+        res_sc["charts_mean"] = float(np.mean(charts_))
+        res_sc["stages_ms"] = {k_: float(np.mean(v_)) for k_, v_ in st_acc.items()
+                               if k_ in ("sizes_order", "pack", "select_place")}
+        secondary["scatter24k_3840x2160_atlas4096"] = res_sc
         sctx.close()
         log("secondary:", json.dumps(secondary))
 

@@ -20,7 +20,7 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortTile = 2048;      // keys per workgroup in one radix pass
 constexpr int kCandStride = 8;       // int32 per candidate in the table
 constexpr int kMaxAtlas = 8192;
-constexpr int kCountGrid = 1024;     // blocks of the occupancy count
+constexpr int kCountGrid = 256;      // workgroups of the occupancy count
 constexpr int kOccBigGrid = 2048;    // blocks of the large-footprint raster
 constexpr int64_t kBigCap = 1 << 20; // queue capacity (more: rasterized where found)
 
@@ -39,6 +39,8 @@ struct FrameState {
   int32_t visible;    // visible triangles (length of the visible list)
   int32_t fp_columns; // full-scale footprint profile columns of the frame (footprint push)
   unsigned long long occupied;
+  uint32_t ticket;    // workgroups of the occupancy count that have finished
+  uint32_t pad;
 };
 
 // Constants of one visibility pass, passed by value (float64).
@@ -209,6 +211,75 @@ __device__ __forceinline__ T block_sum(T v, T* sh) {
   return m;
 }
 
+// ---------------------------------------------------------------------------
+// cross-lane primitives on the DPP (data-parallel primitives) network: the
+// lane moves ride on VALU instructions instead of LDS permutes. Every lane of
+// the wave must be active.
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  // lanes without a source (outside their row, or rows not in ROWS) read 0
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_keep(int v) {
+  // lanes without a source keep their own value
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+
+// Maximum over each row of 16 lanes; every lane of the row receives it
+// (pairs, quads, half rows, rows).
+__device__ __forceinline__ int row16_max(int v) {
+  v = max(v, dpp_keep<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+  v = max(v, dpp_keep<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+  v = max(v, dpp_keep<0x141>(v));  // row_half_mirror
+  v = max(v, dpp_keep<0x140>(v));  // row_mirror
+  return v;
+}
+
+// Maximum over the wave (uniform result).
+__device__ __forceinline__ int wave_max_dpp(int v) {
+  v = row16_max(v);
+  const int a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+  const int c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+  return max(max(a, b), max(c, d));
+}
+
+// Inclusive prefix sum over the wave: shifts by 1, 2, 4 and 8 lanes inside
+// each row of 16, then the totals of rows 0 and 2 into rows 1 and 3, then
+// the total of rows 0-1 into rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v) {
+  v += dpp_u32<0x111>(v);       // row_shr:1
+  v += dpp_u32<0x112>(v);       // row_shr:2
+  v += dpp_u32<0x114>(v);       // row_shr:4
+  v += dpp_u32<0x118>(v);       // row_shr:8
+  v += dpp_u32<0x142, 0xA>(v);  // row_bcast:15
+  v += dpp_u32<0x143, 0xC>(v);  // row_bcast:31
+  return v;
+}
+
+// Block-wide inclusive sum of 32-bit values with one barrier: `sh` holds
+// NW words and must not be the `sh` of the previous call (callers alternate
+// two buffers). *total gets the block sum.
+template <int NT>
+__device__ __forceinline__ uint32_t block_incl_scan_dpp(uint32_t v, uint32_t* sh,
+                                                        uint32_t* total) {
+  constexpr int NW = NT / kWave;
+  const int w = threadIdx.x / kWave;
+  const uint32_t x = wave_incl_scan_dpp(v);
+  if (lane_id() == kWave - 1) sh[w] = x;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const uint32_t s = sh[k];
+    before += k < w ? s : 0u;
+    all += s;
+  }
+  *total = all;
+  return x + before;
+}
+
 __host__ __device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b) {
   int64_t q = a / b;
   return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
@@ -241,9 +312,13 @@ hipError_t launch_index_guard(const int32_t* flag, const Work& w, hipStream_t st
 hipError_t launch_prologue(const float* pos, int64_t V, const uint8_t* vis, const int32_t* nbr,
                            int64_t T, const FrameParams& p, const Work& w, int32_t* cov,
                            int32_t* cot, int uf_init, Marker& mk, hipStream_t st);
+// occ_fill: when not NULL, this [omega][omega] occupancy map is filled with -1
+// by workgroups past the union-find tiles (hook mode 5) or past the box
+// gather (the other modes); both kernels are bound by dependent loads and
+// leave memory bandwidth free.
 hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* nbr, int64_t T,
                          const FrameParams& p, const Work& w, int32_t* cot, int32_t* cov,
-                         fa_chart* charts, Marker& mk, hipStream_t st);
+                         fa_chart* charts, int32_t* occ_fill, Marker& mk, hipStream_t st);
 hipError_t launch_order(const FrameParams& p, const Work& w, fa_chart* charts, int from_accum,
                         hipStream_t st);
 // footprint push: the full-scale profile of every chart (clear, then raster)
@@ -261,11 +336,21 @@ hipError_t launch_uv(const int64_t V, const FrameParams& p, const Work& w, const
 hipError_t launch_uv_corners(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
                              const int32_t* cot, const fa_chart* charts, float* uv,
                              hipStream_t st);
-// count: also count the occupied texels for the frame record (the frame's
+// What an occupancy pass does besides the raster: fill the map with -1 first
+// (unless an earlier launch already did), compute the per-vertex UVs beside
+// the raster (uv != NULL: V vertices, chart of each vertex in cov), and count
+// the occupied texels and write the frame record (meta != NULL: the frame's
 // own atlas; a scaled copy is drawn without).
+struct OccExtras {
+  bool fill = true;
+  float* uv = nullptr;
+  const int32_t* cov = nullptr;
+  int64_t V = 0;
+  fa_atlas_meta* meta = nullptr;
+};
 hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
                             const int32_t* cot, const fa_chart* charts, int32_t* occ,
-                            int small_texels, int lane_texels, bool count, Marker& mk,
+                            int small_texels, int lane_texels, const OccExtras& x, Marker& mk,
                             hipStream_t st);
 // Occupancy of the frame's packing drawn into an atlas of side p.omega (a
 // scaled copy of the frame's atlas): box ranges for that side, then the
@@ -281,8 +366,9 @@ hipError_t launch_reuse_flags(const float* pos, const int32_t* idx, int64_t T, c
 hipError_t launch_visibility(const float* pos, const int32_t* idx, int64_t T, const VisParams& q,
                              int32_t* occl, uint32_t* count, unsigned long long* depth,
                              uint8_t* vis, hipStream_t st);
+// Frame record without an occupancy map.
 hipError_t launch_meta(const FrameParams& p, const Work& w, fa_atlas_meta* meta,
-                       int with_occupancy, hipStream_t st);
+                       hipStream_t st);
 
 // Tuning knobs a frame reads (every accepted value gives the same results).
 struct Knobs {

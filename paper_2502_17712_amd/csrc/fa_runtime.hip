@@ -515,8 +515,10 @@ int run_frame_core(const Knobs& kn, const Work& w, const fa_mesh* mesh, const in
   ok(launch_prologue(mesh->positions, V, visible, nbr, T, p, w, cov, out->chart_of_tri,
                      tiles_start ? 0 : (kn.uf_link_init ? 2 : 1), mk, st));
   if (index_flag) ok(launch_index_guard(index_flag, w, st));
+  // the occupancy map is filled with -1 by spare workgroups of the box gather
+  int32_t* occ_fill = T > 0 ? out->occupancy : nullptr;
   ok(launch_charts(visible, mesh->indices, nbr, T, p, w, out->chart_of_tri, cov, out->charts,
-                   mk, st));
+                   occ_fill, mk, st));
   ok(launch_order(p, w, out->charts, 1, st));
   mk(st);
   ok(launch_footprint(mesh->indices, T, p, w, out->chart_of_tri, out->charts, mk, st));
@@ -524,17 +526,30 @@ int run_frame_core(const Knobs& kn, const Work& w, const fa_mesh* mesh, const in
   mk(st);
   ok(launch_select_place(p, w, out->charts, out->candidates, st));
   mk(st);
-  if (out->uv) {
-    if (p.flags & FA_FLAG_EDGE_ONLY_CHARTS)
+  // per-vertex UVs run beside the occupancy raster when there is one
+  const bool edge_only = (p.flags & FA_FLAG_EDGE_ONLY_CHARTS) != 0;
+  const bool uv_with_occ = out->uv && out->occupancy && !edge_only;
+  if (out->uv && !uv_with_occ) {
+    if (edge_only)
       ok(launch_uv_corners(mesh->indices, T, p, w, out->chart_of_tri, out->charts, out->uv, st));
     else
       ok(launch_uv(V, p, w, cov, out->charts, out->uv, st));
   }
   mk(st);
-  if (out->occupancy)
+  if (out->occupancy) {
+    OccExtras x;
+    x.fill = occ_fill == nullptr;
+    if (uv_with_occ) {
+      x.uv = out->uv;
+      x.cov = cov;
+      x.V = V;
+    }
+    x.meta = out->meta;  // the count launch writes the frame record
     ok(launch_occupancy(mesh->indices, T, p, w, out->chart_of_tri, out->charts, out->occupancy,
-                        kn.small_texels, kn.lane_texels, true, mk, st));
-  ok(launch_meta(p, w, out->meta, out->occupancy != nullptr, st));
+                        kn.small_texels, kn.lane_texels, x, mk, st));
+  } else {
+    ok(launch_meta(p, w, out->meta, st));
+  }
   mk(st);
   return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
 }
@@ -713,7 +728,7 @@ int fa_pack_boxes(fa_ctx* ctx, const float* sizes, int32_t n, int32_t atlas_size
   ok(launch_pack(p, w, ctx->pack_block, false, st));
   ok(launch_select_place(p, w, charts, candidates, st));
   ok(launch_pack_emit(n, charts, placements, w, st));
-  ok(launch_meta(p, w, meta, 0, st));
+  ok(launch_meta(p, w, meta, st));
   return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
 }
 

@@ -310,12 +310,15 @@ __global__ __launch_bounds__(NT) void k_uf_local(const uint8_t* __restrict__ vis
 // global vertex pass merges through every vertex anyway). Then, as in mode 4,
 // each entry's parent becomes its local root and its vertices' minima are
 // lowered to it.
+// Workgroups past the tiles fill the occupancy map with -1 (occ_fill, n4
+// 16-byte words) while the tiles' dependent loads leave memory bandwidth free.
 template <int TILE, int NT, int HS>
 __global__ __launch_bounds__(NT) void k_uf_local_vertex(const int32_t* __restrict__ idx,
                                                         const int32_t* __restrict__ vlist,
                                                         int32_t* __restrict__ parent,
                                                         int32_t* __restrict__ vmin,
-                                                        const FrameState* __restrict__ st) {
+                                                        const FrameState* __restrict__ st,
+                                                        int4* __restrict__ occ_fill, int64_t n4) {
   static_assert((HS & (HS - 1)) == 0, "hash slots: a power of two");
   static_assert(TILE % NT == 0, "whole entries per thread");
   constexpr int kPer = TILE / NT;  // entries per thread: i = threadIdx.x + k NT
@@ -325,7 +328,16 @@ __global__ __launch_bounds__(NT) void k_uf_local_vertex(const int32_t* __restric
   __shared__ unsigned long long tab[HS];
   const int nv = st->visible;
   const int64_t s0 = (int64_t)blockIdx.x * TILE;
-  if (s0 >= nv) return;
+  if (s0 >= nv) {
+    if (occ_fill) {
+      const int64_t active = ((int64_t)nv + TILE - 1) / TILE;
+      const int64_t nb = (int64_t)gridDim.x - active;
+      const int4 neg = make_int4(-1, -1, -1, -1);
+      for (int64_t i = ((int64_t)blockIdx.x - active) * NT + threadIdx.x; i < n4; i += nb * NT)
+        occ_fill[i] = neg;
+    }
+    return;
+  }
   const int cnt = (int)min<int64_t>(TILE, nv - s0);
   // every entry's triangle and vertices are loaded up front (the loads of
   // a thread's entries overlap) and kept in registers until the end
@@ -655,18 +667,32 @@ __device__ __forceinline__ bool triangle_ndc_box(const float4& a, const float4& 
 // serialize on their four accumulator words).
 constexpr int kGatherItems = 4;
 constexpr int kSlots = 64;
+constexpr unsigned kFillBlocks = 1024;  // least workgroups that fill the occupancy map
+constexpr unsigned kFillGroups = 256;   // the same for the 1024-thread union-find tiles
 
 __global__ __launch_bounds__(kBlock) void k_gather_boxes(
     const int32_t* __restrict__ vlist, const int32_t* __restrict__ idx,
     const int32_t* __restrict__ parent, const float4* __restrict__ clip, int32_t* cot,
     int32_t* __restrict__ cov, uint32_t* __restrict__ accum, uint32_t flags,
-    const FrameState* __restrict__ st) {
+    const FrameState* __restrict__ st, int4* __restrict__ occ_fill, int64_t n4) {
   __shared__ int32_t skey[kSlots];
   __shared__ uint32_t sbox[kSlots][4];
-  if (st->status != FA_OK) return;
   const int nv = st->visible;
-  const int64_t base = (int64_t)blockIdx.x * (kBlock * kGatherItems);
-  if (base >= nv) return;
+  const int64_t per = kBlock * kGatherItems;
+  const int64_t active = (nv + per - 1) / per;
+  if ((int64_t)blockIdx.x >= active) {
+    // workgroups past the gather's own fill the occupancy map with -1
+    if (occ_fill) {
+      const int64_t nb = (int64_t)gridDim.x - active;
+      const int4 neg = make_int4(-1, -1, -1, -1);
+      for (int64_t i = ((int64_t)blockIdx.x - active) * kBlock + threadIdx.x; i < n4;
+           i += nb * kBlock)
+        occ_fill[i] = neg;
+    }
+    return;
+  }
+  if (st->status != FA_OK) return;
+  const int64_t base = (int64_t)blockIdx.x * per;
   for (int i = threadIdx.x; i < kSlots; i += blockDim.x) {
     skey[i] = -1;
     sbox[i][0] = sbox[i][1] = 0xFFFFFFFFu;
@@ -829,9 +855,11 @@ hipError_t launch_prologue(const float* pos, int64_t V, const uint8_t* vis, cons
 
 hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* nbr, int64_t T,
                          const FrameParams& p, const Work& w, int32_t* cot, int32_t* cov,
-                         fa_chart* charts, Marker& mk, hipStream_t st) {
+                         fa_chart* charts, int32_t* occ_fill, Marker& mk, hipStream_t st) {
   const unsigned g = visible_grid(T);
   const unsigned vt = std::max(1u, grid_for(T, kTriTile));
+  const int64_t n4 = (int64_t)p.omega * p.omega / 4;
+  bool fill_done = false;
   if (T > 0 && (p.flags & FA_FLAG_EDGE_ONLY_CHARTS)) {
     // edge-connected charts: shared edges only, no vertex passes
     if (p.edge_hooks == 1) {
@@ -857,9 +885,13 @@ hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* 
     if (p.edge_hooks == 1) {
       k_uf_hook<<<g, kBlock, 0, st>>>(vis, nbr, w.vlist, w.parent, 0, w.state);
     } else if (p.edge_hooks == 5) {
-      // tiles of 2048 entries and a 4096-slot table (at most ~3/4 full)
-      k_uf_local_vertex<2048, 1024, 4096><<<std::max(1u, grid_for(T, 2048)), 1024, 0, st>>>(
-          idx, w.vlist, w.parent, w.vmin, w.state);
+      // tiles of 2048 entries and a 4096-slot table (at most ~3/4 full); at
+      // least kFillGroups workgroups past the largest visible list fill the
+      // occupancy map
+      k_uf_local_vertex<2048, 1024, 4096>
+          <<<std::max(1u, grid_for(T, 2048)) + (occ_fill ? kFillGroups : 0u), 1024, 0, st>>>(
+              idx, w.vlist, w.parent, w.vmin, w.state, reinterpret_cast<int4*>(occ_fill), n4);
+      fill_done = true;
     } else if (p.edge_hooks >= 2) {
       const int tile = p.uf_tile;
       const int32_t* vidx = p.edge_hooks == 4 ? idx : nullptr;
@@ -893,8 +925,13 @@ hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* 
     k_assign_roots<<<vt, kBlock, 0, st>>>(w.vlist, w.parent, w.tile_count, cot, charts, w.accum,
                                           p.max_charts, w.state);
     mk(st);
-    k_gather_boxes<<<grid_for(T, kBlock * kGatherItems), kBlock, 0, st>>>(
-        w.vlist, idx, w.parent, w.clip, cot, cov, w.accum, p.flags, w.state);
+    // the fill, unless the union-find tile kernel did it: at least kFillBlocks
+    // workgroups beyond the largest visible list
+    int32_t* gfill = fill_done ? nullptr : occ_fill;
+    const unsigned fill_blocks = gfill ? kFillBlocks : 0u;
+    k_gather_boxes<<<grid_for(T, kBlock * kGatherItems) + fill_blocks, kBlock, 0, st>>>(
+        w.vlist, idx, w.parent, w.clip, cot, cov, w.accum, p.flags, w.state,
+        reinterpret_cast<int4*>(gfill), n4);
   } else {
     mk(st);
   }

@@ -35,15 +35,14 @@
 namespace fa {
 namespace {
 
-// Candidates of frames with at most kPackLds charts keep their prefix sums
-// and sizes in LDS next to the frontline, so the sequential row loop never
-// waits on global memory.
+// Footprint push: candidates of frames with at most kPackLds charts keep
+// their prefix sums and sizes in LDS next to the frontline.
 constexpr int kPackLds = 4096;
 
-// MODE 0: the whole box packing of one candidate. Footprint push in three
-// launches: MODE 1 sizes, fold, overflow and row starts (to global memory;
-// tab[3] = -1 marks a rejected candidate, tab[5] the number of rows with
-// boxes), then k_fp_pool, then MODE 2 the push.
+// Footprint push in three launches: MODE 1 sizes, fold, overflow and row
+// starts (to global memory; tab[3] = -1 marks a rejected candidate, tab[5]
+// the number of rows with boxes), then k_fp_pool, then MODE 2 the push. (The
+// box push is k_pack_box.)
 template <int NT, int MODE>
 __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
                                              const FrameState* __restrict__ st, FrameParams p,
@@ -201,44 +200,7 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
     const int s0 = RS[rr], s1 = RS[rr + 1];
     const long long r = X[s0] >> lg;
     const bool right = (r % 3) != 0;
-    if constexpr (MODE == 0) {
-      // four consecutive boxes per wave step, 16 lanes each (a box's reads,
-      // a 16-lane max, then its writes); a group with a box wider than 64
-      // columns takes its boxes one at a time with the whole wave
-      const int sub = lane >> 4, sl = lane & 15;
-      for (int kb = s0 + 4 * w; kb < s1; kb += 4 * NW) {
-        const int k = kb + sub;
-        const bool act = k < s1;
-        int a = 0, b = 0, x = 0;
-        if (act) {
-          const uint32_t ab = AB[k];
-          a = (int)(ab & 0xFFFFu);
-          b = (int)(ab >> 16);
-          const int o = (int)(X[k] - (r << lg));
-          x = right ? L - o - a : o;
-        }
-        if (__ballot(act && a > kWave)) {
-          for (int q = 0; q < 4 && kb + q < s1; ++q) {
-            const int aq = __shfl(a, 16 * q, kWave), bq = __shfl(b, 16 * q, kWave);
-            const int xq = __shfl(x, 16 * q, kWave);
-            int mx = 0;
-            for (int c = xq + lane; c < xq + aq; c += kWave) mx = max(mx, F[c]);
-            const int y = wave_max<int>(mx);
-            for (int c = xq + lane; c < xq + aq; c += kWave) F[c] = y + bq;
-            if (lane == 0) Y[kb + q] = y;
-            Hw = max(Hw, y + bq);
-          }
-        } else {
-          int mx = 0;
-          for (int c = x + sl; c < x + a; c += 16) mx = max(mx, F[c]);
-#pragma unroll
-          for (int o2 = 1; o2 < 16; o2 <<= 1) mx = max(mx, __shfl_xor(mx, o2, kWave));
-          for (int c = x + sl; c < x + a; c += 16) F[c] = mx + b;
-          if (act && sl == 0) Y[k] = mx;
-          if (act) Hw = max(Hw, mx + b);
-        }
-      }
-    } else {
+    {
       for (int k = s0 + w; k < s1; k += NW) {
         const long long Xk = X[k];
         const uint32_t ab = AB[k];
@@ -292,6 +254,289 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
     const int H = nr > 0 ? max(Hsh[0], Hsh[1]) : 0;
     tab[0] = H <= L ? 1 : 0;
     tab[1] = (int32_t)m;
+    tab[2] = L;
+    tab[3] = H;
+    tab[4] = (int32_t)min(rows, (long long)INT_MAX);
+  }
+}
+
+// Box push of one candidate per workgroup (the default packing). Everything
+// the row loop reads is in LDS, so its only global accesses are the stores of
+// the box positions, which no later instruction of the workgroup waits for:
+//   [2 omega]  frontline F (int32)
+//   [kcap]     fold position of each box of the current chunk, relative to
+//              the chunk's first box (uint32: a chunk spans less than 2^32)
+//   [kcap]     a | b << 16 of each box of the chunk
+//   [kcap + 1] chunk-local starts of the chunk's row segments
+// Frames with more than kcap charts are pushed in chunks of kcap boxes in
+// order, reloaded from the fold written to global memory; a row that
+// straddles two chunks is pushed as two segments (its boxes have disjoint
+// spans, so the split changes nothing). One barrier per segment; the next
+// segment's bounds and first boxes are loaded while the current one is
+// pushed, and cross-lane maxima and scans use DPP lane moves.
+constexpr int kFoldItems = 4;  // consecutive boxes per thread in the fold
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pack_box(const float2* __restrict__ wh,
+                                                 const FrameState* __restrict__ st, FrameParams p,
+                                                 long long* __restrict__ cand_x,
+                                                 uint32_t* __restrict__ cand_ab,
+                                                 int32_t* __restrict__ cand_y,
+                                                 int32_t* __restrict__ cand_tab, int64_t stride,
+                                                 int kcap) {
+  extern __shared__ int32_t F[];
+  constexpr int NW = NT / kWave;
+  __shared__ uint32_t shs[2][NW];
+  __shared__ int32_t shm[NW], shb[NW];
+  __shared__ int32_t Hsh[3];
+  __shared__ long long last_x;
+  __shared__ long long sh64[NW];
+
+  if (st->status != FA_OK) return;
+  const int j = blockIdx.x + 1;
+  const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+  const int C = st->num_charts;
+  const int omega = p.omega, lg = p.log2omega;
+  long long* Xg = cand_x + (int64_t)(j - 1) * stride;
+  uint32_t* ABg = cand_ab + (int64_t)(j - 1) * stride;
+  int32_t* Y = cand_y + (int64_t)(j - 1) * stride;
+  int32_t* tab = cand_tab + (j - 1) * kCandStride;
+  uint32_t* Xr = reinterpret_cast<uint32_t*>(F + 2 * omega);
+  uint32_t* AB = Xr + kcap;
+  int32_t* RS = reinterpret_cast<int32_t*>(AB + kcap);
+
+  // ---- sizes, fold and overflow: kFoldItems consecutive boxes per thread, a
+  // thread-local prefix, then one block scan of the thread sums; the first
+  // chunk goes straight to LDS
+  const float s = (float)j / (float)p.J;
+  const int pad = 2 * p.gutter;
+  long long run = 0;
+  int mloc = INT_MIN, bad = 0;
+  if (tid == 0) last_x = 0;
+  int pass = 0;
+  for (int base = 0; base < C; base += kFoldItems * NT, ++pass) {
+    const int i0 = base + kFoldItems * tid;
+    int a[kFoldItems], b[kFoldItems];
+    uint32_t own = 0;
+#pragma unroll
+    for (int u = 0; u < kFoldItems; ++u) {
+      a[u] = b[u] = 0;
+      if (i0 + u < C) {
+        const float2 v = wh[i0 + u];
+        a[u] = max(p.min_box, (int)ceilf(v.x * s)) + pad;
+        b[u] = max(p.min_box, (int)ceilf(v.y * s)) + pad;
+        if (a[u] > 2 * omega || b[u] > 2 * omega) bad = 1;  // cannot fit: m > omega or H > L
+        a[u] = min(a[u], 2 * omega + 1);  // (the clamp only touches rejected candidates)
+        b[u] = min(b[u], 2 * omega + 1);
+      }
+      own += (uint32_t)a[u];
+    }
+    uint32_t tot;
+    const uint32_t incl = block_incl_scan_dpp<NT>(own, shs[pass & 1], &tot);
+    long long Xi = run + (long long)(incl - own);
+    run += tot;
+#pragma unroll
+    for (int u = 0; u < kFoldItems; ++u) {
+      const int i = i0 + u;
+      if (i < C) {
+        const uint32_t ab = (uint32_t)a[u] | ((uint32_t)b[u] << 16);
+        Xg[i] = Xi;
+        ABg[i] = ab;
+        if (i < kcap) {
+          Xr[i] = (uint32_t)Xi;
+          AB[i] = ab;
+        }
+        if (i == C - 1) last_x = Xi;
+        mloc = max(mloc, (int)(Xi & (long long)(omega - 1)) + a[u] - omega);
+        Xi += a[u];
+      }
+    }
+  }
+  {
+    const int wm = wave_max_dpp(mloc), wb = wave_max_dpp(bad);
+    if (lane == 0) {
+      shm[w] = wm;
+      shb[w] = wb;
+    }
+  }
+  __syncthreads();
+  int m = 0;
+  bad = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    m = max(m, shm[k]);
+    bad = max(bad, shb[k]);
+  }
+  if (bad) {
+    // a box side above 2 omega rejects the candidate; its overflow m and row
+    // count are still reported exactly, from the unclamped widths in 64 bits
+    long long run2 = 0, ml = 0, lx = 0;
+    for (int base = 0; base < C; base += NT) {
+      const int i = base + tid;
+      long long a = 0;
+      if (i < C) a = max(p.min_box, (int)ceilf(wh[i].x * s)) + pad;
+      long long tot;
+      const long long incl = block_incl_scan<long long>(a, sh64, &tot);
+      const long long Xi = run2 + incl - a;
+      run2 += tot;
+      if (i < C) {
+        ml = max(ml, (Xi & (long long)(omega - 1)) + a - omega);
+        if (i == C - 1) lx = Xi;
+      }
+    }
+    ml = block_max<long long>(ml, sh64);
+    lx = block_max<long long>(lx, sh64);
+    if (tid == 0) {
+      tab[0] = 0;
+      tab[1] = (int32_t)min(ml, (long long)INT_MAX);
+      tab[2] = (int32_t)min(ml + omega, (long long)INT_MAX);
+      tab[3] = -1;
+      tab[4] = (int32_t)min((lx >> lg) + 1, (long long)INT_MAX);
+    }
+    return;
+  }
+  const long long rows = C > 0 ? (last_x >> lg) + 1 : 0;
+  if (m > omega) {
+    if (tid == 0) {
+      tab[0] = 0;
+      tab[1] = m;
+      tab[2] = m + omega;
+      tab[3] = -1;
+      tab[4] = (int32_t)min(rows, (long long)INT_MAX);
+    }
+    return;
+  }
+  const int L = omega + m;
+  for (int c = tid; c < L; c += NT) F[c] = 0;
+  if (tid < 3) Hsh[tid] = 0;
+
+  int Hw = 0, seg = 0;
+  bool over = false;
+  const int sub = lane >> 4, sl = lane & 15;
+  for (int c0 = 0; c0 < C && !over; c0 += kcap) {
+    const int cn = min(kcap, C - c0);
+    long long xbase = 0;
+    if (c0 > 0) {
+      // the previous chunk's segments are done (the barrier ending the last
+      // one); reload the next chunk from the fold in global memory
+      xbase = Xg[c0];
+      constexpr int U = 4;  // loads in flight per thread
+      for (int i0 = tid; i0 < cn; i0 += U * NT) {
+        long long xv[U];
+        uint32_t abv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * NT;
+          xv[u] = i < cn ? Xg[c0 + i] : 0;
+          abv[u] = i < cn ? ABg[c0 + i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * NT;
+          if (i < cn) {
+            Xr[i] = (uint32_t)(xv[u] - xbase);
+            AB[i] = abv[u];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // ---- chunk-local segment starts (first box of each row in the chunk)
+    int nr = 0;
+    for (int base = 0; base < cn; base += kFoldItems * NT, ++pass) {
+      const int i0 = base + kFoldItems * tid;
+      uint32_t fl = 0, own = 0;
+#pragma unroll
+      for (int u = 0; u < kFoldItems; ++u) {
+        const int i = i0 + u;
+        const bool f = i < cn && (i == 0 || ((xbase + Xr[i]) >> lg) != ((xbase + Xr[i - 1]) >> lg));
+        fl |= (uint32_t)f << u;
+        own += f;
+      }
+      uint32_t tot;
+      int at = nr + (int)(block_incl_scan_dpp<NT>(own, shs[pass & 1], &tot) - own);
+#pragma unroll
+      for (int u = 0; u < kFoldItems; ++u)
+        if (fl >> u & 1u) RS[at++] = i0 + u;
+      nr += (int)tot;
+    }
+    if (tid == 0) RS[nr] = cn;
+    __syncthreads();
+
+    // ---- push, segment by segment: four consecutive boxes per wave step, 16
+    // lanes each (a box's reads, a 16-lane max, then its writes); a group
+    // with a box wider than 64 columns takes its boxes one at a time with the
+    // whole wave. Segment rr's bounds and the wave's first boxes of it were
+    // loaded during segment rr - 1.
+    int s0 = 0, s1 = nr > 0 ? RS[1] : 0;
+    long long r = nr > 0 ? (xbase + Xr[0]) >> lg : 0;
+    int k0 = 4 * w + sub;
+    uint32_t ab0 = k0 < cn ? AB[k0] : 0u, xr0 = k0 < cn ? Xr[k0] : 0u;
+    for (int rr = 0; rr < nr; ++rr, ++seg) {
+      // next segment: its end, its row and the wave's first boxes
+      const int s1n = rr + 2 <= nr ? RS[rr + 2] : cn;
+      const uint32_t xfirst = rr + 1 < nr ? Xr[s1] : 0u;
+      const int k1 = s1 + 4 * w + sub;
+      const uint32_t ab1 = k1 < cn ? AB[k1] : 0u, xr1 = k1 < cn ? Xr[k1] : 0u;
+      const int hprev = Hsh[(seg + 2) % 3];  // the height after segment seg - 1
+      const long long rbase = (r << lg) - xbase;
+      const bool right = (r % 3) != 0;
+      uint32_t ab = ab0, xr = xr0;
+      for (int kb = s0 + 4 * w; kb < s1; kb += 4 * NW) {
+        const int k = kb + sub;
+        const bool act = k < s1;
+        // the wave's boxes of the next step of this segment
+        const int kn = k + 4 * NW;
+        const uint32_t abn = kn < s1 ? AB[kn] : 0u, xrn = kn < s1 ? Xr[kn] : 0u;
+        int a = 0, b = 0, x = 0;
+        if (act) {
+          a = (int)(ab & 0xFFFFu);
+          b = (int)(ab >> 16);
+          const int o = (int)((long long)xr - rbase);
+          x = right ? L - o - a : o;
+        }
+        if (__ballot(act && a > kWave)) {
+          for (int q = 0; q < 4 && kb + q < s1; ++q) {
+            const int aq = __builtin_amdgcn_readlane(a, 16 * q);
+            const int bq = __builtin_amdgcn_readlane(b, 16 * q);
+            const int xq = __builtin_amdgcn_readlane(x, 16 * q);
+            int mx = 0;
+            for (int c = xq + lane; c < xq + aq; c += kWave) mx = max(mx, F[c]);
+            const int y = wave_max_dpp(mx);
+            for (int c = xq + lane; c < xq + aq; c += kWave) F[c] = y + bq;
+            if (lane == 0) Y[c0 + kb + q] = y;
+            Hw = max(Hw, y + bq);
+          }
+        } else {
+          int mx = 0;
+          for (int c = x + sl; c < x + a; c += 16) mx = max(mx, F[c]);
+          mx = row16_max(mx);
+          for (int c = x + sl; c < x + a; c += 16) F[c] = mx + b;
+          if (act && sl == 0) Y[c0 + k] = mx;
+          if (act) Hw = max(Hw, mx + b);
+        }
+        ab = abn;
+        xr = xrn;
+      }
+      const int hw = wave_max_dpp(Hw);
+      if (lane == 0) atomicMax(&Hsh[seg % 3], hw);
+      __syncthreads();
+      // every wave read the same settled value: all leave at the same segment
+      if (hprev > L) {
+        over = true;
+        break;
+      }
+      s0 = s1;
+      s1 = s1n;
+      r = (xbase + xfirst) >> lg;
+      ab0 = ab1;
+      xr0 = xr1;
+    }
+  }
+  if (tid == 0) {
+    const int H = C > 0 ? max(Hsh[0], max(Hsh[1], Hsh[2])) : 0;
+    tab[0] = H <= L ? 1 : 0;
+    tab[1] = m;
     tab[2] = L;
     tab[3] = H;
     tab[4] = (int32_t)min(rows, (long long)INT_MAX);
@@ -490,6 +735,36 @@ __global__ void k_pack_emit(int32_t n, const fa_chart* __restrict__ charts,
 }  // namespace
 
 namespace {
+// Dynamic LDS of the box push: frontline plus kcap boxes of 12 bytes.
+constexpr int kBoxPushLds = 131072;
+inline int box_kcap(int omega) { return ((kBoxPushLds - 8 * omega - 4) / 12) & ~63; }
+
+hipError_t box_attributes() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_pack_box<256>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kBoxPushLds);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_pack_box<512>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, kBoxPushLds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_pack_box<1024>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, kBoxPushLds);
+}
+
+void box_launch(const FrameParams& p, const Work& w, int block, hipStream_t st) {
+  const int64_t stride = p.max_charts;
+  const int kcap = box_kcap(p.omega);
+  const size_t dyn = (size_t)8 * p.omega + (size_t)12 * kcap + 4;
+  if (block == 1024)
+    k_pack_box<1024><<<p.J, 1024, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab,
+                                             w.cand_y, w.cand_tab, stride, kcap);
+  else if (block == 512)
+    k_pack_box<512><<<p.J, 512, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab,
+                                           w.cand_y, w.cand_tab, stride, kcap);
+  else
+    k_pack_box<256><<<p.J, 256, dyn, st>>>(w.sorted_wh, w.state, p, w.cand_x, w.cand_ab,
+                                           w.cand_y, w.cand_tab, stride, kcap);
+}
+
 template <int MODE>
 hipError_t pack_attributes(int max_dyn_bytes) {
   hipError_t e = hipFuncSetAttribute((const void*)k_pack<256, MODE>,
@@ -522,7 +797,7 @@ void pack_launch(const FrameParams& p, const Work& w, int block, size_t dyn, hip
 
 hipError_t pack_kernel_attributes(int max_frontline_bytes) {
   const int max_dyn_bytes = max_frontline_bytes + kPackLds * 16 + 4;
-  hipError_t e = pack_attributes<0>(max_dyn_bytes);
+  hipError_t e = box_attributes();
   if (e == hipSuccess) e = pack_attributes<1>(max_dyn_bytes);
   if (e == hipSuccess) e = pack_attributes<2>(max_dyn_bytes);
   return e;
@@ -532,7 +807,7 @@ hipError_t launch_pack(const FrameParams& p, const Work& w, int block, bool foot
                        hipStream_t st) {
   const size_t dyn = (size_t)2 * p.omega * sizeof(int32_t) + (size_t)kPackLds * 16 + 4;
   if (!footprint) {
-    pack_launch<0>(p, w, block, dyn, st);
+    box_launch(p, w, block, st);
     return hipGetLastError();
   }
   pack_launch<1>(p, w, block, dyn, st);

@@ -50,17 +50,25 @@ __device__ __forceinline__ float2 to_atlas(const ChartXform& m, float X, float Y
   return make_float2((m.ox + lx * m.s) * m.q, (m.oy + ly * m.s) * m.q);
 }
 
-__global__ void k_uv(int64_t V, FrameParams p, const float4* __restrict__ clip,
-                     const int32_t* __restrict__ cov, const fa_chart* __restrict__ charts,
-                     float2* __restrict__ uv, const FrameState* __restrict__ stp) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= V) return;
+__device__ __forceinline__ void uv_vertex(int64_t v, const FrameParams& p,
+                                          const float4* __restrict__ clip,
+                                          const int32_t* __restrict__ cov,
+                                          const fa_chart* __restrict__ charts,
+                                          float2* __restrict__ uv,
+                                          const FrameState* __restrict__ stp) {
   const FrameState st = *stp;
   const int c = st.status == FA_OK ? cov[v] : -1;
   const float4 q = clip[v];
   float2 r = make_float2(__builtin_nanf(""), __builtin_nanf(""));
   if (c >= 0 && q.w > 0.0f) r = to_atlas(chart_xform(charts[c], p, st), q.x, q.y, q.w);
   uv[v] = r;
+}
+
+__global__ void k_uv(int64_t V, FrameParams p, const float4* __restrict__ clip,
+                     const int32_t* __restrict__ cov, const fa_chart* __restrict__ charts,
+                     float2* __restrict__ uv, const FrameState* __restrict__ stp) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < V) uv_vertex(v, p, clip, cov, charts, uv, stp);
 }
 
 // Per-corner UVs of edge-connected charts: corner k of triangle t is its
@@ -376,15 +384,23 @@ __global__ __launch_bounds__(kOccSmallBlock) void k_occ_small(
     int32_t* __restrict__ occ, ulonglong2* __restrict__ big, int4* __restrict__ big_fp,
     uint32_t big_cap, int small_texels,
     int lane_texels, unsigned long long* __restrict__ big_counter,
-    const FrameState* __restrict__ stp) {
+    const FrameState* __restrict__ stp, unsigned occ_blocks, int64_t V,
+    const int32_t* __restrict__ cov, float2* __restrict__ uv) {
   __shared__ uint32_t wcnt[kOccSmallBlock / kWave], wtil[kOccSmallBlock / kWave];
   __shared__ unsigned long long bbase;
+  if (blockIdx.x >= occ_blocks) {
+    // the blocks past the raster's own compute the per-vertex UVs (they need
+    // the same placement and run beside the raster instead of after it)
+    const int64_t v = (int64_t)(blockIdx.x - occ_blocks) * blockDim.x + threadIdx.x;
+    if (v < V) uv_vertex(v, p, clip, cov, charts, uv, stp);
+    return;
+  }
   const FrameState st = *stp;
   if (st.status != FA_OK) return;
   const int nv = st.visible;
   const int lane = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
   constexpr unsigned long long kLow = (1ull << kSlotShift) - 1;
-  for (int i0 = blockIdx.x * blockDim.x; i0 < nv; i0 += gridDim.x * blockDim.x) {
+  for (int i0 = blockIdx.x * blockDim.x; i0 < nv; i0 += occ_blocks * blockDim.x) {
     const int i = i0 + threadIdx.x;
     const bool valid = i < nv;
     SnapPoly sp;
@@ -548,33 +564,13 @@ __global__ __launch_bounds__(kBlock) void k_occ_big(
   }
 }
 
-// Occupied texels: per-workgroup partial counts (no global atomics; the
-// frame record kernel sums them).
-__global__ void k_occ_count(const int4* __restrict__ occ, int64_t n4,
-                            unsigned long long* __restrict__ partial) {
-  __shared__ unsigned long long sh[kBlock / kWave];
-  unsigned long long cnt = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int4 v = occ[i];
-    cnt += (v.x >= 0) + (v.y >= 0) + (v.z >= 0) + (v.w >= 0);
-  }
-  cnt = block_sum<unsigned long long>(cnt, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = cnt;
-}
-
-// Frame record for the caller; sums the occupancy partial counts when the
-// occupancy map was built.
-__global__ void k_meta(FrameParams p, FrameState* stp,
-                       const unsigned long long* __restrict__ big_counter,
-                       const unsigned long long* __restrict__ partial, int npartial,
-                       fa_atlas_meta* __restrict__ meta) {
-  __shared__ unsigned long long sh[kBlock / kWave];
-  unsigned long long occ = 0;
-  for (int i = threadIdx.x; i < npartial; i += blockDim.x) occ += partial[i];
-  occ = block_sum<unsigned long long>(occ, sh);
-  if (threadIdx.x != 0) return;
-  if (npartial && stp->status == FA_OK) stp->occupied = occ;
+// Frame record for the caller (one thread); `occ` is the occupied texel count
+// when the occupancy map was built.
+__device__ __forceinline__ void write_meta(const FrameParams& p, FrameState* stp,
+                                           const unsigned long long* __restrict__ big_counter,
+                                           bool with_occ, unsigned long long occ,
+                                           fa_atlas_meta* __restrict__ meta) {
+  if (with_occ && stp->status == FA_OK) stp->occupied = occ;
   const FrameState st = *stp;
   fa_atlas_meta m;
   m.status = st.status;
@@ -593,6 +589,56 @@ __global__ void k_meta(FrameParams p, FrameState* stp,
                                                __HIP_MEMORY_SCOPE_AGENT) &
                             ((1ull << 40) - 1));
   *meta = m;
+}
+
+__global__ void k_meta(FrameParams p, FrameState* stp,
+                       const unsigned long long* __restrict__ big_counter,
+                       fa_atlas_meta* __restrict__ meta) {
+  if (threadIdx.x == 0) write_meta(p, stp, big_counter, false, 0ull, meta);
+}
+
+// Occupied texels and the frame record in one launch: every workgroup counts
+// its share of the map and publishes the sum; the last one to finish (the
+// one that draws the last ticket) adds them up and writes the record.
+constexpr int kCountBlock = 1024;
+__global__ __launch_bounds__(kCountBlock) void k_occ_count_meta(
+    FrameParams p, const int4* __restrict__ occ, int64_t n4,
+    unsigned long long* __restrict__ partial, FrameState* stp,
+    const unsigned long long* __restrict__ big_counter, fa_atlas_meta* __restrict__ meta) {
+  __shared__ unsigned long long sh[kCountBlock / kWave];
+  __shared__ uint32_t last;
+  // eight 16-byte loads in flight per thread
+  constexpr int U = 8;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  uint32_t c32 = 0;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < n4; i0 += U * stride) {
+    int4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      v[u] = i0 + u * stride < n4 ? occ[i0 + u * stride] : make_int4(-1, -1, -1, -1);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      c32 += (v[u].x >= 0) + (v[u].y >= 0) + (v[u].z >= 0) + (v[u].w >= 0);
+  }
+  // one thread counts at most 4 texels per 16-byte word it reads: far below 2^32
+  const unsigned long long cnt = block_sum<unsigned long long>((unsigned long long)c32, sh);
+  if (threadIdx.x == 0) {
+    // the sum is stored at device scope and has completed (s_waitcnt on every
+    // counter) before the ticket is taken, so whoever draws the last ticket
+    // reads it with its device-scope load; no cache-wide release is needed
+    __hip_atomic_store(&partial[blockIdx.x], cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);
+    const uint32_t before = __hip_atomic_fetch_add(&stp->ticket, 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+    last = before == gridDim.x - 1 ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!last) return;
+  unsigned long long all = 0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x)
+    all += __hip_atomic_load(&partial[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  all = block_sum<unsigned long long>(all, sh);
+  if (threadIdx.x == 0) write_meta(p, stp, big_counter, true, all, meta);
 }
 
 }  // namespace
@@ -616,27 +662,31 @@ hipError_t launch_uv_corners(const int32_t* idx, int64_t T, const FrameParams& p
 
 hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p, const Work& w,
                             const int32_t* cot, const fa_chart* charts, int32_t* occ,
-                            int small_texels, int lane_texels, bool count, Marker& mk,
+                            int small_texels, int lane_texels, const OccExtras& x, Marker& mk,
                             hipStream_t st) {
   const int64_t n4 = (int64_t)p.omega * p.omega / 4;
-  const unsigned fill_grid = (unsigned)std::min<int64_t>((n4 + kBlock - 1) / kBlock, 4096);
-  k_occ_fill<<<fill_grid, kBlock, 0, st>>>(reinterpret_cast<int4*>(occ), n4, w.state);
-  mk(st);
-  const uint32_t cap = (uint32_t)std::min<int64_t>(2 * std::max<int64_t>(T, 1), kBigCap);
-  if (T > 0) {
-    k_occ_small<<<visible_grid(T), kOccSmallBlock, 0, st>>>(
-        idx, w.vlist, p, w.clip, cot, charts, w.chart_tex, occ, w.big, w.big_fp, cap, small_texels,
-        lane_texels, w.big_counter, w.state);
-    mk(st);
-    k_occ_big<<<kOccBigGrid, kBlock, 0, st>>>(idx, p, w.clip, cot, charts, w.chart_tex, occ,
-                                              w.big, w.big_fp, cap, w.big_counter, w.state);
-  } else {
-    mk(st);
+  if (x.fill) {
+    const unsigned fill_grid = (unsigned)std::min<int64_t>((n4 + kBlock - 1) / kBlock, 4096);
+    k_occ_fill<<<fill_grid, kBlock, 0, st>>>(reinterpret_cast<int4*>(occ), n4, w.state);
   }
   mk(st);
-  if (count)  // a scaled copy (no frame record) needs no count
-    k_occ_count<<<kCountGrid, kBlock, 0, st>>>(reinterpret_cast<const int4*>(occ), n4,
-                                               w.partial);
+  const uint32_t cap = (uint32_t)std::min<int64_t>(2 * std::max<int64_t>(T, 1), kBigCap);
+  const int64_t V = x.uv ? x.V : 0;
+  const unsigned occ_blocks = T > 0 ? visible_grid(T) : 0;
+  const unsigned uv_blocks = (unsigned)((V + kOccSmallBlock - 1) / kOccSmallBlock);
+  if (occ_blocks + uv_blocks > 0)
+    k_occ_small<<<occ_blocks + uv_blocks, kOccSmallBlock, 0, st>>>(
+        idx, w.vlist, p, w.clip, cot, charts, w.chart_tex, occ, w.big, w.big_fp, cap, small_texels,
+        lane_texels, w.big_counter, w.state, occ_blocks, V, x.cov,
+        reinterpret_cast<float2*>(x.uv));
+  mk(st);
+  if (T > 0)
+    k_occ_big<<<kOccBigGrid, kBlock, 0, st>>>(idx, p, w.clip, cot, charts, w.chart_tex, occ,
+                                              w.big, w.big_fp, cap, w.big_counter, w.state);
+  mk(st);
+  if (x.meta)  // a scaled copy (no frame record) needs no count
+    k_occ_count_meta<<<kCountGrid, kCountBlock, 0, st>>>(p, reinterpret_cast<const int4*>(occ), n4,
+                                                         w.partial, w.state, w.big_counter, x.meta);
   mk(st);
   return hipGetLastError();
 }
@@ -668,8 +718,8 @@ hipError_t launch_occupancy_scaled(const int32_t* idx, int64_t T, const FramePar
   k_chart_tex<<<(unsigned)((p.max_charts + kBlock - 1) / kBlock), kBlock, 0, st>>>(
       p, charts, w.chart_tex, w.big_counter, w.state);
   Marker none;
-  return launch_occupancy(idx, T, p, w, cot, charts, occ, small_texels, lane_texels, false,
-                          none, st);
+  OccExtras x;
+  return launch_occupancy(idx, T, p, w, cot, charts, occ, small_texels, lane_texels, x, none, st);
 }
 
 namespace {
@@ -986,9 +1036,8 @@ hipError_t launch_footprint(const int32_t* idx, int64_t T, const FrameParams& p,
 }
 
 hipError_t launch_meta(const FrameParams& p, const Work& w, fa_atlas_meta* meta,
-                       int with_occupancy, hipStream_t st) {
-  k_meta<<<1, kBlock, 0, st>>>(p, w.state, w.big_counter, w.partial,
-                               with_occupancy ? kCountGrid : 0, meta);
+                       hipStream_t st) {
+  k_meta<<<1, kWave, 0, st>>>(p, w.state, w.big_counter, meta);
   return hipGetLastError();
 }
 

@@ -259,27 +259,19 @@ __device__ __forceinline__ void chart_size(const FrameParams& p, const uint4 e, 
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderLds = 1024;
 
-__global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
-    FrameParams p, const uint32_t* __restrict__ accum, fa_chart* __restrict__ charts,
-    uint32_t* __restrict__ keys_a, int32_t* __restrict__ vals_a, uint32_t* __restrict__ keys_b,
-    int32_t* __restrict__ vals_b, float2* __restrict__ sorted_wh, int from_accum,
-    int32_t* __restrict__ fp_off, FrameState* __restrict__ st) {
+// The body for one placement of the keys and values (LDS or global memory),
+// so that every access of the sort has a known address space.
+template <bool LDS>
+__device__ __forceinline__ void order_body(const FrameParams& p, const uint32_t* __restrict__ accum,
+                                           fa_chart* __restrict__ charts, uint32_t* KA,
+                                           int32_t* VA, uint32_t* KB, int32_t* VB, float2* lwh,
+                                           int32_t* __restrict__ vals_out,
+                                           float2* __restrict__ sorted_wh, int from_accum,
+                                           int32_t* __restrict__ fp_off, FrameState* st, int C,
+                                           uint32_t* base, uint32_t (*wcnt)[kRadix],
+                                           uint32_t* sh, long long* sh64) {
   constexpr int NW = kOrderThreads / kWave;
-  __shared__ uint32_t base[kRadix];
-  __shared__ uint32_t wcnt[NW][kRadix];
-  __shared__ uint32_t sh[NW];
-  __shared__ long long sh64[NW];
-  __shared__ uint32_t lk[2][kOrderLds];
-  __shared__ int32_t lv[2][kOrderLds];
-  __shared__ float2 lwh[kOrderLds];
-  if (st->status != FA_OK) return;
-  const int C = min(st->num_charts, p.max_charts);
   const int tid = threadIdx.x, w = tid / kWave;
-  const bool lds = from_accum && C <= kOrderLds;
-  uint32_t* KA = lds ? lk[0] : keys_a;
-  int32_t* VA = lds ? lv[0] : vals_a;
-  uint32_t* KB = lds ? lk[1] : keys_b;
-  int32_t* VB = lds ? lv[1] : vals_b;
   if (from_accum) {
     for (int c = tid; c < C; c += kOrderThreads) {
       uint32_t key;
@@ -294,7 +286,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
       chart_size(p, box, charts[c], key, wh);
       KA[c] = key;
       VA[c] = c;
-      if (lds) lwh[c] = wh;
+      if (LDS) lwh[c] = wh;
     }
     __syncthreads();
   }
@@ -311,7 +303,8 @@ __global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
     {
       const uint32_t v = tid < kRadix ? base[tid] : 0u;
       uint32_t tot;
-      const uint32_t ex = block_incl_scan<uint32_t>(v, sh, &tot) - v;
+      const uint32_t ex = block_incl_scan_dpp<kOrderThreads>(v, sh, &tot) - v;
+      __syncthreads();  // (sh is reused by the next scan)
       if (tid < kRadix) base[tid] = ex;
     }
     for (int c0 = 0; c0 < C; c0 += kOrderThreads) {
@@ -322,6 +315,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
       const int i = c0 + tid;
       const bool valid = i < C;
       const uint32_t key = valid ? kin[i] : 0u;
+      const int32_t val = valid ? vin[i] : 0;
       const uint32_t d = (key >> shift) & (kRadix - 1);
       unsigned long long m = __ballot(valid);
 #pragma unroll
@@ -348,7 +342,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
       if (valid) {
         const uint32_t pos = wcnt[w][d] + rank;
         kout[pos] = key;
-        vout[pos] = vin[i];
+        vout[pos] = val;
       }
       __syncthreads();
     }
@@ -356,9 +350,9 @@ __global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
   for (int i = tid; i < C; i += kOrderThreads) {
     const int c = VA[i];
     fa_chart& ch = charts[c];
-    if (lds) {
+    if (LDS) {
       sorted_wh[i] = lwh[c];
-      vals_a[i] = c;
+      vals_out[i] = c;
     } else {
       sorted_wh[i] = make_float2(ch.oriented_w, ch.oriented_h);
     }
@@ -369,7 +363,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
     for (int base0 = 0; base0 < C; base0 += kOrderThreads) {
       const int c = base0 + tid;
       const long long n =
-          c < C ? (long long)floorf(lds ? lwh[c].x : charts[c].oriented_w) + 1 : 0;
+          c < C ? (long long)floorf(LDS ? lwh[c].x : charts[c].oriented_w) + 1 : 0;
       long long tot;
       const long long incl = block_incl_scan<long long>(n, sh64, &tot);
       if (c < C) fp_off[c] = (int32_t)min(run + incl - n, (long long)p.fp_cap);
@@ -381,6 +375,29 @@ __global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
       if (run > p.fp_cap) st->status = FA_ERR_CAPACITY;
     }
   }
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
+    FrameParams p, const uint32_t* __restrict__ accum, fa_chart* __restrict__ charts,
+    uint32_t* __restrict__ keys_a, int32_t* __restrict__ vals_a, uint32_t* __restrict__ keys_b,
+    int32_t* __restrict__ vals_b, float2* __restrict__ sorted_wh, int from_accum,
+    int32_t* __restrict__ fp_off, FrameState* __restrict__ st) {
+  constexpr int NW = kOrderThreads / kWave;
+  __shared__ uint32_t base[kRadix];
+  __shared__ uint32_t wcnt[NW][kRadix];
+  __shared__ uint32_t sh[NW];
+  __shared__ long long sh64[NW];
+  __shared__ uint32_t lk[2][kOrderLds];
+  __shared__ int32_t lv[2][kOrderLds];
+  __shared__ float2 lwh[kOrderLds];
+  if (st->status != FA_OK) return;
+  const int C = min(st->num_charts, p.max_charts);
+  if (from_accum && C <= kOrderLds)
+    order_body<true>(p, accum, charts, lk[0], lv[0], lk[1], lv[1], lwh, vals_a, sorted_wh,
+                     from_accum, fp_off, st, C, base, wcnt, sh, sh64);
+  else
+    order_body<false>(p, accum, charts, keys_a, vals_a, keys_b, vals_b, nullptr, vals_a,
+                      sorted_wh, from_accum, fp_off, st, C, base, wcnt, sh, sh64);
 }
 
 }  // namespace
