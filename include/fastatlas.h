@@ -355,11 +355,20 @@ int fa_build_atlas_static(const fa_mesh* mesh, const uint8_t* visible, const fa_
  *   FA_TUNE_BATCH_GRAPH       1: fa_build_atlas_batch captures its views into
  *                             a hipGraph once per distinct set of view
  *                             descriptors and replays it (one launch); 0: off
+ *   FA_TUNE_BATCH_LAUNCH      1: fa_build_atlas_batch runs every stage of up to
+ *                             max_views views as one kernel launch (one grid
+ *                             row of workgroups per view), when the context
+ *                             uses hook mode 5 and neither
+ *                             FA_FLAG_FOOTPRINT_PUSH nor FA_FLAG_EDGE_ONLY_CHARTS,
+ *                             every view has uv and occupancy outputs, the
+ *                             mesh has triangles and n <= 256; otherwise (and
+ *                             with 0, the default) each view is launched on
+ *                             its own slot stream
  * fa_set_tuning returns FA_ERR_INVALID_ARG for unknown knobs or values;
  * fa_get_tuning returns the current value or -1. */
 enum { FA_TUNE_PACK_BLOCK = 1, FA_TUNE_OCC_SMALL_TEXELS = 2, FA_TUNE_UF_LINK_INIT = 3,
        FA_TUNE_BATCH_GRAPH = 4, FA_TUNE_UF_EDGE_HOOKS = 5, FA_TUNE_OCC_LANE_TEXELS = 6,
-       FA_TUNE_UF_TILE = 7 };
+       FA_TUNE_UF_TILE = 7, FA_TUNE_BATCH_LAUNCH = 8 };
 int fa_set_tuning(fa_ctx* ctx, int knob, int value);
 int fa_get_tuning(fa_ctx* ctx, int knob);
 

@@ -29,6 +29,7 @@ FA_FLAG_EDGE_ONLY_CHARTS = 2
 FA_FLAG_FOOTPRINT_PUSH = 4
 FA_TUNE_PACK_BLOCK, FA_TUNE_OCC_SMALL_TEXELS, FA_TUNE_UF_LINK_INIT, FA_TUNE_BATCH_GRAPH = 1, 2, 3, 4
 FA_TUNE_UF_EDGE_HOOKS, FA_TUNE_OCC_LANE_TEXELS, FA_TUNE_UF_TILE = 5, 6, 7
+FA_TUNE_BATCH_LAUNCH = 8
 
 
 class fa_config(ctypes.Structure):

@@ -386,6 +386,35 @@ int run_frame_core(const Knobs& kn, const Work& w, const fa_mesh* mesh, const in
                    const uint8_t* visible, const FrameParams& p, const fa_atlas_out* out,
                    const int32_t* index_flag, Marker& mk, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// batched frames: every stage of n views of one mesh in one launch per stage
+// (grid y = view), each view with its own scratch slot and outputs
+// ---------------------------------------------------------------------------
+struct BatchView {
+  FrameParams p;
+  Work w;
+  const uint8_t* visible;
+  int32_t* cot;        // chart_of_tri [T]
+  int32_t* cov;        // chart_of_vert [V] (the slot's scratch when the caller has none)
+  float* uv;           // [V][2]
+  fa_chart* charts;    // [max_charts]
+  int32_t* occ;        // [omega][omega]
+  fa_atlas_meta* meta;
+  int32_t* cand_out;   // [J][4] or NULL
+};
+// The views (device array dev[0..n)) use hook mode 5, the box push, and all
+// have occupancy and UVs; host[0..n) is the same array on the host (for the
+// launch shapes). Every view's results equal fa_build_atlas's for it.
+hipError_t launch_charts_batched(const BatchView* dev, int n, const float* pos,
+                                 const int32_t* idx, const int32_t* nbr, int64_t T, int64_t V,
+                                 hipStream_t st);
+hipError_t launch_order_batched(const BatchView* dev, int n, hipStream_t st);
+hipError_t launch_pack_batched(const BatchView* dev, int n, int J, int64_t max_charts, int block,
+                               hipStream_t st);
+hipError_t launch_occupancy_batched(const BatchView* dev, int n, const int32_t* idx, int64_t T,
+                                    int64_t V, int small_texels, int lane_texels,
+                                    hipStream_t st);
+
 // packer-only path: sizes [n][2] -> charts' oriented sizes and keys
 hipError_t launch_pack_prepare(const float* sizes, int32_t n, const FrameParams& p,
                                const Work& w, fa_chart* charts, hipStream_t st);

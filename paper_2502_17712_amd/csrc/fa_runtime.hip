@@ -29,6 +29,8 @@ enum { kStages = 21 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
+constexpr int kMaxBatchViews = 256;  // views per batched call (more: per-view launches)
+
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
 int log2i(int64_t x) {
@@ -61,6 +63,10 @@ struct fa_ctx {
   uint64_t use_clock = 0;
   std::unordered_map<uint64_t, Scene> scenes;
   int batch_graph = 0;
+  int batch_launch = 0;               // 1: one launch per stage for all views of a batch
+  BatchView* bv_dev = nullptr;        // [kMaxBatchViews] descriptors of the batched views
+  BatchView* bv_host = nullptr;       // their pinned host staging copy
+  hipEvent_t ev_upload = nullptr;     // the last upload from bv_host has been read
   std::string graph_sig;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -203,12 +209,16 @@ int fa_create(const fa_config* cfg_in, fa_ctx** out_ctx) {
     ctx->slot_streams.push_back(s);
     ctx->slot_join.push_back(e);
   }
-  ctx->held_bytes += 4;
+  ctx->held_bytes += 4 + sizeof(BatchView) * kMaxBatchViews;
   if (cfg.hbm_budget_bytes > 0 && (int64_t)ctx->held_bytes > cfg.hbm_budget_bytes) {
     fa_destroy(ctx);
     return FA_ERR_OUT_OF_MEMORY;
   }
   if (hipMalloc(&ctx->check_flag, 4) != hipSuccess ||
+      hipMalloc(&ctx->bv_dev, sizeof(BatchView) * kMaxBatchViews) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->bv_host, sizeof(BatchView) * kMaxBatchViews,
+                    hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_upload, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_done, hipEventDisableTiming) != hipSuccess ||
       hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -241,6 +251,9 @@ void fa_destroy(fa_ctx* ctx) {
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   for (void* a : ctx->arenas) (void)hipFree(a);
   if (ctx->check_flag) (void)hipFree(ctx->check_flag);
+  if (ctx->bv_dev) (void)hipFree(ctx->bv_dev);
+  if (ctx->bv_host) (void)hipHostFree(ctx->bv_host);
+  if (ctx->ev_upload) (void)hipEventDestroy(ctx->ev_upload);
   if (ctx->vis_list) (void)hipFree(ctx->vis_list);
   if (ctx->vis_count) (void)hipFree(ctx->vis_count);
   if (ctx->vis_depth) (void)hipFree(ctx->vis_depth);
@@ -645,6 +658,37 @@ static int enqueue_views(fa_ctx* ctx, const fa_mesh* mesh, Scene* sc, int32_t n,
   return FA_OK;
 }
 
+// Batched launches: the views' descriptors are in ctx->bv_dev; views
+// [r0, r0 + S) run as one round on slots 0..S-1, one launch per stage.
+static int enqueue_batched(fa_ctx* ctx, const fa_mesh* mesh, Scene* sc, int32_t n,
+                           hipStream_t st) {
+  const int S = (int)ctx->slots.size();
+  const int64_t T = mesh->num_triangles, V = mesh->num_vertices;
+  hipError_t e = hipSuccess;
+  auto ok = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
+  for (int r0 = 0; r0 < n; r0 += S) {
+    const int m = std::min(S, n - r0);
+    const BatchView* d = ctx->bv_dev + r0;
+    ok(launch_charts_batched(d, m, mesh->positions, mesh->indices, sc->nbr, T, V, st));
+    ok(launch_order_batched(d, m, st));
+    ok(launch_pack_batched(d, m, ctx->cfg.num_scales, ctx->cfg.max_charts, ctx->pack_block, st));
+    ok(launch_occupancy_batched(d, m, mesh->indices, T, V, ctx->small_texels, ctx->lane_texels,
+                                st));
+  }
+  return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+
+// The batched launches cover the default configuration: vertex-hashed
+// union-find tiles, the box push, and every view with UVs and occupancy.
+static bool batchable(const fa_ctx* ctx, const fa_mesh* mesh, int32_t n, const fa_view* views) {
+  if (!ctx->batch_launch || n > kMaxBatchViews || mesh->num_triangles <= 0) return false;
+  if (ctx->uf_edge_hooks != 5) return false;
+  if (ctx->cfg.flags & (FA_FLAG_FOOTPRINT_PUSH | FA_FLAG_EDGE_ONLY_CHARTS)) return false;
+  for (int i = 0; i < n; ++i)
+    if (!views[i].out.uv || !views[i].out.occupancy) return false;
+  return true;
+}
+
 int fa_build_atlas_batch(fa_ctx* ctx, const fa_mesh* mesh, int32_t n, const fa_view* views,
                          void* stream) {
   if (!ctx || n < 0 || (n > 0 && !views)) return FA_ERR_INVALID_ARG;
@@ -663,6 +707,33 @@ int fa_build_atlas_batch(fa_ctx* ctx, const fa_mesh* mesh, int32_t n, const fa_v
   Scene* sc = nullptr;
   rc = get_scene(ctx, mesh, st, &sc);
   if (rc) return rc;
+  const bool batched = batchable(ctx, mesh, n, views);
+  if (batched) {
+    // descriptors of every view (view i on slot i % S), staged in pinned
+    // memory once the previous batch's upload has been read
+    const int S = (int)ctx->slots.size();
+    if (hipEventSynchronize(ctx->ev_upload) != hipSuccess) return FA_ERR_DEVICE;
+    BatchView* hv = ctx->bv_host;
+    for (int i = 0; i < n; ++i) {
+      const fa_view& v = views[i];
+      BatchView& b = hv[i];
+      b.p = ps[i];
+      b.w = ctx->slots[i % S];
+      b.visible = v.visible;
+      b.cot = v.out.chart_of_tri;
+      b.cov = v.out.chart_of_vert ? v.out.chart_of_vert : b.w.cov;
+      b.uv = v.out.uv;
+      b.charts = v.out.charts;
+      b.occ = v.out.occupancy;
+      b.meta = v.out.meta;
+      b.cand_out = v.out.candidates;
+    }
+    if (hipMemcpyAsync(ctx->bv_dev, hv, sizeof(BatchView) * (size_t)n, hipMemcpyHostToDevice,
+                       st) != hipSuccess ||
+        hipEventRecord(ctx->ev_upload, st) != hipSuccess)
+      return FA_ERR_DEVICE;
+    if (!ctx->batch_graph) return enqueue_batched(ctx, mesh, sc, n, st);
+  }
   const bool timing = ctx->timing;
   ctx->timing = false;  // no stage events inside a batch
   if (!ctx->batch_graph) {
@@ -674,9 +745,9 @@ int fa_build_atlas_batch(fa_ctx* ctx, const fa_mesh* mesh, int32_t n, const fa_v
   // the scene's resident adjacency and every knob that picks kernels
   std::string sig(reinterpret_cast<const char*>(mesh), sizeof(fa_mesh));
   sig.append(reinterpret_cast<const char*>(views), sizeof(fa_view) * (size_t)n);
-  const int64_t knobs[8] = {(int64_t)(intptr_t)sc->nbr, ctx->pack_block, ctx->small_texels,
+  const int64_t knobs[9] = {(int64_t)(intptr_t)sc->nbr, ctx->pack_block, ctx->small_texels,
                             ctx->lane_texels,          ctx->uf_link_init, ctx->uf_edge_hooks,
-                            ctx->uf_tile,              (int64_t)ctx->cfg.flags};
+                            ctx->uf_tile,              (int64_t)ctx->cfg.flags, batched ? 1 : 0};
   sig.append(reinterpret_cast<const char*>(knobs), sizeof(knobs));
   if (!ctx->graph_exec || sig != ctx->graph_sig) {
     drop_graph(ctx);
@@ -684,7 +755,8 @@ int fa_build_atlas_batch(fa_ctx* ctx, const fa_mesh* mesh, int32_t n, const fa_v
       ctx->timing = timing;
       return FA_ERR_DEVICE;
     }
-    rc = enqueue_views(ctx, mesh, sc, n, views, ps, ctx->cap_stream);
+    rc = batched ? enqueue_batched(ctx, mesh, sc, n, ctx->cap_stream)
+                 : enqueue_views(ctx, mesh, sc, n, views, ps, ctx->cap_stream);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
     ctx->timing = timing;
@@ -763,6 +835,10 @@ int fa_set_tuning(fa_ctx* ctx, int knob, int value) {
       if (value < 0 || value > 4096) return FA_ERR_INVALID_ARG;
       ctx->lane_texels = value;
       return FA_OK;
+    case FA_TUNE_BATCH_LAUNCH:
+      if (value != 0 && value != 1) return FA_ERR_INVALID_ARG;
+      ctx->batch_launch = value;
+      return FA_OK;
     default:
       return FA_ERR_INVALID_ARG;
   }
@@ -778,6 +854,7 @@ int fa_get_tuning(fa_ctx* ctx, int knob) {
     case FA_TUNE_UF_EDGE_HOOKS: return ctx->uf_edge_hooks;
     case FA_TUNE_UF_TILE: return ctx->uf_tile;
     case FA_TUNE_OCC_LANE_TEXELS: return ctx->lane_texels;
+    case FA_TUNE_BATCH_LAUNCH: return ctx->batch_launch;
     default: return -1;
   }
 }

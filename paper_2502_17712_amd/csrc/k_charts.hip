@@ -68,7 +68,7 @@ __device__ __forceinline__ void uf_join(int32_t* parent, int u, int v) {
 // starts linked to the smallest of itself and its visible edge neighbours
 // (Alg. 1, first loop); 1: as its own root (same labels); 0: not written (a
 // later pass writes it).
-__global__ void k_prologue(const float* __restrict__ pos, int64_t V, FrameParams p,
+__device__ __forceinline__ void k_prologue_body(const float* __restrict__ pos, int64_t V, FrameParams p,
                            float4* __restrict__ clip, int32_t* __restrict__ vmin,
                            int32_t* __restrict__ cov, const uint8_t* __restrict__ vis,
                            const int32_t* __restrict__ nbr, int64_t T,
@@ -123,6 +123,16 @@ __global__ void k_prologue(const float* __restrict__ pos, int64_t V, FrameParams
   nv = block_sum<uint32_t>(nv, sh);
   if (threadIdx.x == 0) tile_vis[tile] = nv;
 }
+__global__ void k_prologue(const float* __restrict__ pos, int64_t V, FrameParams p,
+                           float4* __restrict__ clip, int32_t* __restrict__ vmin,
+                           int32_t* __restrict__ cov, const uint8_t* __restrict__ vis,
+                           const int32_t* __restrict__ nbr, int64_t T,
+                           int32_t* __restrict__ parent, int32_t* __restrict__ cot,
+                           uint32_t* __restrict__ tile_vis, int uf_init,
+                           unsigned vblocks, FrameState* st,
+                           unsigned long long* __restrict__ big_counter) {
+  k_prologue_body(pos, V, p, clip, vmin, cov, vis, nbr, T, parent, cot, tile_vis, uf_init, vblocks, st, big_counter);
+}
 
 // Sum of cnt[0 .. n) by one workgroup (the exclusive prefix of tile n).
 __device__ __forceinline__ uint32_t tiles_before(const uint32_t* __restrict__ cnt, int64_t n,
@@ -136,7 +146,7 @@ __device__ __forceinline__ uint32_t tiles_before(const uint32_t* __restrict__ cn
 // Each workgroup sums the visible counts of the tiles before its own (a few
 // thousand words at most) instead of waiting for a separate scan; the last
 // one records the total.
-__global__ void k_vis_compact(const uint8_t* __restrict__ vis, int64_t T,
+__device__ __forceinline__ void k_vis_compact_body(const uint8_t* __restrict__ vis, int64_t T,
                               const uint32_t* __restrict__ tile_vis, int32_t* __restrict__ vlist,
                               FrameState* __restrict__ st) {
   __shared__ uint32_t sh[kBlock / kWave];
@@ -155,6 +165,11 @@ __global__ void k_vis_compact(const uint8_t* __restrict__ vis, int64_t T,
   for (int k = 0; k < 4; ++k)
     if (f[k]) vlist[at++] = (int32_t)(base + k);
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) st->visible = (int32_t)(off + tot);
+}
+__global__ void k_vis_compact(const uint8_t* __restrict__ vis, int64_t T,
+                              const uint32_t* __restrict__ tile_vis, int32_t* __restrict__ vlist,
+                              FrameState* __restrict__ st) {
+  k_vis_compact_body(vis, T, tile_vis, vlist, st);
 }
 
 // Hook across every shared edge once (u < v) (Alg. 1, second loop).
@@ -313,7 +328,7 @@ __global__ __launch_bounds__(NT) void k_uf_local(const uint8_t* __restrict__ vis
 // Workgroups past the tiles fill the occupancy map with -1 (occ_fill, n4
 // 16-byte words) while the tiles' dependent loads leave memory bandwidth free.
 template <int TILE, int NT, int HS>
-__global__ __launch_bounds__(NT) void k_uf_local_vertex(const int32_t* __restrict__ idx,
+__device__ __forceinline__ void k_uf_local_vertex_body(const int32_t* __restrict__ idx,
                                                         const int32_t* __restrict__ vlist,
                                                         int32_t* __restrict__ parent,
                                                         int32_t* __restrict__ vmin,
@@ -390,6 +405,15 @@ __global__ __launch_bounds__(NT) void k_uf_local_vertex(const int32_t* __restric
     for (int e = 0; e < 3; ++e) atomicMin(&vmin[vk[k][e]], r);
   }
 }
+template <int TILE, int NT, int HS>
+__global__ __launch_bounds__(NT) void k_uf_local_vertex(const int32_t* __restrict__ idx,
+                                                        const int32_t* __restrict__ vlist,
+                                                        int32_t* __restrict__ parent,
+                                                        int32_t* __restrict__ vmin,
+                                                        const FrameState* __restrict__ st,
+                                                        int4* __restrict__ occ_fill, int64_t n4) {
+  k_uf_local_vertex_body<TILE, NT, HS>(idx, vlist, parent, vmin, st, occ_fill, n4);
+}
 
 // Vertex minimum (Alg. 1, third loop): every visible triangle is compressed
 // to its current root and every vertex records the smallest root among its
@@ -412,7 +436,7 @@ __global__ void k_uf_vertex_min(const int32_t* __restrict__ idx,
 // ancestor of t: a vertex whose minimum equals it needs no join, which skips
 // most of them; along a tile border many lanes of a wave name the same
 // (parent, minimum) pair, and only the lowest lane of each pair joins.
-__global__ void k_uf_vertex_hook(const int32_t* __restrict__ idx,
+__device__ __forceinline__ void k_uf_vertex_hook_body(const int32_t* __restrict__ idx,
                                  const int32_t* __restrict__ vlist, int32_t* parent,
                                  const int32_t* __restrict__ vmin,
                                  const FrameState* __restrict__ st) {
@@ -444,6 +468,12 @@ __global__ void k_uf_vertex_hook(const int32_t* __restrict__ idx,
     }
   }
 }
+__global__ void k_uf_vertex_hook(const int32_t* __restrict__ idx,
+                                 const int32_t* __restrict__ vlist, int32_t* parent,
+                                 const int32_t* __restrict__ vmin,
+                                 const FrameState* __restrict__ st) {
+  k_uf_vertex_hook_body(idx, vlist, parent, vmin, st);
+}
 
 // Flatten every visible triangle to its root and count roots per tile of
 // kTriTile consecutive entries of the visible list. The walk here only reads:
@@ -451,7 +481,7 @@ __global__ void k_uf_vertex_hook(const int32_t* __restrict__ idx,
 // earlier) could land after another thread has set parent[x] to the root and
 // leave x pointing at a non-root, which the later stages would read as the
 // chart's root.
-__global__ void k_uf_flatten_count(const int32_t* __restrict__ vlist, int32_t* parent,
+__device__ __forceinline__ void k_uf_flatten_count_body(const int32_t* __restrict__ vlist, int32_t* parent,
                                    uint32_t* __restrict__ tile_count,
                                    const FrameState* __restrict__ st) {
   __shared__ uint32_t sh[kBlock / kWave];
@@ -476,6 +506,11 @@ __global__ void k_uf_flatten_count(const int32_t* __restrict__ vlist, int32_t* p
   roots = block_sum<uint32_t>(roots, sh);
   if (threadIdx.x == 0) tile_count[blockIdx.x] = roots;
 }
+__global__ void k_uf_flatten_count(const int32_t* __restrict__ vlist, int32_t* parent,
+                                   uint32_t* __restrict__ tile_count,
+                                   const FrameState* __restrict__ st) {
+  k_uf_flatten_count_body(vlist, parent, tile_count, st);
+}
 
 // Chart index of each root = its rank among roots; the visible list ascends
 // with the triangle index, so chart indices ascend with the chart's lowest
@@ -483,7 +518,7 @@ __global__ void k_uf_flatten_count(const int32_t* __restrict__ vlist, int32_t* p
 // the last one records the chart count (above max_charts: FA_ERR_CAPACITY;
 // no chart index at or past max_charts is written, and every later stage
 // stops on the status).
-__global__ void k_assign_roots(const int32_t* __restrict__ vlist,
+__device__ __forceinline__ void k_assign_roots_body(const int32_t* __restrict__ vlist,
                                const int32_t* __restrict__ parent,
                                const uint32_t* __restrict__ tile_count, int32_t* __restrict__ cot,
                                fa_chart* __restrict__ charts, uint32_t* __restrict__ accum,
@@ -521,6 +556,13 @@ __global__ void k_assign_roots(const int32_t* __restrict__ vlist,
     st->num_charts = (int32_t)total;  // reported even when above the capacity
     if (total > (uint32_t)max_charts) st->status = FA_ERR_CAPACITY;
   }
+}
+__global__ void k_assign_roots(const int32_t* __restrict__ vlist,
+                               const int32_t* __restrict__ parent,
+                               const uint32_t* __restrict__ tile_count, int32_t* __restrict__ cot,
+                               fa_chart* __restrict__ charts, uint32_t* __restrict__ accum,
+                               int32_t max_charts, FrameState* __restrict__ st) {
+  k_assign_roots_body(vlist, parent, tile_count, cot, charts, accum, max_charts, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -670,7 +712,7 @@ constexpr int kSlots = 64;
 constexpr unsigned kFillBlocks = 1024;  // least workgroups that fill the occupancy map
 constexpr unsigned kFillGroups = 256;   // the same for the 1024-thread union-find tiles
 
-__global__ __launch_bounds__(kBlock) void k_gather_boxes(
+__device__ __forceinline__ void k_gather_boxes_body(
     const int32_t* __restrict__ vlist, const int32_t* __restrict__ idx,
     const int32_t* __restrict__ parent, const float4* __restrict__ clip, int32_t* cot,
     int32_t* __restrict__ cov, uint32_t* __restrict__ accum, uint32_t flags,
@@ -795,6 +837,13 @@ __global__ __launch_bounds__(kBlock) void k_gather_boxes(
     atomicMax(&accum[4 * cl + 3], sbox[i][3]);
   }
 }
+__global__ __launch_bounds__(kBlock) void k_gather_boxes(
+    const int32_t* __restrict__ vlist, const int32_t* __restrict__ idx,
+    const int32_t* __restrict__ parent, const float4* __restrict__ clip, int32_t* cot,
+    int32_t* __restrict__ cov, uint32_t* __restrict__ accum, uint32_t flags,
+    const FrameState* __restrict__ st, int4* __restrict__ occ_fill, int64_t n4) {
+  k_gather_boxes_body(vlist, idx, parent, clip, cot, cov, accum, flags, st, occ_fill, n4);
+}
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
@@ -816,6 +865,46 @@ __global__ void k_index_guard(const int32_t* __restrict__ flag, FrameState* st) 
     st->status = FA_ERR_INVALID_ARG;
     st->visible = 0;
   }
+}
+
+// ---- batched wrappers (view = blockIdx.y) --------------------------------
+__global__ void k_prologue_b(const BatchView* __restrict__ bv, const float* __restrict__ pos,
+                             int64_t V, const int32_t* __restrict__ nbr, int64_t T,
+                             unsigned vblocks) {
+  const BatchView& v = bv[blockIdx.y];
+  k_prologue_body(pos, V, v.p, v.w.clip, v.w.vmin, v.cov, v.visible, nbr, T, v.w.parent, v.cot,
+                  v.w.tile_vis, 0, vblocks, v.w.state, v.w.big_counter);
+}
+__global__ void k_vis_compact_b(const BatchView* __restrict__ bv, int64_t T) {
+  const BatchView& v = bv[blockIdx.y];
+  k_vis_compact_body(v.visible, T, v.w.tile_vis, v.w.vlist, v.w.state);
+}
+__global__ __launch_bounds__(1024) void k_uf_local_vertex_b(const BatchView* __restrict__ bv,
+                                                            const int32_t* __restrict__ idx) {
+  const BatchView& v = bv[blockIdx.y];
+  k_uf_local_vertex_body<2048, 1024, 4096>(idx, v.w.vlist, v.w.parent, v.w.vmin, v.w.state,
+                                           reinterpret_cast<int4*>(v.occ),
+                                           (int64_t)v.p.omega * v.p.omega / 4);
+}
+__global__ void k_uf_vertex_hook_b(const BatchView* __restrict__ bv,
+                                   const int32_t* __restrict__ idx) {
+  const BatchView& v = bv[blockIdx.y];
+  k_uf_vertex_hook_body(idx, v.w.vlist, v.w.parent, v.w.vmin, v.w.state);
+}
+__global__ void k_uf_flatten_count_b(const BatchView* __restrict__ bv) {
+  const BatchView& v = bv[blockIdx.y];
+  k_uf_flatten_count_body(v.w.vlist, v.w.parent, v.w.tile_count, v.w.state);
+}
+__global__ void k_assign_roots_b(const BatchView* __restrict__ bv) {
+  const BatchView& v = bv[blockIdx.y];
+  k_assign_roots_body(v.w.vlist, v.w.parent, v.w.tile_count, v.cot, v.charts, v.w.accum,
+                      v.p.max_charts, v.w.state);
+}
+__global__ __launch_bounds__(kBlock) void k_gather_boxes_b(const BatchView* __restrict__ bv,
+                                                           const int32_t* __restrict__ idx) {
+  const BatchView& v = bv[blockIdx.y];
+  k_gather_boxes_body(v.w.vlist, idx, v.w.parent, v.w.clip, v.cot, v.cov, v.w.accum, v.p.flags,
+                      v.w.state, nullptr, 0);
 }
 
 }  // namespace
@@ -936,6 +1025,26 @@ hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* 
     mk(st);
   }
   mk(st);
+  return hipGetLastError();
+}
+
+hipError_t launch_charts_batched(const BatchView* dev, int n, const float* pos,
+                                 const int32_t* idx, const int32_t* nbr, int64_t T, int64_t V,
+                                 hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const unsigned vb = std::max(1u, grid_for(V, kBlock));
+  const unsigned tt = grid_for(T, kTriTile);
+  const unsigned vt = std::max(1u, tt);
+  k_prologue_b<<<dim3(vb + tt, n), kBlock, 0, st>>>(dev, pos, V, nbr, T, vb);
+  if (T > 0) {
+    k_vis_compact_b<<<dim3(tt, n), kBlock, 0, st>>>(dev, T);
+    k_uf_local_vertex_b<<<dim3(std::max(1u, grid_for(T, 2048)) + kFillGroups, n), 1024, 0, st>>>(
+        dev, idx);
+    k_uf_vertex_hook_b<<<dim3(visible_grid(T), n), kBlock, 0, st>>>(dev, idx);
+    k_uf_flatten_count_b<<<dim3(vt, n), kBlock, 0, st>>>(dev);
+    k_assign_roots_b<<<dim3(vt, n), kBlock, 0, st>>>(dev);
+    k_gather_boxes_b<<<dim3(grid_for(T, kBlock * kGatherItems), n), kBlock, 0, st>>>(dev, idx);
+  }
   return hipGetLastError();
 }
 

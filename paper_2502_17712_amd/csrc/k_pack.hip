@@ -271,13 +271,20 @@ __global__ __launch_bounds__(NT) void k_pack(const float2* __restrict__ wh,
 // Frames with more than kcap charts are pushed in chunks of kcap boxes in
 // order, reloaded from the fold written to global memory; a row that
 // straddles two chunks is pushed as two segments (its boxes have disjoint
-// spans, so the split changes nothing). One barrier per segment; the next
-// segment's bounds and first boxes are loaded while the current one is
-// pushed, and cross-lane maxima and scans use DPP lane moves.
+// spans, so the split changes nothing). Two barriers per segment (its narrow
+// boxes, then its wider ones); cross-lane maxima and scans use DPP lane
+// moves.
 constexpr int kFoldItems = 4;  // consecutive boxes per thread in the fold
+constexpr int kNarrow = 8;     // boxes up to this wide are pushed by one lane
+
+// Dynamic LDS of the box push: frontline plus kcap boxes of 12 bytes.
+constexpr int kBoxPushLds = 131072;
+__host__ __device__ inline int box_kcap(int omega) {
+  return ((kBoxPushLds - 8 * omega - 4) / 12) & ~63;
+}
 
 template <int NT>
-__global__ __launch_bounds__(NT) void k_pack_box(const float2* __restrict__ wh,
+__device__ __forceinline__ void k_pack_box_body(const float2* __restrict__ wh,
                                                  const FrameState* __restrict__ st, FrameParams p,
                                                  long long* __restrict__ cand_x,
                                                  uint32_t* __restrict__ cand_ab,
@@ -291,6 +298,7 @@ __global__ __launch_bounds__(NT) void k_pack_box(const float2* __restrict__ wh,
   __shared__ int32_t Hsh[3];
   __shared__ long long last_x;
   __shared__ long long sh64[NW];
+  __shared__ int32_t WM[2048], WW[256], LC[2][2];  // mid and wide box lists, their counts
 
   if (st->status != FA_OK) return;
   const int j = blockIdx.x + 1;
@@ -409,6 +417,7 @@ __global__ __launch_bounds__(NT) void k_pack_box(const float2* __restrict__ wh,
   const int L = omega + m;
   for (int c = tid; c < L; c += NT) F[c] = 0;
   if (tid < 3) Hsh[tid] = 0;
+  if (tid < 4) LC[tid >> 1][tid & 1] = 0;
 
   int Hw = 0, seg = 0;
   bool over = false;
@@ -463,60 +472,92 @@ __global__ __launch_bounds__(NT) void k_pack_box(const float2* __restrict__ wh,
     if (tid == 0) RS[nr] = cn;
     __syncthreads();
 
-    // ---- push, segment by segment: four consecutive boxes per wave step, 16
-    // lanes each (a box's reads, a 16-lane max, then its writes); a group
-    // with a box wider than 64 columns takes its boxes one at a time with the
-    // whole wave. Segment rr's bounds and the wave's first boxes of it were
-    // loaded during segment rr - 1.
+    // ---- push, segment by segment, in two phases. A: the threads take the
+    // segment's boxes in order; a box at most kNarrow columns wide is pushed
+    // by its own lane, the others go to a list of mid boxes (up to 64
+    // columns) or of wide ones. B (after a barrier): the mid boxes four per
+    // wave step, 16 lanes each; the wide boxes one per wave. Boxes of a row
+    // have disjoint spans, so the order inside a segment changes nothing.
+    // Bounds of the lists: a row's boxes lie in L <= 2 omega <= 16384
+    // columns, so at most 1820 are wider than 8 and 252 wider than 64.
     int s0 = 0, s1 = nr > 0 ? RS[1] : 0;
     long long r = nr > 0 ? (xbase + Xr[0]) >> lg : 0;
-    int k0 = 4 * w + sub;
-    uint32_t ab0 = k0 < cn ? AB[k0] : 0u, xr0 = k0 < cn ? Xr[k0] : 0u;
     for (int rr = 0; rr < nr; ++rr, ++seg) {
-      // next segment: its end, its row and the wave's first boxes
+      // next segment: its end and its row
       const int s1n = rr + 2 <= nr ? RS[rr + 2] : cn;
       const uint32_t xfirst = rr + 1 < nr ? Xr[s1] : 0u;
-      const int k1 = s1 + 4 * w + sub;
-      const uint32_t ab1 = k1 < cn ? AB[k1] : 0u, xr1 = k1 < cn ? Xr[k1] : 0u;
       const int hprev = Hsh[(seg + 2) % 3];  // the height after segment seg - 1
       const long long rbase = (r << lg) - xbase;
       const bool right = (r % 3) != 0;
-      uint32_t ab = ab0, xr = xr0;
-      for (int kb = s0 + 4 * w; kb < s1; kb += 4 * NW) {
-        const int k = kb + sub;
-        const bool act = k < s1;
-        // the wave's boxes of the next step of this segment
-        const int kn = k + 4 * NW;
-        const uint32_t abn = kn < s1 ? AB[kn] : 0u, xrn = kn < s1 ? Xr[kn] : 0u;
-        int a = 0, b = 0, x = 0;
-        if (act) {
+      int* cnt = LC[seg & 1];
+      for (int k = s0 + tid; k < s1; k += NT) {
+        const uint32_t ab = AB[k];
+        const int a = (int)(ab & 0xFFFFu), b = (int)(ab >> 16);
+        const int o = (int)((long long)Xr[k] - rbase);
+        const int x = right ? L - o - a : o;
+        const bool narrow = a <= kNarrow;
+        if (narrow) {
+          int v[kNarrow];
+#pragma unroll
+          for (int c = 0; c < kNarrow; ++c) v[c] = c < a ? F[x + c] : 0;
+          int mx = 0;
+#pragma unroll
+          for (int c = 0; c < kNarrow; ++c) mx = max(mx, v[c]);
+#pragma unroll
+          for (int c = 0; c < kNarrow; ++c)
+            if (c < a) F[x + c] = mx + b;
+          Y[c0 + k] = mx;
+          Hw = max(Hw, mx + b);
+        }
+        const bool wide = a > kWave;
+        const unsigned long long mm = __ballot(!narrow && !wide), mw = __ballot(wide);
+        const unsigned long long below = lanes_below();
+        int bm = 0, bw = 0;
+        if (lane == __ffsll((long long)__ballot(true)) - 1) {
+          if (mm) bm = atomicAdd(&cnt[0], __popcll(mm));
+          if (mw) bw = atomicAdd(&cnt[1], __popcll(mw));
+        }
+        bm = __builtin_amdgcn_readfirstlane(bm);
+        bw = __builtin_amdgcn_readfirstlane(bw);
+        if (!narrow && !wide) WM[bm + __popcll(mm & below)] = k;
+        if (wide) WW[bw + __popcll(mw & below)] = k;
+      }
+      __syncthreads();
+      const int nm = cnt[0], nwd = cnt[1];
+      if (tid == 0) {
+        LC[(seg + 1) & 1][0] = 0;
+        LC[(seg + 1) & 1][1] = 0;
+      }
+      for (int e0 = 4 * w; e0 < nm; e0 += 4 * NW) {
+        const int e = e0 + sub;
+        int a = 0, b = 0, x = 0, k = 0;
+        if (e < nm) {
+          k = WM[e];
+          const uint32_t ab = AB[k];
           a = (int)(ab & 0xFFFFu);
           b = (int)(ab >> 16);
-          const int o = (int)((long long)xr - rbase);
+          const int o = (int)((long long)Xr[k] - rbase);
           x = right ? L - o - a : o;
         }
-        if (__ballot(act && a > kWave)) {
-          for (int q = 0; q < 4 && kb + q < s1; ++q) {
-            const int aq = __builtin_amdgcn_readlane(a, 16 * q);
-            const int bq = __builtin_amdgcn_readlane(b, 16 * q);
-            const int xq = __builtin_amdgcn_readlane(x, 16 * q);
-            int mx = 0;
-            for (int c = xq + lane; c < xq + aq; c += kWave) mx = max(mx, F[c]);
-            const int y = wave_max_dpp(mx);
-            for (int c = xq + lane; c < xq + aq; c += kWave) F[c] = y + bq;
-            if (lane == 0) Y[c0 + kb + q] = y;
-            Hw = max(Hw, y + bq);
-          }
-        } else {
-          int mx = 0;
-          for (int c = x + sl; c < x + a; c += 16) mx = max(mx, F[c]);
-          mx = row16_max(mx);
-          for (int c = x + sl; c < x + a; c += 16) F[c] = mx + b;
-          if (act && sl == 0) Y[c0 + k] = mx;
-          if (act) Hw = max(Hw, mx + b);
-        }
-        ab = abn;
-        xr = xrn;
+        int mx = 0;
+        for (int c = x + sl; c < x + a; c += 16) mx = max(mx, F[c]);
+        mx = row16_max(mx);
+        for (int c = x + sl; c < x + a; c += 16) F[c] = mx + b;
+        if (e < nm && sl == 0) Y[c0 + k] = mx;
+        if (e < nm) Hw = max(Hw, mx + b);
+      }
+      for (int e = w; e < nwd; e += NW) {
+        const int k = WW[e];
+        const uint32_t ab = AB[k];
+        const int a = (int)(ab & 0xFFFFu), b = (int)(ab >> 16);
+        const int o = (int)((long long)Xr[k] - rbase);
+        const int x = right ? L - o - a : o;
+        int mx = 0;
+        for (int c = x + lane; c < x + a; c += kWave) mx = max(mx, F[c]);
+        const int y = wave_max_dpp(mx);
+        for (int c = x + lane; c < x + a; c += kWave) F[c] = y + b;
+        if (lane == 0) Y[c0 + k] = y;
+        Hw = max(Hw, y + b);
       }
       const int hw = wave_max_dpp(Hw);
       if (lane == 0) atomicMax(&Hsh[seg % 3], hw);
@@ -529,8 +570,6 @@ __global__ __launch_bounds__(NT) void k_pack_box(const float2* __restrict__ wh,
       s0 = s1;
       s1 = s1n;
       r = (xbase + xfirst) >> lg;
-      ab0 = ab1;
-      xr0 = xr1;
     }
   }
   if (tid == 0) {
@@ -541,6 +580,16 @@ __global__ __launch_bounds__(NT) void k_pack_box(const float2* __restrict__ wh,
     tab[3] = H;
     tab[4] = (int32_t)min(rows, (long long)INT_MAX);
   }
+}
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pack_box(const float2* __restrict__ wh,
+                                                 const FrameState* __restrict__ st, FrameParams p,
+                                                 long long* __restrict__ cand_x,
+                                                 uint32_t* __restrict__ cand_ab,
+                                                 int32_t* __restrict__ cand_y,
+                                                 int32_t* __restrict__ cand_tab, int64_t stride,
+                                                 int kcap) {
+  k_pack_box_body<NT>(wh, st, p, cand_x, cand_ab, cand_y, cand_tab, stride, kcap);
 }
 
 // Footprint push: pooled profile of every box of every candidate that its
@@ -611,7 +660,7 @@ __device__ __forceinline__ bool sel_better(int j1, int L1, int j2, int L2) {
   return a > b || (a == b && j1 > j2);
 }
 
-__global__ __launch_bounds__(kBlock) void k_select_place(
+__device__ __forceinline__ void k_select_place_body(
     FrameParams p, const int32_t* __restrict__ cand_tab, FrameState* st,
     int32_t* __restrict__ cand_out, const int32_t* __restrict__ order,
     const long long* __restrict__ cand_x, const uint32_t* __restrict__ cand_ab,
@@ -682,6 +731,29 @@ __global__ __launch_bounds__(kBlock) void k_select_place(
         (int)ceil_div64(2 * ((int64_t)y + b) * om - L, L2) - 1);
   }
 }
+__global__ __launch_bounds__(kBlock) void k_select_place(
+    FrameParams p, const int32_t* __restrict__ cand_tab, FrameState* st,
+    int32_t* __restrict__ cand_out, const int32_t* __restrict__ order,
+    const long long* __restrict__ cand_x, const uint32_t* __restrict__ cand_ab,
+    const int32_t* __restrict__ cand_y, int64_t stride, fa_chart* __restrict__ charts,
+    int4* __restrict__ chart_tex) {
+  k_select_place_body(p, cand_tab, st, cand_out, order, cand_x, cand_ab, cand_y, stride, charts, chart_tex);
+}
+
+// ---- batched wrappers (view = blockIdx.y) --------------------------------
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pack_box_b(const BatchView* __restrict__ bv,
+                                                   int64_t stride) {
+  const BatchView& v = bv[blockIdx.y];
+  k_pack_box_body<NT>(v.w.sorted_wh, v.w.state, v.p, v.w.cand_x, v.w.cand_ab, v.w.cand_y,
+                      v.w.cand_tab, stride, box_kcap(v.p.omega));
+}
+__global__ __launch_bounds__(kBlock) void k_select_place_b(const BatchView* __restrict__ bv,
+                                                           int64_t stride) {
+  const BatchView& v = bv[blockIdx.y];
+  k_select_place_body(v.p, v.w.cand_tab, v.w.state, v.cand_out, v.w.vals_a, v.w.cand_x,
+                      v.w.cand_ab, v.w.cand_y, stride, v.charts, v.w.chart_tex);
+}
 
 // ---- packer-only entry: box sizes in, placements out ---------------------
 __global__ void k_pack_state(FrameState* st, int32_t n) {
@@ -735,19 +807,17 @@ __global__ void k_pack_emit(int32_t n, const fa_chart* __restrict__ charts,
 }  // namespace
 
 namespace {
-// Dynamic LDS of the box push: frontline plus kcap boxes of 12 bytes.
-constexpr int kBoxPushLds = 131072;
-inline int box_kcap(int omega) { return ((kBoxPushLds - 8 * omega - 4) / 12) & ~63; }
 
 hipError_t box_attributes() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_pack_box<256>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, kBoxPushLds);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_pack_box<512>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, kBoxPushLds);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_pack_box<1024>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, kBoxPushLds);
+  const void* ks[6] = {(const void*)k_pack_box<256>,    (const void*)k_pack_box<512>,
+                       (const void*)k_pack_box<1024>,   (const void*)k_pack_box_b<256>,
+                       (const void*)k_pack_box_b<512>, (const void*)k_pack_box_b<1024>};
+  for (const void* k : ks) {
+    const hipError_t e =
+        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kBoxPushLds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 void box_launch(const FrameParams& p, const Work& w, int block, hipStream_t st) {
@@ -841,6 +911,21 @@ hipError_t launch_pack_emit(int32_t n, const fa_chart* charts, int32_t* placemen
   if (n > 0)
     k_pack_emit<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(n, charts, placements,
                                                                          w.state);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_batched(const BatchView* dev, int n, int J, int64_t max_charts, int block,
+                               hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const size_t dyn = (size_t)kBoxPushLds;  // each view sizes its chunks from its own omega
+  if (block == 1024)
+    k_pack_box_b<1024><<<dim3(J, n), 1024, dyn, st>>>(dev, max_charts);
+  else if (block == 512)
+    k_pack_box_b<512><<<dim3(J, n), 512, dyn, st>>>(dev, max_charts);
+  else
+    k_pack_box_b<256><<<dim3(J, n), 256, dyn, st>>>(dev, max_charts);
+  k_select_place_b<<<dim3((unsigned)((max_charts + kBlock - 1) / kBlock), n), kBlock, 0, st>>>(
+      dev, max_charts);
   return hipGetLastError();
 }
 

@@ -377,7 +377,7 @@ __device__ __forceinline__ uint32_t tiles_of(const Footprint& fp, uint32_t* tile
   return *tiles_x * (uint32_t)((fp.ty1 - fp.ty0 + kOccTile) / kOccTile);
 }
 
-__global__ __launch_bounds__(kOccSmallBlock) void k_occ_small(
+__device__ __forceinline__ void k_occ_small_body(
     const int32_t* __restrict__ idx, const int32_t* __restrict__ vlist, FrameParams p,
     const float4* __restrict__ clip, const int32_t* __restrict__ cot,
     const fa_chart* __restrict__ charts, const int4* __restrict__ chart_tex,
@@ -469,12 +469,23 @@ __global__ __launch_bounds__(kOccSmallBlock) void k_occ_small(
     if (__ballot(cb)) raster_expand(fb, cb ? nb : 0, occ, p.omega);
   }
 }
+__global__ __launch_bounds__(kOccSmallBlock) void k_occ_small(
+    const int32_t* __restrict__ idx, const int32_t* __restrict__ vlist, FrameParams p,
+    const float4* __restrict__ clip, const int32_t* __restrict__ cot,
+    const fa_chart* __restrict__ charts, const int4* __restrict__ chart_tex,
+    int32_t* __restrict__ occ, ulonglong2* __restrict__ big, int4* __restrict__ big_fp,
+    uint32_t big_cap, int small_texels,
+    int lane_texels, unsigned long long* __restrict__ big_counter,
+    const FrameState* __restrict__ stp, unsigned occ_blocks, int64_t V,
+    const int32_t* __restrict__ cov, float2* __restrict__ uv) {
+  k_occ_small_body(idx, vlist, p, clip, cot, charts, chart_tex, occ, big, big_fp, big_cap, small_texels, lane_texels, big_counter, stp, occ_blocks, V, cov, uv);
+}
 
 // Queued footprints: their texel ranges cut into 16x16 tiles, concatenated,
 // are split evenly over all waves of the grid; a wave finds its first
 // footprint by a 64-way search over the (increasing) first-tile indices and
 // walks forward, 4 texels per lane.
-__global__ __launch_bounds__(kBlock) void k_occ_big(
+__device__ __forceinline__ void k_occ_big_body(
     const int32_t* __restrict__ idx, FrameParams p, const float4* __restrict__ clip,
     const int32_t* __restrict__ cot, const fa_chart* __restrict__ charts,
     const int4* __restrict__ chart_tex, int32_t* __restrict__ occ,
@@ -563,6 +574,14 @@ __global__ __launch_bounds__(kBlock) void k_occ_big(
     e0 += kWave;
   }
 }
+__global__ __launch_bounds__(kBlock) void k_occ_big(
+    const int32_t* __restrict__ idx, FrameParams p, const float4* __restrict__ clip,
+    const int32_t* __restrict__ cot, const fa_chart* __restrict__ charts,
+    const int4* __restrict__ chart_tex, int32_t* __restrict__ occ,
+    const ulonglong2* __restrict__ big, const int4* __restrict__ big_fp, uint32_t big_cap,
+    const unsigned long long* __restrict__ big_counter, const FrameState* __restrict__ stp) {
+  k_occ_big_body(idx, p, clip, cot, charts, chart_tex, occ, big, big_fp, big_cap, big_counter, stp);
+}
 
 // Frame record for the caller (one thread); `occ` is the occupied texel count
 // when the occupancy map was built.
@@ -601,7 +620,7 @@ __global__ void k_meta(FrameParams p, FrameState* stp,
 // its share of the map and publishes the sum; the last one to finish (the
 // one that draws the last ticket) adds them up and writes the record.
 constexpr int kCountBlock = 1024;
-__global__ __launch_bounds__(kCountBlock) void k_occ_count_meta(
+__device__ __forceinline__ void k_occ_count_meta_body(
     FrameParams p, const int4* __restrict__ occ, int64_t n4,
     unsigned long long* __restrict__ partial, FrameState* stp,
     const unsigned long long* __restrict__ big_counter, fa_atlas_meta* __restrict__ meta) {
@@ -639,6 +658,36 @@ __global__ __launch_bounds__(kCountBlock) void k_occ_count_meta(
     all += __hip_atomic_load(&partial[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   all = block_sum<unsigned long long>(all, sh);
   if (threadIdx.x == 0) write_meta(p, stp, big_counter, true, all, meta);
+}
+__global__ __launch_bounds__(kCountBlock) void k_occ_count_meta(
+    FrameParams p, const int4* __restrict__ occ, int64_t n4,
+    unsigned long long* __restrict__ partial, FrameState* stp,
+    const unsigned long long* __restrict__ big_counter, fa_atlas_meta* __restrict__ meta) {
+  k_occ_count_meta_body(p, occ, n4, partial, stp, big_counter, meta);
+}
+
+// ---- batched wrappers (view = blockIdx.y) --------------------------------
+__global__ __launch_bounds__(kOccSmallBlock) void k_occ_small_b(
+    const BatchView* __restrict__ bv, const int32_t* __restrict__ idx, uint32_t big_cap,
+    int small_texels, int lane_texels, unsigned occ_blocks, int64_t V) {
+  const BatchView& v = bv[blockIdx.y];
+  k_occ_small_body(idx, v.w.vlist, v.p, v.w.clip, v.cot, v.charts, v.w.chart_tex, v.occ, v.w.big,
+                   v.w.big_fp, big_cap, small_texels, lane_texels, v.w.big_counter, v.w.state,
+                   occ_blocks, V, v.cov, reinterpret_cast<float2*>(v.uv));
+}
+__global__ __launch_bounds__(kBlock) void k_occ_big_b(const BatchView* __restrict__ bv,
+                                                      const int32_t* __restrict__ idx,
+                                                      uint32_t big_cap) {
+  const BatchView& v = bv[blockIdx.y];
+  k_occ_big_body(idx, v.p, v.w.clip, v.cot, v.charts, v.w.chart_tex, v.occ, v.w.big, v.w.big_fp,
+                 big_cap, v.w.big_counter, v.w.state);
+}
+__global__ __launch_bounds__(kCountBlock) void k_occ_count_meta_b(
+    const BatchView* __restrict__ bv) {
+  const BatchView& v = bv[blockIdx.y];
+  k_occ_count_meta_body(v.p, reinterpret_cast<const int4*>(v.occ),
+                        (int64_t)v.p.omega * v.p.omega / 4, v.w.partial, v.w.state,
+                        v.w.big_counter, v.meta);
 }
 
 }  // namespace
@@ -1038,6 +1087,21 @@ hipError_t launch_footprint(const int32_t* idx, int64_t T, const FrameParams& p,
 hipError_t launch_meta(const FrameParams& p, const Work& w, fa_atlas_meta* meta,
                        hipStream_t st) {
   k_meta<<<1, kWave, 0, st>>>(p, w.state, w.big_counter, meta);
+  return hipGetLastError();
+}
+
+hipError_t launch_occupancy_batched(const BatchView* dev, int n, const int32_t* idx, int64_t T,
+                                    int64_t V, int small_texels, int lane_texels,
+                                    hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const uint32_t cap = (uint32_t)std::min<int64_t>(2 * std::max<int64_t>(T, 1), kBigCap);
+  const unsigned occ_blocks = T > 0 ? visible_grid(T) : 0;
+  const unsigned uv_blocks = (unsigned)((V + kOccSmallBlock - 1) / kOccSmallBlock);
+  if (occ_blocks + uv_blocks > 0)
+    k_occ_small_b<<<dim3(occ_blocks + uv_blocks, n), kOccSmallBlock, 0, st>>>(
+        dev, idx, cap, small_texels, lane_texels, occ_blocks, V);
+  if (T > 0) k_occ_big_b<<<dim3(kOccBigGrid, n), kBlock, 0, st>>>(dev, idx, cap);
+  k_occ_count_meta_b<<<dim3(kCountGrid, n), kCountBlock, 0, st>>>(dev);
   return hipGetLastError();
 }
 

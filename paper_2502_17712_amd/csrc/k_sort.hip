@@ -377,7 +377,7 @@ __device__ __forceinline__ void order_body(const FrameParams& p, const uint32_t*
   }
 }
 
-__global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
+__device__ __forceinline__ void k_sizes_order_body(
     FrameParams p, const uint32_t* __restrict__ accum, fa_chart* __restrict__ charts,
     uint32_t* __restrict__ keys_a, int32_t* __restrict__ vals_a, uint32_t* __restrict__ keys_b,
     int32_t* __restrict__ vals_b, float2* __restrict__ sorted_wh, int from_accum,
@@ -398,6 +398,19 @@ __global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
   else
     order_body<false>(p, accum, charts, keys_a, vals_a, keys_b, vals_b, nullptr, vals_a,
                       sorted_wh, from_accum, fp_off, st, C, base, wcnt, sh, sh64);
+}
+__global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
+    FrameParams p, const uint32_t* __restrict__ accum, fa_chart* __restrict__ charts,
+    uint32_t* __restrict__ keys_a, int32_t* __restrict__ vals_a, uint32_t* __restrict__ keys_b,
+    int32_t* __restrict__ vals_b, float2* __restrict__ sorted_wh, int from_accum,
+    int32_t* __restrict__ fp_off, FrameState* __restrict__ st) {
+  k_sizes_order_body(p, accum, charts, keys_a, vals_a, keys_b, vals_b, sorted_wh, from_accum, fp_off, st);
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_sizes_order_b(const BatchView* __restrict__ bv) {
+  const BatchView& v = bv[blockIdx.y];
+  k_sizes_order_body(v.p, v.w.accum, v.charts, v.w.keys_a, v.w.vals_a, v.w.keys_b, v.w.vals_b,
+                     v.w.sorted_wh, 1, nullptr, v.w.state);
 }
 
 }  // namespace
@@ -433,6 +446,11 @@ hipError_t launch_order(const FrameParams& p, const Work& w, fa_chart* charts, i
   int32_t* fp_off = (from_accum && p.fp_cap > 0) ? w.fp_off : nullptr;
   k_sizes_order<<<1, kOrderThreads, 0, st>>>(p, w.accum, charts, w.keys_a, w.vals_a, w.keys_b,
                                              w.vals_b, w.sorted_wh, from_accum, fp_off, w.state);
+  return hipGetLastError();
+}
+
+hipError_t launch_order_batched(const BatchView* dev, int n, hipStream_t st) {
+  if (n > 0) k_sizes_order_b<<<dim3(1, n), kOrderThreads, 0, st>>>(dev);
   return hipGetLastError();
 }
 

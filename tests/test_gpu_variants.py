@@ -101,19 +101,51 @@ def _run_batch(ctx, views, mesh):
     return [o.to_numpy() for o in outs]
 
 
+@pytest.mark.parametrize("launch", [0, 1])
 @pytest.mark.parametrize("graph", [0, 1])
-def test_batch_city_views(graph):
+def test_batch_city_views(graph, launch):
+    # launch 1: one kernel launch per stage for the 8 views of each round
     import paper_2502_17712_amd as fa
     views, ctx, want = _batch_setup()
     mesh = mesh_for(views[0])
     ctx.set_tuning(fa.FA_TUNE_BATCH_GRAPH, graph)
+    ctx.set_tuning(fa.FA_TUNE_BATCH_LAUNCH, launch)
     try:
         for rep in range(2 if graph else 1):
-            print(f"[gpu] batch of 16 city views, graph={graph}, pass {rep}", flush=True)
+            print(f"[gpu] batch of 16 city views, graph={graph}, launch={launch}, pass {rep}",
+                  flush=True)
             for g, r in zip(_run_batch(ctx, views, mesh), want):
                 compare(g, r)
     finally:
         ctx.set_tuning(fa.FA_TUNE_BATCH_GRAPH, 0)
+        ctx.set_tuning(fa.FA_TUNE_BATCH_LAUNCH, 0)
+
+
+def test_batch_launch_rounds_and_fallback():
+    """Batched launches on orbit views of uneven atlas size and rate: 7 views on
+    3 slots (three rounds); then a batch with one view lacking its occupancy
+    map, which runs per view and must give the same results."""
+    import paper_2502_17712_amd as fa
+    views = [scenes.orbit_frame(k, atlas_size=om, rate=r)
+             for k, om, r in ((4, 1024, 1.0), (21, 2048, 0.5), (47, 512, 2.0), (66, 4096, 1.0),
+                              (80, 256, 0.5), (99, 1024, 2.0), (117, 2048, 1.0))]
+    ctx = fa.Context(views[0].num_triangles, views[0].num_vertices, max_charts=8192,
+                     max_atlas=4096, max_views=3)
+    ctx.set_tuning(fa.FA_TUNE_BATCH_LAUNCH, 1)
+    mesh = mesh_for(views[0])
+    want = [oracle.build_frame(v) for v in views]
+    print("[gpu] batched launches, 7 views on 3 slots", flush=True)
+    for g, r in zip(_run_batch(ctx, views, mesh), want):
+        compare(g, r)
+    outs = [ctx.outputs(mesh, v.atlas_size, occupancy=(i != 2)) for i, v in enumerate(views[:4])]
+    vis = [torch.as_tensor(v.visible).cuda() for v in views[:4]]
+    print("[gpu] batched launches, one view without occupancy", flush=True)
+    ctx.build_atlas_batch(mesh, [(vis[i], v.view_proj, v.width, v.height, v.atlas_size, v.rate)
+                                 for i, v in enumerate(views[:4])], outs)
+    torch.cuda.synchronize()
+    for i, (o, r) in enumerate(zip(outs, want[:4])):
+        compare(o.to_numpy(), r, occupancy=(i != 2))
+    ctx.close()
 
 
 def test_batch_graph_after_evict():
