@@ -13,6 +13,7 @@ Prints one JSON line (rank 0). See the design doc for the roofline accounting.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import platform
@@ -349,14 +350,49 @@ def main():
 
     tuning = None
     if args.autotune:
+        # greedy search per frame shape (the small, medium and large workloads)
+        # with the loaded table cleared; writes a tuning table
         from paper_2502_17712_amd import autotune
-        cyc = [0]
+        ctx.load_tuning_table("")
+        lines, tuning = [], {}
 
-        def tune_step():  # every trial sees the same spread of frames
-            step(cyc[0])
-            cyc[0] += 1
-        tuning = autotune.tune(ctx, tune_step, out, reps=len(frames), ref_run=lambda: step(0))
-        log("autotune:", json.dumps(tuning))
+        def tune_on(name, ctx_, mesh_, frs, out_):
+            vs = [torch.as_tensor(f.visible).to(dev) for f in frs]
+            cyc = [0]
+
+            def one(k):
+                f = frs[k % len(frs)]
+                ctx_.build_atlas(mesh_, vs[k % len(frs)], f.view_proj, f.width, f.height,
+                                 f.atlas_size, f.rate, out=out_, stream=stream)
+
+            def tune_step():  # every trial sees the same spread of frames
+                one(cyc[0])
+                cyc[0] += 1
+            rep = autotune.tune(ctx_, tune_step, out_, reps=max(len(frs), 16),
+                                ref_run=lambda: one(0))
+            tuning[name] = rep
+            log("autotune:", name, json.dumps(rep["choice"]))
+            return rep["choice"]
+        g0, o0 = scenes.grid_frame(0), scenes.orbit_frame(0)
+        gctx = fa.Context(o0.num_triangles, o0.num_vertices, max_charts=65536, max_atlas=4096,
+                          tuning_table=None)
+        gmesh = fa.Mesh(g0.positions, g0.indices, g0.scene_key)
+        ch = tune_on("grid8k", gctx, gmesh, [g0], gctx.outputs(gmesh, 1024))
+        lines.append(autotune.table_line(0, 20000, 0, 64, ch, "8k-triangle grid, 1024^2"))
+        omesh = fa.Mesh(o0.positions, o0.indices, o0.scene_key)
+        ofr = [scenes.orbit_frame(k) for k in range(0, 120, 15)]
+        ch = tune_on("orbit86k", gctx, omesh, ofr, gctx.outputs(omesh, 2048))
+        lines.append(autotune.table_line(20001, 500000, 0, 64, ch, "86k-triangle orbit, 2048^2"))
+        gctx.close()
+        ch = tune_on("city2m", ctx, mesh, frames, out)
+        lines.append(autotune.table_line(500001, 1 << 30, 0, 64, ch,
+                                         "2.2M-triangle city, 4096^2"))
+        text = autotune.table_text(lines, "written by bench.py --autotune on one MI355X")
+        os.makedirs(os.path.join(HERE, "gpurun_out"), exist_ok=True)
+        with open(os.path.join(HERE, "gpurun_out", "tuning_gfx950.txt"), "w") as fh:
+            fh.write(text)
+        ctx.load_tuning_table(text)
+        log("tuning table:\n" + text)
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
@@ -440,19 +476,28 @@ def main():
             ctx_.build_atlas(m_, v, f.view_proj, f.width, f.height, f.atlas_size, f.rate,
                              out=outs_[f.atlas_size], stream=stream)
         torch.cuda.synchronize()
-        ts = []
-        for _ in range(reps):
-            for m_, f, v in zip(ms_, frs, vs):
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-                ctx_.build_atlas(m_, v, f.view_proj, f.width, f.height, f.atlas_size, f.rate,
-                                 out=outs_[f.atlas_size], stream=stream)
-                b.record(stream)
-                ts.append((a, b))
-        torch.cuda.synchronize()
+        # events made beforehand and the garbage collector held off: a
+        # collection pass inside the timed loop stalls the host between an
+        # event and the frame's launches, and the GPU waits idle
+        ts = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps * len(frs))]
+        gc.collect()
+        gc.disable()
+        try:
+            for rep in range(reps):
+                for k, (m_, f, v) in enumerate(zip(ms_, frs, vs)):
+                    a, b = ts[rep * len(frs) + k]
+                    a.record(stream)
+                    ctx_.build_atlas(m_, v, f.view_proj, f.width, f.height, f.atlas_size,
+                                     f.rate, out=outs_[f.atlas_size], stream=stream)
+                    b.record(stream)
+            torch.cuda.synchronize()
+        finally:
+            gc.enable()
         per_ = np.array([a.elapsed_time(b) for a, b in ts])
         return dict(mean_ms=float(per_.mean()), p50_ms=float(np.percentile(per_, 50)),
-                    p99_ms=float(np.percentile(per_, 99)), frames=len(frs))
+                    p99_ms=float(np.percentile(per_, 99)), max_ms=float(per_.max()),
+                    frames=len(frs))
     secondary = {}
     if not args.no_secondary:
         sctx = fa.Context(T, V, max_charts=65536, max_atlas=4096)
@@ -743,6 +788,8 @@ def main():
         "adjacency_ms": adjacency_ms,
         "stages_ms": stages,
         "tuning": tuning,
+        "tuning_table": (os.path.relpath(fa.TUNING_TABLE, HERE)
+                         if os.path.exists(fa.TUNING_TABLE) else None),
         "large_tiles": meta["large_tiles"],
         "algorithmic_bytes_per_frame": B,
         "frame_hbm_roofline_frac": B / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),

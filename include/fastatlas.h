@@ -372,6 +372,21 @@ enum { FA_TUNE_PACK_BLOCK = 1, FA_TUNE_OCC_SMALL_TEXELS = 2, FA_TUNE_UF_LINK_INI
 int fa_set_tuning(fa_ctx* ctx, int knob, int value);
 int fa_get_tuning(fa_ctx* ctx, int knob);
 
+/* Knobs by frame shape, as an autotuner writes them (text in host memory,
+ * copied; it replaces the context's previous table). One entry per line, '#'
+ * starts a comment:
+ *   t_lo t_hi omega J pack_block small_texels lane_texels uf_link_init
+ *   uf_edge_hooks uf_tile
+ * A frame of T triangles at atlas side omega with the context's J uses the
+ * first entry with t_lo <= T <= t_hi, omega equal (0: any) and J equal (0:
+ * any); frames no entry matches use the fa_set_tuning values. Applies to
+ * fa_build_atlas, fa_build_dual_atlas and the per-view batch path (batched
+ * launches use the context's values). Results never depend on the knobs.
+ * Errors: FA_ERR_INVALID_ARG for a null argument, a malformed line or a value
+ * fa_set_tuning would refuse (the previous table is kept). An empty text
+ * clears the table. */
+int fa_load_tuning_table(fa_ctx* ctx, const char* text);
+
 /* Per-kernel timing: when enabled, fa_build_atlas (with uv and occupancy
  * outputs) records an event after each of its 21 stages (a stage is one
  * kernel, or none when the configuration folds it into another); fa_stage_times

@@ -73,7 +73,8 @@ assert CHART_DTYPE.itemsize == 64 and META_DTYPE.itemsize == 64
 
 EXPORTS = ["fa_create", "fa_destroy", "fa_status_string", "fa_scene_adjacency", "fa_scene_evict",
            "fa_build_atlas", "fa_build_atlas_batch", "fa_pack_boxes", "fa_set_tuning",
-           "fa_get_tuning", "fa_set_stage_timing", "fa_stage_times", "fa_visibility",
+           "fa_get_tuning", "fa_load_tuning_table", "fa_set_stage_timing", "fa_stage_times",
+           "fa_visibility",
            "fa_reuse_flags", "fa_build_dual_atlas", "fa_build_atlas_static", "fa_device_bytes"]
 
 
@@ -97,6 +98,7 @@ def _load():
                                   c_void_p, c_void_p]
     lib.fa_set_tuning.argtypes = [c_void_p, c_int, c_int]
     lib.fa_get_tuning.argtypes = [c_void_p, c_int]
+    lib.fa_load_tuning_table.argtypes = [c_void_p, ctypes.c_char_p]
     lib.fa_set_stage_timing.argtypes = [c_void_p, c_int]
     lib.fa_stage_times.argtypes = [c_void_p, POINTER(c_float), c_int]
     lib.fa_visibility.argtypes = [c_void_p, POINTER(fa_mesh), POINTER(fa_camera),
@@ -111,7 +113,8 @@ def _load():
     lib.fa_build_atlas_static.argtypes = [POINTER(fa_mesh), c_void_p, POINTER(fa_camera), c_int32,
                                           c_float, POINTER(fa_atlas_out), c_void_p]
     for n in ("fa_scene_adjacency", "fa_scene_evict", "fa_build_atlas", "fa_build_atlas_batch",
-              "fa_pack_boxes", "fa_set_tuning", "fa_get_tuning", "fa_set_stage_timing",
+              "fa_pack_boxes", "fa_set_tuning", "fa_get_tuning", "fa_load_tuning_table",
+              "fa_set_stage_timing",
               "fa_stage_times", "fa_visibility", "fa_reuse_flags", "fa_build_dual_atlas",
               "fa_build_atlas_static"):
         getattr(lib, n).restype = c_int
@@ -131,6 +134,7 @@ fa_build_atlas_batch = _lib.fa_build_atlas_batch
 fa_pack_boxes = _lib.fa_pack_boxes
 fa_set_tuning = _lib.fa_set_tuning
 fa_get_tuning = _lib.fa_get_tuning
+fa_load_tuning_table = _lib.fa_load_tuning_table
 fa_set_stage_timing = _lib.fa_set_stage_timing
 fa_stage_times = _lib.fa_stage_times
 fa_visibility = _lib.fa_visibility
@@ -259,18 +263,34 @@ def build_atlas_static(mesh: Mesh, visible, view_proj, width, height, atlas_size
     return out
 
 
+# Knobs by frame shape chosen by the project's autotuner on an MI355X
+# (autotune.tune_table); every context loads it unless told otherwise.
+TUNING_TABLE = os.path.join(_HERE, "tuning_gfx950.txt")
+
+
 class Context:
-    """Owns an fa_ctx (scratch + resident scene adjacency) on one device."""
+    """Owns an fa_ctx (scratch + resident scene adjacency) on one device.
+    tuning_table: path of a tuning table to load (default: TUNING_TABLE when
+    the file exists; None: no table)."""
 
     def __init__(self, max_triangles, max_vertices, max_charts=65536, max_atlas=8192,
                  num_scales=64, gutter=1, min_box=2, flags=0, device=0, max_views=1,
-                 max_profile_columns=0, hbm_budget_bytes=0):
+                 max_profile_columns=0, hbm_budget_bytes=0, tuning_table="default"):
         cfg = fa_config(device, num_scales, max_triangles, max_vertices, max_charts, max_atlas,
                         gutter, min_box, flags, max_views, max_profile_columns, hbm_budget_bytes)
         h = c_void_p()
         _check(fa_create(ctypes.byref(cfg), ctypes.byref(h)), "fa_create")
         self.h = h
         self.cfg = cfg
+        if tuning_table == "default":
+            tuning_table = TUNING_TABLE if os.path.exists(TUNING_TABLE) else None
+        if tuning_table is not None:
+            with open(tuning_table) as fh:
+                self.load_tuning_table(fh.read())
+
+    def load_tuning_table(self, text: str):
+        """Knobs by frame shape (fa_load_tuning_table); '' clears the table."""
+        _check(fa_load_tuning_table(self.h, text.encode()), "fa_load_tuning_table")
 
     def close(self):
         if getattr(self, "h", None):

@@ -91,3 +91,21 @@ def tune(ctx: Context, run, out: AtlasOutputs, reps: int = 30, knobs=None, strea
 def save(report, path):
     with open(path, "w") as f:
         json.dump(report, f, indent=1)
+
+
+TABLE_ORDER = ("pack_block", "occ_small_texels", "occ_lane_texels", "uf_link_init",
+               "uf_edge_hooks", "uf_tile")
+
+
+def table_line(t_lo, t_hi, omega, J, choice, note=""):
+    """One tuning-table entry (fa_load_tuning_table) from a tune() choice."""
+    vals = " ".join(str(int(choice[k])) for k in TABLE_ORDER)
+    return f"{t_lo} {t_hi} {omega} {J} {vals}" + (f"  # {note}" if note else "")
+
+
+def table_text(lines, header=""):
+    head = ["# t_lo t_hi omega J pack_block small_texels lane_texels uf_link_init "
+            "uf_edge_hooks uf_tile"]
+    if header:
+        head.insert(0, "# " + header)
+    return "\n".join(head + list(lines)) + "\n"

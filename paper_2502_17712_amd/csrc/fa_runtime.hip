@@ -17,6 +17,14 @@ using namespace fa;
 
 namespace {
 
+// One entry of the tuning table: the knobs for frames of T in [t_lo, t_hi]
+// triangles at atlas side omega (0: any) with J candidates (0: any).
+struct TuneEntry {
+  int64_t t_lo, t_hi;
+  int32_t omega, J;
+  int32_t pack_block, small_texels, lane_texels, uf_link_init, uf_edge_hooks, uf_tile;
+};
+
 struct Scene {
   int32_t* nbr = nullptr;
   int64_t T = 0, V = 0;
@@ -80,6 +88,7 @@ struct fa_ctx {
   int uf_link_init = 1;
   int uf_edge_hooks = 5;
   int uf_tile = 4096;
+  std::vector<TuneEntry> table;    // knobs by frame shape (fa_load_tuning_table)
   int32_t* check_flag = nullptr;  // device int for index validation
   // visibility pass scratch: occluder list [max_triangles] + its counter, and
   // a depth buffer that grows to the largest grid asked for
@@ -570,13 +579,27 @@ int run_frame_core(const Knobs& kn, const Work& w, const fa_mesh* mesh, const in
 
 extern "C" {
 
+// The knobs of a frame: the first tuning-table entry matching its shape,
+// else the context's own.
+static Knobs frame_knobs(const fa_ctx* ctx, int64_t T, FrameParams* p) {
+  for (const TuneEntry& e : ctx->table) {
+    if (T < e.t_lo || T > e.t_hi || (e.omega && e.omega != p->omega) || (e.J && e.J != p->J))
+      continue;
+    p->edge_hooks = e.uf_edge_hooks;
+    p->uf_tile = e.uf_tile;
+    return Knobs{e.pack_block, e.small_texels, e.lane_texels, e.uf_link_init};
+  }
+  return Knobs{ctx->pack_block, ctx->small_texels, ctx->lane_texels, ctx->uf_link_init};
+}
+
 static int run_frame(fa_ctx* ctx, const Work& w, const fa_mesh* mesh, Scene* sc,
-                     const uint8_t* visible, const FrameParams& p, const fa_atlas_out* out,
+                     const uint8_t* visible, const FrameParams& p_in, const fa_atlas_out* out,
                      hipStream_t st) {
   // one event after every kernel (names in order: fa_stage_times)
   Marker mk;
   if (ctx->timing) { mk.ev = ctx->ev; mk.cap = kStages + 1; }
-  const Knobs kn{ctx->pack_block, ctx->small_texels, ctx->lane_texels, ctx->uf_link_init};
+  FrameParams p = p_in;
+  const Knobs kn = frame_knobs(ctx, mesh->num_triangles, &p);
   const int rc = run_frame_core(kn, w, mesh, sc->nbr, visible, p, out, nullptr, mk, st);
   ctx->ev_marks = mk.n;
   ctx->ev_recorded = ctx->timing && mk.n == kStages + 1;
@@ -802,6 +825,42 @@ int fa_pack_boxes(fa_ctx* ctx, const float* sizes, int32_t n, int32_t atlas_size
   ok(launch_pack_emit(n, charts, placements, w, st));
   ok(launch_meta(p, w, meta, st));
   return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+
+// Parse a tuning table (see fastatlas.h); every value must be one that
+// fa_set_tuning accepts for its knob.
+int fa_load_tuning_table(fa_ctx* ctx, const char* text) {
+  if (!ctx || !text) return FA_ERR_INVALID_ARG;
+  std::vector<TuneEntry> tab;
+  const char* q = text;
+  while (*q) {
+    const char* e = q;
+    while (*e && *e != '\n') ++e;
+    std::string line(q, e);
+    q = *e ? e + 1 : e;
+    const size_t hash = line.find('#');
+    if (hash != std::string::npos) line.resize(hash);
+    if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+    long long v[10];
+    int used = 0;
+    if (std::sscanf(line.c_str(), "%lld %lld %lld %lld %lld %lld %lld %lld %lld %lld %n", &v[0],
+                    &v[1], &v[2], &v[3], &v[4], &v[5], &v[6], &v[7], &v[8], &v[9], &used) != 10 ||
+        line.find_first_not_of(" \t\r", (size_t)used) != std::string::npos)
+      return FA_ERR_INVALID_ARG;
+    TuneEntry t{v[0], v[1], (int32_t)v[2], (int32_t)v[3], (int32_t)v[4], (int32_t)v[5],
+                (int32_t)v[6], (int32_t)v[7], (int32_t)v[8], (int32_t)v[9]};
+    const bool ok = t.t_lo >= 0 && t.t_hi >= t.t_lo && (t.omega == 0 || is_pow2(t.omega)) &&
+                    t.J >= 0 && t.J <= kMaxScales &&
+                    (t.pack_block == 256 || t.pack_block == 512 || t.pack_block == 1024) &&
+                    t.small_texels >= 0 && t.small_texels <= 4096 && t.lane_texels >= 0 &&
+                    t.lane_texels <= 4096 && (t.uf_link_init == 0 || t.uf_link_init == 1) &&
+                    t.uf_edge_hooks >= 0 && t.uf_edge_hooks <= 5 &&
+                    (t.uf_tile == 2048 || t.uf_tile == 4096 || t.uf_tile == 8192);
+    if (!ok) return FA_ERR_INVALID_ARG;
+    tab.push_back(t);
+  }
+  ctx->table = std::move(tab);
+  return FA_OK;
 }
 
 int fa_set_tuning(fa_ctx* ctx, int knob, int value) {

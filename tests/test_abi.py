@@ -51,3 +51,9 @@ def test_create_rejects_bad_config_on_host():
         assert fa.fa_create(ctypes.byref(cfg), ctypes.byref(h)) == fa.FA_ERR_INVALID_ARG, bad
         assert not h.value
     assert fa.fa_status_string(fa.FA_ERR_NOFIT) == b"no candidate scale fits the atlas"
+
+
+def test_tuning_table_rejects_null_arguments():
+    import paper_2502_17712_amd as fa
+    assert fa.fa_load_tuning_table(None, b"") == fa.FA_ERR_INVALID_ARG
+

@@ -26,10 +26,12 @@ def _fa():
 
 
 def ctx_for(J=64, gutter=1, flags=0, max_charts=65536, T=2_300_000, V=1_200_000):
+    # no tuning table: the knob tests set the knobs they check, and a table
+    # entry for the frame's shape would take precedence
     key = (J, gutter, flags, max_charts, T, V)
     if key not in _CTX:
         _CTX[key] = _fa().Context(T, V, max_charts=max_charts, max_atlas=8192, num_scales=J,
-                                  gutter=gutter, flags=flags)
+                                  gutter=gutter, flags=flags, tuning_table=None)
     return _CTX[key]
 
 

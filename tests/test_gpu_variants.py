@@ -211,3 +211,44 @@ def test_hbm_budget_evicts_least_recently_used_scene():
     with pytest.raises(fa.FastAtlasError) as e:
         fa.Context(T, V, max_charts=4096, max_atlas=1024, hbm_budget_bytes=base // 2)
     assert e.value.code == fa.FA_ERR_OUT_OF_MEMORY
+
+
+def test_tuning_table_by_shape():
+    """Knobs chosen per frame shape from a tuning table change no result; a
+    malformed table or a refused value is rejected and the previous table
+    kept."""
+    import os
+    import paper_2502_17712_amd as fa
+    ctx = ctx_for()
+    table = ("# knobs by shape\n"
+             "0 100000 0 64 256 16 0 0 2 8192   # orbit-sized frames\n"
+             "100001 1073741824 4096 64 512 128 16 1 4 2048\n")
+    try:
+        ctx.load_tuning_table(table)
+        for f in (scenes.orbit_frame(21), scenes.city_frame(5)):
+            compare(run_gpu(f, ctx), oracle.build_frame(f))
+        for bad in ("0 10 0 64 256 16 0 0 2", "0 10 0 64 300 16 0 0 2 8192",
+                    "0 10 1000 64 256 16 0 0 2 8192", "10 0 0 64 256 16 0 0 2 8192",
+                    "0 10 0 64 256 16 0 0 7 8192", "0 10 0 64 256 16 0 0 2 8192 x"):
+            with pytest.raises(fa.FastAtlasError) as e:
+                ctx.load_tuning_table(bad)
+            assert e.value.code == fa.FA_ERR_INVALID_ARG, bad
+        # the valid table is still in force
+        f = scenes.orbit_frame(40)
+        compare(run_gpu(f, ctx), oracle.build_frame(f))
+    finally:
+        ctx.load_tuning_table("")  # the shared test context runs without a table
+
+
+def test_default_tuning_table_changes_no_result():
+    """The committed tuning table (loaded by default) on the three workloads."""
+    import os
+    import paper_2502_17712_amd as fa
+    if not os.path.exists(fa.TUNING_TABLE):
+        pytest.skip("no committed tuning table")
+    ctx = fa.Context(2_300_000, 1_200_000, max_charts=65536, max_atlas=4096)
+    for f in (scenes.grid_frame(9), scenes.orbit_frame(70), scenes.city_frame(12),
+              scenes.scatter_frame(3)):
+        compare(run_gpu(f, ctx), oracle.build_frame(f))
+    ctx.close()
+

@@ -60,8 +60,10 @@ def test_static_matches_context_path():
     fa = _fa()
     frames = [_orbit_part(12), scenes.grid_frame(3)]   # the second call is smaller
     assert frames[1].num_triangles < frames[0].num_triangles
+    # library default knobs on both sides (the static entry point has no
+    # tuning table; the raster's tile count in meta depends on the knobs)
     ctx = fa.Context(max(f.num_triangles for f in frames), max(f.num_vertices for f in frames),
-                     max_charts=fa.STATIC_MAX_CHARTS, max_atlas=4096)
+                     max_charts=fa.STATIC_MAX_CHARTS, max_atlas=4096, tuning_table=None)
     for f in frames:
         print(f"[gpu] static vs context: {f.name} T={f.num_triangles}", flush=True)
         mesh = fa.Mesh(f.positions, f.indices, f.scene_key)
@@ -87,7 +89,7 @@ def test_static_errors_and_recovery():
     assert g["meta"]["status"] == fa.FA_ERR_INVALID_ARG
     # a good frame right after is correct again
     ctx = fa.Context(f.num_triangles, f.num_vertices, max_charts=fa.STATIC_MAX_CHARTS,
-                     max_atlas=1024)
+                     max_atlas=1024, tuning_table=None)
     mesh = fa.Mesh(f.positions, f.indices, f.scene_key)
     want = ctx.build_atlas(mesh, torch.as_tensor(f.visible).cuda(), f.view_proj, f.width,
                            f.height, f.atlas_size, f.rate)
