@@ -321,6 +321,11 @@ __device__ __forceinline__ void k_pack_box_body(const float2* __restrict__ wh,
   long long run = 0;
   int mloc = INT_MIN, bad = 0;
   if (tid == 0) last_x = 0;
+  // the frontline is cleared up front (its widest extent, 2 omega): the
+  // fold's barriers order it before the push
+  for (int c = tid; c < 2 * omega; c += NT) F[c] = 0;
+  if (tid < 3) Hsh[tid] = 0;
+  if (tid < 4) LC[tid >> 1][tid & 1] = 0;
   int pass = 0;
   for (int base = 0; base < C; base += kFoldItems * NT, ++pass) {
     const int i0 = base + kFoldItems * tid;
@@ -343,21 +348,25 @@ __device__ __forceinline__ void k_pack_box_body(const float2* __restrict__ wh,
     const uint32_t incl = block_incl_scan_dpp<NT>(own, shs[pass & 1], &tot);
     long long Xi = run + (long long)(incl - own);
     run += tot;
+    uint32_t xs[kFoldItems], abs_[kFoldItems];
 #pragma unroll
     for (int u = 0; u < kFoldItems; ++u) {
       const int i = i0 + u;
+      xs[u] = (uint32_t)Xi;
+      abs_[u] = (uint32_t)a[u] | ((uint32_t)b[u] << 16);
       if (i < C) {
-        const uint32_t ab = (uint32_t)a[u] | ((uint32_t)b[u] << 16);
         Xg[i] = Xi;
-        ABg[i] = ab;
-        if (i < kcap) {
-          Xr[i] = (uint32_t)Xi;
-          AB[i] = ab;
-        }
+        ABg[i] = abs_[u];
         if (i == C - 1) last_x = Xi;
         mloc = max(mloc, (int)(Xi & (long long)(omega - 1)) + a[u] - omega);
         Xi += a[u];
       }
+    }
+    // the first chunk to LDS, one 16-byte store per array (i0 is a multiple
+    // of 4 and kcap of 64; entries past C are never read)
+    if (i0 < kcap) {
+      *reinterpret_cast<uint4*>(Xr + i0) = make_uint4(xs[0], xs[1], xs[2], xs[3]);
+      *reinterpret_cast<uint4*>(AB + i0) = make_uint4(abs_[0], abs_[1], abs_[2], abs_[3]);
     }
   }
   {
@@ -415,9 +424,6 @@ __device__ __forceinline__ void k_pack_box_body(const float2* __restrict__ wh,
     return;
   }
   const int L = omega + m;
-  for (int c = tid; c < L; c += NT) F[c] = 0;
-  if (tid < 3) Hsh[tid] = 0;
-  if (tid < 4) LC[tid >> 1][tid & 1] = 0;
 
   int Hw = 0, seg = 0;
   bool over = false;
@@ -455,12 +461,17 @@ __device__ __forceinline__ void k_pack_box_body(const float2* __restrict__ wh,
     for (int base = 0; base < cn; base += kFoldItems * NT, ++pass) {
       const int i0 = base + kFoldItems * tid;
       uint32_t fl = 0, own = 0;
+      if (i0 < cn) {
+        const uint4 q = *reinterpret_cast<const uint4*>(Xr + i0);
+        const uint32_t xv[kFoldItems + 1] = {i0 > 0 ? Xr[i0 - 1] : 0u, q.x, q.y, q.z, q.w};
 #pragma unroll
-      for (int u = 0; u < kFoldItems; ++u) {
-        const int i = i0 + u;
-        const bool f = i < cn && (i == 0 || ((xbase + Xr[i]) >> lg) != ((xbase + Xr[i - 1]) >> lg));
-        fl |= (uint32_t)f << u;
-        own += f;
+        for (int u = 0; u < kFoldItems; ++u) {
+          const int i = i0 + u;
+          const bool f =
+              i < cn && (i == 0 || ((xbase + xv[u + 1]) >> lg) != ((xbase + xv[u]) >> lg));
+          fl |= (uint32_t)f << u;
+          own += f;
+        }
       }
       uint32_t tot;
       int at = nr + (int)(block_incl_scan_dpp<NT>(own, shs[pass & 1], &tot) - own);

@@ -199,8 +199,10 @@ __device__ __forceinline__ void snap_polygon(int64_t t, const int32_t* __restric
   } else {
     poly[0] = a; poly[1] = b; poly[2] = cc; poly[3] = cc; n = 3;
   }
-  for (int k = 0; k < n; ++k)
-    if (!(poly[k].w > 0.0f)) return;
+  // constant indices only (a runtime index would place the polygon in memory)
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (k < n && !(poly[k].w > 0.0f)) return;
   const ChartXform m = chart_xform(charts[c], p, st);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -501,7 +503,10 @@ __device__ __forceinline__ void k_occ_big_body(
   const ulonglong2 lastv = big[nent - 1];
   const uint64_t total = (lastv.y & kLow) + (lastv.y >> kSlotShift);
   const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
-  const uint64_t wid = (uint64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  // the wave index through readfirstlane: the compiler then knows it (and all
+  // loop bounds below) to be uniform and keeps the tile loop's control scalar
+  const uint64_t wid = (uint64_t)blockIdx.x * (kBlock / kWave) +
+                       (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const uint64_t per = (total + nwaves - 1) / nwaves;
   const uint64_t k0 = wid * per, k1 = min<uint64_t>(total, k0 + per);
   if (k0 >= k1) return;
@@ -554,19 +559,33 @@ __device__ __forceinline__ void k_occ_big_body(
                           (uint32_t)rl((int)(uint32_t)base, j);
       const uint64_t nj = (uint64_t)(uint32_t)rl((int)(uint32_t)nt, j);
       const uint32_t txj = (uint32_t)rl((int)tiles_x, j);
-      const uint64_t t0 = (k0 > bj ? k0 : bj) - bj;
-      const uint64_t t1 = (k1 < bj + nj ? k1 : bj + nj) - bj;
-      const Edges dy = madd(Edges{0, 0, 0}, kRows, step_y(fp));
-      for (uint64_t tt = t0; tt < t1; ++tt) {
-        const int tx = fp.tx0 + kOccTile * (int)(tt % txj) + lx;
-        const int ty0 = fp.ty0 + kOccTile * (int)(tt / txj) + ly;
-        Edges ev = edges_at(fp, tx, ty0);
+      // a footprint has fewer than 2^32 tiles (at most (omega / 16)^2)
+      const uint32_t t0 = (uint32_t)((k0 > bj ? k0 : bj) - bj);
+      const uint32_t t1 = (uint32_t)((k1 < bj + nj ? k1 : bj + nj) - bj);
+      // The edge functions are linear in the texel: at the lane's texel they
+      // are their value at the tile's first texel (uniform, scalar unit) plus
+      // the lane's offset, fixed per footprint.
+      const Edges dx = step_x(fp), dy = step_y(fp);
+      const Edges off = madd(madd(Edges{0, 0, 0}, lx, dx), ly, dy);
+      const Edges dq = madd(Edges{0, 0, 0}, kRows, dy);
+      const int64_t row_step = (int64_t)kRows * p.omega;
+      uint32_t ti = t0 % txj, tj = t0 / txj;  // tile column and row, stepped below
+      for (uint32_t tt = t0; tt < t1; ++tt) {
+        const int ox = fp.tx0 + kOccTile * (int)ti, oy = fp.ty0 + kOccTile * (int)tj;
+        const Edges eo = edges_at(fp, ox, oy);
+        Edges ev{eo.e0 + off.e0, eo.e1 + off.e1, eo.e2 + off.e2};
+        const int tx = ox + lx, ty0 = oy + ly;
+        const bool col = tx <= fp.tx1;
+        int32_t* dst = occ + (int64_t)ty0 * p.omega + tx;
 #pragma unroll
         for (int q = 0; q < kOccTile / kRows; ++q) {
-          const int ty = ty0 + q * kRows;
-          if (tx <= fp.tx1 && ty <= fp.ty1 && inside(ev))
-            occ[(int64_t)ty * p.omega + tx] = fp.chart;
-          add(ev, dy);
+          if (col && ty0 + q * kRows <= fp.ty1 && inside(ev)) *dst = fp.chart;
+          add(ev, dq);
+          dst += row_step;
+        }
+        if (++ti == txj) {
+          ti = 0;
+          ++tj;
         }
       }
     }
