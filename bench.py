@@ -356,7 +356,11 @@ def main():
         ctx.load_tuning_table("")
         lines, tuning = [], {}
 
+        defaults = {k: ctx.get_tuning(k) for k in autotune.KNOBS}
+
         def tune_on(name, ctx_, mesh_, frs, out_):
+            for k, v in defaults.items():  # every search starts from the library defaults
+                ctx_.set_tuning(k, v)
             vs = [torch.as_tensor(f.visible).to(dev) for f in frs]
             cyc = [0]
 
@@ -382,8 +386,15 @@ def main():
         omesh = fa.Mesh(o0.positions, o0.indices, o0.scene_key)
         ofr = [scenes.orbit_frame(k) for k in range(0, 120, 15)]
         ch = tune_on("orbit86k", gctx, omesh, ofr, gctx.outputs(omesh, 2048))
-        lines.append(autotune.table_line(20001, 500000, 0, 64, ch, "86k-triangle orbit, 2048^2"))
+        lines.append(autotune.table_line(20001, 150000, 0, 64, ch, "86k-triangle orbit, 2048^2"))
         gctx.close()
+        # the many-chart workload (24,000 boxes, ~23k charts per frame)
+        s0 = scenes.scatter_frame(0)
+        smesh = fa.Mesh(s0.positions, s0.indices, s0.scene_key)
+        sfr = [scenes.scatter_frame(k) for k in range(0, 16, 2)]
+        ch = tune_on("scatter288k", ctx, smesh, sfr, ctx.outputs(smesh, 4096))
+        lines.append(autotune.table_line(150001, 500000, 0, 64, ch,
+                                         "288k-triangle scatter, ~23k charts, 4096^2"))
         ch = tune_on("city2m", ctx, mesh, frames, out)
         lines.append(autotune.table_line(500001, 1 << 30, 0, 64, ch,
                                          "2.2M-triangle city, 4096^2"))

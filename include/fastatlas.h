@@ -377,8 +377,9 @@ int fa_get_tuning(fa_ctx* ctx, int knob);
  * starts a comment:
  *   t_lo t_hi omega J pack_block small_texels lane_texels uf_link_init
  *   uf_edge_hooks uf_tile
- * A frame of T triangles at atlas side omega with the context's J uses the
- * first entry with t_lo <= T <= t_hi, omega equal (0: any) and J equal (0:
+ * A frame on a mesh of T triangles (fa_mesh.num_triangles, not the visible
+ * count) at atlas side omega with the context's J uses the first entry with
+ * t_lo <= T <= t_hi, omega equal (0: any) and J equal (0:
  * any); frames no entry matches use the fa_set_tuning values. Applies to
  * fa_build_atlas, fa_build_dual_atlas and the per-view batch path (batched
  * launches use the context's values). Results never depend on the knobs.

@@ -488,20 +488,35 @@ __device__ __forceinline__ void k_uf_flatten_count_body(const int32_t* __restric
   const int nv = st->visible;
   const int64_t base = (int64_t)blockIdx.x * kTriTile + (int64_t)threadIdx.x * 4;
   if ((int64_t)blockIdx.x * kTriTile >= nv) return;
+  // the four walks of a thread advance together, so that their dependent
+  // loads are in flight at the same time (constant indices keep the arrays
+  // in registers)
+  int t[4], r[4], up[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) t[k] = base + k < nv ? vlist[base + k] : -1;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    r[k] = t[k];
+    up[k] = t[k] >= 0 ? aload(&parent[t[k]]) : t[k];
+  }
+  bool more = true;
+  while (more) {
+    more = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (up[k] != r[k]) {
+        r[k] = up[k];
+        up[k] = aload(&parent[r[k]]);
+        more = true;
+      }
+    }
+  }
   uint32_t roots = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int64_t i = base + k;
-    if (i < nv) {
-      const int t = vlist[i];
-      int r = t, up = aload(&parent[t]);
-      while (up != r) {
-        r = up;
-        up = aload(&parent[r]);
-      }
-      if (r != t) astore(&parent[t], r);
-      roots += (r == t);
-    }
+    if (t[k] < 0) continue;
+    if (r[k] != t[k]) astore(&parent[t[k]], r[k]);
+    roots += (r[k] == t[k]);
   }
   roots = block_sum<uint32_t>(roots, sh);
   if (threadIdx.x == 0) tile_count[blockIdx.x] = roots;
