@@ -43,10 +43,42 @@ __device__ __forceinline__ int uf_root(int32_t* parent, int x) {
   }
 }
 
+// The roots of u and of v by uf_root's walk, the two walks advancing
+// together so that their dependent loads overlap.
+__device__ __forceinline__ void uf_root2(int32_t* parent, int u, int v, int& ru, int& rv) {
+  int cu = parent[u], cv = parent[v], pu = u, pv = v;
+  bool du = cu == u, dv = cv == v;
+  while (!(du && dv)) {
+    const int nu = du ? cu : parent[cu];
+    const int nv = dv ? cv : parent[cv];
+    if (!du) {
+      if (nu >= cu) {
+        du = true;
+      } else {
+        astore(&parent[pu], nu);
+        pu = cu;
+        cu = nu;
+      }
+    }
+    if (!dv) {
+      if (nv >= cv) {
+        dv = true;
+      } else {
+        astore(&parent[pv], nv);
+        pv = cv;
+        cv = nv;
+      }
+    }
+  }
+  ru = cu;
+  rv = cv;
+}
+
 // Join the trees of u and v: the larger root is hooked below the smaller one
 // with a compare-and-swap; on failure continue from the value that won.
 __device__ __forceinline__ void uf_join(int32_t* parent, int u, int v) {
-  int ru = uf_root(parent, u), rv = uf_root(parent, v);
+  int ru, rv;
+  uf_root2(parent, u, v, ru, rv);
   while (ru != rv) {
     if (ru < rv) {
       int old = atomicCAS(&parent[rv], rv, ru);
@@ -134,11 +166,21 @@ __global__ void k_prologue(const float* __restrict__ pos, int64_t V, FrameParams
   k_prologue_body(pos, V, p, clip, vmin, cov, vis, nbr, T, parent, cot, tile_vis, uf_init, vblocks, st, big_counter);
 }
 
-// Sum of cnt[0 .. n) by one workgroup (the exclusive prefix of tile n).
+// Sum of cnt[0 .. n) by one workgroup (the exclusive prefix of tile n);
+// each thread issues eight loads before it adds any.
 __device__ __forceinline__ uint32_t tiles_before(const uint32_t* __restrict__ cnt, int64_t n,
                                                  uint32_t* sh) {
   uint32_t v = 0;
-  for (int64_t u = threadIdx.x; u < n; u += blockDim.x) v += cnt[u];
+  for (int64_t u0 = threadIdx.x; u0 < n; u0 += 8 * (int64_t)blockDim.x) {
+    uint32_t x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t u = u0 + (int64_t)j * blockDim.x;
+      x[j] = u < n ? cnt[u] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v += x[j];
+  }
   return block_sum<uint32_t>(v, sh);
 }
 
@@ -722,7 +764,7 @@ __device__ __forceinline__ bool triangle_ndc_box(const float4& a, const float4& 
 // registers, then merged into a small per-workgroup table in LDS, and only the
 // table is flushed with global atomics (large charts would otherwise
 // serialize on their four accumulator words).
-constexpr int kGatherItems = 4;
+constexpr int kGatherItems = 2;
 constexpr int kSlots = 64;
 constexpr unsigned kFillBlocks = 1024;  // least workgroups that fill the occupancy map
 constexpr unsigned kFillGroups = 256;   // the same for the 1024-thread union-find tiles
