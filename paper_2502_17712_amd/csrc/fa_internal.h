@@ -21,6 +21,8 @@ constexpr int kSortTile = 2048;      // keys per workgroup in one radix pass
 constexpr int kCandStride = 8;       // int32 per candidate in the table
 constexpr int kMaxAtlas = 8192;
 constexpr int kCountGrid = 256;      // workgroups of the occupancy count
+constexpr int kOrderGroups = 32;     // workgroups of the chart order above 1024 charts
+static_assert(kOrderGroups <= kCountGrid, "the order's chunk sums use Work::partial");
 constexpr int kOccBigGrid = 2048;    // blocks of the large-footprint raster
 constexpr int64_t kBigCap = 1 << 20; // queue capacity (more: rasterized where found)
 
@@ -40,7 +42,7 @@ struct FrameState {
   int32_t fp_columns; // full-scale footprint profile columns of the frame (footprint push)
   unsigned long long occupied;
   uint32_t ticket;    // workgroups of the occupancy count that have finished
-  uint32_t pad;
+  uint32_t order_sync;  // barrier arrivals of the many-chart order (kOrderGroups workgroups)
 };
 
 // Constants of one visibility pass, passed by value (float64).
@@ -87,7 +89,7 @@ struct Work {
   int32_t* vals_a;
   uint32_t* keys_b;
   int32_t* vals_b;
-  uint32_t* hist;        // [kRadix * tiles(max_charts)]
+  uint32_t* hist;        // [kRadix * max(tiles(max_charts), kOrderGroups)]
   float2* sorted_wh;     // [max_charts] oriented sizes in packing order
   long long* cand_x;     // [J][max_charts] prefix sums
   uint32_t* cand_ab;     // [J][max_charts] a | b << 16

@@ -166,7 +166,7 @@ int fa_create(const fa_config* cfg_in, fa_ctx** out_ctx) {
   const size_t V = (size_t)std::max<int64_t>(cfg.max_vertices, 1);
   const size_t C = (size_t)cfg.max_charts, J = (size_t)cfg.num_scales;
   const size_t tiles = T / kTriTile + 2;
-  const size_t sort_tiles = C / kSortTile + 2;
+  const size_t sort_tiles = std::max<size_t>(C / kSortTile + 2, kOrderGroups);
   struct Part { void** p; size_t bytes; };
   ctx->slots.resize(cfg.max_views);
   for (int v = 0; v < cfg.max_views; ++v) {

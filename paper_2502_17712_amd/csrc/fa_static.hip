@@ -46,7 +46,8 @@ size_t carve(char* base, Work* w, AdjTmp* adj, int32_t** nbr, int32_t** flag) {
     return p;
   };
   const size_t T = kStaticT, V = kStaticV, C = kStaticC, J = kStaticJ;
-  const size_t tiles = T / kTriTile + 2, sort_tiles = C / kSortTile + 2;
+  const size_t tiles = T / kTriTile + 2,
+               sort_tiles = std::max<size_t>(C / kSortTile + 2, kOrderGroups);
   const size_t big = std::min<size_t>(2 * T, (size_t)kBigCap);
   Work& x = *w;
   x = Work{};

@@ -377,21 +377,244 @@ __device__ __forceinline__ void order_body(const FrameParams& p, const uint32_t*
   }
 }
 
+// ---- many charts: the same two passes over kOrderGroups workgroups -------
+// Above kOrderLds charts one workgroup spends most of its time waiting on
+// global memory round by round, so frames with many charts split the items
+// into kOrderGroups contiguous chunks. Each pass is: chunk histograms of the
+// digit, a barrier of all the launch's workgroups, then every workgroup
+// derives its own digit offsets from all the histograms (digit-major order
+// keeps the sort stable) and scatters its chunk with the same in-workgroup
+// ranking as above. Everything another workgroup reads goes through
+// agent-scope loads and stores (the workgroups sit on different XCDs, each
+// with its own L2).
+
+// Barrier of the launch's workgroups. There are far fewer of them than CUs,
+// so all are resident; the wait is bounded anyway, and a workgroup that gives
+// up reports FA_ERR_DEVICE and leaves. Each thread's stores have completed
+// (s_waitcnt) before its workgroup takes its ticket.
+constexpr uint32_t kSyncSpins = 1u << 22;
+__device__ __forceinline__ bool order_sync(FrameState* st, uint32_t target, int* flag) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(&st->order_sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t spins = 0;
+    while (__hip_atomic_load(&st->order_sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+               target &&
+           spins < kSyncSpins) {
+      __builtin_amdgcn_s_sleep(2);
+      ++spins;
+    }
+    *flag = spins < kSyncSpins;
+    if (!*flag) st->status = FA_ERR_DEVICE;
+  }
+  __syncthreads();
+  return *flag != 0;
+}
+
+__device__ __forceinline__ uint32_t aload_u(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void astore_u(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t aload_i(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void astore_i(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Digit histogram of keys [lo, hi) into row `b` of the block-major table.
+__device__ __forceinline__ void chunk_hist(const uint32_t* kin, int lo, int hi, int shift, int b,
+                                           uint32_t* hist, uint32_t* cnt) {
+  const int tid = threadIdx.x;
+  if (tid < kRadix) cnt[tid] = 0;
+  __syncthreads();
+  for (int i = lo + tid; i < hi; i += kOrderThreads)
+    atomicAdd(&cnt[(aload_u(&kin[i]) >> shift) & (kRadix - 1)], 1u);
+  __syncthreads();
+  if (tid < kRadix) astore_u(&hist[b * kRadix + tid], cnt[tid]);
+}
+
+// This workgroup's first output position per digit: all items of smaller
+// digits, then the items of the same digit in earlier chunks.
+__device__ __forceinline__ void chunk_base(const uint32_t* hist, int b, uint32_t* base,
+                                           uint32_t* sh) {
+  const int tid = threadIdx.x;
+  uint32_t tot = 0, before = 0;
+  if (tid < kRadix) {
+    uint32_t x[kOrderGroups];
+#pragma unroll
+    for (int g = 0; g < kOrderGroups; ++g) x[g] = aload_u(&hist[g * kRadix + tid]);
+#pragma unroll
+    for (int g = 0; g < kOrderGroups; ++g) {
+      tot += x[g];
+      before += g < b ? x[g] : 0u;
+    }
+  }
+  uint32_t all;
+  const uint32_t incl = block_incl_scan_dpp<kOrderThreads>(tot, sh, &all);
+  if (tid < kRadix) base[tid] = incl - tot + before;
+  __syncthreads();
+}
+
+// Stable scatter of items [lo, hi) by the digit at `shift`, from this
+// workgroup's offsets `base`.
+__device__ __forceinline__ void chunk_scatter(const uint32_t* kin, const int32_t* vin,
+                                              uint32_t* kout, int32_t* vout, int lo, int hi,
+                                              int shift, uint32_t* base,
+                                              uint32_t (*wcnt)[kRadix]) {
+  constexpr int NW = kOrderThreads / kWave;
+  const int tid = threadIdx.x, w = tid / kWave;
+  for (int c0 = lo; c0 < hi; c0 += kOrderThreads) {
+    uint32_t* flat = &wcnt[0][0];
+#pragma unroll
+    for (int k = 0; k < NW * kRadix / kOrderThreads; ++k) flat[tid + k * kOrderThreads] = 0u;
+    __syncthreads();
+    const int i = c0 + tid;
+    const bool valid = i < hi;
+    const uint32_t key = valid ? aload_u(&kin[i]) : 0u;
+    const int32_t val = valid ? aload_i(&vin[i]) : 0;
+    const uint32_t d = (key >> shift) & (kRadix - 1);
+    unsigned long long m = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < kRadixBits; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const unsigned long long bb = __ballot(on);
+      m &= on ? bb : ~bb;
+    }
+    const unsigned long long below = m & lanes_below();
+    const uint32_t rank = (uint32_t)__popcll(below);
+    if (valid && below == 0) wcnt[w][d] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (tid < kRadix) {
+      uint32_t run = base[tid];
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        const uint32_t c = wcnt[k][tid];
+        wcnt[k][tid] = run;
+        run += c;
+      }
+      base[tid] = run;
+    }
+    __syncthreads();
+    if (valid) {
+      const uint32_t pos = wcnt[w][d] + rank;
+      astore_u(&kout[pos], key);
+      astore_i(&vout[pos], val);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void order_multi(const FrameParams& p, const uint32_t* __restrict__ accum,
+                                            fa_chart* __restrict__ charts, uint32_t* KA,
+                                            int32_t* VA, uint32_t* KB, int32_t* VB,
+                                            float2* __restrict__ sorted_wh, int from_accum,
+                                            int32_t* __restrict__ fp_off, FrameState* st, int C,
+                                            uint32_t* hist, unsigned long long* part,
+                                            uint32_t* base, uint32_t (*wcnt)[kRadix],
+                                            uint32_t* sh, long long* sh64, int* flag) {
+  const int tid = threadIdx.x, b = blockIdx.x;
+  const int chunk = (C + kOrderGroups - 1) / kOrderGroups;
+  const int lo = min(C, b * chunk), hi = min(C, lo + chunk);
+  const uint32_t G = gridDim.x;
+  // sizes of this chunk's charts (the oriented size also as agent-scope
+  // words: another workgroup copies it into the packing order)
+  long long cols = 0;
+  for (int c = lo + tid; c < hi; c += kOrderThreads) {
+    float2 wh;
+    if (from_accum) {
+      uint4 box;
+      box.x = aload_u(&accum[4 * c + 0]);
+      box.y = aload_u(&accum[4 * c + 1]);
+      box.z = aload_u(&accum[4 * c + 2]);
+      box.w = aload_u(&accum[4 * c + 3]);
+      uint32_t key;
+      chart_size(p, box, charts[c], key, wh);
+      astore_u(&KA[c], key);
+      astore_i(&VA[c], c);
+      astore_i(reinterpret_cast<int32_t*>(&charts[c].oriented_w), __float_as_int(wh.x));
+      astore_i(reinterpret_cast<int32_t*>(&charts[c].oriented_h), __float_as_int(wh.y));
+    } else {
+      wh = make_float2(charts[c].oriented_w, charts[c].oriented_h);
+    }
+    if (fp_off) cols += (long long)floorf(wh.x) + 1;
+  }
+  if (fp_off) {
+    const long long s = block_sum<long long>(cols, sh64);
+    if (tid == 0)
+      __hip_atomic_store(&part[b], (unsigned long long)s, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+  chunk_hist(KA, lo, hi, 0, b, hist, base);
+  if (!order_sync(st, G, flag)) return;
+  if (fp_off) {
+    // footprint columns in chart order: earlier chunks' sums, then this one's
+    long long run = 0, total = 0;
+    for (int g = 0; g < (int)G; ++g) {
+      const long long v = (long long)__hip_atomic_load(&part[g], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+      run += g < b ? v : 0;
+      total += v;
+    }
+    for (int c0 = lo; c0 < hi; c0 += kOrderThreads) {
+      const int c = c0 + tid;
+      const long long n = c < hi ? (long long)floorf(__int_as_float(aload_i(
+                                       reinterpret_cast<const int32_t*>(&charts[c].oriented_w)))) + 1
+                                 : 0;
+      long long tot;
+      const long long incl = block_incl_scan<long long>(n, sh64, &tot);
+      if (c < hi) fp_off[c] = (int32_t)min(run + incl - n, (long long)p.fp_cap);
+      run += tot;
+    }
+    if (b == (int)G - 1 && tid == 0) {
+      fp_off[C] = (int32_t)min(total, (long long)p.fp_cap);
+      st->fp_columns = (int32_t)min(total, (long long)p.fp_cap);
+      if (total > p.fp_cap) st->status = FA_ERR_CAPACITY;
+    }
+  }
+  chunk_base(hist, b, base, sh);
+  chunk_scatter(KA, VA, KB, VB, lo, hi, 0, base, wcnt);
+  if (!order_sync(st, 2 * G, flag)) return;
+  chunk_hist(KB, lo, hi, kRadixBits, b, hist, base);
+  if (!order_sync(st, 3 * G, flag)) return;
+  chunk_base(hist, b, base, sh + kOrderThreads / kWave);
+  chunk_scatter(KB, VB, KA, VA, lo, hi, kRadixBits, base, wcnt);
+  if (!order_sync(st, 4 * G, flag)) return;
+  for (int i = lo + tid; i < hi; i += kOrderThreads) {
+    const int c = aload_i(&VA[i]);
+    const float w = __int_as_float(aload_i(reinterpret_cast<const int32_t*>(&charts[c].oriented_w)));
+    const float h = __int_as_float(aload_i(reinterpret_cast<const int32_t*>(&charts[c].oriented_h)));
+    sorted_wh[i] = make_float2(w, h);
+    charts[c].order_rank = i;
+  }
+}
+
 __device__ __forceinline__ void k_sizes_order_body(
     FrameParams p, const uint32_t* __restrict__ accum, fa_chart* __restrict__ charts,
     uint32_t* __restrict__ keys_a, int32_t* __restrict__ vals_a, uint32_t* __restrict__ keys_b,
     int32_t* __restrict__ vals_b, float2* __restrict__ sorted_wh, int from_accum,
-    int32_t* __restrict__ fp_off, FrameState* __restrict__ st) {
+    int32_t* __restrict__ fp_off, FrameState* __restrict__ st, uint32_t* __restrict__ hist,
+    unsigned long long* __restrict__ part) {
   constexpr int NW = kOrderThreads / kWave;
   __shared__ uint32_t base[kRadix];
   __shared__ uint32_t wcnt[NW][kRadix];
-  __shared__ uint32_t sh[NW];
+  __shared__ uint32_t sh[2 * NW];
   __shared__ long long sh64[NW];
   __shared__ uint32_t lk[2][kOrderLds];
   __shared__ int32_t lv[2][kOrderLds];
   __shared__ float2 lwh[kOrderLds];
+  __shared__ int flag;
   if (st->status != FA_OK) return;
   const int C = min(st->num_charts, p.max_charts);
+  if (gridDim.x > 1 && C > kOrderLds) {
+    order_multi(p, accum, charts, keys_a, vals_a, keys_b, vals_b, sorted_wh, from_accum, fp_off,
+                st, C, hist, part, base, wcnt, sh, sh64, &flag);
+    return;
+  }
+  if (blockIdx.x != 0) return;
   if (from_accum && C <= kOrderLds)
     order_body<true>(p, accum, charts, lk[0], lv[0], lk[1], lv[1], lwh, vals_a, sorted_wh,
                      from_accum, fp_off, st, C, base, wcnt, sh, sh64);
@@ -403,14 +626,16 @@ __global__ __launch_bounds__(kOrderThreads) void k_sizes_order(
     FrameParams p, const uint32_t* __restrict__ accum, fa_chart* __restrict__ charts,
     uint32_t* __restrict__ keys_a, int32_t* __restrict__ vals_a, uint32_t* __restrict__ keys_b,
     int32_t* __restrict__ vals_b, float2* __restrict__ sorted_wh, int from_accum,
-    int32_t* __restrict__ fp_off, FrameState* __restrict__ st) {
-  k_sizes_order_body(p, accum, charts, keys_a, vals_a, keys_b, vals_b, sorted_wh, from_accum, fp_off, st);
+    int32_t* __restrict__ fp_off, FrameState* __restrict__ st, uint32_t* __restrict__ hist,
+    unsigned long long* __restrict__ part) {
+  k_sizes_order_body(p, accum, charts, keys_a, vals_a, keys_b, vals_b, sorted_wh, from_accum,
+                     fp_off, st, hist, part);
 }
 
 __global__ __launch_bounds__(kOrderThreads) void k_sizes_order_b(const BatchView* __restrict__ bv) {
   const BatchView& v = bv[blockIdx.y];
   k_sizes_order_body(v.p, v.w.accum, v.charts, v.w.keys_a, v.w.vals_a, v.w.keys_b, v.w.vals_b,
-                     v.w.sorted_wh, 1, nullptr, v.w.state);
+                     v.w.sorted_wh, 1, nullptr, v.w.state, v.w.hist, v.w.partial);
 }
 
 }  // namespace
@@ -444,12 +669,16 @@ hipError_t launch_adjacency(const int32_t* idx, int64_t T, int64_t V, const AdjT
 hipError_t launch_order(const FrameParams& p, const Work& w, fa_chart* charts, int from_accum,
                         hipStream_t st) {
   int32_t* fp_off = (from_accum && p.fp_cap > 0) ? w.fp_off : nullptr;
-  k_sizes_order<<<1, kOrderThreads, 0, st>>>(p, w.accum, charts, w.keys_a, w.vals_a, w.keys_b,
-                                             w.vals_b, w.sorted_wh, from_accum, fp_off, w.state);
+  k_sizes_order<<<kOrderGroups, kOrderThreads, 0, st>>>(p, w.accum, charts, w.keys_a, w.vals_a,
+                                                        w.keys_b, w.vals_b, w.sorted_wh,
+                                                        from_accum, fp_off, w.state, w.hist,
+                                                        w.partial);
   return hipGetLastError();
 }
 
 hipError_t launch_order_batched(const BatchView* dev, int n, hipStream_t st) {
+  // one workgroup per view: the many-chart barrier needs all its workgroups
+  // resident at once, which kOrderGroups times the views need not be
   if (n > 0) k_sizes_order_b<<<dim3(1, n), kOrderThreads, 0, st>>>(dev);
   return hipGetLastError();
 }

@@ -628,15 +628,19 @@ def scene_scatter(seed: int = 4, count: int = 24000):
 
 
 def scatter_frame(frame: int = 0, rate: float = 1.0, atlas_size: int = 4096,
-                  width: int = 3840, height: int = 2160, seed: int = 4) -> Frame:
+                  width: int = 3840, height: int = 2160, seed: int = 4,
+                  count: int = 24000) -> Frame:
     """~24k small boxes (288k triangles), 3840x2160 view, 4096^2 atlas: about
     20k charts per frame (every visible box is its own chart). Frame f turns
-    the camera by f degrees of yaw about the origin."""
-    pos, tris = _cached(("scatter", seed), lambda: scene_scatter(seed))
+    the camera by f degrees of yaw about the origin. `count` boxes instead of
+    24,000 give a scene of 12 x count triangles (its own scene key)."""
+    pos, tris = _cached(("scatter", seed, count), lambda: scene_scatter(seed, count))
     yaw = math.radians(float(frame))
     eye = np.zeros(3)
     d = np.array([math.cos(yaw), math.sin(yaw), 0.0])
     cam = make_camera(eye, eye + d, width, height, 0.1, 1000.0)
     vis = visible_set(pos, tris, cam)
-    return Frame(f"scatter24k/s{seed}f{frame}", pos, tris, vis, cam.view_proj, width, height,
-                 atlas_size, rate, 4000 + seed, cam.eye, cam.near, 0)
+    key = 4000 + seed if count == 24000 else 7_000_000 + 16 * count + seed
+    name = "scatter24k" if count == 24000 else f"scatter{count}"
+    return Frame(f"{name}/s{seed}f{frame}", pos, tris, vis, cam.view_proj, width, height,
+                 atlas_size, rate, key, cam.eye, cam.near, 0)

@@ -537,13 +537,15 @@ def _fp_frame(kind, k, omega, rate):
         return scenes.grid_frame(k, atlas_size=omega, rate=rate)
     if kind == "orbit":
         return scenes.orbit_frame(k, atlas_size=omega, rate=rate)
+    if kind == "scatter":  # 6000 boxes: several thousand charts, the many-chart order
+        return scenes.scatter_frame(k, rate=rate, atlas_size=omega, count=6000)
     return scenes.city_frame(k, rate=rate, atlas_size=omega)
 
 
 @pytest.mark.parametrize("kind,k,omega,rate", [("grid", 3, 256, 1.0), ("grid", 11, 512, 2.0),
                                                ("grid", 20, 1024, 1.0), ("orbit", 20, 512, 1.0),
                                                ("orbit", 77, 2048, 1.0), ("city", 5, 4096, 1.0),
-                                               ("city", 9, 2048, 2.0)])
+                                               ("city", 9, 2048, 2.0), ("scatter", 2, 4096, 1.0)])
 def test_footprint_push(kind, k, omega, rate):
     f = _fp_frame(kind, k, omega, rate)
     g = run_gpu(f, ctx_for(flags=FP))
@@ -582,6 +584,19 @@ def test_footprint_empty_frame_and_batch():
     torch.cuda.synchronize()
     for x, o in zip(frames, outs):
         compare(o.to_numpy(), oracle.build_frame(x, footprint=True))
+
+
+def test_footprint_capacity_many_charts():
+    # the profile-column total above the capacity, found by the many-chart
+    # order (its last workgroup sums every chunk)
+    fa = _fa()
+    f = _fp_frame("scatter", 4, 4096, 1.0)
+    assert oracle.build_frame(f)["num_charts"] > 1024
+    ctx = fa.Context(f.num_triangles, f.num_vertices, max_charts=65536, max_atlas=4096, flags=FP,
+                     max_profile_columns=2000, tuning_table=None)
+    g = run_gpu(f, ctx)
+    assert g["meta"]["status"] == fa.FA_ERR_CAPACITY
+    ctx.close()
 
 
 def test_footprint_capacity_and_dual_rejected():

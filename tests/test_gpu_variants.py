@@ -148,6 +148,25 @@ def test_batch_launch_rounds_and_fallback():
     ctx.close()
 
 
+@pytest.mark.parametrize("launch", [0, 1])
+def test_batch_many_chart_views(launch):
+    """Views with thousands of charts: per view (the order over many
+    workgroups) and in batched launches (one workgroup per view)."""
+    import paper_2502_17712_amd as fa
+    views = [scenes.scatter_frame(k, count=6000, atlas_size=om, rate=r)
+             for k, om, r in ((0, 4096, 1.0), (3, 2048, 0.5), (7, 4096, 2.0))]
+    ctx = fa.Context(views[0].num_triangles, views[0].num_vertices, max_charts=65536,
+                     max_atlas=4096, max_views=3, tuning_table=None)
+    ctx.set_tuning(fa.FA_TUNE_BATCH_LAUNCH, launch)
+    mesh = mesh_for(views[0])
+    want = [oracle.build_frame(v) for v in views]
+    assert min(w["num_charts"] for w in want) > 1024
+    print(f"[gpu] batch of 3 scatter views, launch={launch}", flush=True)
+    for g, r in zip(_run_batch(ctx, views, mesh), want):
+        compare(g, r)
+    ctx.close()
+
+
 def test_batch_graph_after_evict():
     """A cached batch graph must not outlive the adjacency it reads: evict the
     scene, rebuild it, replay the same descriptors."""

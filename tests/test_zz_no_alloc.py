@@ -78,6 +78,24 @@ def test_static_matches_context_path():
     ctx.close()
 
 
+def test_static_many_charts():
+    # 3000 charts: the order runs over several workgroups in both entry points
+    fa = _fa()
+    f = scenes.scatter_frame(0, count=3000, atlas_size=2048)
+    ctx = fa.Context(f.num_triangles, f.num_vertices, max_charts=fa.STATIC_MAX_CHARTS,
+                     max_atlas=2048, tuning_table=None)
+    print(f"[gpu] static vs context: {f.name} T={f.num_triangles}", flush=True)
+    mesh = fa.Mesh(f.positions, f.indices, f.scene_key)
+    want = ctx.build_atlas(mesh, torch.as_tensor(f.visible).cuda(), f.view_proj, f.width,
+                           f.height, f.atlas_size, f.rate)
+    torch.cuda.synchronize()
+    want = want.to_numpy()
+    assert want["meta"]["status"] == 0 and want["meta"]["num_charts"] > 1024
+    out = fa.AtlasOutputs(f.num_triangles, f.num_vertices, fa.STATIC_MAX_CHARTS, f.atlas_size, 64)
+    _same(_static(fa, f, mesh, out), want)
+    ctx.close()
+
+
 def test_static_errors_and_recovery():
     fa = _fa()
     f = scenes.grid_frame(5)
