@@ -44,28 +44,28 @@ def kernel_bytes(name, T, V, Tv, Vv, C, J, omega, occupied):
     """Algorithmic bytes of one launch of a kernel (what it must read and write
     at minimum); the per-unit figures are listed in the design doc."""
     per = {
-        "prologue": V * (12 + 16 + 4 + 4) + T * (1 + 4),
+        "prologue": V * (4 + 4) + T * (1 + 4),
         "vis_compact": T * 1 + Tv * 4,
         "uf_hook": Tv * (4 + 12 + 3 + 4),
         "uf_vertex_min": Tv * (4 + 4 + 12 + 12),
         "uf_vertex_hook": Tv * (4 + 12 + 12 + 4),
         "uf_flatten": Tv * (4 + 4 + 4),
         "assign_roots": Tv * (4 + 4) + C * (4 + 4 + 16),
-        "gather_boxes": Tv * (4 + 4 + 4 + 12 + 48 + 12) + C * 16,
+        "gather_boxes": Tv * (4 + 4 + 4 + 12 + 36 + 12) + C * 16,
         "sizes_order": C * (16 + 64 + 8 + 16),
         "pack": J * C * (8 + 16),
         "select_place": C * (16 + 16),
-        "uv": V * (16 + 4 + 8) + C * 64,
+        "uv": V * (4 + 8) + Vv * 12 + C * 64,
         "occ_fill": omega * omega * 4,
-        "occ_small": Tv * (4 + 4 + 12 + 48) + occupied * 4,
+        "occ_small": Tv * (4 + 4 + 12 + 36) + occupied * 4,
         # the two occupancy raster kernels are one job split by footprint size:
         # geometry of every visible triangle read once, every covered texel
         # written once; the small-footprint launch also computes the UVs
-        # (chart of every vertex read, UV of every vertex written, clip
-        # position of every vertex with a chart read, chart records read)
-        "occ_small+occ_big": Tv * (4 + 4 + 12 + 48) + occupied * 4
-                             + V * (4 + 8) + Vv * 16 + C * 64,
-        "occ_raster_only": Tv * (4 + 4 + 12 + 48) + occupied * 4,
+        # (chart of every vertex read, UV of every vertex written, position
+        # of every vertex with a chart read, chart records read)
+        "occ_small+occ_big": Tv * (4 + 4 + 12 + 36) + occupied * 4
+                             + V * (4 + 8) + Vv * 12 + C * 64,
+        "occ_raster_only": Tv * (4 + 4 + 12 + 36) + occupied * 4,
         "occ_count": omega * omega * 4,
     }
     return per.get(name)

@@ -76,9 +76,28 @@ struct FrameParams {
   int64_t pool_stride; // footprint push: pooled profile entries per candidate
 };
 
+// Clip position of vertex v: clip = M (x, y, z, 1)^T, each row summed left to
+// right. The one definition every kernel uses, so that every reader of a
+// vertex gets the same bits; the frame stores no clip positions (reading the
+// 12-byte position costs less than writing and reading back 16 bytes).
+__device__ __forceinline__ float4 clip_of(const float* __restrict__ pos, int64_t v,
+                                          const FrameParams& p) {
+  const float x = pos[3 * v], y = pos[3 * v + 1], z = pos[3 * v + 2];
+  float r[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float acc = p.M[4 * i] * x;
+    acc = acc + p.M[4 * i + 1] * y;
+    acc = acc + p.M[4 * i + 2] * z;
+    r[i] = acc + p.M[4 * i + 3];
+  }
+  return make_float4(r[0], r[1], r[2], r[3]);
+}
+
 // Scratch buffers of one context (sized by the capacities).
 struct Work {
-  float4* clip;          // [V]
+  const float* pos;      // [V][3] the frame's mesh positions (set per frame; clip positions are
+                         // computed where they are read, with clip_of)
   int32_t* parent;       // [T]
   int32_t* vmin;         // [V]
   int32_t* cov;          // [V] when the caller passes no chart_of_vert
@@ -311,7 +330,7 @@ hipError_t launch_index_check(const int32_t* idx, int64_t n, int64_t V, int32_t*
                               hipStream_t st);
 hipError_t launch_index_guard(const int32_t* flag, const Work& w, hipStream_t st);
 
-hipError_t launch_prologue(const float* pos, int64_t V, const uint8_t* vis, const int32_t* nbr,
+hipError_t launch_prologue(int64_t V, const uint8_t* vis, const int32_t* nbr,
                            int64_t T, const FrameParams& p, const Work& w, int32_t* cov,
                            int32_t* cot, int uf_init, Marker& mk, hipStream_t st);
 // occ_fill: when not NULL, this [omega][omega] occupancy map is filled with -1

@@ -172,7 +172,7 @@ int fa_create(const fa_config* cfg_in, fa_ctx** out_ctx) {
   for (int v = 0; v < cfg.max_views; ++v) {
     Work& w = ctx->slots[v];
     std::vector<Part> parts = {
-        {(void**)&w.clip, sizeof(float4) * V},   {(void**)&w.parent, 4 * T},
+        {(void**)&w.parent, 4 * T},
         {(void**)&w.vmin, 4 * V},                {(void**)&w.cov, 4 * V},
         {(void**)&w.tile_count, 4 * tiles},
         {(void**)&w.tile_vis, 4 * tiles},
@@ -522,10 +522,12 @@ static int frame_params(const fa_ctx* ctx, const fa_camera* cam, int32_t atlas, 
 
 namespace fa {
 // Every stage of one frame on stream st with scratch w (see fa_internal.h).
-int run_frame_core(const Knobs& kn, const Work& w, const fa_mesh* mesh, const int32_t* nbr,
+int run_frame_core(const Knobs& kn, const Work& slot, const fa_mesh* mesh, const int32_t* nbr,
                    const uint8_t* visible, const FrameParams& p, const fa_atlas_out* out,
                    const int32_t* index_flag, Marker& mk, hipStream_t st) {
   const int64_t T = mesh->num_triangles, V = mesh->num_vertices;
+  Work w = slot;
+  w.pos = mesh->positions;
   int32_t* cov = out->chart_of_vert ? out->chart_of_vert : w.cov;
   hipError_t e = hipSuccess;
   auto ok = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
@@ -534,7 +536,7 @@ int run_frame_core(const Knobs& kn, const Work& w, const fa_mesh* mesh, const in
   // charts use them unless the global edge hook is chosen)
   const bool tiles_start = (p.flags & FA_FLAG_EDGE_ONLY_CHARTS) ? p.edge_hooks != 1
                                                                 : p.edge_hooks >= 2;
-  ok(launch_prologue(mesh->positions, V, visible, nbr, T, p, w, cov, out->chart_of_tri,
+  ok(launch_prologue(V, visible, nbr, T, p, w, cov, out->chart_of_tri,
                      tiles_start ? 0 : (kn.uf_link_init ? 2 : 1), mk, st));
   if (index_flag) ok(launch_index_guard(index_flag, w, st));
   // the occupancy map is filled with -1 by spare workgroups of the box gather
@@ -642,9 +644,10 @@ int fa_build_dual_atlas(fa_ctx* ctx, const fa_mesh* mesh, const uint8_t* visible
   Scene* sc = nullptr;
   rc = get_scene(ctx, mesh, st, &sc);
   if (rc) return rc;
-  const Work& w = ctx->slots[0];
+  Work w = ctx->slots[0];
   rc = run_frame(ctx, w, mesh, sc, visible, p, out, st);
   if (rc) return rc;
+  w.pos = mesh->positions;
   FrameParams pl = p;
   pl.omega = atlas_size >> low_shift;
   pl.log2omega = p.log2omega - low_shift;
@@ -742,6 +745,7 @@ int fa_build_atlas_batch(fa_ctx* ctx, const fa_mesh* mesh, int32_t n, const fa_v
       BatchView& b = hv[i];
       b.p = ps[i];
       b.w = ctx->slots[i % S];
+      b.w.pos = mesh->positions;
       b.visible = v.visible;
       b.cot = v.out.chart_of_tri;
       b.cov = v.out.chart_of_vert ? v.out.chart_of_vert : b.w.cov;

@@ -51,7 +51,7 @@ size_t carve(char* base, Work* w, AdjTmp* adj, int32_t** nbr, int32_t** flag) {
   const size_t big = std::min<size_t>(2 * T, (size_t)kBigCap);
   Work& x = *w;
   x = Work{};
-  x.clip = (float4*)take(sizeof(float4) * V);
+  x.pos = nullptr;  // the frame's mesh positions, set per frame
   x.parent = (int32_t*)take(4 * T);
   x.vmin = (int32_t*)take(4 * V);
   x.cov = (int32_t*)take(4 * V);

@@ -92,16 +92,15 @@ __device__ __forceinline__ void uf_join(int32_t* parent, int u, int v) {
   }
 }
 
-// Prologue of a frame: frame state, clip transform of every vertex
-// (clip = M (x, y, z, 1)^T, rows summed left to right), per-vertex scratch,
+// Prologue of a frame: frame state, per-vertex scratch (vertex minima and
+// chart_of_vert = -1; clip positions are computed where they are read),
 // chart_of_tri = -1, the union-find start of every visible triangle and the
 // visible count of every tile of kTriTile triangles. Blocks [0, vblocks)
 // handle vertices, the rest triangle tiles. uf_init 2: a visible triangle
 // starts linked to the smallest of itself and its visible edge neighbours
 // (Alg. 1, first loop); 1: as its own root (same labels); 0: not written (a
 // later pass writes it).
-__device__ __forceinline__ void k_prologue_body(const float* __restrict__ pos, int64_t V, FrameParams p,
-                           float4* __restrict__ clip, int32_t* __restrict__ vmin,
+__device__ __forceinline__ void k_prologue_body(int64_t V, int32_t* __restrict__ vmin,
                            int32_t* __restrict__ cov, const uint8_t* __restrict__ vis,
                            const int32_t* __restrict__ nbr, int64_t T,
                            int32_t* __restrict__ parent, int32_t* __restrict__ cot,
@@ -118,16 +117,6 @@ __device__ __forceinline__ void k_prologue_body(const float* __restrict__ pos, i
     }
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
-    const float x = pos[3 * v], y = pos[3 * v + 1], z = pos[3 * v + 2];
-    float r[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      float acc = p.M[4 * i] * x;
-      acc = acc + p.M[4 * i + 1] * y;
-      acc = acc + p.M[4 * i + 2] * z;
-      r[i] = acc + p.M[4 * i + 3];
-    }
-    clip[v] = make_float4(r[0], r[1], r[2], r[3]);
     astore(&vmin[v], INT_MAX);
     cov[v] = -1;
     return;
@@ -155,15 +144,14 @@ __device__ __forceinline__ void k_prologue_body(const float* __restrict__ pos, i
   nv = block_sum<uint32_t>(nv, sh);
   if (threadIdx.x == 0) tile_vis[tile] = nv;
 }
-__global__ void k_prologue(const float* __restrict__ pos, int64_t V, FrameParams p,
-                           float4* __restrict__ clip, int32_t* __restrict__ vmin,
+__global__ void k_prologue(int64_t V, int32_t* __restrict__ vmin,
                            int32_t* __restrict__ cov, const uint8_t* __restrict__ vis,
                            const int32_t* __restrict__ nbr, int64_t T,
                            int32_t* __restrict__ parent, int32_t* __restrict__ cot,
                            uint32_t* __restrict__ tile_vis, int uf_init,
                            unsigned vblocks, FrameState* st,
                            unsigned long long* __restrict__ big_counter) {
-  k_prologue_body(pos, V, p, clip, vmin, cov, vis, nbr, T, parent, cot, tile_vis, uf_init, vblocks, st, big_counter);
+  k_prologue_body(V, vmin, cov, vis, nbr, T, parent, cot, tile_vis, uf_init, vblocks, st, big_counter);
 }
 
 // Sum of cnt[0 .. n) by one workgroup (the exclusive prefix of tile n);
@@ -771,8 +759,8 @@ constexpr unsigned kFillGroups = 256;   // the same for the 1024-thread union-fi
 
 __device__ __forceinline__ void k_gather_boxes_body(
     const int32_t* __restrict__ vlist, const int32_t* __restrict__ idx,
-    const int32_t* __restrict__ parent, const float4* __restrict__ clip, int32_t* cot,
-    int32_t* __restrict__ cov, uint32_t* __restrict__ accum, uint32_t flags,
+    const int32_t* __restrict__ parent, const float* __restrict__ pos, int32_t* cot,
+    int32_t* __restrict__ cov, uint32_t* __restrict__ accum, const FrameParams& p,
     const FrameState* __restrict__ st, int4* __restrict__ occ_fill, int64_t n4) {
   __shared__ int32_t skey[kSlots];
   __shared__ uint32_t sbox[kSlots][4];
@@ -817,7 +805,7 @@ __device__ __forceinline__ void k_gather_boxes_body(
 #pragma unroll
   for (int k = 0; k < kGatherItems; ++k)
 #pragma unroll
-    for (int e = 0; e < 3; ++e) q[k][e] = clip[vi[k][e]];
+    for (int e = 0; e < 3; ++e) q[k][e] = clip_of(pos, vi[k][e], p);
   // items are taken from slot 0 and shifted down after each one: constant
   // indices keep the arrays in registers (the clipping body is too large to
   // unroll, and a runtime index would move them to scratch memory)
@@ -828,7 +816,7 @@ __device__ __forceinline__ void k_gather_boxes_body(
     float4 box = make_float4(0.f, 0.f, 0.f, 0.f);
     if (valid) {
       cot[tv[0]] = c;
-      if (flags & FA_FLAG_EDGE_ONLY_CHARTS) {
+      if (p.flags & FA_FLAG_EDGE_ONLY_CHARTS) {
         // a vertex may touch several edge-connected charts: keep the smallest
         // (chart_of_vert starts at -1, the largest unsigned value)
 #pragma unroll
@@ -839,7 +827,7 @@ __device__ __forceinline__ void k_gather_boxes_body(
         cov[vi[0][1]] = c;
         cov[vi[0][2]] = c;
       }
-      has = triangle_ndc_box(q[0][0], q[0][1], q[0][2], !(flags & FA_FLAG_NO_SIDE_CLIP), box);
+      has = triangle_ndc_box(q[0][0], q[0][1], q[0][2], !(p.flags & FA_FLAG_NO_SIDE_CLIP), box);
     }
 #pragma unroll
     for (int m = 0; m + 1 < kGatherItems; ++m) {
@@ -896,10 +884,10 @@ __device__ __forceinline__ void k_gather_boxes_body(
 }
 __global__ __launch_bounds__(kBlock) void k_gather_boxes(
     const int32_t* __restrict__ vlist, const int32_t* __restrict__ idx,
-    const int32_t* __restrict__ parent, const float4* __restrict__ clip, int32_t* cot,
-    int32_t* __restrict__ cov, uint32_t* __restrict__ accum, uint32_t flags,
+    const int32_t* __restrict__ parent, const float* __restrict__ pos, int32_t* cot,
+    int32_t* __restrict__ cov, uint32_t* __restrict__ accum, FrameParams p,
     const FrameState* __restrict__ st, int4* __restrict__ occ_fill, int64_t n4) {
-  k_gather_boxes_body(vlist, idx, parent, clip, cot, cov, accum, flags, st, occ_fill, n4);
+  k_gather_boxes_body(vlist, idx, parent, pos, cot, cov, accum, p, st, occ_fill, n4);
 }
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
@@ -925,11 +913,10 @@ __global__ void k_index_guard(const int32_t* __restrict__ flag, FrameState* st) 
 }
 
 // ---- batched wrappers (view = blockIdx.y) --------------------------------
-__global__ void k_prologue_b(const BatchView* __restrict__ bv, const float* __restrict__ pos,
-                             int64_t V, const int32_t* __restrict__ nbr, int64_t T,
+__global__ void k_prologue_b(const BatchView* __restrict__ bv, int64_t V, const int32_t* __restrict__ nbr, int64_t T,
                              unsigned vblocks) {
   const BatchView& v = bv[blockIdx.y];
-  k_prologue_body(pos, V, v.p, v.w.clip, v.w.vmin, v.cov, v.visible, nbr, T, v.w.parent, v.cot,
+  k_prologue_body(V, v.w.vmin, v.cov, v.visible, nbr, T, v.w.parent, v.cot,
                   v.w.tile_vis, 0, vblocks, v.w.state, v.w.big_counter);
 }
 __global__ void k_vis_compact_b(const BatchView* __restrict__ bv, int64_t T) {
@@ -960,7 +947,7 @@ __global__ void k_assign_roots_b(const BatchView* __restrict__ bv) {
 __global__ __launch_bounds__(kBlock) void k_gather_boxes_b(const BatchView* __restrict__ bv,
                                                            const int32_t* __restrict__ idx) {
   const BatchView& v = bv[blockIdx.y];
-  k_gather_boxes_body(v.w.vlist, idx, v.w.parent, v.w.clip, v.cot, v.cov, v.w.accum, v.p.flags,
+  k_gather_boxes_body(v.w.vlist, idx, v.w.parent, v.w.pos, v.cot, v.cov, v.w.accum, v.p,
                       v.w.state, nullptr, 0);
 }
 
@@ -984,12 +971,12 @@ unsigned visible_grid(int64_t T) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((T + kBlock - 1) / kBlock, 2048));
 }
 
-hipError_t launch_prologue(const float* pos, int64_t V, const uint8_t* vis, const int32_t* nbr,
+hipError_t launch_prologue(int64_t V, const uint8_t* vis, const int32_t* nbr,
                            int64_t T, const FrameParams& p, const Work& w, int32_t* cov,
                            int32_t* cot, int uf_init, Marker& mk, hipStream_t st) {
   const unsigned vb = std::max(1u, grid_for(V, kBlock));
   const unsigned tt = grid_for(T, kTriTile);
-  k_prologue<<<vb + tt, kBlock, 0, st>>>(pos, V, p, w.clip, w.vmin, cov, vis, nbr, T, w.parent,
+  k_prologue<<<vb + tt, kBlock, 0, st>>>(V, w.vmin, cov, vis, nbr, T, w.parent,
                                          cot, w.tile_vis, uf_init, vb, w.state,
                                          w.big_counter);
   mk(st);
@@ -1076,7 +1063,7 @@ hipError_t launch_charts(const uint8_t* vis, const int32_t* idx, const int32_t* 
     int32_t* gfill = fill_done ? nullptr : occ_fill;
     const unsigned fill_blocks = gfill ? kFillBlocks : 0u;
     k_gather_boxes<<<grid_for(T, kBlock * kGatherItems) + fill_blocks, kBlock, 0, st>>>(
-        w.vlist, idx, w.parent, w.clip, cot, cov, w.accum, p.flags, w.state,
+        w.vlist, idx, w.parent, w.pos, cot, cov, w.accum, p, w.state,
         reinterpret_cast<int4*>(gfill), n4);
   } else {
     mk(st);
@@ -1092,7 +1079,7 @@ hipError_t launch_charts_batched(const BatchView* dev, int n, const float* pos,
   const unsigned vb = std::max(1u, grid_for(V, kBlock));
   const unsigned tt = grid_for(T, kTriTile);
   const unsigned vt = std::max(1u, tt);
-  k_prologue_b<<<dim3(vb + tt, n), kBlock, 0, st>>>(dev, pos, V, nbr, T, vb);
+  k_prologue_b<<<dim3(vb + tt, n), kBlock, 0, st>>>(dev, V, nbr, T, vb);
   if (T > 0) {
     k_vis_compact_b<<<dim3(tt, n), kBlock, 0, st>>>(dev, T);
     k_uf_local_vertex_b<<<dim3(std::max(1u, grid_for(T, 2048)) + kFillGroups, n), 1024, 0, st>>>(

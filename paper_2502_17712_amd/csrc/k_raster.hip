@@ -51,31 +51,33 @@ __device__ __forceinline__ float2 to_atlas(const ChartXform& m, float X, float Y
 }
 
 __device__ __forceinline__ void uv_vertex(int64_t v, const FrameParams& p,
-                                          const float4* __restrict__ clip,
+                                          const float* __restrict__ pos,
                                           const int32_t* __restrict__ cov,
                                           const fa_chart* __restrict__ charts,
                                           float2* __restrict__ uv,
                                           const FrameState* __restrict__ stp) {
   const FrameState st = *stp;
   const int c = st.status == FA_OK ? cov[v] : -1;
-  const float4 q = clip[v];
   float2 r = make_float2(__builtin_nanf(""), __builtin_nanf(""));
-  if (c >= 0 && q.w > 0.0f) r = to_atlas(chart_xform(charts[c], p, st), q.x, q.y, q.w);
+  if (c >= 0) {  // a vertex without a chart needs no position
+    const float4 q = clip_of(pos, v, p);
+    if (q.w > 0.0f) r = to_atlas(chart_xform(charts[c], p, st), q.x, q.y, q.w);
+  }
   uv[v] = r;
 }
 
-__global__ void k_uv(int64_t V, FrameParams p, const float4* __restrict__ clip,
+__global__ void k_uv(int64_t V, FrameParams p, const float* __restrict__ pos,
                      const int32_t* __restrict__ cov, const fa_chart* __restrict__ charts,
                      float2* __restrict__ uv, const FrameState* __restrict__ stp) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < V) uv_vertex(v, p, clip, cov, charts, uv, stp);
+  if (v < V) uv_vertex(v, p, pos, cov, charts, uv, stp);
 }
 
 // Per-corner UVs of edge-connected charts: corner k of triangle t is its
 // vertex mapped through the chart of t (a vertex on a seam between charts
 // gets one UV per chart). One thread per triangle writes its 24 bytes.
 __global__ void k_uv_corners(int64_t T, FrameParams p, const int32_t* __restrict__ idx,
-                             const float4* __restrict__ clip, const int32_t* __restrict__ cot,
+                             const float* __restrict__ pos, const int32_t* __restrict__ cot,
                              const fa_chart* __restrict__ charts, float2* __restrict__ uv,
                              const FrameState* __restrict__ stp) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -91,7 +93,7 @@ __global__ void k_uv_corners(int64_t T, FrameParams p, const int32_t* __restrict
   const ChartXform m = chart_xform(charts[c], p, st);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const float4 q = clip[idx[3 * t + k]];
+    const float4 q = clip_of(pos, idx[3 * t + k], p);
     uv[3 * t + k] = q.w > 0.0f ? to_atlas(m, q.x, q.y, q.w) : make_float2(nan, nan);
   }
 }
@@ -179,7 +181,7 @@ struct SnapPoly {
 };
 
 __device__ __forceinline__ void snap_polygon(int64_t t, const int32_t* __restrict__ idx,
-                                             const float4* __restrict__ clip,
+                                             const float* __restrict__ pos,
                                              const int32_t* __restrict__ cot,
                                              const fa_chart* __restrict__ charts,
                                              const FrameParams& p, const FrameState& st,
@@ -188,7 +190,8 @@ __device__ __forceinline__ void snap_polygon(int64_t t, const int32_t* __restric
   const int c = cot[t];
   sp.chart = c;
   if (c < 0) return;
-  const float4 a = clip[idx[3 * t]], b = clip[idx[3 * t + 1]], cc = clip[idx[3 * t + 2]];
+  const float4 a = clip_of(pos, idx[3 * t], p), b = clip_of(pos, idx[3 * t + 1], p),
+               cc = clip_of(pos, idx[3 * t + 2], p);
   if (outside<0>(a, b, cc) || outside<1>(a, b, cc) || outside<2>(a, b, cc) ||
       outside<3>(a, b, cc) || outside<4>(a, b, cc) || outside<5>(a, b, cc))
     return;
@@ -381,7 +384,7 @@ __device__ __forceinline__ uint32_t tiles_of(const Footprint& fp, uint32_t* tile
 
 __device__ __forceinline__ void k_occ_small_body(
     const int32_t* __restrict__ idx, const int32_t* __restrict__ vlist, FrameParams p,
-    const float4* __restrict__ clip, const int32_t* __restrict__ cot,
+    const float* __restrict__ pos, const int32_t* __restrict__ cot,
     const fa_chart* __restrict__ charts, const int4* __restrict__ chart_tex,
     int32_t* __restrict__ occ, ulonglong2* __restrict__ big, int4* __restrict__ big_fp,
     uint32_t big_cap, int small_texels,
@@ -394,7 +397,7 @@ __device__ __forceinline__ void k_occ_small_body(
     // the blocks past the raster's own compute the per-vertex UVs (they need
     // the same placement and run beside the raster instead of after it)
     const int64_t v = (int64_t)(blockIdx.x - occ_blocks) * blockDim.x + threadIdx.x;
-    if (v < V) uv_vertex(v, p, clip, cov, charts, uv, stp);
+    if (v < V) uv_vertex(v, p, pos, cov, charts, uv, stp);
     return;
   }
   const FrameState st = *stp;
@@ -409,7 +412,7 @@ __device__ __forceinline__ void k_occ_small_body(
     sp.n = 0;
     sp.chart = -1;
     const int t = valid ? vlist[i] : 0;
-    if (valid) snap_polygon(t, idx, clip, cot, charts, p, st, sp);
+    if (valid) snap_polygon(t, idx, pos, cot, charts, p, st, sp);
     Footprint fa, fb;
     const int4 box = sp.n > 0 ? chart_tex[sp.chart] : make_int4(0, -1, 0, -1);
     const bool oka = sp.n > 0 && fan_footprint(sp, 0, box, p.omega, fa);
@@ -473,14 +476,14 @@ __device__ __forceinline__ void k_occ_small_body(
 }
 __global__ __launch_bounds__(kOccSmallBlock) void k_occ_small(
     const int32_t* __restrict__ idx, const int32_t* __restrict__ vlist, FrameParams p,
-    const float4* __restrict__ clip, const int32_t* __restrict__ cot,
+    const float* __restrict__ pos, const int32_t* __restrict__ cot,
     const fa_chart* __restrict__ charts, const int4* __restrict__ chart_tex,
     int32_t* __restrict__ occ, ulonglong2* __restrict__ big, int4* __restrict__ big_fp,
     uint32_t big_cap, int small_texels,
     int lane_texels, unsigned long long* __restrict__ big_counter,
     const FrameState* __restrict__ stp, unsigned occ_blocks, int64_t V,
     const int32_t* __restrict__ cov, float2* __restrict__ uv) {
-  k_occ_small_body(idx, vlist, p, clip, cot, charts, chart_tex, occ, big, big_fp, big_cap, small_texels, lane_texels, big_counter, stp, occ_blocks, V, cov, uv);
+  k_occ_small_body(idx, vlist, p, pos, cot, charts, chart_tex, occ, big, big_fp, big_cap, small_texels, lane_texels, big_counter, stp, occ_blocks, V, cov, uv);
 }
 
 // Queued footprints: their texel ranges cut into 16x16 tiles, concatenated,
@@ -488,7 +491,7 @@ __global__ __launch_bounds__(kOccSmallBlock) void k_occ_small(
 // footprint by a 64-way search over the (increasing) first-tile indices and
 // walks forward, 4 texels per lane.
 __device__ __forceinline__ void k_occ_big_body(
-    const int32_t* __restrict__ idx, FrameParams p, const float4* __restrict__ clip,
+    const int32_t* __restrict__ idx, FrameParams p, const float* __restrict__ pos,
     const int32_t* __restrict__ cot, const fa_chart* __restrict__ charts,
     const int4* __restrict__ chart_tex, int32_t* __restrict__ occ,
     const ulonglong2* __restrict__ big, const int4* __restrict__ big_fp, uint32_t big_cap,
@@ -594,12 +597,12 @@ __device__ __forceinline__ void k_occ_big_body(
   }
 }
 __global__ __launch_bounds__(kBlock) void k_occ_big(
-    const int32_t* __restrict__ idx, FrameParams p, const float4* __restrict__ clip,
+    const int32_t* __restrict__ idx, FrameParams p, const float* __restrict__ pos,
     const int32_t* __restrict__ cot, const fa_chart* __restrict__ charts,
     const int4* __restrict__ chart_tex, int32_t* __restrict__ occ,
     const ulonglong2* __restrict__ big, const int4* __restrict__ big_fp, uint32_t big_cap,
     const unsigned long long* __restrict__ big_counter, const FrameState* __restrict__ stp) {
-  k_occ_big_body(idx, p, clip, cot, charts, chart_tex, occ, big, big_fp, big_cap, big_counter, stp);
+  k_occ_big_body(idx, p, pos, cot, charts, chart_tex, occ, big, big_fp, big_cap, big_counter, stp);
 }
 
 // Frame record for the caller (one thread); `occ` is the occupied texel count
@@ -690,7 +693,7 @@ __global__ __launch_bounds__(kOccSmallBlock) void k_occ_small_b(
     const BatchView* __restrict__ bv, const int32_t* __restrict__ idx, uint32_t big_cap,
     int small_texels, int lane_texels, unsigned occ_blocks, int64_t V) {
   const BatchView& v = bv[blockIdx.y];
-  k_occ_small_body(idx, v.w.vlist, v.p, v.w.clip, v.cot, v.charts, v.w.chart_tex, v.occ, v.w.big,
+  k_occ_small_body(idx, v.w.vlist, v.p, v.w.pos, v.cot, v.charts, v.w.chart_tex, v.occ, v.w.big,
                    v.w.big_fp, big_cap, small_texels, lane_texels, v.w.big_counter, v.w.state,
                    occ_blocks, V, v.cov, reinterpret_cast<float2*>(v.uv));
 }
@@ -698,7 +701,7 @@ __global__ __launch_bounds__(kBlock) void k_occ_big_b(const BatchView* __restric
                                                       const int32_t* __restrict__ idx,
                                                       uint32_t big_cap) {
   const BatchView& v = bv[blockIdx.y];
-  k_occ_big_body(idx, v.p, v.w.clip, v.cot, v.charts, v.w.chart_tex, v.occ, v.w.big, v.w.big_fp,
+  k_occ_big_body(idx, v.p, v.w.pos, v.cot, v.charts, v.w.chart_tex, v.occ, v.w.big, v.w.big_fp,
                  big_cap, v.w.big_counter, v.w.state);
 }
 __global__ __launch_bounds__(kCountBlock) void k_occ_count_meta_b(
@@ -715,7 +718,7 @@ hipError_t launch_uv(const int64_t V, const FrameParams& p, const Work& w, const
                      const fa_chart* charts, float* uv, hipStream_t st) {
   if (V > 0)
     k_uv<<<(unsigned)((V + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-        V, p, w.clip, cov, charts, reinterpret_cast<float2*>(uv), w.state);
+        V, p, w.pos, cov, charts, reinterpret_cast<float2*>(uv), w.state);
   return hipGetLastError();
 }
 
@@ -724,7 +727,7 @@ hipError_t launch_uv_corners(const int32_t* idx, int64_t T, const FrameParams& p
                              hipStream_t st) {
   if (T > 0)
     k_uv_corners<<<(unsigned)((T + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-        T, p, idx, w.clip, cot, charts, reinterpret_cast<float2*>(uv), w.state);
+        T, p, idx, w.pos, cot, charts, reinterpret_cast<float2*>(uv), w.state);
   return hipGetLastError();
 }
 
@@ -744,12 +747,12 @@ hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p,
   const unsigned uv_blocks = (unsigned)((V + kOccSmallBlock - 1) / kOccSmallBlock);
   if (occ_blocks + uv_blocks > 0)
     k_occ_small<<<occ_blocks + uv_blocks, kOccSmallBlock, 0, st>>>(
-        idx, w.vlist, p, w.clip, cot, charts, w.chart_tex, occ, w.big, w.big_fp, cap, small_texels,
+        idx, w.vlist, p, w.pos, cot, charts, w.chart_tex, occ, w.big, w.big_fp, cap, small_texels,
         lane_texels, w.big_counter, w.state, occ_blocks, V, x.cov,
         reinterpret_cast<float2*>(x.uv));
   mk(st);
   if (T > 0)
-    k_occ_big<<<kOccBigGrid, kBlock, 0, st>>>(idx, p, w.clip, cot, charts, w.chart_tex, occ,
+    k_occ_big<<<kOccBigGrid, kBlock, 0, st>>>(idx, p, w.pos, cot, charts, w.chart_tex, occ,
                                               w.big, w.big_fp, cap, w.big_counter, w.state);
   mk(st);
   if (x.meta)  // a scaled copy (no frame record) needs no count
@@ -835,7 +838,7 @@ struct FpSetup {
 };
 __device__ __forceinline__ void fp_setup(int i, int nv, const int32_t* __restrict__ vlist,
                                          const int32_t* __restrict__ idx,
-                                         const float4* __restrict__ clip,
+                                         const float* __restrict__ pos,
                                          const int32_t* __restrict__ cot,
                                          const fa_chart* __restrict__ charts,
                                          const int32_t* __restrict__ fp_off, const FrameParams& p,
@@ -847,8 +850,9 @@ __device__ __forceinline__ void fp_setup(int i, int nv, const int32_t* __restric
   const float halfW = 0.5f * (float)p.W, halfH = 0.5f * (float)p.H;
   const int t = vlist[i];
   const int c = cot[t];
-  const float4 a = clip[idx[3 * (int64_t)t]], b = clip[idx[3 * (int64_t)t + 1]],
-               cc = clip[idx[3 * (int64_t)t + 2]];
+  const float4 a = clip_of(pos, idx[3 * (int64_t)t], p),
+               b = clip_of(pos, idx[3 * (int64_t)t + 1], p),
+               cc = clip_of(pos, idx[3 * (int64_t)t + 2], p);
   const bool out = c < 0 || outside<0>(a, b, cc) || outside<1>(a, b, cc) ||
                    outside<2>(a, b, cc) || outside<3>(a, b, cc) || outside<4>(a, b, cc) ||
                    outside<5>(a, b, cc);
@@ -893,7 +897,7 @@ __device__ __forceinline__ void fp_setup(int i, int nv, const int32_t* __restric
 // group; the blocks past the groups clear the profile.
 __global__ __launch_bounds__(kBlock) void k_fp_count(
     const int32_t* __restrict__ vlist, const int32_t* __restrict__ idx,
-    const float4* __restrict__ clip, const int32_t* __restrict__ cot,
+    const float* __restrict__ pos, const int32_t* __restrict__ cot,
     const fa_chart* __restrict__ charts, const int32_t* __restrict__ fp_off,
     unsigned long long* __restrict__ group_items, int2* __restrict__ prof, unsigned count_blocks,
     FrameParams p, const FrameState* __restrict__ stp) {
@@ -912,7 +916,7 @@ __global__ __launch_bounds__(kBlock) void k_fp_count(
   for (int g = (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave); g < groups;
        g += nw) {
     FpSetup s;
-    fp_setup(g * kWave + lane_id(), nv, vlist, idx, clip, cot, charts, fp_off, p, s);
+    fp_setup(g * kWave + lane_id(), nv, vlist, idx, pos, cot, charts, fp_off, p, s);
     const int tot = wave_sum<int>(s.cnt);
     if (lane_id() == 0) group_items[g] = (unsigned long long)tot;
   }
@@ -954,7 +958,7 @@ constexpr int kFpWin = 1024;
 
 __global__ __launch_bounds__(kBlock) void k_fp_raster(
     const int32_t* __restrict__ vlist, const int32_t* __restrict__ idx,
-    const float4* __restrict__ clip, const int32_t* __restrict__ cot,
+    const float* __restrict__ pos, const int32_t* __restrict__ cot,
     const fa_chart* __restrict__ charts, const int32_t* __restrict__ fp_off,
     const unsigned long long* __restrict__ group_first, int2* __restrict__ prof, FrameParams p,
     const FrameState* __restrict__ stp) {
@@ -988,7 +992,7 @@ __global__ __launch_bounds__(kBlock) void k_fp_raster(
     const unsigned long long gfirst = group_first[g];
     if (gfirst >= k1) break;
     FpSetup s;
-    fp_setup(g * kWave + lane, nv, vlist, idx, clip, cot, charts, fp_off, p, s);
+    fp_setup(g * kWave + lane, nv, vlist, idx, pos, cot, charts, fp_off, p, s);
     const int incl = wave_incl_scan<int>(s.cnt);
     const int gtot = __shfl(incl, kWave - 1, kWave);
     // this wave's items of the group: [ia, ib) in group-local numbering
@@ -1090,13 +1094,13 @@ hipError_t launch_footprint(const int32_t* idx, int64_t T, const FrameParams& p,
     const unsigned cb = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>((T + kBlock - 1) / kBlock, 2048));
     const unsigned clear = (unsigned)std::min<int64_t>(1024, (p.fp_cap + kBlock - 1) / kBlock);
-    k_fp_count<<<cb + clear, kBlock, 0, st>>>(w.vlist, idx, w.clip, cot, charts, w.fp_off,
+    k_fp_count<<<cb + clear, kBlock, 0, st>>>(w.vlist, idx, w.pos, cot, charts, w.fp_off,
                                               w.fp_group, w.fp_prof, cb, p, w.state);
   }
   mk(st);
   if (p.fp_cap > 0 && T > 0) {
     k_fp_scan<<<1, 1024, 0, st>>>(w.fp_group, w.state);
-    k_fp_raster<<<visible_grid(T), kBlock, 0, st>>>(w.vlist, idx, w.clip, cot, charts, w.fp_off,
+    k_fp_raster<<<visible_grid(T), kBlock, 0, st>>>(w.vlist, idx, w.pos, cot, charts, w.fp_off,
                                                     w.fp_group, w.fp_prof, p, w.state);
   }
   mk(st);
