@@ -65,8 +65,9 @@ def output_bytes(T, V, max_charts, atlas_size, J):
 def reservation_bytes(T, V, max_charts, atlas_size, J):
     """What admission reserves for one request: its outputs plus the frame's
     working set in the slot's scratch, T (9 B: chart, parent, visibility) +
-    V (32 B: clip position, UV, vertex chart, vertex minimum) + max_charts
-    (64 B record + 16 B per candidate) + 4 omega^2 (occupancy) + 1 MiB."""
+    V (32 B: UV, vertex chart and vertex minimum take 16 B; the rest is
+    headroom) + max_charts (64 B record + 16 B per candidate) + 4 omega^2
+    (occupancy) + 1 MiB."""
     return (9 * T + 32 * V + max_charts * (64 + 16 * J) + 4 * atlas_size * atlas_size
             + (1 << 20))
 
