@@ -392,7 +392,8 @@ int fa_load_tuning_table(fa_ctx* ctx, const char* text);
  * outputs) records an event after each of its 21 stages (a stage is one
  * kernel, or none when the configuration folds it into another); fa_stage_times
  * (after the stream completed) fills up to n floats with milliseconds for, in
- * order: prologue (state, clip transform, union-find start), vis_scan,
+ * order: prologue (state, per-vertex and per-triangle scratch, union-find
+ * start), vis_scan,
  * vis_compact (list of the visible triangles), uf_hook, uf_vertex_min,
  * uf_vertex_hook, uf_flatten, chart_scan, assign_roots, gather_boxes,
  * sizes_order, fp_count, fp_raster (footprint profiles: item counts and

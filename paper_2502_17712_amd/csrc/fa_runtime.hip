@@ -269,8 +269,9 @@ void fa_destroy(fa_ctx* ctx) {
   delete ctx;
 }
 
-// The cached batch graph bakes in the resident adjacency of its scene: drop it
-// whenever a scene's adjacency is freed.
+// The cached batch graph bakes in the resident adjacency of its scene and the
+// knobs of the tuning table: drop it whenever a scene's adjacency is freed or
+// a table is loaded.
 static void drop_graph(fa_ctx* ctx) {
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
   if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
@@ -864,6 +865,7 @@ int fa_load_tuning_table(fa_ctx* ctx, const char* text) {
     tab.push_back(t);
   }
   ctx->table = std::move(tab);
+  drop_graph(ctx);  // a captured batch baked in the previous table's knobs
   return FA_OK;
 }
 

@@ -189,6 +189,26 @@ def test_batch_graph_after_evict():
     ctx.close()
 
 
+def test_batch_graph_after_table_change():
+    """A cached batch graph is captured with the knobs the tuning table picks;
+    loading another table drops it, and the next batch (re-captured) still
+    equals the oracle."""
+    import paper_2502_17712_amd as fa
+    views = [scenes.orbit_frame(k, atlas_size=om) for k, om in ((7, 1024), (61, 2048))]
+    ctx = fa.Context(views[0].num_triangles, views[0].num_vertices, max_charts=8192,
+                     max_atlas=4096, max_views=2, tuning_table=None)
+    ctx.set_tuning(fa.FA_TUNE_BATCH_GRAPH, 1)
+    mesh = mesh_for(views[0])
+    want = [oracle.build_frame(v) for v in views]
+    tables = ("0 1073741824 0 64 256 16 0 0 2 8192\n", "0 1073741824 0 64 1024 64 64 1 5 2048\n")
+    for rep, table in enumerate(tables + tables):
+        ctx.load_tuning_table(table)
+        print(f"[gpu] batch graph after table {rep}", flush=True)
+        for g, r in zip(_run_batch(ctx, views, mesh), want):
+            compare(g, r)
+    ctx.close()
+
+
 # ---------------------------------------------------------------------------
 # the context's device-memory cap (fa_config.hbm_budget_bytes)
 # ---------------------------------------------------------------------------
