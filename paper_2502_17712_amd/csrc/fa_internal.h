@@ -42,7 +42,8 @@ struct FrameState {
   int32_t fp_columns; // full-scale footprint profile columns of the frame (footprint push)
   unsigned long long occupied;
   uint32_t ticket;    // workgroups of the occupancy count that have finished
-  uint32_t order_sync;  // barrier arrivals of the many-chart order (kOrderGroups workgroups)
+  uint32_t order_claim[5];  // many-chart order: chunks claimed per phase
+  uint32_t order_done[4];   // ... and chunks finished per phase
 };
 
 // Constants of one visibility pass, passed by value (float64).

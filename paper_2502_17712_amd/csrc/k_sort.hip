@@ -377,30 +377,48 @@ __device__ __forceinline__ void order_body(const FrameParams& p, const uint32_t*
   }
 }
 
-// ---- many charts: the same two passes over kOrderGroups workgroups -------
+// ---- many charts: the same two passes over kOrderGroups chunks ------------
 // Above kOrderLds charts one workgroup spends most of its time waiting on
 // global memory round by round, so frames with many charts split the items
-// into kOrderGroups contiguous chunks. Each pass is: chunk histograms of the
-// digit, a barrier of all the launch's workgroups, then every workgroup
-// derives its own digit offsets from all the histograms (digit-major order
-// keeps the sort stable) and scatters its chunk with the same in-workgroup
-// ranking as above. Everything another workgroup reads goes through
-// agent-scope loads and stores (the workgroups sit on different XCDs, each
-// with its own L2).
+// into kOrderGroups contiguous chunks, processed by the launch's workgroups
+// in five phases: sizes and digit-0 histograms, digit-0 scatter, digit-1
+// histograms, digit-1 scatter, copy into packing order. In every phase each
+// workgroup claims chunks from a counter until none are left; the next phase
+// starts once every chunk of this one is finished. A chunk's digit offsets
+// come from all the histograms (digit-major, so the sort stays stable) and
+// the in-workgroup ranking above. Any one resident workgroup can finish a
+// phase by itself, so the order makes progress however few of the launch's
+// workgroups the device runs at once (other streams may hold the rest).
+// Everything another workgroup reads goes through agent-scope loads and
+// stores (the workgroups sit on different XCDs, each with its own L2).
 
-// Barrier of the launch's workgroups. There are far fewer of them than CUs,
-// so all are resident; the wait is bounded anyway, and a workgroup that gives
-// up reports FA_ERR_DEVICE and leaves. Each thread's stores have completed
-// (s_waitcnt) before its workgroup takes its ticket.
-constexpr uint32_t kSyncSpins = 1u << 22;
-__device__ __forceinline__ bool order_sync(FrameState* st, uint32_t target, int* flag) {
+// Claim the next chunk of a phase (uniform over the workgroup).
+__device__ __forceinline__ int claim_chunk(uint32_t* ctr, int* slot) {
+  __syncthreads();  // every thread has read the previous claim
+  if (threadIdx.x == 0)
+    *slot = (int)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  return *slot;
+}
+
+// A chunk is finished once every thread's stores have completed.
+__device__ __forceinline__ void chunk_done(uint32_t* ctr) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until all kOrderGroups chunks of a phase are finished. Only chunks
+// that some running workgroup has claimed are outstanding, so the wait ends;
+// it is bounded anyway, and a workgroup that gives up reports FA_ERR_DEVICE.
+constexpr uint32_t kSyncSpins = 1u << 22;
+__device__ __forceinline__ bool phase_wait(uint32_t* ctr, FrameState* st, int* flag) {
+  __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(&st->order_sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t spins = 0;
-    while (__hip_atomic_load(&st->order_sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-               target &&
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+               (uint32_t)kOrderGroups &&
            spins < kSyncSpins) {
       __builtin_amdgcn_s_sleep(2);
       ++spins;
@@ -515,80 +533,106 @@ __device__ __forceinline__ void order_multi(const FrameParams& p, const uint32_t
                                             int32_t* __restrict__ fp_off, FrameState* st, int C,
                                             uint32_t* hist, unsigned long long* part,
                                             uint32_t* base, uint32_t (*wcnt)[kRadix],
-                                            uint32_t* sh, long long* sh64, int* flag) {
-  const int tid = threadIdx.x, b = blockIdx.x;
-  const int chunk = (C + kOrderGroups - 1) / kOrderGroups;
-  const int lo = min(C, b * chunk), hi = min(C, lo + chunk);
-  const uint32_t G = gridDim.x;
-  // sizes of this chunk's charts (the oriented size also as agent-scope
-  // words: another workgroup copies it into the packing order)
-  long long cols = 0;
-  for (int c = lo + tid; c < hi; c += kOrderThreads) {
-    float2 wh;
-    if (from_accum) {
-      uint4 box;
-      box.x = aload_u(&accum[4 * c + 0]);
-      box.y = aload_u(&accum[4 * c + 1]);
-      box.z = aload_u(&accum[4 * c + 2]);
-      box.w = aload_u(&accum[4 * c + 3]);
-      uint32_t key;
-      chart_size(p, box, charts[c], key, wh);
-      astore_u(&KA[c], key);
-      astore_i(&VA[c], c);
-      astore_i(reinterpret_cast<int32_t*>(&charts[c].oriented_w), __float_as_int(wh.x));
-      astore_i(reinterpret_cast<int32_t*>(&charts[c].oriented_h), __float_as_int(wh.y));
-    } else {
-      wh = make_float2(charts[c].oriented_w, charts[c].oriented_h);
+                                            uint32_t* sh, long long* sh64, int* flag,
+                                            int* slot) {
+  const int tid = threadIdx.x;
+  constexpr int G = kOrderGroups;
+  const int chunk = (C + G - 1) / G;
+  // phase 0: sizes of a chunk's charts (the oriented size also as agent-scope
+  // words: another workgroup copies it into the packing order), the chunk's
+  // footprint columns and its digit-0 histogram
+  for (int ch; (ch = claim_chunk(&st->order_claim[0], slot)) < G;) {
+    const int lo = min(C, ch * chunk), hi = min(C, lo + chunk);
+    long long cols = 0;
+    for (int c = lo + tid; c < hi; c += kOrderThreads) {
+      float2 wh;
+      if (from_accum) {
+        uint4 box;
+        box.x = aload_u(&accum[4 * c + 0]);
+        box.y = aload_u(&accum[4 * c + 1]);
+        box.z = aload_u(&accum[4 * c + 2]);
+        box.w = aload_u(&accum[4 * c + 3]);
+        uint32_t key;
+        chart_size(p, box, charts[c], key, wh);
+        astore_u(&KA[c], key);
+        astore_i(&VA[c], c);
+        astore_i(reinterpret_cast<int32_t*>(&charts[c].oriented_w), __float_as_int(wh.x));
+        astore_i(reinterpret_cast<int32_t*>(&charts[c].oriented_h), __float_as_int(wh.y));
+      } else {
+        wh = make_float2(charts[c].oriented_w, charts[c].oriented_h);
+      }
+      if (fp_off) cols += (long long)floorf(wh.x) + 1;
     }
-    if (fp_off) cols += (long long)floorf(wh.x) + 1;
+    if (fp_off) {
+      const long long sum = block_sum<long long>(cols, sh64);
+      if (tid == 0)
+        __hip_atomic_store(&part[ch], (unsigned long long)sum, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    chunk_hist(KA, lo, hi, 0, ch, hist, base);
+    chunk_done(&st->order_done[0]);
   }
-  if (fp_off) {
-    const long long s = block_sum<long long>(cols, sh64);
-    if (tid == 0)
-      __hip_atomic_store(&part[b], (unsigned long long)s, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+  if (!phase_wait(&st->order_done[0], st, flag)) return;
+  // phase 1: footprint columns in chart order, digit-0 scatter
+  for (int ch; (ch = claim_chunk(&st->order_claim[1], slot)) < G;) {
+    const int lo = min(C, ch * chunk), hi = min(C, lo + chunk);
+    if (fp_off) {
+      long long run = 0, total = 0;  // earlier chunks' columns, all chunks'
+      for (int g = 0; g < G; ++g) {
+        const long long v = (long long)__hip_atomic_load(&part[g], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+        run += g < ch ? v : 0;
+        total += v;
+      }
+      for (int c0 = lo; c0 < hi; c0 += kOrderThreads) {
+        const int c = c0 + tid;
+        const long long n =
+            c < hi ? (long long)floorf(__int_as_float(aload_i(
+                         reinterpret_cast<const int32_t*>(&charts[c].oriented_w)))) + 1
+                   : 0;
+        long long tot;
+        const long long incl = block_incl_scan<long long>(n, sh64, &tot);
+        if (c < hi) fp_off[c] = (int32_t)min(run + incl - n, (long long)p.fp_cap);
+        run += tot;
+      }
+      if (ch == G - 1 && tid == 0) {
+        fp_off[C] = (int32_t)min(total, (long long)p.fp_cap);
+        st->fp_columns = (int32_t)min(total, (long long)p.fp_cap);
+        if (total > p.fp_cap) st->status = FA_ERR_CAPACITY;
+      }
+    }
+    chunk_base(hist, ch, base, sh);
+    chunk_scatter(KA, VA, KB, VB, lo, hi, 0, base, wcnt);
+    chunk_done(&st->order_done[1]);
   }
-  chunk_hist(KA, lo, hi, 0, b, hist, base);
-  if (!order_sync(st, G, flag)) return;
-  if (fp_off) {
-    // footprint columns in chart order: earlier chunks' sums, then this one's
-    long long run = 0, total = 0;
-    for (int g = 0; g < (int)G; ++g) {
-      const long long v = (long long)__hip_atomic_load(&part[g], __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-      run += g < b ? v : 0;
-      total += v;
-    }
-    for (int c0 = lo; c0 < hi; c0 += kOrderThreads) {
-      const int c = c0 + tid;
-      const long long n = c < hi ? (long long)floorf(__int_as_float(aload_i(
-                                       reinterpret_cast<const int32_t*>(&charts[c].oriented_w)))) + 1
-                                 : 0;
-      long long tot;
-      const long long incl = block_incl_scan<long long>(n, sh64, &tot);
-      if (c < hi) fp_off[c] = (int32_t)min(run + incl - n, (long long)p.fp_cap);
-      run += tot;
-    }
-    if (b == (int)G - 1 && tid == 0) {
-      fp_off[C] = (int32_t)min(total, (long long)p.fp_cap);
-      st->fp_columns = (int32_t)min(total, (long long)p.fp_cap);
-      if (total > p.fp_cap) st->status = FA_ERR_CAPACITY;
-    }
+  if (!phase_wait(&st->order_done[1], st, flag)) return;
+  // phase 2: digit-1 histograms of the digit-0 order
+  for (int ch; (ch = claim_chunk(&st->order_claim[2], slot)) < G;) {
+    const int lo = min(C, ch * chunk), hi = min(C, lo + chunk);
+    chunk_hist(KB, lo, hi, kRadixBits, ch, hist, base);
+    chunk_done(&st->order_done[2]);
   }
-  chunk_base(hist, b, base, sh);
-  chunk_scatter(KA, VA, KB, VB, lo, hi, 0, base, wcnt);
-  if (!order_sync(st, 2 * G, flag)) return;
-  chunk_hist(KB, lo, hi, kRadixBits, b, hist, base);
-  if (!order_sync(st, 3 * G, flag)) return;
-  chunk_base(hist, b, base, sh + kOrderThreads / kWave);
-  chunk_scatter(KB, VB, KA, VA, lo, hi, kRadixBits, base, wcnt);
-  if (!order_sync(st, 4 * G, flag)) return;
-  for (int i = lo + tid; i < hi; i += kOrderThreads) {
-    const int c = aload_i(&VA[i]);
-    const float w = __int_as_float(aload_i(reinterpret_cast<const int32_t*>(&charts[c].oriented_w)));
-    const float h = __int_as_float(aload_i(reinterpret_cast<const int32_t*>(&charts[c].oriented_h)));
-    sorted_wh[i] = make_float2(w, h);
-    charts[c].order_rank = i;
+  if (!phase_wait(&st->order_done[2], st, flag)) return;
+  // phase 3: digit-1 scatter
+  for (int ch; (ch = claim_chunk(&st->order_claim[3], slot)) < G;) {
+    const int lo = min(C, ch * chunk), hi = min(C, lo + chunk);
+    chunk_base(hist, ch, base, sh + kOrderThreads / kWave);
+    chunk_scatter(KB, VB, KA, VA, lo, hi, kRadixBits, base, wcnt);
+    chunk_done(&st->order_done[3]);
+  }
+  if (!phase_wait(&st->order_done[3], st, flag)) return;
+  // phase 4: sizes in packing order and each chart's rank
+  for (int ch; (ch = claim_chunk(&st->order_claim[4], slot)) < G;) {
+    const int lo = min(C, ch * chunk), hi = min(C, lo + chunk);
+    for (int i = lo + tid; i < hi; i += kOrderThreads) {
+      const int c = aload_i(&VA[i]);
+      const float w =
+          __int_as_float(aload_i(reinterpret_cast<const int32_t*>(&charts[c].oriented_w)));
+      const float h =
+          __int_as_float(aload_i(reinterpret_cast<const int32_t*>(&charts[c].oriented_h)));
+      sorted_wh[i] = make_float2(w, h);
+      charts[c].order_rank = i;
+    }
   }
 }
 
@@ -606,12 +650,12 @@ __device__ __forceinline__ void k_sizes_order_body(
   __shared__ uint32_t lk[2][kOrderLds];
   __shared__ int32_t lv[2][kOrderLds];
   __shared__ float2 lwh[kOrderLds];
-  __shared__ int flag;
+  __shared__ int flag, slot;
   if (st->status != FA_OK) return;
   const int C = min(st->num_charts, p.max_charts);
   if (gridDim.x > 1 && C > kOrderLds) {
     order_multi(p, accum, charts, keys_a, vals_a, keys_b, vals_b, sorted_wh, from_accum, fp_off,
-                st, C, hist, part, base, wcnt, sh, sh64, &flag);
+                st, C, hist, part, base, wcnt, sh, sh64, &flag, &slot);
     return;
   }
   if (blockIdx.x != 0) return;
@@ -677,9 +721,7 @@ hipError_t launch_order(const FrameParams& p, const Work& w, fa_chart* charts, i
 }
 
 hipError_t launch_order_batched(const BatchView* dev, int n, hipStream_t st) {
-  // one workgroup per view: the many-chart barrier needs all its workgroups
-  // resident at once, which kOrderGroups times the views need not be
-  if (n > 0) k_sizes_order_b<<<dim3(1, n), kOrderThreads, 0, st>>>(dev);
+  if (n > 0) k_sizes_order_b<<<dim3(kOrderGroups, n), kOrderThreads, 0, st>>>(dev);
   return hipGetLastError();
 }
 

@@ -167,6 +167,28 @@ def test_batch_many_chart_views(launch):
     ctx.close()
 
 
+def test_many_chart_order_under_concurrency():
+    """24 views with thousands of charts on 24 streams at once: far more
+    order workgroups than the device holds at one time, so most frames'
+    chunks are claimed by whichever of their workgroups run first; every view
+    must still equal the oracle."""
+    import paper_2502_17712_amd as fa
+    picks = [(k, om) for k in (0, 2, 4, 6, 8, 10) for om in (4096, 2048)]
+    views = [scenes.scatter_frame(k, count=6000, atlas_size=om) for k, om in picks] * 2
+    ctx = fa.Context(views[0].num_triangles, views[0].num_vertices, max_charts=8192,
+                     max_atlas=4096, max_views=24, tuning_table=None)
+    ctx.set_tuning(fa.FA_TUNE_BATCH_LAUNCH, 0)   # one stream per view
+    mesh = mesh_for(views[0])
+    want = [oracle.build_frame(v) for v in views[:len(picks)]] * 2
+    assert min(w["num_charts"] for w in want) > 1024
+    for rep in range(2):
+        print(f"[gpu] 24 concurrent many-chart views, pass {rep}", flush=True)
+        for g, r in zip(_run_batch(ctx, views, mesh), want):
+            assert g["meta"]["status"] == 0
+            compare(g, r)
+    ctx.close()
+
+
 def test_batch_graph_after_evict():
     """A cached batch graph must not outlive the adjacency it reads: evict the
     scene, rebuild it, replay the same descriptors."""
