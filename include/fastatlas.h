@@ -23,8 +23,11 @@
  * - The synchronous return value reports argument and capacity errors found
  *   on the host (FA_ERR_INVALID_ARG, FA_ERR_CAPACITY, FA_ERR_OUT_OF_MEMORY,
  *   FA_ERR_DEVICE). Conditions discovered on the device (no candidate scale
- *   fits: FA_ERR_NOFIT; more charts than max_charts: FA_ERR_CAPACITY) are
- *   written to meta->status when the stream work completes.
+ *   fits: FA_ERR_NOFIT; more charts than max_charts: FA_ERR_CAPACITY; a
+ *   bounded wait between the workgroups of the chart order of a frame with
+ *   more than 1024 charts that gave up, which the ordering's design rules out
+ *   short of a device fault: FA_ERR_DEVICE) are written to meta->status when
+ *   the stream work completes.
  * - A context is not thread-safe: use it from one host thread at a time.
  *   Calls on one context must not overlap on different streams (they share
  *   the context's scratch); use one context per concurrent stream.

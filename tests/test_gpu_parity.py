@@ -239,8 +239,11 @@ def _oracle_pack(sizes, omega, J=64, g=1, mmin=2):
     return js, table, pl
 
 
+# 1024 and 1025 boxes sit on either side of the one-workgroup order; above
+# it the order runs in 32 chunks (1025: a short last chunk)
 @pytest.mark.parametrize("n,omega,seed", [(0, 1024, 0), (1, 64, 1), (7, 64, 2), (1000, 1024, 3),
-                                          (20000, 4096, 4), (60000, 8192, 5)])
+                                          (1024, 1024, 6), (1025, 2048, 7), (20000, 4096, 4),
+                                          (33000, 4096, 8), (60000, 8192, 5)])
 def test_pack_boxes(n, omega, seed):
     rng = np.random.default_rng(seed)
     # heavy-tailed sizes: many tiny boxes, some large ones
