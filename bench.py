@@ -293,7 +293,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the no-occupancy, copy, visibility and reuse measurements")
     ap.add_argument("--serve-rate", type=float, nargs="+",
-                    default=[60.0, 250.0, 1000.0, 2000.0, 5000.0, 10000.0, 20000.0])
+                    default=[60.0, 250.0, 1000.0, 2000.0, 5000.0, 10000.0, 20000.0, 50000.0])
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 4 plain device copies of 256 MiB (counter calibration)")
@@ -739,11 +739,12 @@ def main():
                                           coarse=pz.coarse))
             return out_
         served = {}
-        for slots in (8, 1):
+        # continuous: 8 slots of one request; fifo: one slot; micro_batched:
+        # 4 slots of up to 8 same-scene requests in one batched call
+        for kind, slots, nb in (("continuous", 8, 1), ("fifo", 1, 1), ("micro_batched", 4, 8)):
             srv = serve.Server(smeshes, slots=slots, hbm_budget=16 << 30, max_atlas=4096,
-                               tuning={k_: ctx.get_tuning(k_) for k_ in TUNED})
-            srv.run(make_reqs(max(args.serve_rate), 64))  # warm-up
-            kind = "continuous" if slots > 1 else "fifo"
+                               tuning={k_: ctx.get_tuning(k_) for k_ in TUNED}, batch=nb)
+            srv.run(make_reqs(max(args.serve_rate), 256))  # warm-up (fills the output pool)
             served[kind] = {}
             for lam in args.serve_rate:
                 reqs = make_reqs(lam, min(args.serve_requests, int(lam * 5) + 64))
@@ -751,7 +752,7 @@ def main():
                 res_ = srv.run(reqs)
                 wall3 = time.perf_counter() - w3
                 assert all(r.meta["status"] == 0 for r in res_)
-                served[kind][f"{lam:g}"] = dict(slots=slots, offered_req_per_s=lam,
+                served[kind][f"{lam:g}"] = dict(slots=slots, batch=nb, offered_req_per_s=lam,
                                                  **serve.summarize(res_, wall3))
             if slots > 1:
                 # the same stream with the visible sets computed on the device
@@ -761,8 +762,9 @@ def main():
                 res_ = srv.run(reqs)
                 wall3 = time.perf_counter() - w3
                 assert all(r.meta["status"] == 0 for r in res_)
-                served["continuous_device_visibility"] = {f"{lam:g}": dict(
-                    slots=slots, offered_req_per_s=lam, **serve.summarize(res_, wall3))}
+                served[kind + "_device_visibility"] = {f"{lam:g}": dict(
+                    slots=slots, batch=nb, offered_req_per_s=lam,
+                    **serve.summarize(res_, wall3))}
             srv.close()
         log("served:", json.dumps(served))
 

@@ -158,7 +158,9 @@ typedef struct fa_atlas_meta {
   float rate;            /* requested texels per pixel (per axis)                */
   int64_t occupied_texels; /* texels claimed in the occupancy map (0 if none)    */
   int64_t visible_triangles;
-  int64_t large_tiles;   /* diagnostic: 16x16-texel tiles rasterized cooperatively */
+  int64_t large_tiles;   /* diagnostic: 16x16-texel tiles rasterized cooperatively
+                            by the occupancy kernels that ran (batched launches
+                            split the work their own way)                       */
 } fa_atlas_meta;
 
 typedef struct fa_atlas_out {

@@ -6,6 +6,7 @@ table, placements, layout meta and occupancy; UVs within 1e-4 texels (they
 are computed with the same float32 operations, so they are expected to be
 bit-identical too).
 """
+import collections
 import sys
 
 import numpy as np
@@ -465,6 +466,73 @@ def test_serve_mix_equals_alone():
         assert r.meta["status"] == 0
     ivs = sorted((r.start, r.finish) for r in out)
     assert all(s1 >= f0 - 1e-3 for (_, f0), (s1, _) in zip(ivs, ivs[1:]))
+
+
+def test_serve_batched_mix_equals_alone():
+    """Micro-batched serving: requests that arrive together are atlased in
+    batched calls of up to 6 views of one scene; each request's results,
+    written into recycled output buffers full of stale values, are identical
+    to the same request run alone, with precomputed and device-computed
+    visible sets."""
+    import paper_2502_17712_amd as fa
+    from paper_2502_17712_amd import serve
+    from synth import requests as rq
+    meshes_np = rq.scene_meshes()
+    meshes = {k: fa.Mesh(p, t, key) for k, (p, t, key) in meshes_np.items()}
+    pools = {"grid": rq.pose_pool("grid", 4, seed=1), "orbit": rq.pose_pool("orbit", 4, seed=2),
+             "city": rq.pose_pool("city", 3, seed=3)}
+    stream = rq.poisson_stream(5000.0, 36, pools, clients=8, seed=5)
+    vis = {(s, i): torch.as_tensor(pools[s][i].visible).cuda() for s in pools
+           for i in range(len(pools[s]))}
+    reqs = []
+    for rid, (a, c, s, i, om, r) in enumerate(stream):
+        pz = pools[s][i]
+        # every third request leaves its visible set to the device
+        reqs.append(serve.Request(rid, s, None if rid % 3 == 2 else vis[(s, i)], pz.view_proj,
+                                  pz.width, pz.height, om, r, arrival=a * 0.01, client=c,
+                                  eye=tuple(pz.eye), near=pz.near, coarse=pz.coarse))
+    print("[gpu] micro-batched serve of 36 requests, 2 slots of 6 views", flush=True)
+    srv = serve.Server(meshes, slots=2, hbm_budget=8 << 30, max_charts=8192, max_atlas=4096,
+                       batch=6)
+    ctx0 = srv.slots[0][0]
+    for q in reqs:  # stale buffers in the pool: every output element must be rewritten
+        key = (q.scene, q.atlas_size)
+        if len(srv.pool[key]) < 2:
+            o = ctx0.outputs(meshes[q.scene], q.atlas_size)
+            for t in (o.chart_of_tri, o.chart_of_vert, o.charts, o.occupancy, o.meta,
+                      o.candidates):
+                t.fill_(0x5A5A5A5A)
+            o.uv.fill_(1234.5)
+            srv.pool[key].append(o)
+    torch.cuda.synchronize()
+    res = {r.rid: r for r in srv.run(reqs, keep_outputs=True)}
+    srv.close()
+    assert sorted(res) == [q.rid for q in reqs]
+    # batches formed: several requests share a slot and a start
+    groups = collections.Counter((r.slot, r.start) for r in res.values())
+    assert max(groups.values()) >= 2, groups
+    alone = fa.Context(max(m.num_triangles for m in meshes.values()),
+                       max(m.num_vertices for m in meshes.values()), max_charts=8192,
+                       max_atlas=4096)
+    for q in reqs:
+        mesh = meshes[q.scene]
+        v = q.visible
+        if v is None:
+            v = alone.visibility(mesh, q.view_proj, q.width, q.height, q.eye, q.near, q.coarse)
+        o = alone.build_atlas(mesh, v, q.view_proj, q.width, q.height, q.atlas_size, q.rate)
+        torch.cuda.synchronize()
+        a, b = o.to_numpy(), res[q.rid].out.to_numpy()
+        for k in ("chart_of_tri", "chart_of_vert", "occupancy", "candidates"):
+            assert np.array_equal(a[k], b[k]), (q.rid, k)
+        assert np.array_equal(a["charts"], b["charts"]), q.rid
+        assert np.array_equal(bits(a["uv"]), bits(b["uv"])), q.rid
+        # the meta read from pinned host memory is the output's own record
+        assert b["meta"] == res[q.rid].meta, q.rid
+        # large_tiles counts the cooperative raster tiles of whichever
+        # occupancy kernels ran (batched launches split the work their own way)
+        drop = lambda m: {k: v for k, v in m.items() if k != "large_tiles"}
+        assert drop(a["meta"]) == drop(b["meta"]), q.rid
+    alone.close()
 
 
 @pytest.mark.parametrize("link,hooks", [(0, 0), (0, 1), (0, 2), (0, 3), (0, 4), (0, 5), (1, 0),
