@@ -159,8 +159,7 @@ typedef struct fa_atlas_meta {
   int64_t occupied_texels; /* texels claimed in the occupancy map (0 if none)    */
   int64_t visible_triangles;
   int64_t large_tiles;   /* diagnostic: 16x16-texel tiles rasterized cooperatively
-                            by the occupancy kernels that ran (batched launches
-                            split the work their own way)                       */
+                            (depends on the small_texels knob)                  */
 } fa_atlas_meta;
 
 typedef struct fa_atlas_out {
@@ -386,8 +385,11 @@ int fa_get_tuning(fa_ctx* ctx, int knob);
  * count) at atlas side omega with the context's J uses the first entry with
  * t_lo <= T <= t_hi, omega equal (0: any) and J equal (0:
  * any); frames no entry matches use the fa_set_tuning values. Applies to
- * fa_build_atlas, fa_build_dual_atlas and the per-view batch path (batched
- * launches use the context's values). Results never depend on the knobs.
+ * fa_build_atlas, fa_build_dual_atlas and the per-view batch path; batched
+ * launches take pack_block, small_texels and lane_texels from the entry
+ * every view of the call matches (the context's values when the views match
+ * different entries) and always run the vertex-hashed union-find tiles.
+ * Results never depend on the knobs.
  * Errors: FA_ERR_INVALID_ARG for a null argument, a malformed line or a value
  * fa_set_tuning would refuse (the previous table is kept). An empty text
  * clears the table. */

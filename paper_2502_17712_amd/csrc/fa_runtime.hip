@@ -686,9 +686,10 @@ static int enqueue_views(fa_ctx* ctx, const fa_mesh* mesh, Scene* sc, int32_t n,
 }
 
 // Batched launches: the views' descriptors are in ctx->bv_dev; views
-// [r0, r0 + S) run as one round on slots 0..S-1, one launch per stage.
+// [r0, r0 + S) run as one round on slots 0..S-1, one launch per stage, with
+// the packing and raster-split knobs kn.
 static int enqueue_batched(fa_ctx* ctx, const fa_mesh* mesh, Scene* sc, int32_t n,
-                           hipStream_t st) {
+                           const Knobs& kn, hipStream_t st) {
   const int S = (int)ctx->slots.size();
   const int64_t T = mesh->num_triangles, V = mesh->num_vertices;
   hipError_t e = hipSuccess;
@@ -698,11 +699,28 @@ static int enqueue_batched(fa_ctx* ctx, const fa_mesh* mesh, Scene* sc, int32_t 
     const BatchView* d = ctx->bv_dev + r0;
     ok(launch_charts_batched(d, m, mesh->positions, mesh->indices, sc->nbr, T, V, st));
     ok(launch_order_batched(d, m, st));
-    ok(launch_pack_batched(d, m, ctx->cfg.num_scales, ctx->cfg.max_charts, ctx->pack_block, st));
-    ok(launch_occupancy_batched(d, m, mesh->indices, T, V, ctx->small_texels, ctx->lane_texels,
-                                st));
+    ok(launch_pack_batched(d, m, ctx->cfg.num_scales, ctx->cfg.max_charts, kn.pack_block, st));
+    ok(launch_occupancy_batched(d, m, mesh->indices, T, V, kn.small_texels, kn.lane_texels, st));
   }
   return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+
+// The knobs of a batched round: the tuning-table entry of the views' shape
+// when every view picks the same one, else the context's own. (The batched
+// union-find is always the vertex-hashed tile mode, whatever the entry's
+// hook mode; the charts are the same in every mode.)
+static Knobs batch_knobs(const fa_ctx* ctx, int64_t T, int32_t n,
+                         const std::vector<FrameParams>& ps) {
+  FrameParams q = ps[0];
+  const Knobs k0 = frame_knobs(ctx, T, &q);
+  for (int i = 1; i < n; ++i) {
+    q = ps[i];
+    const Knobs ki = frame_knobs(ctx, T, &q);
+    if (ki.pack_block != k0.pack_block || ki.small_texels != k0.small_texels ||
+        ki.lane_texels != k0.lane_texels)
+      return Knobs{ctx->pack_block, ctx->small_texels, ctx->lane_texels, ctx->uf_link_init};
+  }
+  return k0;
 }
 
 // The batched launches cover the default configuration: vertex-hashed
@@ -735,6 +753,7 @@ int fa_build_atlas_batch(fa_ctx* ctx, const fa_mesh* mesh, int32_t n, const fa_v
   rc = get_scene(ctx, mesh, st, &sc);
   if (rc) return rc;
   const bool batched = batchable(ctx, mesh, n, views);
+  const Knobs bkn = batch_knobs(ctx, mesh->num_triangles, n, ps);
   if (batched) {
     // descriptors of every view (view i on slot i % S), staged in pinned
     // memory once the previous batch's upload has been read
@@ -760,7 +779,7 @@ int fa_build_atlas_batch(fa_ctx* ctx, const fa_mesh* mesh, int32_t n, const fa_v
                        st) != hipSuccess ||
         hipEventRecord(ctx->ev_upload, st) != hipSuccess)
       return FA_ERR_DEVICE;
-    if (!ctx->batch_graph) return enqueue_batched(ctx, mesh, sc, n, st);
+    if (!ctx->batch_graph) return enqueue_batched(ctx, mesh, sc, n, bkn, st);
   }
   const bool timing = ctx->timing;
   ctx->timing = false;  // no stage events inside a batch
@@ -783,7 +802,7 @@ int fa_build_atlas_batch(fa_ctx* ctx, const fa_mesh* mesh, int32_t n, const fa_v
       ctx->timing = timing;
       return FA_ERR_DEVICE;
     }
-    rc = batched ? enqueue_batched(ctx, mesh, sc, n, ctx->cap_stream)
+    rc = batched ? enqueue_batched(ctx, mesh, sc, n, bkn, ctx->cap_stream)
                  : enqueue_views(ctx, mesh, sc, n, views, ps, ctx->cap_stream);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);

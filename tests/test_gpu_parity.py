@@ -527,11 +527,7 @@ def test_serve_batched_mix_equals_alone():
         assert np.array_equal(a["charts"], b["charts"]), q.rid
         assert np.array_equal(bits(a["uv"]), bits(b["uv"])), q.rid
         # the meta read from pinned host memory is the output's own record
-        assert b["meta"] == res[q.rid].meta, q.rid
-        # large_tiles counts the cooperative raster tiles of whichever
-        # occupancy kernels ran (batched launches split the work their own way)
-        drop = lambda m: {k: v for k, v in m.items() if k != "large_tiles"}
-        assert drop(a["meta"]) == drop(b["meta"]), q.rid
+        assert a["meta"] == b["meta"] == res[q.rid].meta, q.rid
     alone.close()
 
 
