@@ -92,6 +92,9 @@ __device__ __forceinline__ void uf_join(int32_t* parent, int u, int v) {
   }
 }
 
+constexpr int kProVerts = 4;  // vertices per prologue thread
+static_assert(kTriTile % kBlock == 0, "prologue threads take whole strides of a tile");
+
 // Prologue of a frame: frame state, per-vertex scratch (vertex minima and
 // chart_of_vert = -1; clip positions are computed where they are read),
 // chart_of_tri = -1, the union-find start of every visible triangle and the
@@ -115,18 +118,25 @@ __device__ __forceinline__ void k_prologue_body(int64_t V, int32_t* __restrict__
       *st = s;
       *big_counter = 0ull;
     }
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= V) return;
-    astore(&vmin[v], INT_MAX);
-    cov[v] = -1;
+    // kProVerts vertices per thread, a workgroup apart (contiguous stores)
+    const int64_t v0 = (int64_t)blockIdx.x * (blockDim.x * kProVerts) + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kProVerts; ++k) {
+      const int64_t v = v0 + (int64_t)k * blockDim.x;
+      if (v < V) {
+        astore(&vmin[v], INT_MAX);
+        cov[v] = -1;
+      }
+    }
     return;
   }
+  // four triangles of the tile per thread, a workgroup apart
   const unsigned tile = blockIdx.x - vblocks;
-  const int64_t base = (int64_t)tile * kTriTile + (int64_t)threadIdx.x * 4;
+  const int64_t base = (int64_t)tile * kTriTile + (int64_t)threadIdx.x;
   uint32_t nv = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int64_t t = base + k;
+  for (int k = 0; k < kTriTile / kBlock; ++k) {
+    const int64_t t = base + (int64_t)k * kBlock;
     if (t >= T) break;
     cot[t] = -1;
     if (!vis[t]) continue;
@@ -974,7 +984,7 @@ unsigned visible_grid(int64_t T) {
 hipError_t launch_prologue(int64_t V, const uint8_t* vis, const int32_t* nbr,
                            int64_t T, const FrameParams& p, const Work& w, int32_t* cov,
                            int32_t* cot, int uf_init, Marker& mk, hipStream_t st) {
-  const unsigned vb = std::max(1u, grid_for(V, kBlock));
+  const unsigned vb = std::max(1u, grid_for(V, kBlock * kProVerts));
   const unsigned tt = grid_for(T, kTriTile);
   k_prologue<<<vb + tt, kBlock, 0, st>>>(V, w.vmin, cov, vis, nbr, T, w.parent,
                                          cot, w.tile_vis, uf_init, vb, w.state,
@@ -1076,7 +1086,7 @@ hipError_t launch_charts_batched(const BatchView* dev, int n, const float* pos,
                                  const int32_t* idx, const int32_t* nbr, int64_t T, int64_t V,
                                  hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const unsigned vb = std::max(1u, grid_for(V, kBlock));
+  const unsigned vb = std::max(1u, grid_for(V, kBlock * kProVerts));
   const unsigned tt = grid_for(T, kTriTile);
   const unsigned vt = std::max(1u, tt);
   k_prologue_b<<<dim3(vb + tt, n), kBlock, 0, st>>>(dev, V, nbr, T, vb);

@@ -50,27 +50,47 @@ __device__ __forceinline__ float2 to_atlas(const ChartXform& m, float X, float Y
   return make_float2((m.ox + lx * m.s) * m.q, (m.oy + ly * m.s) * m.q);
 }
 
-__device__ __forceinline__ void uv_vertex(int64_t v, const FrameParams& p,
-                                          const float* __restrict__ pos,
-                                          const int32_t* __restrict__ cov,
-                                          const fa_chart* __restrict__ charts,
-                                          float2* __restrict__ uv,
-                                          const FrameState* __restrict__ stp) {
+// Per-vertex UVs of workgroup ub of a UV grid (k_uv, or the workgroups past
+// the small-footprint raster's own, which need the same placement and run
+// beside the raster instead of after it): each thread takes PER vertices a
+// workgroup apart, so every load and store of a wave is one contiguous run,
+// and issues their chart loads before any dependent load.
+template <int PER>
+__device__ __forceinline__ void uv_block(unsigned ub, const FrameParams& p,
+                                         const float* __restrict__ pos,
+                                         const int32_t* __restrict__ cov,
+                                         const fa_chart* __restrict__ charts,
+                                         float2* __restrict__ uv, int64_t V,
+                                         const FrameState* __restrict__ stp) {
   const FrameState st = *stp;
-  const int c = st.status == FA_OK ? cov[v] : -1;
-  float2 r = make_float2(__builtin_nanf(""), __builtin_nanf(""));
-  if (c >= 0) {  // a vertex without a chart needs no position
-    const float4 q = clip_of(pos, v, p);
-    if (q.w > 0.0f) r = to_atlas(chart_xform(charts[c], p, st), q.x, q.y, q.w);
+  const int64_t v0 = (int64_t)ub * (blockDim.x * PER) + threadIdx.x;
+  int c[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int64_t v = v0 + (int64_t)k * blockDim.x;
+    c[k] = (v < V && st.status == FA_OK) ? cov[v] : -1;
   }
-  uv[v] = r;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int64_t v = v0 + (int64_t)k * blockDim.x;
+    float2 r = make_float2(__builtin_nanf(""), __builtin_nanf(""));
+    if (c[k] >= 0) {  // a vertex without a chart needs no position
+      const float4 q = clip_of(pos, v, p);
+      if (q.w > 0.0f) r = to_atlas(chart_xform(charts[c[k]], p, st), q.x, q.y, q.w);
+    }
+    if (v < V) uv[v] = r;
+  }
 }
+
+// Vertices per UV thread: 4 for one frame; 8 in batched launches, whose
+// grids hold every view's UV workgroups (fewer, longer waves launch faster
+// there, and cost one frame about 0.2 us).
+constexpr int kUvPerFrame = 4, kUvPerBatch = 8;
 
 __global__ void k_uv(int64_t V, FrameParams p, const float* __restrict__ pos,
                      const int32_t* __restrict__ cov, const fa_chart* __restrict__ charts,
                      float2* __restrict__ uv, const FrameState* __restrict__ stp) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < V) uv_vertex(v, p, pos, cov, charts, uv, stp);
+  uv_block<kUvPerFrame>(blockIdx.x, p, pos, cov, charts, uv, V, stp);
 }
 
 // Per-corner UVs of edge-connected charts: corner k of triangle t is its
@@ -382,6 +402,7 @@ __device__ __forceinline__ uint32_t tiles_of(const Footprint& fp, uint32_t* tile
   return *tiles_x * (uint32_t)((fp.ty1 - fp.ty0 + kOccTile) / kOccTile);
 }
 
+template <int UV_PER>
 __device__ __forceinline__ void k_occ_small_body(
     const int32_t* __restrict__ idx, const int32_t* __restrict__ vlist, FrameParams p,
     const float* __restrict__ pos, const int32_t* __restrict__ cot,
@@ -394,10 +415,7 @@ __device__ __forceinline__ void k_occ_small_body(
   __shared__ uint32_t wcnt[kOccSmallBlock / kWave], wtil[kOccSmallBlock / kWave];
   __shared__ unsigned long long bbase;
   if (blockIdx.x >= occ_blocks) {
-    // the blocks past the raster's own compute the per-vertex UVs (they need
-    // the same placement and run beside the raster instead of after it)
-    const int64_t v = (int64_t)(blockIdx.x - occ_blocks) * blockDim.x + threadIdx.x;
-    if (v < V) uv_vertex(v, p, pos, cov, charts, uv, stp);
+    uv_block<UV_PER>(blockIdx.x - occ_blocks, p, pos, cov, charts, uv, V, stp);
     return;
   }
   const FrameState st = *stp;
@@ -483,7 +501,9 @@ __global__ __launch_bounds__(kOccSmallBlock) void k_occ_small(
     int lane_texels, unsigned long long* __restrict__ big_counter,
     const FrameState* __restrict__ stp, unsigned occ_blocks, int64_t V,
     const int32_t* __restrict__ cov, float2* __restrict__ uv) {
-  k_occ_small_body(idx, vlist, p, pos, cot, charts, chart_tex, occ, big, big_fp, big_cap, small_texels, lane_texels, big_counter, stp, occ_blocks, V, cov, uv);
+  k_occ_small_body<kUvPerFrame>(idx, vlist, p, pos, cot, charts, chart_tex, occ, big, big_fp,
+                                big_cap, small_texels, lane_texels, big_counter, stp, occ_blocks,
+                                V, cov, uv);
 }
 
 // Queued footprints: their texel ranges cut into 16x16 tiles, concatenated,
@@ -693,7 +713,7 @@ __global__ __launch_bounds__(kOccSmallBlock) void k_occ_small_b(
     const BatchView* __restrict__ bv, const int32_t* __restrict__ idx, uint32_t big_cap,
     int small_texels, int lane_texels, unsigned occ_blocks, int64_t V) {
   const BatchView& v = bv[blockIdx.y];
-  k_occ_small_body(idx, v.w.vlist, v.p, v.w.pos, v.cot, v.charts, v.w.chart_tex, v.occ, v.w.big,
+  k_occ_small_body<kUvPerBatch>(idx, v.w.vlist, v.p, v.w.pos, v.cot, v.charts, v.w.chart_tex, v.occ, v.w.big,
                    v.w.big_fp, big_cap, small_texels, lane_texels, v.w.big_counter, v.w.state,
                    occ_blocks, V, v.cov, reinterpret_cast<float2*>(v.uv));
 }
@@ -717,7 +737,7 @@ __global__ __launch_bounds__(kCountBlock) void k_occ_count_meta_b(
 hipError_t launch_uv(const int64_t V, const FrameParams& p, const Work& w, const int32_t* cov,
                      const fa_chart* charts, float* uv, hipStream_t st) {
   if (V > 0)
-    k_uv<<<(unsigned)((V + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+    k_uv<<<(unsigned)((V + kBlock * kUvPerFrame - 1) / (kBlock * kUvPerFrame)), kBlock, 0, st>>>(
         V, p, w.pos, cov, charts, reinterpret_cast<float2*>(uv), w.state);
   return hipGetLastError();
 }
@@ -744,7 +764,8 @@ hipError_t launch_occupancy(const int32_t* idx, int64_t T, const FrameParams& p,
   const uint32_t cap = (uint32_t)std::min<int64_t>(2 * std::max<int64_t>(T, 1), kBigCap);
   const int64_t V = x.uv ? x.V : 0;
   const unsigned occ_blocks = T > 0 ? visible_grid(T) : 0;
-  const unsigned uv_blocks = (unsigned)((V + kOccSmallBlock - 1) / kOccSmallBlock);
+  const unsigned uv_blocks = (unsigned)((V + kOccSmallBlock * kUvPerFrame - 1) /
+                                         (kOccSmallBlock * kUvPerFrame));
   if (occ_blocks + uv_blocks > 0)
     k_occ_small<<<occ_blocks + uv_blocks, kOccSmallBlock, 0, st>>>(
         idx, w.vlist, p, w.pos, cot, charts, w.chart_tex, occ, w.big, w.big_fp, cap, small_texels,
@@ -1119,7 +1140,8 @@ hipError_t launch_occupancy_batched(const BatchView* dev, int n, const int32_t* 
   if (n <= 0) return hipSuccess;
   const uint32_t cap = (uint32_t)std::min<int64_t>(2 * std::max<int64_t>(T, 1), kBigCap);
   const unsigned occ_blocks = T > 0 ? visible_grid(T) : 0;
-  const unsigned uv_blocks = (unsigned)((V + kOccSmallBlock - 1) / kOccSmallBlock);
+  const unsigned uv_blocks = (unsigned)((V + kOccSmallBlock * kUvPerBatch - 1) /
+                                         (kOccSmallBlock * kUvPerBatch));
   if (occ_blocks + uv_blocks > 0)
     k_occ_small_b<<<dim3(occ_blocks + uv_blocks, n), kOccSmallBlock, 0, st>>>(
         dev, idx, cap, small_texels, lane_texels, occ_blocks, V);
