@@ -358,13 +358,14 @@ __global__ __launch_bounds__(NT) void k_uf_local(const uint8_t* __restrict__ vis
 
 // Hook mode 5: the tile of TILE list entries is joined in LDS through shared
 // vertices instead of shared edges (a shared edge is a shared vertex): every
-// vertex reference is entered into an LDS hash table of (vertex << 32 | first
-// entry) words, and an entry that finds its vertex already there joins that
-// entry's set. This also merges the pieces of a chart that touch only at a
-// vertex inside the tile. A vertex that finds no free slot is skipped (the
-// global vertex pass merges through every vertex anyway). Then, as in mode 4,
-// each entry's parent becomes its local root and its vertices' minima are
-// lowered to it.
+// vertex reference is entered into an LDS hash table of (vertex << 32 |
+// entry) words, where the first entry to claim a vertex owns it; every entry
+// is joined with the owners of its vertices, and so all entries naming one
+// vertex end in one set. This also merges the pieces of a chart that touch
+// only at a vertex inside the tile. A vertex that finds no free slot is
+// skipped (the global vertex pass merges through every vertex anyway). Then,
+// as in mode 4, each entry's parent becomes its local root and its vertices'
+// minima are lowered to it.
 // Workgroups past the tiles fill the occupancy map with -1 (occ_fill, n4
 // 16-byte words) while the tiles' dependent loads leave memory bandwidth free.
 template <int TILE, int NT, int HS>
@@ -414,24 +415,67 @@ __device__ __forceinline__ void k_uf_local_vertex_body(const int32_t* __restrict
   }
   for (int h = threadIdx.x; h < HS; h += NT) tab[h] = kFree;
   __syncthreads();
+  // 1. every vertex reference enters the hash table; the first entry to
+  //    claim a vertex's slot owns it
+  int hs[kPer][3];  // slot of each reference, -1 when the table had no room
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     const int i = threadIdx.x + k * NT;
-    if (i >= cnt) continue;
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
+      hs[k][e] = -1;
+      if (i >= cnt) continue;
       const int v = vk[k][e];
       const unsigned long long mine = ((unsigned long long)(uint32_t)v << 32) | (uint32_t)i;
       uint32_t h = ((uint32_t)v * 2654435761u) & (HS - 1);
       for (int probe = 0; probe < 32; ++probe) {
         const unsigned long long old = atomicCAS(&tab[h], kFree, mine);
-        if (old == kFree) break;                    // first entry with this vertex
-        if ((uint32_t)(old >> 32) == (uint32_t)v) {  // joined through the vertex
-          lds_join(lp, i, (int)(uint32_t)old);
+        if (old == kFree) {  // first entry with this vertex
+          hs[k][e] = (int)h;
+          break;
+        }
+        if ((uint32_t)(old >> 32) == (uint32_t)v) {  // another entry owns it
+          hs[k][e] = (int)h;
           break;
         }
         h = (h + 1) & (HS - 1);
       }
+    }
+  }
+  __syncthreads();
+  // 2. each entry starts linked to the smallest of itself and the owners of
+  //    its vertices (never above itself, so no cycles), then one step
+  //    towards that node's own start
+  int mo[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = threadIdx.x + k * NT;
+    mo[k] = i;
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+      if (hs[k][e] >= 0) mo[k] = min(mo[k], (int)(uint32_t)tab[hs[k][e]]);
+    if (i < cnt) lp[i] = mo[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = threadIdx.x + k * NT;
+    if (i >= cnt) continue;
+    const int q = lds_get(lp, mo[k]);
+    if (q != mo[k]) lds_put(lp, i, q);
+  }
+  __syncthreads();
+  // 3. each entry joins the owners of its other vertices (none when both
+  //    already hang from the same node)
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = threadIdx.x + k * NT;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      if (hs[k][e] < 0) continue;
+      const int o = (int)(uint32_t)tab[hs[k][e]];
+      if (o == mo[k] || lds_get(lp, o) == lds_get(lp, i)) continue;
+      lds_join(lp, i, o);
     }
   }
   __syncthreads();
@@ -441,8 +485,12 @@ __device__ __forceinline__ void k_uf_local_vertex_body(const int32_t* __restrict
     if (i >= cnt) continue;
     const int r = lv[lds_root(lp, i)];
     astore(&parent[tk[k]], r);
+    // every reference to a vertex in the tile is in this set, so the owner's
+    // reference alone lowers the vertex minimum (and each reference that
+    // found no slot lowers its own)
 #pragma unroll
-    for (int e = 0; e < 3; ++e) atomicMin(&vmin[vk[k][e]], r);
+    for (int e = 0; e < 3; ++e)
+      if (hs[k][e] < 0 || (int)(uint32_t)tab[hs[k][e]] == i) atomicMin(&vmin[vk[k][e]], r);
   }
 }
 template <int TILE, int NT, int HS>
@@ -475,11 +523,18 @@ __global__ void k_uf_vertex_min(const int32_t* __restrict__ idx,
 // its vertices, merging charts that share only a vertex. parent[t] is an
 // ancestor of t: a vertex whose minimum equals it needs no join, which skips
 // most of them; along a tile border many lanes of a wave name the same
-// (parent, minimum) pair, and only the lowest lane of each pair joins.
+// (parent, minimum) pair, and only the lowest lane of each pair joins, once
+// per workgroup (an LDS set of the pairs taken).
 __device__ __forceinline__ void k_uf_vertex_hook_body(const int32_t* __restrict__ idx,
                                  const int32_t* __restrict__ vlist, int32_t* parent,
                                  const int32_t* __restrict__ vmin,
                                  const FrameState* __restrict__ st) {
+  // ordered (parent, minimum) pairs this workgroup has joined or is
+  // joining: a repeated pair needs no second join
+  constexpr int kPairSlots = 512;
+  __shared__ unsigned long long pairs[kPairSlots];
+  for (int h = threadIdx.x; h < kPairSlots; h += blockDim.x) pairs[h] = ~0ull;
+  __syncthreads();
   const int nv = st->visible;
   const int lane = lane_id();
   for (int i0 = blockIdx.x * blockDim.x; i0 < nv; i0 += gridDim.x * blockDim.x) {
@@ -504,7 +559,21 @@ __device__ __forceinline__ void k_uf_vertex_hook_body(const int32_t* __restrict_
         if (lane == leader) keep = true;
         todo &= ~__ballot(want && a == la && b == lb);
       }
-      if (keep) uf_join(parent, a, b);
+      if (keep) {
+        const unsigned long long key = ((unsigned long long)(uint32_t)a << 32) | (uint32_t)b;
+        uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 40) & (kPairSlots - 1);
+        bool fresh = true;
+        for (int probe = 0; probe < 16; ++probe) {
+          const unsigned long long old = atomicCAS(&pairs[h], ~0ull, key);
+          if (old == ~0ull) break;
+          if (old == key) {
+            fresh = false;
+            break;
+          }
+          h = (h + 1) & (kPairSlots - 1);
+        }
+        if (fresh) uf_join(parent, a, b);  // a full table only costs extra joins
+      }
     }
   }
 }
