@@ -25,7 +25,8 @@
  *   FA_ERR_DEVICE). Conditions discovered on the device (no candidate scale
  *   fits: FA_ERR_NOFIT; more charts than max_charts: FA_ERR_CAPACITY; a
  *   bounded wait between the workgroups of the chart order of a frame with
- *   more than 1024 charts that gave up, which the ordering's design rules out
+ *   more than 2048 charts (1024 for fa_pack_boxes) that gave up, which the
+ *   ordering's design rules out
  *   short of a device fault: FA_ERR_DEVICE) are written to meta->status when
  *   the stream work completes.
  * - A context is not thread-safe: use it from one host thread at a time.

@@ -257,7 +257,8 @@ __device__ __forceinline__ void chart_size(const FrameParams& p, const uint4 e, 
 // floor(oriented width) + 1, are laid out in chart order (exclusive scan);
 // a total above the capacity ends the frame with FA_ERR_CAPACITY.
 constexpr int kOrderThreads = 1024;
-constexpr int kOrderLds = 1024;
+constexpr int kOrderLds = 2048;     // most charts whose keys, values and sizes fit in LDS
+constexpr int kOrderSingle = 1024;  // most charts one workgroup orders in global memory
 
 // The body for one placement of the keys and values (LDS or global memory),
 // so that every access of the sort has a known address space.
@@ -653,13 +654,14 @@ __device__ __forceinline__ void k_sizes_order_body(
   __shared__ int flag, slot;
   if (st->status != FA_OK) return;
   const int C = min(st->num_charts, p.max_charts);
-  if (gridDim.x > 1 && C > kOrderLds) {
+  const bool in_lds = from_accum && C <= kOrderLds;
+  if (gridDim.x > 1 && !in_lds && C > kOrderSingle) {
     order_multi(p, accum, charts, keys_a, vals_a, keys_b, vals_b, sorted_wh, from_accum, fp_off,
                 st, C, hist, part, base, wcnt, sh, sh64, &flag, &slot);
     return;
   }
   if (blockIdx.x != 0) return;
-  if (from_accum && C <= kOrderLds)
+  if (in_lds)
     order_body<true>(p, accum, charts, lk[0], lv[0], lk[1], lv[1], lwh, vals_a, sorted_wh,
                      from_accum, fp_off, st, C, base, wcnt, sh, sh64);
   else
