@@ -421,7 +421,11 @@ __device__ __forceinline__ void k_occ_small_body(
   const FrameState st = *stp;
   if (st.status != FA_OK) return;
   const int nv = st.visible;
-  const int lane = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  // the launch's block size, as a constant: a loop over a runtime wave count
+  // is unrolled eight times with live temporaries (100 instead of 89 VGPRs:
+  // four instead of five resident waves per SIMD)
+  constexpr int nw = kOccSmallBlock / kWave;
   constexpr unsigned long long kLow = (1ull << kSlotShift) - 1;
   for (int i0 = blockIdx.x * blockDim.x; i0 < nv; i0 += occ_blocks * blockDim.x) {
     const int i = i0 + threadIdx.x;

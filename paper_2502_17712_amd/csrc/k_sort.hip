@@ -579,6 +579,8 @@ __device__ __forceinline__ void order_multi(const FrameParams& p, const uint32_t
     const int lo = min(C, ch * chunk), hi = min(C, lo + chunk);
     if (fp_off) {
       long long run = 0, total = 0;  // earlier chunks' columns, all chunks'
+      // (four loads at a time: all 32 at once spill registers to scratch)
+#pragma unroll 4
       for (int g = 0; g < G; ++g) {
         const long long v = (long long)__hip_atomic_load(&part[g], __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
