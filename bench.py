@@ -285,7 +285,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--autotune", action="store_true",
-                    help="tune the knobs on the first frame first (default: library defaults)")
+                    help="tune the knobs per workload first and write a tuning table "
+                         "(default: the committed table)")
+    ap.add_argument("--tune-out", default="tuning_table.txt",
+                    help="where --autotune writes the table it found")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-dual", action="store_true")
@@ -399,8 +402,9 @@ def main():
         lines.append(autotune.table_line(500001, 1 << 30, 0, 64, ch,
                                          "2.2M-triangle city, 4096^2"))
         text = autotune.table_text(lines, "written by bench.py --autotune on one MI355X")
-        os.makedirs(os.path.join(HERE, "gpurun_out"), exist_ok=True)
-        with open(os.path.join(HERE, "gpurun_out", "tuning_gfx950.txt"), "w") as fh:
+        out_dir = os.path.dirname(os.path.abspath(args.tune_out))
+        os.makedirs(out_dir, exist_ok=True)
+        with open(args.tune_out, "w") as fh:
             fh.write(text)
         ctx.load_tuning_table(text)
         log("tuning table:\n" + text)
