@@ -158,6 +158,18 @@ def test_scatter_many_charts(frame, rate):
     compare(run_gpu(f, ctx_for()), r)
 
 
+@pytest.mark.parametrize("count,frame", [(1000, 2), (1500, 0), (1500, 3), (1800, 5),
+                                         (2200, 1)])
+def test_scatter_order_around_lds_capacity(count, frame):
+    """Frames of about 900 to 2100 charts: the chart order keeps up to 2048
+    charts in one workgroup's LDS and splits larger frames over 32 workgroups;
+    both sides of that limit match the oracle."""
+    f = scenes.scatter_frame(frame, count=count)
+    r = oracle.build_frame(f)
+    assert 800 <= r["num_charts"] <= 2200, r["num_charts"]
+    compare(run_gpu(f, ctx_for()), r)
+
+
 def test_city_frames_more():
     for fr in (9, 23):
         f = scenes.city_frame(fr)
