@@ -182,15 +182,45 @@ __device__ __forceinline__ uint32_t tiles_before(const uint32_t* __restrict__ cn
   return block_sum<uint32_t>(v, sh);
 }
 
+// Exclusive prefix of the tiles' visible counts, in place, by one
+// workgroup: each thread takes kScanPer consecutive tiles, one block scan
+// (the compaction of a batched launch then reads its tile's offset instead of
+// summing every earlier tile, which with many views in one launch costs more
+// than this extra launch; one frame keeps the sums).
+constexpr int kScanPer = 4;
+__device__ __forceinline__ void k_tile_scan_body(uint32_t* tile_vis, unsigned tiles) {
+  __shared__ uint32_t sh[1024 / kWave];
+  uint32_t run = 0;
+  for (unsigned b0 = 0; b0 < tiles; b0 += blockDim.x * kScanPer) {
+    const unsigned i0 = b0 + threadIdx.x * kScanPer;
+    uint32_t v[kScanPer], mine = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      v[k] = i0 + k < tiles ? tile_vis[i0 + k] : 0u;
+      mine += v[k];
+    }
+    uint32_t tot;
+    uint32_t at = run + block_incl_scan<uint32_t>(mine, sh, &tot) - mine;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      if (i0 + k < tiles) tile_vis[i0 + k] = at;
+      at += v[k];
+    }
+    run += tot;
+  }
+}
+
 // Stable compaction of the visible triangles into vlist (ascending index).
-// Each workgroup sums the visible counts of the tiles before its own (a few
-// thousand words at most) instead of waiting for a separate scan; the last
-// one records the total.
+// For one frame each workgroup sums the visible counts of the tiles before
+// its own (a few thousand words at most) instead of waiting for a separate
+// scan; batched launches scan first (scanned). The last workgroup records
+// the total.
 __device__ __forceinline__ void k_vis_compact_body(const uint8_t* __restrict__ vis, int64_t T,
                               const uint32_t* __restrict__ tile_vis, int32_t* __restrict__ vlist,
-                              FrameState* __restrict__ st) {
+                              FrameState* __restrict__ st, bool scanned = false) {
   __shared__ uint32_t sh[kBlock / kWave];
-  const uint32_t off = tiles_before(tile_vis, blockIdx.x, sh);
+  // scanned: tile_vis holds each tile's exclusive prefix (k_tile_scan_body)
+  const uint32_t off = scanned ? tile_vis[blockIdx.x] : tiles_before(tile_vis, blockIdx.x, sh);
   const int64_t base = (int64_t)blockIdx.x * kTriTile + (int64_t)threadIdx.x * 4;
   bool f[4];
   uint32_t mine = 0;
@@ -998,9 +1028,13 @@ __global__ void k_prologue_b(const BatchView* __restrict__ bv, int64_t V, const 
   k_prologue_body(V, v.w.vmin, v.cov, v.visible, nbr, T, v.w.parent, v.cot,
                   v.w.tile_vis, 0, vblocks, v.w.state, v.w.big_counter);
 }
+__global__ __launch_bounds__(1024) void k_tile_scan_b(const BatchView* __restrict__ bv,
+                                                      unsigned tiles) {
+  k_tile_scan_body(bv[blockIdx.y].w.tile_vis, tiles);
+}
 __global__ void k_vis_compact_b(const BatchView* __restrict__ bv, int64_t T) {
   const BatchView& v = bv[blockIdx.y];
-  k_vis_compact_body(v.visible, T, v.w.tile_vis, v.w.vlist, v.w.state);
+  k_vis_compact_body(v.visible, T, v.w.tile_vis, v.w.vlist, v.w.state, true);
 }
 __global__ __launch_bounds__(1024) void k_uf_local_vertex_b(const BatchView* __restrict__ bv,
                                                             const int32_t* __restrict__ idx) {
@@ -1160,6 +1194,7 @@ hipError_t launch_charts_batched(const BatchView* dev, int n, const float* pos,
   const unsigned vt = std::max(1u, tt);
   k_prologue_b<<<dim3(vb + tt, n), kBlock, 0, st>>>(dev, V, nbr, T, vb);
   if (T > 0) {
+    k_tile_scan_b<<<dim3(1, n), 1024, 0, st>>>(dev, tt);
     k_vis_compact_b<<<dim3(tt, n), kBlock, 0, st>>>(dev, T);
     k_uf_local_vertex_b<<<dim3(std::max(1u, grid_for(T, 2048)) + kFillGroups, n), 1024, 0, st>>>(
         dev, idx);
